@@ -1,0 +1,151 @@
+/*
+ * arbgpu — arbitrary-precision ball dot products and matrix products on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (Johansson 2019, Section 2 and Section 3): given balls
+ * x_i = [m_i +- r_i], y_i = [m'_i +- r'_i], an optional initial ball and a
+ * sub flag, compute a ball [m +- r] containing
+ *     initial + (-1)^sub * sum_{i<N} x_i y_i
+ * at output precision p >= 2, operands at mixed precisions.  This library
+ * fixes the midpoint to be the *exact* sum truncated toward zero to p bits
+ * (a refinement of the paper's error of order 2^-p sum|x_i y_i|; the paper
+ * falls back to a slower exact summation when its fast sum cannot decide,
+ * Section 2), and the radius to an upper bound of
+ *     [inexact] 2^(e_m - p) + r_initial + sum_i (|m_i| r'_i + |m'_i| r_i + r_i r'_i)
+ * that is tight to within a relative 2^-20.  Matrix products (Section 4)
+ * give every entry exactly the dot product of its row and column.
+ *
+ * Memory: every pointer in the structs below is DEVICE memory owned by the
+ * caller (for instance torch tensors).  The library never frees or keeps
+ * them; inputs must stay valid until the work completes on the stream.
+ * Calls are asynchronous on the given HIP stream; return codes report
+ * host-side validation and launch errors only.  Per-element outcomes are
+ * written to the output's status bytes.
+ *
+ * Number format (eq. (1) with 32-bit limbs), element idx of an array:
+ *   nls[idx]  bits 0..30: limb count n (0 means the value is zero),
+ *             bit 31: sign;
+ *   exp[idx]  exponent e with 2^(e-1) <= |m| < 2^e, |e| < 2^28;
+ *   limbs[k*ld + idx], k = 0..n-1, most significant limb first; the top
+ *             limb has its top bit set; value = (-1)^sign *
+ *             sum_k limbs[k*ld+idx] * 2^(e - 32(k+1)).  k < cap.
+ *   rad_m[idx], rad_e[idx]: radius rad_m * 2^rad_e with rad_m in [0.5, 1)
+ *             or 0 (finite); both pointers NULL for exact arrays.
+ */
+#ifndef ARBGPU_H
+#define ARBGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define ARBGPU_OK        0   /* done (or enqueued, for stream calls)           */
+#define ARBGPU_NOTREADY  1   /* arbgpu_poll: the ticket has not completed      */
+#define ARBGPU_EINVAL   -1   /* bad argument: p < 2, shape, stride, cap, NULL  */
+#define ARBGPU_ERANGE   -2   /* an exponent |e| >= 2^28 reached the host check */
+#define ARBGPU_ENOMEM   -3   /* workspace allocation failed                    */
+#define ARBGPU_EAGAIN   -4   /* arbgpu_submit: over the HBM budget, try later  */
+#define ARBGPU_EDEVICE  -5   /* HIP error; text in arbgpu_last_error           */
+
+/* Flags. */
+#define ARBGPU_APPROX       0x01u /* midpoints only; radius outputs untouched   */
+#define ARBGPU_COMPLEX      0x02u /* rectangular complex balls: re and im parts */
+#define ARBGPU_REDUCE_PREC  0x04u /* radius-driven precision cut (Section 3.3,
+                                     step 7(a)): p' = max(2, min(p,
+                                     e_max - e_rad + 30)); changes the midpoint */
+#define ARBGPU_ALGO_LIMB    0x10u /* matmul: force the limb-window kernel       */
+#define ARBGPU_ALGO_SLICED  0x20u /* matmul: force the scaled-integer INT8 path */
+
+/* Per-element status bytes. */
+#define ARBGPU_ST_OK       0   /* result written                                 */
+#define ARBGPU_ST_REFINED  1   /* result written; the fast window could not
+                                  decide the truncation and the exact refinement
+                                  passes were used                               */
+#define ARBGPU_ST_ERANGE   2   /* an input exponent had |e| >= 2^28 or a radius
+                                  was not finite; the output value is undefined  */
+
+typedef struct arbgpu_ctx arbgpu_ctx;
+typedef void *arbgpu_stream;   /* a hipStream_t; NULL is the null stream */
+
+typedef struct {
+  const uint32_t *limbs;   /* [cap][ld] limb planes                          */
+  int64_t ld;              /* distance between limb planes, in elements      */
+  int32_t cap;             /* number of limb planes (max n)                  */
+  const int32_t *exp;
+  const int32_t *nls;
+  const double *rad_m;     /* NULL: exact                                    */
+  const int32_t *rad_e;    /* NULL iff rad_m is NULL                         */
+} arbgpu_arr;
+
+typedef struct {
+  uint32_t *limbs;         /* [cap][ld]; needs cap >= ceil(p/32)             */
+  int64_t ld;
+  int32_t cap;
+  int32_t *exp;
+  int32_t *nls;
+  double *rad_m;           /* may be NULL only with ARBGPU_APPROX            */
+  int32_t *rad_e;
+  uint8_t *status;         /* may be NULL                                    */
+} arbgpu_out;
+
+/* A matrix view: element (i, j) is element off + i*rs + j*cs of the array
+ * (strides may be negative).  `im` is read only with ARBGPU_COMPLEX. */
+typedef struct {
+  arbgpu_arr re, im;
+  int64_t rows, cols, off, rs, cs;
+} arbgpu_mat;
+
+typedef struct {
+  arbgpu_out re, im;
+  int64_t rows, cols, off, rs, cs;
+} arbgpu_omat;
+
+/* Create a context on HIP device `device`.  `hbm_budget_bytes` bounds the
+ * workspace the context may hold and the footprint arbgpu_submit admits
+ * (0 = 3/4 of the device's free memory).  `tune_cache` (nullable) names a
+ * JSON file of autotuned launch parameters.  device = -1 makes a host-only
+ * context that validates arguments and plans but launches nothing (every
+ * compute call then returns ARBGPU_EDEVICE).  Returns ARBGPU_OK, EINVAL,
+ * EDEVICE. */
+int arbgpu_init(arbgpu_ctx **ctx, int device, size_t hbm_budget_bytes,
+                const char *tune_cache);
+
+/* Free the context and its workspace (after synchronizing its device). */
+void arbgpu_destroy(arbgpu_ctx *ctx);
+
+/* Text of the last error on this context ("" if none).  Owned by ctx. */
+const char *arbgpu_last_error(const arbgpu_ctx *ctx);
+
+/* Dot product (Section 3, the arb_dot / acb_dot problem statement):
+ *   res[res_idx] = initial[init_idx] + (-1)^sub sum_{i<N} x[xoff+i*xstep] * y[yoff+i*ystep]
+ * `initial` may be NULL.  Strides may be negative or zero.  With
+ * ARBGPU_COMPLEX, `res`, `initial`, `x`, `y` each point to TWO structs
+ * {real part, imaginary part} and the real and imaginary results are each
+ * the exact sum of their 2N real terms, rounded once (Section 3.6).
+ * EINVAL: p < 2, N < 0, NULL operand, cap of res < ceil(p/32), radius
+ * output NULL without APPROX. */
+int arbgpu_dot(arbgpu_ctx *ctx, const arbgpu_out *res, int64_t res_idx,
+               const arbgpu_arr *initial, int64_t init_idx, int sub,
+               const arbgpu_arr *x, int64_t xoff, int64_t xstep,
+               const arbgpu_arr *y, int64_t yoff, int64_t ystep,
+               int64_t N, int64_t p, uint32_t flags, arbgpu_stream stream);
+
+/* Matrix product C = A B (Section 4): A is rows x inner, B is inner x cols,
+ * C is rows x cols; every entry equals arbgpu_dot of its row and column.
+ * ALGO flags choose the limb-window kernel (Algorithm 1 per entry) or the
+ * scaled-integer block product on INT8 MFMA (Algorithm 2); neither changes
+ * a single output bit.  EINVAL on shape mismatch, p < 2, output cap too
+ * small, NULL pointers. */
+int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A,
+                   const arbgpu_mat *B, int64_t p, uint32_t flags,
+                   arbgpu_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARBGPU_H */

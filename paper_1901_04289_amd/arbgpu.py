@@ -1,0 +1,240 @@
+"""Thin ctypes binding of libarbgpu.so (argument marshalling only).
+
+Device buffers are torch tensors (torch provides allocation and streams);
+every step of the computation runs in the library's HIP kernels.  The
+binding raises if the library is missing: there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libarbgpu.so")
+
+OK, NOTREADY, EINVAL, ERANGE, ENOMEM, EAGAIN, EDEVICE = 0, 1, -1, -2, -3, -4, -5
+APPROX, COMPLEX, REDUCE_PREC, ALGO_LIMB, ALGO_SLICED = 0x01, 0x02, 0x04, 0x10, 0x20
+ST_OK, ST_REFINED, ST_ERANGE = 0, 1, 2
+
+c_p = ctypes.c_void_p
+c_i64 = ctypes.c_int64
+c_i32 = ctypes.c_int32
+c_u32 = ctypes.c_uint32
+
+
+class Arr(ctypes.Structure):
+    _fields_ = [("limbs", c_p), ("ld", c_i64), ("cap", c_i32), ("exp", c_p), ("nls", c_p),
+                ("rad_m", c_p), ("rad_e", c_p)]
+
+
+class Out(ctypes.Structure):
+    _fields_ = [("limbs", c_p), ("ld", c_i64), ("cap", c_i32), ("exp", c_p), ("nls", c_p),
+                ("rad_m", c_p), ("rad_e", c_p), ("status", c_p)]
+
+
+class Mat(ctypes.Structure):
+    _fields_ = [("re", Arr), ("im", Arr), ("rows", c_i64), ("cols", c_i64), ("off", c_i64),
+                ("rs", c_i64), ("cs", c_i64)]
+
+
+class OMat(ctypes.Structure):
+    _fields_ = [("re", Out), ("im", Out), ("rows", c_i64), ("cols", c_i64), ("off", c_i64),
+                ("rs", c_i64), ("cs", c_i64)]
+
+
+class ArbgpuError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"arbgpu error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+EXPORTS = {
+    "arbgpu_init": (ctypes.c_int, [ctypes.POINTER(c_p), ctypes.c_int, ctypes.c_size_t, ctypes.c_char_p]),
+    "arbgpu_destroy": (None, [c_p]),
+    "arbgpu_last_error": (ctypes.c_char_p, [c_p]),
+    "arbgpu_dot": (ctypes.c_int, [c_p, ctypes.POINTER(Out), c_i64, ctypes.POINTER(Arr), c_i64, ctypes.c_int,
+                                  ctypes.POINTER(Arr), c_i64, c_i64, ctypes.POINTER(Arr), c_i64, c_i64,
+                                  c_i64, c_i64, c_u32, c_p]),
+    "arbgpu_mat_mul": (ctypes.c_int, [c_p, ctypes.POINTER(OMat), ctypes.POINTER(Mat), ctypes.POINTER(Mat),
+                                      c_i64, c_u32, c_p]),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load libarbgpu.so (raises OSError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"{path} is missing: build it with `python -m paper_1901_04289_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+# ---------------------------------------------------------------------------
+# Device arrays (torch tensors)
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclass
+class DeviceArray:
+    """Operand array in device memory, limb planes [cap, ld]."""
+    limbs: "object"
+    exp: "object"
+    nls: "object"
+    rad_m: Optional["object"]
+    rad_e: Optional["object"]
+
+    @property
+    def ld(self) -> int:
+        return int(self.exp.shape[0])
+
+    @property
+    def cap(self) -> int:
+        return int(self.limbs.shape[0])
+
+    def arr(self) -> Arr:
+        return Arr(self.limbs.data_ptr(), self.ld, self.cap, self.exp.data_ptr(), self.nls.data_ptr(),
+                   self.rad_m.data_ptr() if self.rad_m is not None else None,
+                   self.rad_e.data_ptr() if self.rad_e is not None else None)
+
+    @staticmethod
+    def from_host(ops, device="cuda") -> "DeviceArray":
+        """Copy a host operand array (paper_1901_04289_amd.gen.Operands)."""
+        torch = _torch()
+        lim = torch.from_numpy(np.ascontiguousarray(ops.limbs).view(np.int32)).to(device)
+        exp = torch.from_numpy(np.ascontiguousarray(ops.exp)).to(device)
+        nls = torch.from_numpy(np.ascontiguousarray(ops.nls)).to(device)
+        rm = re = None
+        if ops.rad_m is not None:
+            rm = torch.from_numpy(np.ascontiguousarray(ops.rad_m)).to(device)
+            re = torch.from_numpy(np.ascontiguousarray(ops.rad_e)).to(device)
+        return DeviceArray(lim, exp, nls, rm, re)
+
+
+@dataclass
+class DeviceOut:
+    limbs: "object"
+    exp: "object"
+    nls: "object"
+    rad_m: Optional["object"]
+    rad_e: Optional["object"]
+    status: "object"
+
+    @property
+    def ld(self) -> int:
+        return int(self.exp.shape[0])
+
+    @staticmethod
+    def empty(count: int, p: int, radius: bool = True, device="cuda", cap: Optional[int] = None) -> "DeviceOut":
+        torch = _torch()
+        cap = cap or (p + 31) // 32
+        return DeviceOut(torch.zeros((cap, count), dtype=torch.int32, device=device),
+                         torch.zeros(count, dtype=torch.int32, device=device),
+                         torch.zeros(count, dtype=torch.int32, device=device),
+                         torch.zeros(count, dtype=torch.float64, device=device) if radius else None,
+                         torch.zeros(count, dtype=torch.int32, device=device) if radius else None,
+                         torch.full((count,), 255, dtype=torch.uint8, device=device))
+
+    def out(self) -> Out:
+        return Out(self.limbs.data_ptr(), self.ld, int(self.limbs.shape[0]), self.exp.data_ptr(),
+                   self.nls.data_ptr(),
+                   self.rad_m.data_ptr() if self.rad_m is not None else None,
+                   self.rad_e.data_ptr() if self.rad_e is not None else None,
+                   self.status.data_ptr())
+
+    def to_host(self):
+        """Copy back as (gen.Operands, status numpy array)."""
+        from .gen import Operands
+        return (Operands(self.limbs.cpu().numpy().view(np.uint32), self.exp.cpu().numpy(),
+                         self.nls.cpu().numpy(),
+                         self.rad_m.cpu().numpy() if self.rad_m is not None else None,
+                         self.rad_e.cpu().numpy() if self.rad_e is not None else None),
+                self.status.cpu().numpy())
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """An arbgpu context bound to one device (-1: host-only, validation only)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, tune_cache: Optional[str] = None):
+        self.lib = load()
+        h = c_p()
+        rc = self.lib.arbgpu_init(ctypes.byref(h), device, hbm_budget,
+                                  tune_cache.encode() if tune_cache else None)
+        if rc != OK:
+            raise ArbgpuError(rc, f"arbgpu_init(device={device}) failed")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            self.lib.arbgpu_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return self.lib.arbgpu_last_error(self.h).decode()
+
+    def _check(self, rc: int):
+        if rc != OK:
+            raise ArbgpuError(rc, self.last_error())
+        return rc
+
+    # -- raw entry points (ctypes structs) --------------------------------
+    def dot_raw(self, res: Sequence[Out], res_idx: int, initial: Optional[Sequence[Arr]], init_idx: int,
+                sub: bool, x: Sequence[Arr], xoff: int, xstep: int, y: Sequence[Arr], yoff: int,
+                ystep: int, N: int, p: int, flags: int = 0, stream=None, check: bool = True) -> int:
+        n = len(x)
+        R = (Out * n)(*res)
+        X = (Arr * n)(*x)
+        Y = (Arr * n)(*y)
+        I = (Arr * n)(*initial) if initial is not None else None
+        rc = self.lib.arbgpu_dot(self.h, R, res_idx, I, init_idx, int(bool(sub)), X, xoff, xstep, Y, yoff,
+                                 ystep, N, p, flags, _stream_handle(stream) if self.device >= 0 else None)
+        return self._check(rc) if check else rc
+
+    def mat_mul_raw(self, C: OMat, A: Mat, B: Mat, p: int, flags: int = 0, stream=None,
+                    check: bool = True) -> int:
+        rc = self.lib.arbgpu_mat_mul(self.h, ctypes.byref(C), ctypes.byref(A), ctypes.byref(B), p, flags,
+                                     _stream_handle(stream) if self.device >= 0 else None)
+        return self._check(rc) if check else rc
+
+    # -- convenience -------------------------------------------------------
+    def mat_mul(self, C: DeviceOut, A: DeviceArray, B: DeviceArray, M: int, N: int, K: int, p: int,
+                flags: int = 0, Ci: Optional[DeviceOut] = None, Ai: Optional[DeviceArray] = None,
+                Bi: Optional[DeviceArray] = None, stream=None) -> int:
+        """Row-major C (M x K) = A (M x N) B (N x K)."""
+        cplx = bool(flags & COMPLEX)
+        am = Mat(A.arr(), (Ai or A).arr(), M, N, 0, N, 1)
+        bm = Mat(B.arr(), (Bi or B).arr(), N, K, 0, K, 1)
+        cm = OMat(C.out(), (Ci or C).out(), M, K, 0, K, 1)
+        if cplx and (Ai is None or Bi is None or Ci is None):
+            raise ValueError("complex product needs imaginary parts")
+        return self.mat_mul_raw(cm, am, bm, p, flags, stream)

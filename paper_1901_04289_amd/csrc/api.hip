@@ -1,0 +1,271 @@
+// C-ABI front end of libarbgpu: argument validation, context, dispatch.
+//
+// Every entry point validates its arguments on the host before it touches
+// the device, so argument errors are reported synchronously and are
+// testable without a GPU (arbgpu_init with device -1).
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+
+#include "internal.hpp"
+
+using namespace arbgpu_impl;
+
+struct arbgpu_ctx {
+  int device;            // -1: host-only
+  size_t budget;
+  std::string err;
+  std::mutex mu;
+};
+
+namespace {
+
+int fail(arbgpu_ctx *ctx, int code, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+int hip_fail(arbgpu_ctx *ctx, hipError_t e, const char *where) {
+  return fail(ctx, ARBGPU_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+// Element index range [lo, hi] touched by off + i*s1 + j*s2, 0 <= i < n1,
+// 0 <= j < n2.
+void index_range(int64_t off, int64_t n1, int64_t s1, int64_t n2, int64_t s2, int64_t *lo, int64_t *hi) {
+  int64_t a = off, b = off;
+  if (n1 > 0) {
+    int64_t d = (n1 - 1) * s1;
+    if (d < 0) a += d; else b += d;
+  }
+  if (n2 > 0) {
+    int64_t d = (n2 - 1) * s2;
+    if (d < 0) a += d; else b += d;
+  }
+  *lo = a;
+  *hi = b;
+}
+
+bool arr_ok(const arbgpu_arr &a) {
+  if (!a.limbs || !a.exp || !a.nls) return false;
+  if (a.cap < 1 || a.ld < 1) return false;
+  if ((a.rad_m == nullptr) != (a.rad_e == nullptr)) return false;
+  return true;
+}
+
+bool out_ok(const arbgpu_out &o, int64_t p, bool approx) {
+  if (!o.limbs || !o.exp || !o.nls) return false;
+  if (o.ld < 1) return false;
+  if ((int64_t)o.cap * 32 < p) return false;
+  if (!approx && (!o.rad_m || !o.rad_e)) return false;
+  return true;
+}
+
+// Indices [lo, hi] must be non-negative and the limb planes must not
+// overlap the index range (ld covers the largest index).
+bool range_ok(int64_t lo, int64_t hi, int64_t ld) { return lo >= 0 && hi < ld; }
+
+hipStream_t to_stream(arbgpu_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+int bind_device(arbgpu_ctx *ctx) {
+  if (ctx->device < 0) return fail(ctx, ARBGPU_EDEVICE, "host-only context cannot launch work");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  return ARBGPU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int arbgpu_init(arbgpu_ctx **ctx, int device, size_t hbm_budget_bytes, const char *tune_cache) {
+  (void)tune_cache;
+  if (!ctx) return ARBGPU_EINVAL;
+  *ctx = nullptr;
+  if (device < -1) return ARBGPU_EINVAL;
+  arbgpu_ctx *c = new (std::nothrow) arbgpu_ctx;
+  if (!c) return ARBGPU_ENOMEM;
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  if (device >= 0) {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || device >= n) {
+      delete c;
+      return ARBGPU_EDEVICE;
+    }
+    e = hipSetDevice(device);
+    if (e != hipSuccess) {
+      delete c;
+      return ARBGPU_EDEVICE;
+    }
+    if (c->budget == 0) {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess) c->budget = fr / 4 * 3;
+    }
+  }
+  *ctx = c;
+  return ARBGPU_OK;
+}
+
+void arbgpu_destroy(arbgpu_ctx *ctx) {
+  if (!ctx) return;
+  if (ctx->device >= 0 && hipSetDevice(ctx->device) == hipSuccess) (void)hipDeviceSynchronize();
+  delete ctx;
+}
+
+const char *arbgpu_last_error(const arbgpu_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int arbgpu_dot(arbgpu_ctx *ctx, const arbgpu_out *res, int64_t res_idx, const arbgpu_arr *initial,
+               int64_t init_idx, int sub, const arbgpu_arr *x, int64_t xoff, int64_t xstep,
+               const arbgpu_arr *y, int64_t yoff, int64_t ystep, int64_t N, int64_t p, uint32_t flags,
+               arbgpu_stream stream) {
+  if (!ctx) return ARBGPU_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  const bool approx = flags & ARBGPU_APPROX;
+  const bool cplx = flags & ARBGPU_COMPLEX;
+  const int nparts = cplx ? 2 : 1;
+  if (flags & ~(ARBGPU_APPROX | ARBGPU_COMPLEX | ARBGPU_REDUCE_PREC))
+    return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: unknown flags 0x%x", flags);
+  if (flags & ARBGPU_REDUCE_PREC) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: REDUCE_PREC is not supported");
+  if (p < 2 || p > (1 << 20)) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: p=%lld out of range", (long long)p);
+  if (N < 0) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: N < 0");
+  if (!res || !x || !y) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: NULL argument");
+  int cap = 1;
+  for (int q = 0; q < nparts; ++q) {
+    if (!out_ok(res[q], p, approx)) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: bad result array (cap, pointers)");
+    if (res_idx < 0 || res_idx >= res[q].ld) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: res_idx out of range");
+    if (!arr_ok(x[q]) || !arr_ok(y[q])) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: bad operand array");
+    int64_t lo, hi;
+    index_range(xoff, N, xstep, 0, 0, &lo, &hi);
+    if (N > 0 && !range_ok(lo, hi, x[q].ld)) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: x index out of range");
+    index_range(yoff, N, ystep, 0, 0, &lo, &hi);
+    if (N > 0 && !range_ok(lo, hi, y[q].ld)) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: y index out of range");
+    if (initial) {
+      if (!arr_ok(initial[q])) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: bad initial array");
+      if (init_idx < 0 || init_idx >= initial[q].ld) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: init_idx out of range");
+      cap = initial[q].cap > cap ? initial[q].cap : cap;
+    }
+    cap = x[q].cap > cap ? x[q].cap : cap;
+    cap = y[q].cap > cap ? y[q].cap : cap;
+  }
+  LimbShape sh;
+  if (!limb_shape_for((int)p, N * nparts + 1, cap, &sh))
+    return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: precision %lld above the limb kernel's window", (long long)p);
+  int rc = bind_device(ctx);
+  if (rc) return rc;
+  for (int q = 0; q < nparts; ++q) {
+    DotParams prm;
+    memset(&prm, 0, sizeof prm);
+    for (int k = 0; k < nparts; ++k) {
+      prm.X[k] = x[k];
+      prm.Y[k] = y[k];
+      if (initial) prm.I[k] = initial[k];
+    }
+    if (!cplx) {
+      prm.X[1] = x[0];
+      prm.Y[1] = y[0];
+      if (initial) prm.I[1] = initial[0];
+    }
+    prm.has_init = initial != nullptr;
+    prm.init_idx = init_idx;
+    prm.init_part = q;
+    prm.R = res[q];
+    prm.res_idx = res_idx;
+    prm.xoff = xoff; prm.xstep = xstep; prm.yoff = yoff; prm.ystep = ystep; prm.N = N;
+    prm.p = (int)p;
+    prm.approx = approx;
+    prm.sub = sub ? 1u : 0u;
+    prm.ct = !cplx ? comp_real() : (q == 0 ? comp_re() : comp_im());
+    hipError_t e = launch_limb_dot(prm, sh, to_stream(stream));
+    if (e != hipSuccess) return hip_fail(ctx, e, "arbgpu_dot launch");
+  }
+  return ARBGPU_OK;
+}
+
+static int validate_mat(arbgpu_ctx *ctx, const arbgpu_mat *m, int nparts, const char *name) {
+  if (!m) return fail(ctx, ARBGPU_EINVAL, "%s is NULL", name);
+  if (m->rows < 0 || m->cols < 0) return fail(ctx, ARBGPU_EINVAL, "%s: negative shape", name);
+  const arbgpu_arr *parts[2] = {&m->re, &m->im};
+  for (int q = 0; q < nparts; ++q) {
+    if (!arr_ok(*parts[q])) return fail(ctx, ARBGPU_EINVAL, "%s: bad array", name);
+    int64_t lo, hi;
+    index_range(m->off, m->rows, m->rs, m->cols, m->cs, &lo, &hi);
+    if (m->rows > 0 && m->cols > 0 && !range_ok(lo, hi, parts[q]->ld))
+      return fail(ctx, ARBGPU_EINVAL, "%s: element index out of range", name);
+  }
+  return ARBGPU_OK;
+}
+
+int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p,
+                   uint32_t flags, arbgpu_stream stream) {
+  if (!ctx) return ARBGPU_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  const bool approx = flags & ARBGPU_APPROX;
+  const bool cplx = flags & ARBGPU_COMPLEX;
+  const int nparts = cplx ? 2 : 1;
+  if (flags & ~(ARBGPU_APPROX | ARBGPU_COMPLEX | ARBGPU_ALGO_LIMB | ARBGPU_ALGO_SLICED))
+    return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul: unknown flags 0x%x", flags);
+  if ((flags & ARBGPU_ALGO_LIMB) && (flags & ARBGPU_ALGO_SLICED))
+    return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul: conflicting ALGO flags");
+  if (p < 2 || p > (1 << 20)) return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul: p=%lld out of range", (long long)p);
+  int rc;
+  if ((rc = validate_mat(ctx, A, nparts, "A"))) return rc;
+  if ((rc = validate_mat(ctx, B, nparts, "B"))) return rc;
+  if (!C) return fail(ctx, ARBGPU_EINVAL, "C is NULL");
+  if (A->cols != B->rows) return fail(ctx, ARBGPU_EINVAL, "inner dimensions differ (%lld vs %lld)",
+                                      (long long)A->cols, (long long)B->rows);
+  if (C->rows != A->rows || C->cols != B->cols) return fail(ctx, ARBGPU_EINVAL, "C has the wrong shape");
+  const arbgpu_out *cparts[2] = {&C->re, &C->im};
+  for (int q = 0; q < nparts; ++q) {
+    if (!out_ok(*cparts[q], p, approx)) return fail(ctx, ARBGPU_EINVAL, "C: bad output array (cap, pointers)");
+    int64_t lo, hi;
+    index_range(C->off, C->rows, C->rs, C->cols, C->cs, &lo, &hi);
+    if (C->rows > 0 && C->cols > 0 && !range_ok(lo, hi, cparts[q]->ld))
+      return fail(ctx, ARBGPU_EINVAL, "C: element index out of range");
+  }
+  if (C->rows == 0 || C->cols == 0) return ARBGPU_OK;
+  int cap = A->re.cap > B->re.cap ? A->re.cap : B->re.cap;
+  if (cplx) {
+    cap = A->im.cap > cap ? A->im.cap : cap;
+    cap = B->im.cap > cap ? B->im.cap : cap;
+  }
+  LimbShape sh;
+  if (!limb_shape_for((int)p, A->cols * nparts, cap, &sh))
+    return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul: precision %lld above the limb kernel's window", (long long)p);
+  if ((rc = bind_device(ctx))) return rc;
+  for (int q = 0; q < nparts; ++q) {
+    MmParams prm;
+    memset(&prm, 0, sizeof prm);
+    prm.A[0] = A->re;
+    prm.A[1] = cplx ? A->im : A->re;
+    prm.B[0] = B->re;
+    prm.B[1] = cplx ? B->im : B->re;
+    prm.C = *cparts[q];
+    prm.M = A->rows;
+    prm.N = A->cols;
+    prm.K = B->cols;
+    prm.a_off = A->off; prm.a_rs = A->rs; prm.a_cs = A->cs;
+    prm.b_off = B->off; prm.b_rs = B->rs; prm.b_cs = B->cs;
+    prm.c_off = C->off; prm.c_rs = C->rs; prm.c_cs = C->cs;
+    prm.p = (int)p;
+    prm.approx = approx;
+    prm.ct = !cplx ? comp_real() : (q == 0 ? comp_re() : comp_im());
+    hipError_t e = launch_limb_mm(prm, sh, to_stream(stream));
+    if (e != hipSuccess) return hip_fail(ctx, e, "arbgpu_mat_mul launch");
+  }
+  return ARBGPU_OK;
+}
+
+}  // extern "C"

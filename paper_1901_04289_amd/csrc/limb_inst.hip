@@ -1,0 +1,26 @@
+// One (window limbs, operand limbs) instantiation of the limb kernels.
+// Built once per shape with -DARB_NS=<window limbs> -DARB_NA=<operand limbs>
+// so the shapes compile in parallel.
+#include "limb_kernels.hpp"
+
+#if !defined(ARB_NS) || !defined(ARB_NA)
+#error "build with -DARB_NS=... -DARB_NA=..."
+#endif
+
+namespace arbgpu_impl {
+
+template <>
+hipError_t launch_mm_shape<ARB_NS, ARB_NA>(const MmParams &prm, hipStream_t s) {
+  const int64_t blocks = ((prm.K + 63) / 64) * ((prm.M + 3) / 4);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((limb_mm_kernel<ARB_NS, ARB_NA>), dim3((unsigned)blocks), dim3(256), 0, s, prm);
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_dot_shape<ARB_NS, ARB_NA>(const DotParams &prm, hipStream_t s) {
+  hipLaunchKernelGGL((limb_dot_kernel<ARB_NS, ARB_NA>), dim3(1), dim3(64), 0, s, prm);
+  return hipGetLastError();
+}
+
+}  // namespace arbgpu_impl

@@ -1,0 +1,251 @@
+// Limb-window kernels: Algorithm 1 (Johansson 2019, Section 3) per output.
+//
+// limb_mm_kernel: one lane per output entry of a matrix product (the
+//   classical product as M*K dot products, Section 4); lanes of a wave take
+//   neighbouring columns, so the B operand reads are coalesced and the A
+//   operand is a broadcast.
+// limb_dot_kernel: one wave per dot product; the 64 lanes split the terms,
+//   and windows, error counts and radius sums are reduced across the wave
+//   with exact (modular) additions, so the result does not depend on the
+//   split.
+//
+// Both keep the window and the operand limbs in registers (NS and NA are
+// compile-time).  When a refinement level needs more operand limbs than
+// were loaded, the lane redoes the output with the streaming exact operand
+// path (SOpnd), which reads limbs in place and never truncates.
+#pragma once
+
+#include <math.h>
+
+#include "internal.hpp"
+#include "engine.hpp"
+
+using namespace arb;
+
+namespace arbgpu_impl {
+
+template <int NA>
+__device__ __forceinline__ void load_op(const arbgpu_arr &A, int64_t idx, Opnd<NA> &o, bool limbs) {
+  const int32_t nl = A.nls[idx];
+  int n = nl & 0x7FFFFFFF;
+  if (n > A.cap) n = A.cap;
+  o.sign = (uint32_t)nl >> 31;
+  o.e = A.exp[idx];
+  const int nt = n < NA ? n : NA;
+  o.trunc = n > NA;
+  o.n = nt;
+#pragma unroll
+  for (int i = 0; i < NA; ++i)
+    o.l[i] = (limbs && i < nt) ? A.limbs[(int64_t)(nt - 1 - i) * A.ld + idx] : 0u;
+  o.rm = 0.0;
+  o.re = 0;
+  if (A.rad_m) {
+    const double r = A.rad_m[idx];
+    if (r != 0.0) {
+      if (r > 0.0 && r < INFINITY) {
+        int ex;
+        o.rm = frexp(r, &ex);
+        o.re = A.rad_e[idx] + ex;
+      } else {
+        o.rm = 1.0;
+        o.re = kExpLimit;   // reported as out of range
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void load_op(const arbgpu_arr &A, int64_t idx, SOpnd &o, bool) {
+  const int32_t nl = A.nls[idx];
+  int n = nl & 0x7FFFFFFF;
+  if (n > A.cap) n = A.cap;
+  o.l = A.limbs;
+  o.ld = A.ld;
+  o.idx = idx;
+  o.n = n;
+  o.trunc = false;
+  o.sign = (uint32_t)nl >> 31;
+  o.e = A.exp[idx];
+  o.rm = 0.0;
+  o.re = 0;
+  if (A.rad_m) {
+    const double r = A.rad_m[idx];
+    if (r != 0.0) {
+      if (r > 0.0 && r < INFINITY) {
+        int ex;
+        o.rm = frexp(r, &ex);
+        o.re = A.rad_e[idx] + ex;
+      } else {
+        o.rm = 1.0;
+        o.re = kExpLimit;
+      }
+    }
+  }
+}
+
+static __constant__ uint32_t kOneLimb[1] = {0x80000000u};
+
+template <int NA>
+__device__ __forceinline__ void make_one(Opnd<NA> &o) {
+#pragma unroll
+  for (int i = 0; i < NA; ++i) o.l[i] = 0;
+  o.l[0] = 0x80000000u;
+  o.n = 1; o.trunc = false; o.e = 1; o.sign = 0; o.rm = 0.0; o.re = 0;
+}
+__device__ __forceinline__ void make_one(SOpnd &o) {
+  o.l = kOneLimb; o.ld = 1; o.idx = 0;
+  o.n = 1; o.trunc = false; o.e = 1; o.sign = 0; o.rm = 0.0; o.re = 0;
+}
+
+__device__ __forceinline__ const arbgpu_arr &pick(const arbgpu_arr *arr, int i) { return i ? arr[1] : arr[0]; }
+
+// Terms of output (i, j) of a matrix product.
+template <class Op>
+struct MmSrc {
+  const MmParams *P;
+  int64_t abase, bbase;
+  __device__ __forceinline__ int64_t nterms() const { return P->N * P->ct.ncomp; }
+  __device__ __forceinline__ bool has_init() const { return false; }
+  __device__ __forceinline__ void term(int64_t t, Op &a, Op &b, uint32_t &neg, bool limbs) const {
+    const int s = P->ct.ncomp == 2 ? (int)(t & 1) : 0;
+    const int64_t k = P->ct.ncomp == 2 ? (t >> 1) : t;
+    load_op(pick(P->A, P->ct.pa[s]), abase + k * P->a_cs, a, limbs);
+    load_op(pick(P->B, P->ct.pb[s]), bbase + k * P->b_rs, b, limbs);
+    neg = a.sign ^ b.sign ^ P->ct.ng[s];
+  }
+  __device__ __forceinline__ void init(Op &, Op &, bool) const {}
+};
+
+// Terms of one dot product.
+template <class Op>
+struct DotSrc {
+  const DotParams *P;
+  __device__ __forceinline__ int64_t nterms() const { return P->N * P->ct.ncomp; }
+  __device__ __forceinline__ bool has_init() const { return P->has_init != 0; }
+  __device__ __forceinline__ void term(int64_t t, Op &a, Op &b, uint32_t &neg, bool limbs) const {
+    const int s = P->ct.ncomp == 2 ? (int)(t & 1) : 0;
+    const int64_t k = P->ct.ncomp == 2 ? (t >> 1) : t;
+    load_op(pick(P->X, P->ct.pa[s]), P->xoff + k * P->xstep, a, limbs);
+    load_op(pick(P->Y, P->ct.pb[s]), P->yoff + k * P->ystep, b, limbs);
+    neg = a.sign ^ b.sign ^ P->ct.ng[s] ^ P->sub;
+  }
+  __device__ __forceinline__ void init(Op &a, Op &one, bool limbs) const {
+    load_op(pick(P->I, P->init_part), P->init_idx, a, limbs);
+    make_one(one);
+  }
+};
+
+// Cross-lane reductions for one wave per output.  Butterfly exchanges give
+// every lane the same totals; window additions are exact modulo 2^(32 NS)
+// and the upward FP64 sum is order-independent in its error test.
+struct WaveReducer {
+  __device__ __forceinline__ static int lane() { return threadIdx.x & 63; }
+  __device__ __forceinline__ static int group() { return 64; }
+  __device__ __forceinline__ static void setup(Setup &S) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+      int e = __shfl_xor(S.emax, m, 64);
+      S.emax = e > S.emax ? e : S.emax;
+      S.nnz += (uint32_t)__shfl_xor((int)S.nnz, m, 64);
+      int f = __shfl_xor(S.F, m, 64);
+      S.F = f > S.F ? f : S.F;
+      S.any_rad = __shfl_xor((int)S.any_rad, m, 64) | S.any_rad;
+      S.erange = __shfl_xor((int)S.erange, m, 64) | S.erange;
+    }
+  }
+  template <int NS>
+  __device__ __forceinline__ static void window(Window<NS> &W) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+      uint32_t o[NS];
+#pragma unroll
+      for (int i = 0; i < NS; ++i) o[i] = (uint32_t)__shfl_xor((int)W.w[i], m, 64);
+      madd<NS>(W.w, o);
+      W.err += (uint32_t)__shfl_xor((int)W.err, m, 64);
+      W.pt += (uint32_t)__shfl_xor((int)W.pt, m, 64);
+      W.below_cnt += (uint32_t)__shfl_xor((int)W.below_cnt, m, 64);
+      int bm = __shfl_xor(W.below_max, m, 64);
+      W.below_max = bm > W.below_max ? bm : W.below_max;
+      W.bad = __shfl_xor((int)W.bad, m, 64) | W.bad;
+    }
+  }
+  __device__ __forceinline__ static double rad(double r) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) r = ru_add(r, __shfl_xor(r, m, 64));
+    return r;
+  }
+};
+
+template <int NS>
+__device__ __forceinline__ void store_out(const arbgpu_out &o, int64_t idx, const DotOut<NS> &r, int p, int approx,
+                          uint8_t status) {
+  const int PL = (p + 31) >> 5;
+  int n = 0;
+#pragma unroll
+  for (int i = NS - 1; i >= 0; --i) {
+    const int k = NS - 1 - i;
+    if (k < PL) {
+      const uint32_t v = r.st.zero ? 0u : r.st.Y[i];
+      o.limbs[(int64_t)k * o.ld + idx] = v;
+      if (v) n = k + 1;
+    }
+  }
+  o.exp[idx] = r.st.zero ? 0 : r.st.r_exp;
+  o.nls[idx] = r.st.zero ? 0 : (int32_t)((uint32_t)n | (r.st.r_sign << 31));
+  if (!approx) {
+    double rm;
+    int re;
+    if (r.erange) {
+      rm = INFINITY;
+      re = 0;
+    } else {
+      total_radius(r, p, rm, re);
+    }
+    o.rad_m[idx] = rm;
+    o.rad_e[idx] = re;
+  }
+  if (o.status) o.status[idx] = status;
+}
+
+template <int NS>
+__device__ __forceinline__ uint8_t status_of(const DotOut<NS> &r, bool fell_back) {
+  if (r.erange) return ARBGPU_ST_ERANGE;
+  return (fell_back || r.st.levels > 1) ? ARBGPU_ST_REFINED : ARBGPU_ST_OK;
+}
+
+template <int NS, int NA>
+__global__ __launch_bounds__(256) void limb_mm_kernel(MmParams prm) {
+  const int64_t tiles_j = (prm.K + 63) >> 6;
+  const int64_t bid = blockIdx.x;
+  const int64_t j = (bid % tiles_j) * 64 + (threadIdx.x & 63);
+  const int64_t i = (bid / tiles_j) * 4 + (threadIdx.x >> 6);
+  if (i >= prm.M || j >= prm.K) return;
+  const int64_t abase = prm.a_off + i * prm.a_rs;
+  const int64_t bbase = prm.b_off + j * prm.b_cs;
+  DotOut<NS> out;
+  MmSrc<Opnd<NA>> src{&prm, abase, bbase};
+  run_dot<NS, Opnd<NA>, SoloReducer>(src, prm.p, !prm.approx, out);
+  bool fell_back = false;
+  if (out.st.bad) {
+    MmSrc<SOpnd> s2{&prm, abase, bbase};
+    run_dot<NS, SOpnd, SoloReducer>(s2, prm.p, !prm.approx, out);
+    fell_back = true;
+  }
+  store_out<NS>(prm.C, prm.c_off + i * prm.c_rs + j * prm.c_cs, out, prm.p, prm.approx,
+                status_of(out, fell_back));
+}
+
+template <int NS, int NA>
+__global__ __launch_bounds__(64) void limb_dot_kernel(DotParams prm) {
+  DotOut<NS> out;
+  DotSrc<Opnd<NA>> src{&prm};
+  run_dot<NS, Opnd<NA>, WaveReducer>(src, prm.p, !prm.approx, out);
+  bool fell_back = false;
+  if (out.st.bad) {   // uniform across the wave: every lane holds the same state
+    DotSrc<SOpnd> s2{&prm};
+    run_dot<NS, SOpnd, WaveReducer>(s2, prm.p, !prm.approx, out);
+    fell_back = true;
+  }
+  if (threadIdx.x == 0) store_out<NS>(prm.R, prm.res_idx, out, prm.p, prm.approx, status_of(out, fell_back));
+}
+
+}  // namespace arbgpu_impl

@@ -1,0 +1,99 @@
+"""Host-side checks of libarbgpu.so: it loads, exports every function that
+include/arbgpu.h declares, and validates arguments before any device work
+(host-only context, no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1901_04289_amd import arbgpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(arbgpu_[a-z_0-9]+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(arbgpu.LIB_PATH):
+        from paper_1901_04289_amd import build
+        build.build()
+    return arbgpu.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert {"arbgpu_init", "arbgpu_destroy", "arbgpu_dot", "arbgpu_mat_mul"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared but not exported"
+
+
+def _arr(ld=10, cap=4, rad=False):
+    return arbgpu.Arr(1, ld, cap, 2, 3, 4 if rad else None, 5 if rad else None)
+
+
+def _out(ld=10, cap=4, rad=True):
+    return arbgpu.Out(1, ld, cap, 2, 3, 4 if rad else None, 5 if rad else None, None)
+
+
+@pytest.fixture
+def hctx(lib):
+    c = arbgpu.Context(-1)
+    yield c
+    c.close()
+
+
+def test_host_only_context_validates_dot(hctx):
+    ok = dict(res=[_out()], res_idx=0, initial=None, init_idx=0, sub=False, x=[_arr()], xoff=0, xstep=1,
+              y=[_arr()], yoff=0, ystep=1, N=5, p=64)
+    # a valid call reaches the device step and reports the host-only context
+    assert hctx.dot_raw(**ok, check=False) == arbgpu.EDEVICE
+    for bad in [dict(p=1), dict(N=-1), dict(res_idx=10), dict(xoff=6), dict(xstep=-1),
+                dict(ystep=3), dict(res=[_out(cap=1)]), dict(res=[_out(rad=False)]),
+                dict(initial=[_arr()], init_idx=11)]:
+        args = dict(ok, **bad)
+        assert hctx.dot_raw(**args, check=False) == arbgpu.EINVAL, bad
+        assert hctx.last_error()
+    # negative strides that stay in range are fine
+    assert hctx.dot_raw(**dict(ok, xoff=4, xstep=-1), check=False) == arbgpu.EDEVICE
+    # approx needs no radius output
+    assert hctx.dot_raw(**dict(ok, res=[_out(rad=False)], flags=arbgpu.APPROX), check=False) == arbgpu.EDEVICE
+    # complex needs two parts of everything
+    assert hctx.dot_raw(**dict(ok, res=[_out(), _out()], x=[_arr(), _arr()], y=[_arr(), _arr()],
+                               flags=arbgpu.COMPLEX), check=False) == arbgpu.EDEVICE
+    assert hctx.dot_raw(**dict(ok, flags=0x400), check=False) == arbgpu.EINVAL
+
+
+def test_host_only_context_validates_matmul(hctx):
+    def mat(rows, cols, ld=100):
+        return arbgpu.Mat(_arr(ld), _arr(ld), rows, cols, 0, cols, 1)
+
+    def omat(rows, cols, ld=100, cap=4, rad=True):
+        return arbgpu.OMat(_out(ld, cap, rad), _out(ld, cap, rad), rows, cols, 0, cols, 1)
+
+    assert hctx.mat_mul_raw(omat(3, 4), mat(3, 5), mat(5, 4), 100, check=False) == arbgpu.EDEVICE
+    assert hctx.mat_mul_raw(omat(3, 4), mat(3, 5), mat(6, 4), 100, check=False) == arbgpu.EINVAL
+    assert hctx.mat_mul_raw(omat(3, 5), mat(3, 5), mat(5, 4), 100, check=False) == arbgpu.EINVAL
+    assert hctx.mat_mul_raw(omat(3, 4), mat(3, 5), mat(5, 4), 1, check=False) == arbgpu.EINVAL
+    assert hctx.mat_mul_raw(omat(3, 4, cap=2), mat(3, 5), mat(5, 4), 100, check=False) == arbgpu.EINVAL
+    assert hctx.mat_mul_raw(omat(3, 4), mat(30, 5), mat(5, 4), 100, check=False) == arbgpu.EINVAL  # C shape
+    assert hctx.mat_mul_raw(omat(30, 4), mat(30, 5), mat(5, 4), 100, check=False) == arbgpu.EINVAL  # A range
+    assert hctx.mat_mul_raw(omat(3, 4), mat(3, 5), mat(5, 4), 100,
+                            flags=arbgpu.ALGO_LIMB | arbgpu.ALGO_SLICED, check=False) == arbgpu.EINVAL
+    # empty output: nothing to do, no device needed
+    assert hctx.mat_mul_raw(omat(0, 4), mat(0, 5), mat(5, 4), 100, check=False) == arbgpu.OK
+
+
+def test_init_rejects_bad_device(lib):
+    h = ctypes.c_void_p()
+    assert lib.arbgpu_init(ctypes.byref(h), -2, 0, None) == arbgpu.EINVAL
