@@ -16,12 +16,54 @@
 
 using namespace arbgpu_impl;
 
-struct arbgpu_ctx {
-  int device;            // -1: host-only
-  size_t budget;
-  std::string err;
-  std::mutex mu;
-};
+arbgpu_ctx::~arbgpu_ctx() {
+  for (auto &b : ws)
+    if (b.ptr) (void)hipFree(b.ptr);
+}
+
+namespace arbgpu_impl {
+
+int set_error(arbgpu_ctx *ctx, int code, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+void *ws_get(arbgpu_ctx *ctx, int slot, size_t bytes) {
+  if ((int)ctx->ws.size() < WS_COUNT) ctx->ws.resize(WS_COUNT);
+  arbgpu_ctx::Buf &b = ctx->ws[slot];
+  if (bytes == 0) bytes = 256;
+  if (b.size >= bytes) return b.ptr;
+  if (b.ptr) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.size = 0;
+  }
+  size_t total = bytes;
+  for (int i = 0; i < (int)ctx->ws.size(); ++i) total += ctx->ws[i].size;
+  if (ctx->budget && total > ctx->budget) {
+    set_error(ctx, ARBGPU_ENOMEM, "workspace of %zu bytes exceeds the HBM budget %zu", total, ctx->budget);
+    return nullptr;
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    set_error(ctx, ARBGPU_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    return nullptr;
+  }
+  b.ptr = p;
+  b.size = bytes;
+  return p;
+}
+
+}  // namespace arbgpu_impl
 
 namespace {
 
@@ -241,10 +283,14 @@ int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
     cap = A->im.cap > cap ? A->im.cap : cap;
     cap = B->im.cap > cap ? B->im.cap : cap;
   }
+  if ((rc = bind_device(ctx))) return rc;
+  if (!(flags & ARBGPU_ALGO_LIMB)) {
+    rc = sliced_mat_mul(ctx, C, A, B, p, flags, to_stream(stream), (flags & ARBGPU_ALGO_SLICED) != 0);
+    if (rc != kNotApplicable) return rc;
+  }
   LimbShape sh;
   if (!limb_shape_for((int)p, A->cols * nparts, cap, &sh))
     return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul: precision %lld above the limb kernel's window", (long long)p);
-  if ((rc = bind_device(ctx))) return rc;
   for (int q = 0; q < nparts; ++q) {
     MmParams prm;
     memset(&prm, 0, sizeof prm);

@@ -5,9 +5,48 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "../../include/arbgpu.h"
 
+// Context: one device, one error string, a grow-only device workspace.
+struct arbgpu_ctx {
+  int device;            // -1: host-only
+  size_t budget;
+  std::string err;
+  std::mutex mu;
+  struct Buf {
+    void *ptr = nullptr;
+    size_t size = 0;
+  };
+  std::vector<Buf> ws;   // indexed by workspace slot
+  ~arbgpu_ctx();
+};
+
 namespace arbgpu_impl {
+
+// Workspace slots (each holds one growing device buffer).
+enum WsSlot {
+  WS_STATS = 0, WS_PLANES_A, WS_PLANES_B, WS_PLANES_B2, WS_D, WS_T, WS_TABLES,
+  WS_RAD_A, WS_RAD_B, WS_RAD_OUT, WS_COUNT
+};
+
+// Device buffer of at least `bytes` in workspace slot `slot` (nullptr and
+// the context error set on failure).  Grows by reallocation; the previous
+// contents are not kept.
+void *ws_get(arbgpu_ctx *ctx, int slot, size_t bytes);
+
+int set_error(arbgpu_ctx *ctx, int code, const char *fmt, ...);
+
+// Scaled-integer INT8-MFMA matrix product; returns ARBGPU_OK, an error, or
+// kNotApplicable when the operands need the limb kernel (more than one
+// block under the height bound, inner length below the basecase, exponent
+// range errors to be flagged per element).
+constexpr int kNotApplicable = 100;
+int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B,
+                   int64_t p, uint32_t flags, hipStream_t s, bool forced);
 
 // Which operand parts form the terms of one real output (Section 3.6: the
 // real part of a complex dot is the 2N-term real dot of a c and -(b d), the

@@ -19,6 +19,7 @@
 #include <stdint.h>
 
 #ifndef ARB_HD
+#include <hip/hip_runtime.h>
 #define ARB_HD __host__ __device__ __forceinline__
 #endif
 

@@ -1,0 +1,566 @@
+// Scaled-integer block product on INT8 MFMA (Algorithm 2 of Johansson 2019,
+// Section 4.1; FLINT's integer product replaced by an exact sliced product).
+//
+// For a block of inner indices, row i of A is scaled by 2^-v2_i and column
+// j of B by 2^-v2_j (the lowest set bit over the line, Section 4.1) so that
+// both become integer matrices X, Y.  Each integer is written in balanced
+// base 256, x = sum_a d_a 256^a with d_a in [-128, 127], as L int8 digit
+// planes.  Then
+//     T = X Y = sum_c 256^c D_c,   D_c = sum_{a+b=c} X_a Y_b,
+// where every X_a Y_b is an int8 GEMM with int32 accumulation.  A diagonal
+// group of at most P pairs keeps |D| < P K 2^14 < 2^31, so the int32 planes
+// are exact.  The recombination streams the diagonals from c = 0 upward with
+// one int64 carry per entry and emits the bytes of T, which is exact; the
+// entry C_ij = T_ij 2^(v2_i + v2_j) is then truncated to p bits once.
+//
+// Radii (Section 4.1, last paragraph): |A| R_B + R_A (|B| + R_B) in FP64
+// with upward rounding, each row and column scaled into the double range.
+#include <math.h>
+
+#include "engine.hpp"
+#include "sliced.hpp"
+
+using namespace arb;
+
+namespace arbgpu_impl {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// ---------------------------------------------------------------------------
+// element access
+// ---------------------------------------------------------------------------
+
+// Part and sign of inner index k under an inner layout mode (see SliceParams).
+__device__ __forceinline__ void inner_map(int mode, int64_t len, int64_t k, int &part, int64_t &kk, uint32_t &neg) {
+  part = 0;
+  kk = k;
+  neg = 0;
+  if (mode == 0) return;
+  const bool second = k >= len;
+  kk = second ? k - len : k;
+  if (mode == 1) { part = second ? 1 : 0; neg = second ? 1u : 0u; }
+  else if (mode == 2) { part = second ? 0 : 1; }
+  else { part = second ? 1 : 0; }
+}
+
+__device__ __forceinline__ const arbgpu_arr &part_of(const arbgpu_arr *p, int i) { return i ? p[1] : p[0]; }
+
+// position of the lowest set bit of |m| (INT32_MAX for zero)
+__device__ __forceinline__ int low_bit(const arbgpu_arr &A, int64_t idx, int n, int e) {
+  for (int q = n - 1; q >= 0; --q) {
+    uint32_t v = A.limbs[(int64_t)q * A.ld + idx];
+    if (v) return e - 32 * (q + 1) + __builtin_ctz(v);
+  }
+  return 0x7FFFFFFF;
+}
+
+__device__ __forceinline__ int elem_n(const arbgpu_arr &A, int64_t idx) {
+  int n = A.nls[idx] & 0x7FFFFFFF;
+  return n > A.cap ? A.cap : n;
+}
+
+// ---------------------------------------------------------------------------
+// statistics: top exponent and lowest set bit per line
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void stats_elem(const StatsParams &P, int64_t line, int64_t k, int &top, int &v2,
+                                          int &prec, int &bad) {
+  for (int q = 0; q < P.nparts; ++q) {
+    const arbgpu_arr &A = part_of(P.part, q);
+    const int64_t idx = P.off + line * P.line_stride + (P.k0 + k) * P.elem_stride;
+    const int n = elem_n(A, idx);
+    if (n == 0) continue;
+    const int e = A.exp[idx];
+    if (e >= kExpLimit || e <= -kExpLimit) { bad = 1; continue; }
+    const int lb = low_bit(A, idx, n, e);
+    if (lb == 0x7FFFFFFF) continue;
+    top = e > top ? e : top;
+    v2 = lb < v2 ? lb : v2;
+    prec = (e - lb) > prec ? (e - lb) : prec;
+  }
+}
+
+__global__ __launch_bounds__(256) void stats_rows_kernel(StatsParams P) {
+  const int64_t line = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (line >= P.lines) return;
+  int top = -0x7FFFFFFF - 1, v2 = 0x7FFFFFFF, prec = 0, bad = 0;
+  for (int64_t k = lane; k < P.len; k += 64) stats_elem(P, line, k, top, v2, prec, bad);
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    int t = __shfl_xor(top, m, 64); top = t > top ? t : top;
+    int v = __shfl_xor(v2, m, 64); v2 = v < v2 ? v : v2;
+    int q = __shfl_xor(prec, m, 64); prec = q > prec ? q : prec;
+    bad |= __shfl_xor(bad, m, 64);
+  }
+  if (lane == 0) {
+    P.out.top[line] = top;
+    P.out.v2[line] = v2;
+    if (v2 != 0x7FFFFFFF) atomicMax(&P.gmax[0], top - v2);
+    atomicMax(&P.gmax[1], prec);
+    if (bad) atomicMax(&P.gmax[2], 1);
+  }
+}
+
+__global__ __launch_bounds__(256) void stats_cols_kernel(StatsParams P) {
+  const int64_t line = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (line >= P.lines) return;
+  int top = -0x7FFFFFFF - 1, v2 = 0x7FFFFFFF, prec = 0, bad = 0;
+  for (int64_t k = 0; k < P.len; ++k) stats_elem(P, line, k, top, v2, prec, bad);
+  P.out.top[line] = top;
+  P.out.v2[line] = v2;
+  if (v2 != 0x7FFFFFFF) atomicMax(&P.gmax[0], top - v2);
+  atomicMax(&P.gmax[1], prec);
+  if (bad) atomicMax(&P.gmax[2], 1);
+}
+
+// ---------------------------------------------------------------------------
+// slicing into balanced base-256 digit planes
+// ---------------------------------------------------------------------------
+
+// Bits [32w - s, 32w - s + 32) of the limb integer M (least significant limb
+// is limb n-1 in memory), zero outside.
+__device__ __forceinline__ uint32_t mant_chunk(const arbgpu_arr &A, int64_t idx, int n, int64_t o) {
+  // o: bit offset into M (may be negative)
+  const int64_t li = o >= 0 ? (o >> 5) : -((31 - o) >> 5);
+  const uint32_t r = (uint32_t)(o - 32 * li);
+  auto get = [&](int64_t i) -> uint32_t {
+    return (i >= 0 && i < n) ? A.limbs[(int64_t)(n - 1 - i) * A.ld + idx] : 0u;
+  };
+  const uint32_t lo = get(li), hi = get(li + 1);
+  return r ? ((lo >> r) | (hi << (32u - r))) : lo;
+}
+
+__global__ __launch_bounds__(256) void slice_kernel(SliceParams P) {
+  const int64_t kq = P.k_pad >> 2;
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (gid >= P.lines_pad * kq) return;
+  const int64_t line = gid / kq;
+  const int64_t q = gid - line * kq;
+  const int64_t len_total = (P.mode == 0) ? P.len : 2 * P.len;
+  const int L = P.L;
+  const int nw = (L + 3) >> 2;
+  // per-element state
+  int64_t idx[4];
+  int part[4], n[4];
+  int64_t s[4];
+  uint32_t sg[4];
+  uint32_t cy[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t k = 4 * q + t;
+    n[t] = 0; s[t] = 0; sg[t] = 0; cy[t] = 0; idx[t] = 0; part[t] = 0;
+    if (line < P.lines && k < len_total) {
+      int64_t kk;
+      uint32_t ng;
+      inner_map(P.mode, P.len, k, part[t], kk, ng);
+      const arbgpu_arr &A = part_of(P.part, part[t]);
+      idx[t] = P.off + line * P.line_stride + (P.k0 + kk) * P.elem_stride;
+      const int nn = elem_n(A, idx[t]);
+      if (nn) {
+        const int32_t nl = A.nls[idx[t]];
+        n[t] = nn;
+        sg[t] = ((uint32_t)nl >> 31) ^ ng;
+        s[t] = (int64_t)A.exp[idx[t]] - 32 * (int64_t)nn - P.v2[line];
+      }
+    }
+  }
+  const int64_t plane = P.lines_pad * P.k_pad;
+  uint32_t *base = reinterpret_cast<uint32_t *>(P.planes + line * P.k_pad + 4 * q);
+  for (int w = 0; w < nw; ++w) {
+    // offset B = sum_{a<L} 128 * 256^a, restricted to this 32-bit chunk
+    const int nbytes = (L - 4 * w) >= 4 ? 4 : (L - 4 * w);
+    const uint32_t bmask = nbytes == 4 ? 0xFFFFFFFFu : ((1u << (8 * nbytes)) - 1u);
+    const uint32_t Bc = 0x80808080u & bmask;
+    uint32_t y[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      uint32_t x = 0;
+      if (n[t]) x = mant_chunk(part_of(P.part, part[t]), idx[t], n[t], 32 * (int64_t)w - s[t]);
+      uint64_t v;
+      if (!sg[t]) {
+        v = (uint64_t)Bc + x + cy[t];
+        cy[t] = (uint32_t)(v >> 32);
+      } else {
+        v = (uint64_t)Bc - x - cy[t];
+        cy[t] = (uint32_t)((v >> 63) & 1u);
+      }
+      y[t] = ((uint32_t)v) ^ 0x80808080u;   // byte u - 128 as int8 is u ^ 0x80
+    }
+    // transpose 4 elements x 4 digits into 4 plane words
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int a = 4 * w + b;
+      if (a < L) {
+        const uint32_t word = ((y[0] >> (8 * b)) & 0xFFu) | (((y[1] >> (8 * b)) & 0xFFu) << 8) |
+                              (((y[2] >> (8 * b)) & 0xFFu) << 16) | (((y[3] >> (8 * b)) & 0xFFu) << 24);
+        base[(a * plane) >> 2] = word;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// INT8 MFMA diagonal-group product
+// ---------------------------------------------------------------------------
+//
+// Workgroup: 256 threads, output tile 256 x 256; wave w owns the 128 x 128
+// quarter (w / 2, w % 2) as 4 x 4 blocks of v_mfma_i32_32x32x32_i8.  The
+// inner loop runs over (slice pair, 128-byte K step); A and B tiles are
+// staged through LDS (double buffered, 2 x 64 KiB) with the 16-byte chunk
+// index XOR-swizzled by (row >> 1) & 7 so that 16 consecutive rows hit 16
+// distinct bank groups.  Operand fragment of lane l: row (l % 32), inner
+// bytes [16 (l / 32), +16) of a 32-byte K slice; result of lane l, register
+// r: column l % 32, row 8 (r / 4) + 4 (l / 32) + r % 4.
+
+__device__ __forceinline__ int swz(int row, int chunk) { return row * kKStep + ((chunk ^ ((row >> 1) & 7)) << 4); }
+
+__global__ __launch_bounds__(256) void mfma_diag_kernel(MfmaParams P) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2][2][kTile * kKStep];  // [buf][A/B]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int ntiles = P.ntm * P.ntn;
+  const int g = blockIdx.x / ntiles;
+  const int t = blockIdx.x - g * ntiles;
+  const int tm = t / P.ntn, tn = t - tm * P.ntn;
+  const DiagGroup G = P.groups[g];
+  const int64_t ksteps = P.Kp / kKStep;
+  const int64_t nsteps = (int64_t)(G.a1 - G.a0) * ksteps;
+  const int64_t planeA = P.Mp * P.Kp, planeB = P.Np * P.Kp;
+
+  v16i acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
+
+  // global -> register staging: thread covers chunk (tid & 7) of rows
+  // (tid >> 3) + 32 u, u = 0..7, for A and for B
+  const int srow = tid >> 3, schunk = tid & 7;
+  v4i stA[8], stB[8];
+  auto gload = [&](int64_t step) {
+    const int64_t pr = step / ksteps;
+    const int64_t ks = step - pr * ksteps;
+    const int a = G.a0 + (int)pr;
+    const int b = G.c - a;
+    const int8_t *pa = P.A + a * planeA + ((int64_t)tm * kTile + srow) * P.Kp + ks * kKStep + schunk * 16;
+    const int8_t *pb = P.B + b * planeB + ((int64_t)tn * kTile + srow) * P.Kp + ks * kKStep + schunk * 16;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      stA[u] = *reinterpret_cast<const v4i *>(pa + (int64_t)u * 32 * P.Kp);
+      stB[u] = *reinterpret_cast<const v4i *>(pb + (int64_t)u * 32 * P.Kp);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int row = srow + 32 * u;
+      *reinterpret_cast<v4i *>(&lds[buf][0][swz(row, schunk)]) = stA[u];
+      *reinterpret_cast<v4i *>(&lds[buf][1][swz(row, schunk)]) = stB[u];
+    }
+  };
+
+  if (nsteps > 0) {
+    gload(0);
+    lstore(0);
+  }
+  __syncthreads();
+  for (int64_t step = 0; step < nsteps; ++step) {
+    const int buf = (int)(step & 1);
+    if (step + 1 < nsteps) gload(step + 1);
+    const uint8_t *la = lds[buf][0];
+    const uint8_t *lb = lds[buf][1];
+#pragma unroll
+    for (int kk = 0; kk < kKStep / 32; ++kk) {
+      const int chunk = kk * 2 + (lane >> 5);
+      v4i fa[4], fb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int ra = wm * 128 + i * 32 + (lane & 31);
+        const int rb = wn * 128 + i * 32 + (lane & 31);
+        fa[i] = *reinterpret_cast<const v4i *>(la + swz(ra, chunk));
+        fb[i] = *reinterpret_cast<const v4i *>(lb + swz(rb, chunk));
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    if (step + 1 < nsteps) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: int32 partial plane of this diagonal group
+  int32_t *D = P.D + (int64_t)G.slot * P.M * P.N;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = (int64_t)tm * kTile + wm * 128 + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const int64_t col = (int64_t)tn * kTile + wn * 128 + j * 32 + (lane & 31);
+        if (row < P.M && col < P.N) D[row * P.N + col] = acc[i][j][r];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// carry recombination and truncation to p bits
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void recombine_kernel(RecombParams P) {
+  const int64_t MN = P.M * P.N;
+  const int64_t ij = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (ij >= MN) return;
+  const int64_t i = ij / P.N, j = ij - i * P.N;
+  uint32_t *T = P.T + ij;
+  const int nq = (P.Lc + 3) >> 2;
+  int64_t carry = 0;
+  for (int w = 0; w < nq; ++w) {
+    uint32_t limb = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int c = 4 * w + b;
+      if (c < P.Lc) {
+        int64_t s = 0;
+        for (int sl = P.slot_of[c]; sl < P.slot_of[c + 1]; ++sl) s += P.D[(int64_t)sl * MN + ij];
+        carry += s;
+      }
+      limb |= ((uint32_t)carry & 0xFFu) << (8 * b);
+      carry >>= 8;
+    }
+    T[(int64_t)w * MN] = limb;
+  }
+  T[(int64_t)nq * MN] = (uint32_t)carry;
+  T[(int64_t)(nq + 1) * MN] = (uint32_t)((uint64_t)carry >> 32);
+  const int nT = nq + 2;
+
+  // magnitude of the two's-complement integer, limb by limb
+  const bool neg = (T[(int64_t)(nT - 1) * MN] >> 31) != 0;
+  int z = nT;   // lowest nonzero limb
+  for (int q = 0; q < nT; ++q)
+    if (T[(int64_t)q * MN]) { z = q; break; }
+  auto mag = [&](int q) -> uint32_t {
+    if (q < 0 || q >= nT) return 0u;
+    const uint32_t v = T[(int64_t)q * MN];
+    if (!neg) return v;
+    return q > z ? ~v : (q == z ? (uint32_t)(0u - v) : 0u);
+  };
+  int qt = -1;
+  for (int q = nT - 1; q >= 0; --q)
+    if (mag(q)) { qt = q; break; }
+  const arbgpu_out &C = P.C;
+  const int64_t oidx = P.c_off + i * P.c_rs + j * P.c_cs;
+  const int PL = (P.p + 31) >> 5;
+  if (qt < 0) {
+    for (int k = 0; k < PL; ++k) C.limbs[(int64_t)k * C.ld + oidx] = 0u;
+    C.exp[oidx] = 0;
+    C.nls[oidx] = 0;
+    if (!P.approx) {
+      double rm = 0.0;
+      int re = 0;
+      if (P.rin_m) { rm = P.rin_m[ij]; re = P.rin_e[ij]; }
+      C.rad_m[oidx] = rm;
+      C.rad_e[oidx] = re;
+    }
+    if (C.status) C.status[oidx] = ARBGPU_ST_OK;
+    return;
+  }
+  const int64_t bl = 32 * (int64_t)qt + (32 - __builtin_clz(mag(qt)));
+  auto bits32 = [&](int64_t lo) -> uint32_t {   // bits [lo, lo + 32) of |T|
+    const int64_t q0 = lo >= 0 ? (lo >> 5) : -((31 - lo) >> 5);
+    const uint32_t r = (uint32_t)(lo - 32 * q0);
+    const uint32_t a = mag((int)q0), b = mag((int)q0 + 1);
+    return r ? ((a >> r) | (b << (32u - r))) : a;
+  };
+  int nout = 0;
+  for (int k = 0; k < PL; ++k) {
+    uint32_t v = bits32(bl - 32 * (int64_t)(k + 1));
+    if (k == PL - 1) v &= 0xFFFFFFFFu << (32 * PL - P.p);
+    C.limbs[(int64_t)k * C.ld + oidx] = v;
+    if (v) nout = k + 1;
+  }
+  // bits of |T| below position bl - p
+  const int64_t cut = bl - P.p;
+  bool inexact = false;
+  if (cut > 0) {
+    const int64_t qc = cut >> 5;
+    for (int64_t q = 0; q < qc && !inexact; ++q) inexact = mag((int)q) != 0;
+    const uint32_t rc = (uint32_t)(cut & 31);
+    if (!inexact && rc) inexact = (mag((int)qc) & ((1u << rc) - 1u)) != 0;
+  }
+  const int em = (int)(bl + P.rowv2[i] + P.colv2[j]);
+  C.exp[oidx] = em;
+  C.nls[oidx] = (int32_t)((uint32_t)nout | (neg ? 0x80000000u : 0u));
+  if (!P.approx) {
+    double rm = 0.0, m0 = 0.0;
+    int re = 0, e0 = 0;
+    if (P.rin_m) { m0 = P.rin_m[ij]; e0 = P.rin_e[ij]; }
+    ru_add_ext(m0, e0, inexact ? 0.5 : 0.0, em - P.p + 1, rm, re);
+    C.rad_m[oidx] = rm;
+    C.rad_e[oidx] = re;
+  }
+  if (C.status) C.status[oidx] = ARBGPU_ST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// radius matrices (FP64, rounded up, per-line exponent frames)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double mag_upper_mem(const arbgpu_arr &A, int64_t idx, int n) {
+  const uint32_t top = A.limbs[idx];
+  const uint32_t second = n > 1 ? A.limbs[A.ld + idx] : 0u;
+  uint32_t rest = 0;
+  for (int q = 2; q < n; ++q) rest |= A.limbs[(int64_t)q * A.ld + idx];
+  const uint64_t v = ((uint64_t)top << 32) | second;
+  const uint64_t m53 = (v >> 11) + (((v & 0x7FFull) != 0 || rest != 0) ? 1 : 0);
+  return (double)m53 * 0x1p-53;
+}
+
+// One wave per line: frame = max exponent bound over the line, then the
+// scaled upper bounds.  A side writes [line][k]; B side writes [k][line].
+__global__ __launch_bounds__(256) void rad_prep_kernel(RadPrepParams P) {
+  const int64_t line = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (line >= P.lines) return;
+  const int64_t lt = (P.mode == 0) ? P.len : 2 * P.len;
+  int F = -0x7FFFFFFF - 1;
+  for (int64_t k = lane; k < lt; k += 64) {
+    int part;
+    int64_t kk;
+    uint32_t ng;
+    inner_map(P.mode, P.len, k, part, kk, ng);
+    const arbgpu_arr &A = part_of(P.part, part);
+    const int64_t idx = P.off + line * P.line_stride + kk * P.elem_stride;
+    const int n = elem_n(A, idx);
+    int f = -0x7FFFFFFF - 1;
+    if (n) f = A.exp[idx];
+    if (A.rad_m) {
+      const double r = A.rad_m[idx];
+      if (r != 0.0) {
+        int ex;
+        (void)frexp(r, &ex);
+        const int re = A.rad_e[idx] + ex;
+        f = re > f ? re : f;
+      }
+    }
+    if (P.side == 1 && f != -0x7FFFFFFF - 1) f += 1;   // |b| + r < 2^(max + 1)
+    F = f > F ? f : F;
+  }
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    int o = __shfl_xor(F, m, 64);
+    F = o > F ? o : F;
+  }
+  if (F == -0x7FFFFFFF - 1) F = 0;
+  if (lane == 0) P.scale[line] = F;
+  for (int64_t k = lane; k < lt; k += 64) {
+    int part;
+    int64_t kk;
+    uint32_t ng;
+    inner_map(P.mode, P.len, k, part, kk, ng);
+    const arbgpu_arr &A = part_of(P.part, part);
+    const int64_t idx = P.off + line * P.line_stride + kk * P.elem_stride;
+    const int n = elem_n(A, idx);
+    double m = 0.0, r = 0.0;
+    if (n) m = ru_scale_down(mag_upper_mem(A, idx, n), A.exp[idx] - F);
+    if (A.rad_m) {
+      const double rr = A.rad_m[idx];
+      if (rr != 0.0) {
+        int ex;
+        const double rm = frexp(rr, &ex);
+        r = ru_scale_down(rm, A.rad_e[idx] + ex - F);
+      }
+    }
+    const int64_t o = (P.side == 0) ? line * lt + k : k * P.lines + line;
+    P.v0[o] = (P.side == 0) ? m : ru_add(m, r);
+    P.v1[o] = r;
+  }
+}
+
+// rho_in(i, j) = sum_k a_m[i][k] b_r[k][j] + a_r[i][k] b_mr[k][j], rounded up,
+// in the frame 2^(a_s[i] + b_s[j]).
+__global__ __launch_bounds__(256) void rad_gemm_kernel(RadGemmParams P) {
+  const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= P.M || j >= P.N) return;
+  double acc = 0.0;
+  const double *am = P.a_m + i * P.Kt, *ar = P.a_r + i * P.Kt;
+  for (int64_t k = 0; k < P.Kt; ++k) {
+    const double x0 = am[k], x1 = ar[k];
+    const double y0 = P.b_r[k * P.N + j], y1 = P.b_mr[k * P.N + j];
+    if (x0 != 0.0 && y0 != 0.0) acc = ru_add(acc, ru_mul(x0, y0));
+    if (x1 != 0.0 && y1 != 0.0) acc = ru_add(acc, ru_mul(x1, y1));
+  }
+  double m = 0.0;
+  int e = 0;
+  if (acc != 0.0) {
+    int ex;
+    m = frexp(acc, &ex);
+    e = P.a_s[i] + P.b_s[j] + ex;
+  }
+  P.out_m[i * P.N + j] = m;
+  P.out_e[i * P.N + j] = e;
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static inline unsigned nblk(int64_t n, int64_t per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_stats_rows(const StatsParams &P, hipStream_t s) {
+  if (P.lines == 0) return hipSuccess;
+  hipLaunchKernelGGL(stats_rows_kernel, dim3(nblk(P.lines, 4)), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_stats_cols(const StatsParams &P, hipStream_t s) {
+  if (P.lines == 0) return hipSuccess;
+  hipLaunchKernelGGL(stats_cols_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_slice(const SliceParams &P, hipStream_t s) {
+  const int64_t n = P.lines_pad * (P.k_pad >> 2);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(slice_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_mfma(const MfmaParams &P, hipStream_t s) {
+  const int64_t n = (int64_t)P.ngroups * P.ntm * P.ntn;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(mfma_diag_kernel, dim3((unsigned)n), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_recombine(const RecombParams &P, hipStream_t s) {
+  const int64_t n = P.M * P.N;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(recombine_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_rad_prep(const RadPrepParams &P, hipStream_t s) {
+  if (P.lines == 0) return hipSuccess;
+  hipLaunchKernelGGL(rad_prep_kernel, dim3(nblk(P.lines, 4)), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_rad_gemm(const RadGemmParams &P, hipStream_t s) {
+  if (P.M == 0 || P.N == 0) return hipSuccess;
+  hipLaunchKernelGGL(rad_gemm_kernel, dim3(nblk(P.N, 64), nblk(P.M, 4)), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace arbgpu_impl

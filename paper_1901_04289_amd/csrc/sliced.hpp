@@ -1,0 +1,102 @@
+// Scaled-integer block product on INT8 MFMA (Algorithm 2, Johansson 2019,
+// Section 4): interfaces shared by the sliced kernels and the front end.
+#pragma once
+
+#include "internal.hpp"
+
+namespace arbgpu_impl {
+
+constexpr int kTile = 256;       // output tile edge of the MFMA kernel
+constexpr int kKStep = 128;      // inner bytes per pipeline step
+constexpr int kMaxSlices = 512;  // digit planes per operand (height < 4095 bits)
+
+// Per-row / per-column statistics over the inner index range of a block.
+struct LineStats {
+  int32_t *top;    // max exponent over nonzero entries (INT32_MIN: none)
+  int32_t *v2;     // min lowest-set-bit position (INT32_MAX: none)
+};
+
+struct StatsParams {
+  arbgpu_arr part[2];        // operand parts (re, im)
+  int nparts;
+  int64_t lines, len;        // number of rows (A) / columns (B), inner length
+  int64_t off, line_stride, elem_stride;
+  int64_t k0;                // first inner index of the block
+  LineStats out;
+  int32_t *gmax;             // [0] max height, [1] max precision, [2] erange flag
+};
+
+// One operand of the block product, sliced into balanced base-256 digits.
+struct SliceParams {
+  arbgpu_arr part[2];
+  int64_t lines, len;        // lines = rows of A (or columns of B); len = inner length per part
+  int64_t off, line_stride, elem_stride;
+  int64_t k0;
+  int mode;                  // 0: real; 1: [re; -im] (inner 2 len); 2: [im; re]; 3: [re, im]
+  int64_t lines_pad, k_pad;  // plane shape [L][lines_pad][k_pad]
+  int L;                     // number of digit planes
+  const int32_t *v2;         // scaling per line: value * 2^-v2 is an integer
+  int8_t *planes;
+};
+
+// A diagonal group: slice pairs (a, c - a) for a in [a0, a1), summed into
+// one int32 partial plane `slot`.
+struct DiagGroup {
+  int32_t c, a0, a1, slot;
+};
+
+struct MfmaParams {
+  const int8_t *A;       // [LA][Mp][Kp]
+  const int8_t *B;       // [LB][Np][Kp]
+  int32_t *D;            // [nslots][M][N]
+  const DiagGroup *groups;
+  int64_t M, N, Mp, Np, Kp;
+  int ntm, ntn;          // tiles along M and N
+  int ngroups;
+};
+
+struct RecombParams {
+  const int32_t *D;        // [nslots][M][N]
+  const int32_t *slot_of;  // [Lc + 1]: slots of diagonal c are slot_of[c] .. slot_of[c+1]-1
+  int Lc;                  // number of diagonals (LA + LB - 1)
+  int64_t M, N;
+  uint32_t *T;             // [nT][M*N] two's complement limbs, least significant first
+  int nT;
+  const int32_t *rowv2, *colv2;
+  arbgpu_out C;
+  int64_t c_off, c_rs, c_cs;
+  int p;
+  int approx;
+  const double *rin_m;     // propagated radius per entry (nullable)
+  const int32_t *rin_e;
+};
+
+struct RadPrepParams {
+  arbgpu_arr part[2];
+  int nparts;
+  int64_t lines, len, off, line_stride, elem_stride;
+  int mode;                // as in SliceParams (inner index layout)
+  int side;                // 0: A side -> (|m|, r); 1: B side -> (|m| + r, r)
+  int32_t *scale;          // per-line exponent frame
+  double *v0, *v1;         // [lines][len_total] scaled upper bounds
+};
+
+struct RadGemmParams {
+  const double *a_m, *a_r;   // [M][Kt]: |A| and R_A, row-scaled
+  const double *b_mr, *b_r;  // [N][Kt]: |B| + R_B and R_B, column-scaled
+  const int32_t *a_s, *b_s;  // row / column frames
+  int64_t M, N, Kt;
+  double *out_m;             // [M*N]
+  int32_t *out_e;
+};
+
+hipError_t launch_stats_rows(const StatsParams &P, hipStream_t s);
+hipError_t launch_stats_cols(const StatsParams &P, hipStream_t s);
+hipError_t launch_slice(const SliceParams &P, hipStream_t s);
+hipError_t launch_mfma(const MfmaParams &P, hipStream_t s);
+hipError_t launch_recombine(const RecombParams &P, hipStream_t s);
+hipError_t launch_rad_prep(const RadPrepParams &P, hipStream_t s);
+hipError_t launch_rad_gemm(const RadGemmParams &P, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+
+}  // namespace arbgpu_impl

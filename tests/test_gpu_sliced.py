@@ -1,0 +1,159 @@
+"""GPU parity of the scaled-integer INT8-MFMA matrix product (Algorithm 2)
+against the exact oracle and against the limb kernel, through the C-ABI."""
+
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_04289_amd import arbgpu, gen
+from tests.arbcheck import compare_entry
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = arbgpu.Context(0)
+    yield c
+    c.close()
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def run(ctx, A, B, M, N, K, p, flags, Ai=None, Bi=None):
+    import torch
+    dA, dB = arbgpu.DeviceArray.from_host(A), arbgpu.DeviceArray.from_host(B)
+    dAi = arbgpu.DeviceArray.from_host(Ai) if Ai is not None else None
+    dBi = arbgpu.DeviceArray.from_host(Bi) if Bi is not None else None
+    rad = not (flags & arbgpu.APPROX)
+    C = arbgpu.DeviceOut.empty(M * K, p, radius=rad)
+    Ci = arbgpu.DeviceOut.empty(M * K, p, radius=rad) if flags & arbgpu.COMPLEX else None
+    ctx.mat_mul(C, dA, dB, M, N, K, p, flags, Ci=Ci, Ai=dAi, Bi=dBi)
+    torch.cuda.synchronize()
+    return C.to_host(), (Ci.to_host() if Ci is not None else None)
+
+
+def check(out, st, want, entries, K, approx=False):
+    bad = []
+    for (i, j) in entries:
+        e = compare_entry(gen.to_canonical(out, i * K + j), want(i, j), int(st[i * K + j]), approx)
+        if e:
+            bad.append(((i, j), e))
+    assert not bad, bad[:5]
+
+
+def test_sliced_config0_full(ctx):
+    w = gen.config0()
+    say("sliced config0 64x64x64 p=128")
+    (out, st), _ = run(ctx, w.A, w.B, w.M, w.N, w.K, w.p, arbgpu.ALGO_SLICED)
+    Ac = gen.canonical_matrix(w.A, w.M, w.N, w.N, 1)
+    Bc = gen.canonical_matrix(w.B, w.N, w.K, w.K, 1)
+    C = oracle.mat_mul(Ac, Bc, w.p)
+    check(out, st, lambda i, j: C[i][j], [(i, j) for i in range(w.M) for j in range(w.K)], w.K)
+    assert (st == 0).all()
+
+
+@pytest.mark.parametrize("seed,M,N,K,p,prec,erange,rshift", [
+    (1, 5, 37, 70, 100, 120, 20, 110),       # ragged everywhere, balls, zeros
+    (2, 300, 130, 257, 64, 64, 3, None),     # several tiles, K not a multiple of 128
+    (3, 17, 300, 9, 333, 400, 40, 300),      # long inner dimension, wide operands
+    (4, 1, 31, 1, 2, 50, 2, None),           # p = 2
+])
+def test_sliced_random_parity(ctx, seed, M, N, K, p, prec, erange, rshift):
+    rng = gen.rng_for(20, seed)
+    A = gen.random_operands(rng, M * N, rng.integers(1, prec + 1, M * N), -erange, erange,
+                            radius_shift=rshift, zero_frac=0.1)
+    B = gen.random_operands(rng, N * K, rng.integers(1, prec + 1, N * K), -erange, erange,
+                            radius_shift=rshift, zero_frac=0.1)
+    if M > 2:
+        A.limbs[:, N:2 * N] = 0
+        A.nls[N:2 * N] = 0
+    say(f"sliced random seed={seed} {M}x{N}x{K} p={p}")
+    (out, st), _ = run(ctx, A, B, M, N, K, p, arbgpu.ALGO_SLICED)
+    Ac = gen.canonical_matrix(A, M, N, N, 1)
+    Bc = gen.canonical_matrix(B, N, K, K, 1)
+    ent = [(i, j) for i in range(M) for j in range(K)]
+    if len(ent) > 250:
+        ent = random.Random(seed).sample(ent, 250)
+    cols = {}
+    def want(i, j):
+        if j not in cols:
+            cols[j] = [Bc[k][j] for k in range(N)]
+        return oracle.dot(Ac[i], cols[j], p)
+    check(out, st, want, ent, K)
+
+
+def test_sliced_exact_T(ctx):
+    # p larger than every exact sum: the output mantissa is the whole integer
+    # block product T, so this checks T bit for bit
+    rng = gen.rng_for(21, 0)
+    M, N, K = 40, 90, 33
+    A = gen.random_operands(rng, M * N, 200, -6, 6)
+    B = gen.random_operands(rng, N * K, 160, -6, 6)
+    p = 600
+    say("sliced exact T")
+    (out, st), _ = run(ctx, A, B, M, N, K, p, arbgpu.ALGO_SLICED)
+    Ac = gen.canonical_matrix(A, M, N, N, 1)
+    Bc = gen.canonical_matrix(B, N, K, K, 1)
+    e, f, T = oracle.block_product([[x[0] for x in r] for r in Ac], [[x[0] for x in r] for r in Bc],
+                                   list(range(N)))
+    for i in range(M):
+        for j in range(K):
+            got = gen.to_canonical(out, i * K + j)
+            want = oracle.truncate(T[i][j], -e[i] - f[j], p)
+            assert not want[1]
+            assert got[0] == want[0], (i, j)
+            assert got[1] is None
+
+
+def test_sliced_complex(ctx):
+    rng = gen.rng_for(22, 0)
+    M, N, K, p = 6, 45, 5, 120
+    parts = [gen.random_operands(rng, c, 130, -10, 10, radius_shift=125, zero_frac=0.05)
+             for c in (M * N, M * N, N * K, N * K)]
+    say("sliced complex")
+    (out, st), (outi, sti) = run(ctx, parts[0], parts[2], M, N, K, p, arbgpu.COMPLEX | arbgpu.ALGO_SLICED,
+                                 Ai=parts[1], Bi=parts[3])
+    A = [[(gen.to_canonical(parts[0], i * N + k), gen.to_canonical(parts[1], i * N + k)) for k in range(N)]
+         for i in range(M)]
+    B = [[(gen.to_canonical(parts[2], k * K + j), gen.to_canonical(parts[3], k * K + j)) for j in range(K)]
+         for k in range(N)]
+    C = oracle.cmat_mul(A, B, p)
+    for i in range(M):
+        for j in range(K):
+            re, im = C[i][j]
+            assert compare_entry(gen.to_canonical(out, i * K + j), re, int(st[i * K + j])) is None
+            assert compare_entry(gen.to_canonical(outi, i * K + j), im, int(sti[i * K + j])) is None
+
+
+def test_config1_sliced_equals_limb_and_oracle(ctx):
+    w = gen.config1()
+    say("config1 sliced vs limb 512^3 p=256")
+    (o1, s1), _ = run(ctx, w.A, w.B, w.M, w.N, w.K, w.p, arbgpu.ALGO_SLICED)
+    (o2, s2), _ = run(ctx, w.A, w.B, w.M, w.N, w.K, w.p, arbgpu.ALGO_LIMB)
+    # identical midpoints everywhere
+    assert np.array_equal(o1.limbs, o2.limbs)
+    assert np.array_equal(o1.exp, o2.exp) and np.array_equal(o1.nls, o2.nls)
+    r = random.Random(3)
+    ent = [(r.randrange(w.M), r.randrange(w.K)) for _ in range(30)]
+    rows = {i: [gen.to_canonical(w.A, i * w.N + k) for k in range(w.N)] for i, _ in ent}
+    cols = {j: [gen.to_canonical(w.B, k * w.K + j) for k in range(w.N)] for _, j in ent}
+    check(o1, s1, lambda i, j: oracle.dot(rows[i], cols[j], w.p), ent, w.K)
+
+
+def test_config2_sliced_sampled(ctx):
+    w = gen.config2()
+    say("config2 sliced 2048^3 p=512")
+    (out, st), _ = run(ctx, w.A, w.B, w.M, w.N, w.K, w.p, arbgpu.ALGO_SLICED)
+    assert (st == 0).all()
+    r = random.Random(4)
+    ent = [(r.randrange(w.M), r.randrange(w.K)) for _ in range(10)] + [(0, 0), (w.M - 1, w.K - 1)]
+    rows = {i: [gen.to_canonical(w.A, i * w.N + k) for k in range(w.N)] for i, _ in ent}
+    cols = {j: [gen.to_canonical(w.B, k * w.K + j) for k in range(w.N)] for _, j in ent}
+    check(out, st, lambda i, j: oracle.dot(rows[i], cols[j], w.p), ent, w.K)
