@@ -144,6 +144,22 @@ int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A,
                    const arbgpu_mat *B, int64_t p, uint32_t flags,
                    arbgpu_stream stream);
 
+/* Per-kernel timing with HIP events recorded on the caller's stream around
+ * each launch (for measurement; off by default).  arbgpu_timing(ctx, 1)
+ * clears old records and starts recording, 0 stops.  arbgpu_timing_read
+ * waits for the recorded launches of `kernel` ("mfma", "slice", "stats",
+ * "recombine", "rad_gemm", "limb_mm", "limb_dot") and returns their total
+ * milliseconds and count.  EINVAL on NULL arguments. */
+int arbgpu_timing(arbgpu_ctx *ctx, int enable);
+
+/* Shape of the last scaled-integer product run on this context: writes up
+ * to n of {digit planes of A, digit planes of B, int32 partial planes,
+ * diagonal groups, inner length, rows, cols, parts} to out (host memory).
+ * All zero before the first such product.  EINVAL on NULL. */
+int arbgpu_plan_info(arbgpu_ctx *ctx, int64_t *out, int n);
+int arbgpu_timing_read(arbgpu_ctx *ctx, const char *kernel, double *ms_total,
+                       int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

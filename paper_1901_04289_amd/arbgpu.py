@@ -64,6 +64,10 @@ EXPORTS = {
                                   c_i64, c_i64, c_u32, c_p]),
     "arbgpu_mat_mul": (ctypes.c_int, [c_p, ctypes.POINTER(OMat), ctypes.POINTER(Mat), ctypes.POINTER(Mat),
                                       c_i64, c_u32, c_p]),
+    "arbgpu_timing": (ctypes.c_int, [c_p, ctypes.c_int]),
+    "arbgpu_plan_info": (ctypes.c_int, [c_p, ctypes.POINTER(c_i64), ctypes.c_int]),
+    "arbgpu_timing_read": (ctypes.c_int, [c_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(c_i64)]),
 }
 
 
@@ -206,6 +210,23 @@ class Context:
         if rc != OK:
             raise ArbgpuError(rc, self.last_error())
         return rc
+
+    def timing(self, enable: bool = True):
+        self._check(self.lib.arbgpu_timing(self.h, int(enable)))
+
+    def plan_info(self):
+        """Shape of the last scaled-integer product (dict)."""
+        buf = (c_i64 * 8)()
+        self._check(self.lib.arbgpu_plan_info(self.h, buf, 8))
+        keys = ["slices_a", "slices_b", "partial_planes", "groups", "inner", "rows", "cols", "parts"]
+        return dict(zip(keys, list(buf)))
+
+    def timing_read(self, kernel: str):
+        """(total milliseconds, launches) of the recorded launches of `kernel`."""
+        ms = ctypes.c_double()
+        n = c_i64()
+        self._check(self.lib.arbgpu_timing_read(self.h, kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     # -- raw entry points (ctypes structs) --------------------------------
     def dot_raw(self, res: Sequence[Out], res_idx: int, initial: Optional[Sequence[Arr]], init_idx: int,

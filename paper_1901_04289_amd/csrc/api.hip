@@ -17,6 +17,10 @@
 using namespace arbgpu_impl;
 
 arbgpu_ctx::~arbgpu_ctx() {
+  for (auto &t : timed) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
   for (auto &b : ws)
     if (b.ptr) (void)hipFree(b.ptr);
 }
@@ -169,6 +173,45 @@ void arbgpu_destroy(arbgpu_ctx *ctx) {
 
 const char *arbgpu_last_error(const arbgpu_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
 
+int arbgpu_timing(arbgpu_ctx *ctx, int enable) {
+  if (!ctx) return ARBGPU_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (auto &t : ctx->timed) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  ctx->timed.clear();
+  ctx->timing = enable != 0;
+  return ARBGPU_OK;
+}
+
+int arbgpu_plan_info(arbgpu_ctx *ctx, int64_t *out, int n) {
+  if (!ctx || !out || n < 0) return ARBGPU_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (int i = 0; i < n; ++i) out[i] = i < 8 ? ctx->last_plan[i] : 0;
+  return ARBGPU_OK;
+}
+
+int arbgpu_timing_read(arbgpu_ctx *ctx, const char *kernel, double *ms_total, int64_t *launches) {
+  if (!ctx || !kernel || !ms_total || !launches) return ARBGPU_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  double tot = 0.0;
+  int64_t n = 0;
+  for (auto &t : ctx->timed) {
+    if (strcmp(t.name, kernel) != 0) continue;
+    hipError_t e = hipEventSynchronize(t.stop);
+    if (e != hipSuccess) return fail(ctx, ARBGPU_EDEVICE, "hipEventSynchronize: %s", hipGetErrorString(e));
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, t.start, t.stop);
+    if (e != hipSuccess) return fail(ctx, ARBGPU_EDEVICE, "hipEventElapsedTime: %s", hipGetErrorString(e));
+    tot += ms;
+    ++n;
+  }
+  *ms_total = tot;
+  *launches = n;
+  return ARBGPU_OK;
+}
+
 int arbgpu_dot(arbgpu_ctx *ctx, const arbgpu_out *res, int64_t res_idx, const arbgpu_arr *initial,
                int64_t init_idx, int sub, const arbgpu_arr *x, int64_t xoff, int64_t xstep,
                const arbgpu_arr *y, int64_t yoff, int64_t ystep, int64_t N, int64_t p, uint32_t flags,
@@ -230,6 +273,7 @@ int arbgpu_dot(arbgpu_ctx *ctx, const arbgpu_out *res, int64_t res_idx, const ar
     prm.approx = approx;
     prm.sub = sub ? 1u : 0u;
     prm.ct = !cplx ? comp_real() : (q == 0 ? comp_re() : comp_im());
+    KernelTimer kt(ctx, "limb_dot", to_stream(stream));
     hipError_t e = launch_limb_dot(prm, sh, to_stream(stream));
     if (e != hipSuccess) return hip_fail(ctx, e, "arbgpu_dot launch");
   }
@@ -308,6 +352,7 @@ int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
     prm.p = (int)p;
     prm.approx = approx;
     prm.ct = !cplx ? comp_real() : (q == 0 ? comp_re() : comp_im());
+    KernelTimer kt(ctx, "limb_mm", to_stream(stream));
     hipError_t e = launch_limb_mm(prm, sh, to_stream(stream));
     if (e != hipSuccess) return hip_fail(ctx, e, "arbgpu_mat_mul launch");
   }

@@ -22,6 +22,16 @@ struct arbgpu_ctx {
     size_t size = 0;
   };
   std::vector<Buf> ws;   // indexed by workspace slot
+  // per-kernel event timing (arbgpu_timing)
+  bool timing = false;
+  struct TimedLaunch {
+    const char *name;
+    hipEvent_t start, stop;
+  };
+  std::vector<TimedLaunch> timed;
+  // shape of the last scaled-integer product: digit planes of A and B,
+  // partial planes, diagonal groups, inner length, rows, cols
+  int64_t last_plan[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   ~arbgpu_ctx();
 };
 
@@ -39,6 +49,25 @@ enum WsSlot {
 void *ws_get(arbgpu_ctx *ctx, int slot, size_t bytes);
 
 int set_error(arbgpu_ctx *ctx, int code, const char *fmt, ...);
+
+// Records HIP events around one kernel launch on `s` when the context's
+// timing is enabled.
+struct KernelTimer {
+  arbgpu_ctx *ctx;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  const char *name;
+  KernelTimer(arbgpu_ctx *c, const char *n, hipStream_t st) : ctx(c), s(st), name(n) {
+    if (ctx && ctx->timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+      (void)hipEventRecord(a, s);
+  }
+  ~KernelTimer() {
+    if (a && b) {
+      (void)hipEventRecord(b, s);
+      ctx->timed.push_back({name, a, b});
+    }
+  }
+};
 
 // Scaled-integer INT8-MFMA matrix product; returns ARBGPU_OK, an error, or
 // kNotApplicable when the operands need the limb kernel (more than one

@@ -16,11 +16,6 @@ namespace {
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-struct Planned {
-  int LA, LB;
-  int64_t Mp, Np, Kp;
-};
-
 }  // namespace
 
 int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p,
@@ -57,14 +52,17 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
   sp.lines = M; sp.len = K; sp.off = A->off; sp.line_stride = A->rs; sp.elem_stride = A->cs; sp.k0 = 0;
   sp.out = LineStats{rtop, rv2};
   sp.gmax = gA;
-  if ((e = launch_stats_rows(sp, s)) != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "stats: %s", hipGetErrorString(e));
   StatsParams sq = sp;
   sq.part[0] = B->re;
   sq.part[1] = cplx ? B->im : B->re;
   sq.lines = N; sq.len = K; sq.off = B->off; sq.line_stride = B->cs; sq.elem_stride = B->rs;
   sq.out = LineStats{ctop, cv2};
   sq.gmax = gB;
-  if ((e = launch_stats_cols(sq, s)) != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "stats: %s", hipGetErrorString(e));
+  {
+    KernelTimer t_stats(ctx, "stats", s);
+    if ((e = launch_stats_rows(sp, s)) == hipSuccess) e = launch_stats_cols(sq, s);
+  }
+  if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "stats: %s", hipGetErrorString(e));
   int32_t g[8];
   if ((e = hipMemcpyAsync(g, gA, sizeof g, hipMemcpyDeviceToHost, s)) != hipSuccess ||
       (e = hipStreamSynchronize(s)) != hipSuccess)
@@ -99,6 +97,10 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
   std::stable_sort(groups.begin(), groups.end(),
                    [](const DiagGroup &x, const DiagGroup &y) { return (x.a1 - x.a0) > (y.a1 - y.a0); });
   const int nq = (Lc + 3) / 4, nT = nq + 2;
+  {
+    const int64_t plan[8] = {LA, LB, nslots, (int64_t)groups.size(), Kt, M, N, nparts};
+    memcpy(ctx->last_plan, plan, sizeof plan);
+  }
 
   // ---- workspace ------------------------------------------------------------
   const size_t bytesA = (size_t)LA * Mp * Kp, bytesB = (size_t)LB * Np * Kp;
@@ -163,6 +165,7 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
       rad_out_e[q] = (int32_t *)((double *)ro + (size_t)nparts * M * N) + (size_t)q * M * N;
       rg.out_m = rad_out_m[q];
       rg.out_e = rad_out_e[q];
+      KernelTimer tg(ctx, "rad_gemm", s);
       if ((e = launch_rad_gemm(rg, s)) != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "rad gemm: %s", hipGetErrorString(e));
     }
   }
@@ -175,16 +178,20 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
   sa.lines = M; sa.len = K; sa.off = A->off; sa.line_stride = A->rs; sa.elem_stride = A->cs; sa.k0 = 0;
   sa.mode = cplx ? 3 : 0;
   sa.lines_pad = Mp; sa.k_pad = Kp; sa.L = LA; sa.v2 = rv2; sa.planes = planesA;
-  if ((e = launch_slice(sa, s)) != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "slice: %s", hipGetErrorString(e));
-  for (int q = 0; q < nparts; ++q) {
-    SliceParams sb = sa;
-    sb.part[0] = B->re;
-    sb.part[1] = cplx ? B->im : B->re;
-    sb.lines = N; sb.off = B->off; sb.line_stride = B->cs; sb.elem_stride = B->rs;
-    sb.mode = !cplx ? 0 : (q == 0 ? 1 : 2);
-    sb.lines_pad = Np; sb.L = LB; sb.v2 = cv2; sb.planes = q == 0 ? planesB : planesB2;
-    if ((e = launch_slice(sb, s)) != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "slice: %s", hipGetErrorString(e));
+  {
+    KernelTimer t_slice(ctx, "slice", s);
+    e = launch_slice(sa, s);
+    for (int q = 0; q < nparts && e == hipSuccess; ++q) {
+      SliceParams sb = sa;
+      sb.part[0] = B->re;
+      sb.part[1] = cplx ? B->im : B->re;
+      sb.lines = N; sb.off = B->off; sb.line_stride = B->cs; sb.elem_stride = B->rs;
+      sb.mode = !cplx ? 0 : (q == 0 ? 1 : 2);
+      sb.lines_pad = Np; sb.L = LB; sb.v2 = cv2; sb.planes = q == 0 ? planesB : planesB2;
+      e = launch_slice(sb, s);
+    }
   }
+  if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "slice: %s", hipGetErrorString(e));
 
   // ---- product and recombination per output part ------------------------------
   const arbgpu_out *cparts[2] = {&C->re, &C->im};
@@ -197,7 +204,12 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
     mp.M = M; mp.N = N; mp.Mp = Mp; mp.Np = Np; mp.Kp = Kp;
     mp.ntm = (int)(Mp / kTile); mp.ntn = (int)(Np / kTile);
     mp.ngroups = (int)groups.size();
-    if ((e = launch_mfma(mp, s)) != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "mfma: %s", hipGetErrorString(e));
+    hipError_t em;
+    {
+      KernelTimer tm(ctx, "mfma", s);
+      em = launch_mfma(mp, s);
+    }
+    if ((e = em) != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "mfma: %s", hipGetErrorString(e));
     RecombParams rp;
     rp.D = D; rp.slot_of = dslot; rp.Lc = Lc; rp.M = M; rp.N = N; rp.T = T; rp.nT = nT;
     rp.rowv2 = rv2; rp.colv2 = cv2;
@@ -207,6 +219,7 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
     rp.approx = approx;
     rp.rin_m = rad_out_m[q];
     rp.rin_e = rad_out_e[q];
+    KernelTimer tr(ctx, "recombine", s);
     if ((e = launch_recombine(rp, s)) != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "recombine: %s", hipGetErrorString(e));
   }
   return ARBGPU_OK;
