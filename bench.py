@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also copy a buffer of this many MiB once (reference kernel for HBM counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU design is "
@@ -128,6 +130,15 @@ def main():
     C = arbgpu.DeviceOut.empty(M * K, p, radius=True)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
+
+    if a.copy_calibration_mib:
+        src = torch.empty(a.copy_calibration_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # sliced INT8 MFMA path
     for _ in range(a.warmup):

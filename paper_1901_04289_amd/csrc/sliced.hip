@@ -81,6 +81,7 @@ __device__ __forceinline__ void stats_elem(const StatsParams &P, int64_t line, i
   }
 }
 
+// One wave per row: lanes stride the inner index (coalesced for row-major A).
 __global__ __launch_bounds__(256) void stats_rows_kernel(StatsParams P) {
   const int64_t line = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -95,24 +96,50 @@ __global__ __launch_bounds__(256) void stats_rows_kernel(StatsParams P) {
     bad |= __shfl_xor(bad, m, 64);
   }
   if (lane == 0) {
-    P.out.top[line] = top;
-    P.out.v2[line] = v2;
-    if (v2 != 0x7FFFFFFF) atomicMax(&P.gmax[0], top - v2);
+    atomicMax(&P.out.top[line], top);
+    atomicMin(&P.out.v2[line], v2);
     atomicMax(&P.gmax[1], prec);
     if (bad) atomicMax(&P.gmax[2], 1);
   }
 }
 
+// Columns: lane = column (coalesced for row-major B), one wave per chunk of
+// 64 inner indices; partial results merge with atomics.
 __global__ __launch_bounds__(256) void stats_cols_kernel(StatsParams P) {
-  const int64_t line = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (line >= P.lines) return;
+  const int64_t nct = (P.lines + 63) >> 6;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t ct = w % nct, kc = w / nct;
+  const int64_t line = ct * 64 + (threadIdx.x & 63);
+  const int64_t k0 = kc * 64;
+  if (line >= P.lines || k0 >= P.len) return;
+  const int64_t k1 = k0 + 64 < P.len ? k0 + 64 : P.len;
   int top = -0x7FFFFFFF - 1, v2 = 0x7FFFFFFF, prec = 0, bad = 0;
-  for (int64_t k = 0; k < P.len; ++k) stats_elem(P, line, k, top, v2, prec, bad);
-  P.out.top[line] = top;
-  P.out.v2[line] = v2;
-  if (v2 != 0x7FFFFFFF) atomicMax(&P.gmax[0], top - v2);
-  atomicMax(&P.gmax[1], prec);
+  for (int64_t k = k0; k < k1; ++k) stats_elem(P, line, k, top, v2, prec, bad);
+  if (top != -0x7FFFFFFF - 1) atomicMax(&P.out.top[line], top);
+  if (v2 != 0x7FFFFFFF) atomicMin(&P.out.v2[line], v2);
+  if (prec) atomicMax(&P.gmax[1], prec);
   if (bad) atomicMax(&P.gmax[2], 1);
+}
+
+__global__ __launch_bounds__(256) void stats_init_kernel(LineStats S, int64_t lines) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < lines) {
+    S.top[i] = -0x7FFFFFFF - 1;
+    S.v2[i] = 0x7FFFFFFF;
+  }
+}
+
+// Largest integer height top - v2 over nonzero lines.
+__global__ __launch_bounds__(256) void stats_height_kernel(LineStats S, int64_t lines, int32_t *gmax) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int h = 0;
+  if (i < lines && S.v2[i] != 0x7FFFFFFF) h = S.top[i] - S.v2[i];
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    int o = __shfl_xor(h, m, 64);
+    h = o > h ? o : h;
+  }
+  if ((threadIdx.x & 63) == 0 && h > 0) atomicMax(&gmax[0], h);
 }
 
 // ---------------------------------------------------------------------------
@@ -216,18 +243,26 @@ __global__ __launch_bounds__(256) void slice_kernel(SliceParams P) {
 
 __device__ __forceinline__ int swz(int row, int chunk) { return row * kKStep + ((chunk ^ ((row >> 1) & 7)) << 4); }
 
-__global__ __launch_bounds__(256) void mfma_diag_kernel(MfmaParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void mfma_diag_kernel(MfmaParams P) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[2][2][kTile * kKStep];  // [buf][A/B]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int ntiles = P.ntm * P.ntn;
-  const int g = blockIdx.x / ntiles;
-  const int t = blockIdx.x - g * ntiles;
-  const int tm = t / P.ntn, tn = t - tm * P.ntn;
+  // Workgroups are handed to the 8 XCDs round-robin by id.  Work item
+  // (group, tile) for XCD x = id % 8, slot = id / 8: groups x, x + 8, ...
+  // (the host sorted groups by size, so every XCD gets a similar share),
+  // tiles of one group in order, so the workgroups resident on one XCD
+  // share A row blocks and B column blocks in that XCD's L2.
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7, slot = bid >> 3;
+  const int g = xcd + 8 * (slot / ntiles);
+  const int t = slot % ntiles;
   const DiagGroup G = P.groups[g];
-  const int64_t ksteps = P.Kp / kKStep;
-  const int64_t nsteps = (int64_t)(G.a1 - G.a0) * ksteps;
+  if (G.slot < 0) return;   // padding group
+  const int tm = t / P.ntn, tn = t - tm * P.ntn;
+  const int ksteps = (int)(P.Kp / kKStep);
+  const int nsteps = (G.a1 - G.a0) * ksteps;
   const int64_t planeA = P.Mp * P.Kp, planeB = P.Np * P.Kp;
 
   v16i acc[4][4];
@@ -239,60 +274,105 @@ __global__ __launch_bounds__(256) void mfma_diag_kernel(MfmaParams P) {
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
 
   // global -> register staging: thread covers chunk (tid & 7) of rows
-  // (tid >> 3) + 32 u, u = 0..7, for A and for B
+  // (tid >> 3) + 32 u, u = 0..7, for A and for B; the loads for step s + 1
+  // are issued at the start of step s and stored to LDS at its end.
   const int srow = tid >> 3, schunk = tid & 7;
+  const int8_t *baseA = P.A + ((int64_t)tm * kTile + srow) * P.Kp + schunk * 16;
+  const int8_t *baseB = P.B + ((int64_t)tn * kTile + srow) * P.Kp + schunk * 16;
+  const int64_t rowstep = 32 * P.Kp;
   v4i stA[8], stB[8];
-  auto gload = [&](int64_t step) {
-    const int64_t pr = step / ksteps;
-    const int64_t ks = step - pr * ksteps;
-    const int a = G.a0 + (int)pr;
+  auto gload = [&](v4i (&sa)[8], v4i (&sb)[8], int pr, int ks) {
+    const int a = G.a0 + pr;
     const int b = G.c - a;
-    const int8_t *pa = P.A + a * planeA + ((int64_t)tm * kTile + srow) * P.Kp + ks * kKStep + schunk * 16;
-    const int8_t *pb = P.B + b * planeB + ((int64_t)tn * kTile + srow) * P.Kp + ks * kKStep + schunk * 16;
+    const int8_t *pa = baseA + a * planeA + ks * kKStep;
+    const int8_t *pb = baseB + b * planeB + ks * kKStep;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      stA[u] = *reinterpret_cast<const v4i *>(pa + (int64_t)u * 32 * P.Kp);
-      stB[u] = *reinterpret_cast<const v4i *>(pb + (int64_t)u * 32 * P.Kp);
+      sa[u] = *reinterpret_cast<const v4i *>(pa + u * rowstep);
+      sb[u] = *reinterpret_cast<const v4i *>(pb + u * rowstep);
     }
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](const v4i (&sa)[8], const v4i (&sb)[8], int buf) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int row = srow + 32 * u;
-      *reinterpret_cast<v4i *>(&lds[buf][0][swz(row, schunk)]) = stA[u];
-      *reinterpret_cast<v4i *>(&lds[buf][1][swz(row, schunk)]) = stB[u];
+      *reinterpret_cast<v4i *>(&lds[buf][0][swz(row, schunk)]) = sa[u];
+      *reinterpret_cast<v4i *>(&lds[buf][1][swz(row, schunk)]) = sb[u];
     }
   };
+  // fragment offsets of this lane inside a 256 x 128 tile, per 32-byte K
+  // slice; row block i adds i * 32 rows, which leaves the swizzle unchanged
+  int offA[4], offB[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int chunk = kk * 2 + (lane >> 5);
+    offA[kk] = swz(wm * 128 + (lane & 31), chunk);
+    offB[kk] = swz(wn * 128 + (lane & 31), chunk);
+  }
 
   if (nsteps > 0) {
-    gload(0);
-    lstore(0);
+    gload(stA, stB, 0, 0);
+    lstore(stA, stB, 0);
   }
   __syncthreads();
-  for (int64_t step = 0; step < nsteps; ++step) {
-    const int buf = (int)(step & 1);
-    if (step + 1 < nsteps) gload(step + 1);
+  int pr = 0, ks = 0;
+  for (int step = 0; step < nsteps; ++step) {
+    const int buf = step & 1;
+    int npr = pr, nks = ks + 1;
+    if (nks == ksteps) { nks = 0; ++npr; }
+    // The body is branch-free so that the scheduler can interleave memory
+    // traffic with the MFMAs.  On the last step the prefetch re-reads the
+    // current step (a valid address) and the store fills the idle buffer.
+    const bool more = step + 1 < nsteps;
+    gload(stA, stB, more ? npr : pr, more ? nks : ks);
     const uint8_t *la = lds[buf][0];
     const uint8_t *lb = lds[buf][1];
+    v4i fa[2][4], fb[2][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      fa[0][i] = *reinterpret_cast<const v4i *>(la + offA[0] + i * 32 * kKStep);
+      fb[0][i] = *reinterpret_cast<const v4i *>(lb + offB[0] + i * 32 * kKStep);
+    }
 #pragma unroll
     for (int kk = 0; kk < kKStep / 32; ++kk) {
-      const int chunk = kk * 2 + (lane >> 5);
-      v4i fa[4], fb[4];
+      const int cur = kk & 1, nxt = cur ^ 1;
+      if (kk + 1 < kKStep / 32) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int ra = wm * 128 + i * 32 + (lane & 31);
-        const int rb = wn * 128 + i * 32 + (lane & 31);
-        fa[i] = *reinterpret_cast<const v4i *>(la + swz(ra, chunk));
-        fb[i] = *reinterpret_cast<const v4i *>(lb + swz(rb, chunk));
+        for (int i = 0; i < 4; ++i) {
+          fa[nxt][i] = *reinterpret_cast<const v4i *>(la + offA[kk + 1] + i * 32 * kKStep);
+          fb[nxt][i] = *reinterpret_cast<const v4i *>(lb + offB[kk + 1] + i * 32 * kKStep);
+        }
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[i], fb[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[cur][i], fb[cur][j], acc[i][j], 0, 0, 0);
     }
-    if (step + 1 < nsteps) lstore(buf ^ 1);
+    lstore(stA, stB, buf ^ 1);
+    // Instruction order for the scheduler (masks: 0x008 MFMA, 0x020 VMEM
+    // read, 0x100 DS read, 0x200 DS write): global loads first, the first
+    // slice's fragments, then each slice's 16 MFMAs with the next slice's 8
+    // fragment reads spread between them, and the LDS stores of the next
+    // step spread over the last slice.
+    __builtin_amdgcn_sched_group_barrier(0x020, 16, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+#pragma unroll
+    for (int kk = 0; kk < kKStep / 32 - 1; ++kk) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+    }
     __syncthreads();
+    pr = npr;
+    ks = nks;
   }
 
   // epilogue: int32 partial plane of this diagonal group
@@ -521,12 +601,19 @@ static inline unsigned nblk(int64_t n, int64_t per) { return (unsigned)((n + per
 
 hipError_t launch_stats_rows(const StatsParams &P, hipStream_t s) {
   if (P.lines == 0) return hipSuccess;
+  hipLaunchKernelGGL(stats_init_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P.out, P.lines);
   hipLaunchKernelGGL(stats_rows_kernel, dim3(nblk(P.lines, 4)), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(stats_height_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P.out, P.lines, P.gmax);
   return hipGetLastError();
 }
 hipError_t launch_stats_cols(const StatsParams &P, hipStream_t s) {
   if (P.lines == 0) return hipSuccess;
-  hipLaunchKernelGGL(stats_cols_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(stats_init_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P.out, P.lines);
+  if (P.len > 0) {
+    const int64_t waves = ((P.lines + 63) / 64) * ((P.len + 63) / 64);
+    hipLaunchKernelGGL(stats_cols_kernel, dim3(nblk(waves, 4)), dim3(256), 0, s, P);
+  }
+  hipLaunchKernelGGL(stats_height_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P.out, P.lines, P.gmax);
   return hipGetLastError();
 }
 hipError_t launch_slice(const SliceParams &P, hipStream_t s) {
@@ -536,7 +623,9 @@ hipError_t launch_slice(const SliceParams &P, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_mfma(const MfmaParams &P, hipStream_t s) {
+  // the group table is padded to a multiple of 8 (see the kernel's mapping)
   const int64_t n = (int64_t)P.ngroups * P.ntm * P.ntn;
+  if (P.ngroups % 8 != 0) return hipErrorInvalidValue;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(mfma_diag_kernel, dim3((unsigned)n), dim3(256), 0, s, P);
   return hipGetLastError();

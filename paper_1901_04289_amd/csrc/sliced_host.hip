@@ -96,9 +96,11 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
   slot_of[Lc] = nslots;
   std::stable_sort(groups.begin(), groups.end(),
                    [](const DiagGroup &x, const DiagGroup &y) { return (x.a1 - x.a0) > (y.a1 - y.a0); });
+  const int ngroups_real = (int)groups.size();
+  while (groups.size() % 8) groups.push_back(DiagGroup{0, 0, 0, -1});   // padding for the XCD mapping
   const int nq = (Lc + 3) / 4, nT = nq + 2;
   {
-    const int64_t plan[8] = {LA, LB, nslots, (int64_t)groups.size(), Kt, M, N, nparts};
+    const int64_t plan[8] = {LA, LB, nslots, ngroups_real, Kt, M, N, nparts};
     memcpy(ctx->last_plan, plan, sizeof plan);
   }
 
