@@ -144,11 +144,28 @@ int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A,
                    const arbgpu_mat *B, int64_t p, uint32_t flags,
                    arbgpu_stream stream);
 
+/* Block partition of Algorithm 2 (Section 4.1) for the product A B at
+ * precision p: the inner index range is cut greedily, from index 0 upward,
+ * into ranges over which every row of A and every column of B keeps integer
+ * height (highest exponent minus lowest set bit over its nonzero entries,
+ * both parts together with ARBGPU_COMPLEX) at most
+ * floor(1.25 min(p, max(p_A, p_B)) + 192), p_M being the largest number of
+ * significant bits of an entry of M.  A range shorter than 30 indices is
+ * extended to min(30, remaining) and marked as a basecase chunk (evaluated
+ * with dot products).  Writes min(*nblocks, max_blocks) pairs
+ * (bounds[2i], bounds[2i+1]) = (k0, k1) and kinds[i] (0 block, 1 basecase)
+ * to HOST arrays and the total count to *nblocks; synchronizes `stream`.
+ * Only ARBGPU_COMPLEX is accepted in flags.  EINVAL on NULL pointers, shape
+ * mismatch, p < 2, an exponent outside (-2^28, 2^28). */
+int arbgpu_plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
+                       int64_t p, uint32_t flags, int64_t *bounds, int32_t *kinds,
+                       int64_t max_blocks, int64_t *nblocks, arbgpu_stream stream);
+
 /* Per-kernel timing with HIP events recorded on the caller's stream around
  * each launch (for measurement; off by default).  arbgpu_timing(ctx, 1)
  * clears old records and starts recording, 0 stops.  arbgpu_timing_read
  * waits for the recorded launches of `kernel` ("mfma", "slice", "stats",
- * "recombine", "rad_gemm", "limb_mm", "limb_dot") and returns their total
+ * "recombine", "rad_gemm", "plan", "merge", "limb_mm", "limb_dot") and returns their total
  * milliseconds and count.  EINVAL on NULL arguments. */
 int arbgpu_timing(arbgpu_ctx *ctx, int enable);
 

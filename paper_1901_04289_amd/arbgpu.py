@@ -64,6 +64,9 @@ EXPORTS = {
                                   c_i64, c_i64, c_u32, c_p]),
     "arbgpu_mat_mul": (ctypes.c_int, [c_p, ctypes.POINTER(OMat), ctypes.POINTER(Mat), ctypes.POINTER(Mat),
                                       c_i64, c_u32, c_p]),
+    "arbgpu_plan_blocks": (ctypes.c_int, [c_p, ctypes.POINTER(Mat), ctypes.POINTER(Mat), c_i64, c_u32,
+                                          ctypes.POINTER(c_i64), ctypes.POINTER(ctypes.c_int32), c_i64,
+                                          ctypes.POINTER(c_i64), c_p]),
     "arbgpu_timing": (ctypes.c_int, [c_p, ctypes.c_int]),
     "arbgpu_plan_info": (ctypes.c_int, [c_p, ctypes.POINTER(c_i64), ctypes.c_int]),
     "arbgpu_timing_read": (ctypes.c_int, [c_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -247,7 +250,27 @@ class Context:
                                      _stream_handle(stream) if self.device >= 0 else None)
         return self._check(rc) if check else rc
 
+    def plan_blocks_raw(self, A: Mat, B: Mat, p: int, flags: int = 0, stream=None):
+        """Block partition of the inner range: list of (k0, k1, kind), kind 0
+        a scaled-integer block, 1 a basecase chunk."""
+        cap = max(1, A.cols // 30 + 2)
+        bounds = (c_i64 * (2 * cap))()
+        kinds = (ctypes.c_int32 * cap)()
+        nb = c_i64()
+        self._check(self.lib.arbgpu_plan_blocks(self.h, ctypes.byref(A), ctypes.byref(B), p, flags, bounds, kinds,
+                                                cap, ctypes.byref(nb),
+                                                _stream_handle(stream) if self.device >= 0 else None))
+        n = min(nb.value, cap)
+        return [(bounds[2 * i], bounds[2 * i + 1], kinds[i]) for i in range(n)]
+
     # -- convenience -------------------------------------------------------
+    def plan_blocks(self, A: DeviceArray, B: DeviceArray, M: int, N: int, K: int, p: int, flags: int = 0,
+                    Ai: Optional[DeviceArray] = None, Bi: Optional[DeviceArray] = None, stream=None):
+        """Partition for row-major A (M x N) times B (N x K)."""
+        am = Mat(A.arr(), (Ai or A).arr(), M, N, 0, N, 1)
+        bm = Mat(B.arr(), (Bi or B).arr(), N, K, 0, K, 1)
+        return self.plan_blocks_raw(am, bm, p, flags, stream)
+
     def mat_mul(self, C: DeviceOut, A: DeviceArray, B: DeviceArray, M: int, N: int, K: int, p: int,
                 flags: int = 0, Ci: Optional[DeviceOut] = None, Ai: Optional[DeviceArray] = None,
                 Bi: Optional[DeviceArray] = None, stream=None) -> int:

@@ -359,4 +359,24 @@ int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
   return ARBGPU_OK;
 }
 
+int arbgpu_plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags,
+                       int64_t *bounds, int32_t *kinds, int64_t max_blocks, int64_t *nblocks, arbgpu_stream stream) {
+  if (!ctx) return ARBGPU_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (flags & ~ARBGPU_COMPLEX) return fail(ctx, ARBGPU_EINVAL, "arbgpu_plan_blocks: unknown flags 0x%x", flags);
+  const int nparts = (flags & ARBGPU_COMPLEX) ? 2 : 1;
+  if (p < 2 || p > (1 << 20)) return fail(ctx, ARBGPU_EINVAL, "arbgpu_plan_blocks: p=%lld out of range", (long long)p);
+  if (!nblocks || max_blocks < 0 || (max_blocks > 0 && (!bounds || !kinds)))
+    return fail(ctx, ARBGPU_EINVAL, "arbgpu_plan_blocks: bad output arrays");
+  int rc;
+  if ((rc = validate_mat(ctx, A, nparts, "A"))) return rc;
+  if ((rc = validate_mat(ctx, B, nparts, "B"))) return rc;
+  if (A->cols != B->rows) return fail(ctx, ARBGPU_EINVAL, "inner dimensions differ (%lld vs %lld)",
+                                      (long long)A->cols, (long long)B->rows);
+  *nblocks = 0;
+  if (A->cols == 0) return ARBGPU_OK;
+  if ((rc = bind_device(ctx))) return rc;
+  return plan_partition(ctx, A, B, p, flags, to_stream(stream), bounds, kinds, max_blocks, nblocks);
+}
+
 }  // extern "C"

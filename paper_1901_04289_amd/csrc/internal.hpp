@@ -40,7 +40,7 @@ namespace arbgpu_impl {
 // Workspace slots (each holds one growing device buffer).
 enum WsSlot {
   WS_STATS = 0, WS_PLANES_A, WS_PLANES_B, WS_PLANES_B2, WS_D, WS_T, WS_TABLES,
-  WS_RAD_A, WS_RAD_B, WS_RAD_OUT, WS_COUNT
+  WS_RAD_A, WS_RAD_B, WS_RAD_OUT, WS_PLAN, WS_BLOCKS, WS_COUNT
 };
 
 // Device buffer of at least `bytes` in workspace slot `slot` (nullptr and
@@ -76,6 +76,11 @@ struct KernelTimer {
 constexpr int kNotApplicable = 100;
 int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B,
                    int64_t p, uint32_t flags, hipStream_t s, bool forced);
+
+// Block partition of Algorithm 2 for the product A B at precision p:
+// writes up to max_blocks (k0, k1) pairs and kinds to host arrays.
+int plan_partition(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags,
+                   hipStream_t s, int64_t *bounds, int32_t *kinds, int64_t max_blocks, int64_t *nblocks);
 
 // Which operand parts form the terms of one real output (Section 3.6: the
 // real part of a complex dot is the 2N-term real dot of a c and -(b d), the

@@ -65,7 +65,7 @@ __device__ __forceinline__ int elem_n(const arbgpu_arr &A, int64_t idx) {
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ void stats_elem(const StatsParams &P, int64_t line, int64_t k, int &top, int &v2,
-                                          int &prec, int &bad) {
+                                          int &prec, int &bad, int &amax) {
   for (int q = 0; q < P.nparts; ++q) {
     const arbgpu_arr &A = part_of(P.part, q);
     const int64_t idx = P.off + line * P.line_stride + (P.k0 + k) * P.elem_stride;
@@ -78,6 +78,9 @@ __device__ __forceinline__ void stats_elem(const StatsParams &P, int64_t line, i
     top = e > top ? e : top;
     v2 = lb < v2 ? lb : v2;
     prec = (e - lb) > prec ? (e - lb) : prec;
+    const int ae = e < 0 ? -e : e, al = lb < 0 ? -lb : lb;
+    amax = ae > amax ? ae : amax;
+    amax = al > amax ? al : amax;
   }
 }
 
@@ -86,20 +89,22 @@ __global__ __launch_bounds__(256) void stats_rows_kernel(StatsParams P) {
   const int64_t line = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (line >= P.lines) return;
-  int top = -0x7FFFFFFF - 1, v2 = 0x7FFFFFFF, prec = 0, bad = 0;
-  for (int64_t k = lane; k < P.len; k += 64) stats_elem(P, line, k, top, v2, prec, bad);
+  int top = -0x7FFFFFFF - 1, v2 = 0x7FFFFFFF, prec = 0, bad = 0, amax = 0;
+  for (int64_t k = lane; k < P.len; k += 64) stats_elem(P, line, k, top, v2, prec, bad, amax);
 #pragma unroll
   for (int m = 1; m < 64; m <<= 1) {
     int t = __shfl_xor(top, m, 64); top = t > top ? t : top;
     int v = __shfl_xor(v2, m, 64); v2 = v < v2 ? v : v2;
     int q = __shfl_xor(prec, m, 64); prec = q > prec ? q : prec;
     bad |= __shfl_xor(bad, m, 64);
+    int a = __shfl_xor(amax, m, 64); amax = a > amax ? a : amax;
   }
   if (lane == 0) {
     atomicMax(&P.out.top[line], top);
     atomicMin(&P.out.v2[line], v2);
     atomicMax(&P.gmax[1], prec);
     if (bad) atomicMax(&P.gmax[2], 1);
+    if (amax) atomicMax(&P.gmax[3], amax);
   }
 }
 
@@ -113,12 +118,13 @@ __global__ __launch_bounds__(256) void stats_cols_kernel(StatsParams P) {
   const int64_t k0 = kc * 64;
   if (line >= P.lines || k0 >= P.len) return;
   const int64_t k1 = k0 + 64 < P.len ? k0 + 64 : P.len;
-  int top = -0x7FFFFFFF - 1, v2 = 0x7FFFFFFF, prec = 0, bad = 0;
-  for (int64_t k = k0; k < k1; ++k) stats_elem(P, line, k, top, v2, prec, bad);
+  int top = -0x7FFFFFFF - 1, v2 = 0x7FFFFFFF, prec = 0, bad = 0, amax = 0;
+  for (int64_t k = k0; k < k1; ++k) stats_elem(P, line, k, top, v2, prec, bad, amax);
   if (top != -0x7FFFFFFF - 1) atomicMax(&P.out.top[line], top);
   if (v2 != 0x7FFFFFFF) atomicMin(&P.out.v2[line], v2);
   if (prec) atomicMax(&P.gmax[1], prec);
   if (bad) atomicMax(&P.gmax[2], 1);
+  if (amax) atomicMax(&P.gmax[3], amax);
 }
 
 __global__ __launch_bounds__(256) void stats_init_kernel(LineStats S, int64_t lines) {
@@ -502,90 +508,182 @@ __device__ __forceinline__ double mag_upper_mem(const arbgpu_arr &A, int64_t idx
   return (double)m53 * 0x1p-53;
 }
 
-// One wave per line: frame = max exponent bound over the line, then the
-// scaled upper bounds.  A side writes [line][k]; B side writes [k][line].
+// x * 2^d (x >= 0, d <= 0) exactly, for the radius products.  Values that
+// would land below 2^-480 raise the tiny flag instead (the products of two
+// such values could leave the normal range) and read as 0: the exact
+// per-entry kernel then recomputes every radius.
+__device__ __forceinline__ double rad_scaled(double x, int d, int32_t *tiny) {
+  if (x == 0.0) return 0.0;
+  int ex;
+  (void)frexp(x, &ex);
+  if (ex + d < -480) {
+    atomicOr(tiny, 1);
+    return 0.0;
+  }
+  return ldexp(x, d);
+}
+
+// (|b| + r) * 2^-F rounded up: an r too small to matter at the precision of
+// |b| bumps |b| by one ulp instead.
+__device__ __forceinline__ double rad_scaled_sum(double m, int dm, double r, int dr, int32_t *tiny) {
+  const double ms = rad_scaled(m, dm, tiny);
+  if (r == 0.0) return ms;
+  int ex;
+  (void)frexp(r, &ex);
+  if (ex + dr < -480 && ms >= 0x1p-420) return next_up(ms);   // r * 2^dr < ulp(ms)
+  return ru_add(ms, rad_scaled(r, dr, tiny));
+}
+
+__device__ __forceinline__ void rad_elem(const arbgpu_arr &A, int64_t idx, double &m, int &e, double &r, int &re) {
+  const int n = elem_n(A, idx);
+  m = 0.0;
+  e = 0;
+  r = 0.0;
+  re = 0;
+  if (n) {
+    m = mag_upper_mem(A, idx, n);
+    e = A.exp[idx];
+  }
+  if (A.rad_m) {
+    const double rr = A.rad_m[idx];
+    if (rr != 0.0) {
+      int ex;
+      r = frexp(rr, &ex);
+      re = A.rad_e[idx] + ex;
+    }
+  }
+}
+
+// One wave per line: two exponent frames per line, one for each value
+// array (A side: |a| and r_a; B side: |b| + r_b and r_b), then the scaled
+// upper bounds.  A side writes [line][k]; B side writes [k][line].
 __global__ __launch_bounds__(256) void rad_prep_kernel(RadPrepParams P) {
   const int64_t line = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (line >= P.lines) return;
   const int64_t lt = (P.mode == 0) ? P.len : 2 * P.len;
-  int F = -0x7FFFFFFF - 1;
+  constexpr int kNone = -0x7FFFFFFF - 1;
+  int F0 = kNone, F1 = kNone;
   for (int64_t k = lane; k < lt; k += 64) {
     int part;
     int64_t kk;
     uint32_t ng;
     inner_map(P.mode, P.len, k, part, kk, ng);
     const arbgpu_arr &A = part_of(P.part, part);
-    const int64_t idx = P.off + line * P.line_stride + kk * P.elem_stride;
-    const int n = elem_n(A, idx);
-    int f = -0x7FFFFFFF - 1;
-    if (n) f = A.exp[idx];
-    if (A.rad_m) {
-      const double r = A.rad_m[idx];
-      if (r != 0.0) {
-        int ex;
-        (void)frexp(r, &ex);
-        const int re = A.rad_e[idx] + ex;
-        f = re > f ? re : f;
-      }
+    double m, r;
+    int e, re;
+    rad_elem(A, P.off + line * P.line_stride + kk * P.elem_stride, m, e, r, re);
+    int f0 = m != 0.0 ? e : kNone;
+    const int f1 = r != 0.0 ? re : kNone;
+    if (P.side == 1) {   // |b| + r_b < 2^(max(e, re) + 1)
+      f0 = f1 > f0 ? f1 : f0;
+      if (f0 != kNone) f0 += 1;
     }
-    if (P.side == 1 && f != -0x7FFFFFFF - 1) f += 1;   // |b| + r < 2^(max + 1)
-    F = f > F ? f : F;
+    F0 = f0 > F0 ? f0 : F0;
+    F1 = f1 > F1 ? f1 : F1;
   }
 #pragma unroll
   for (int m = 1; m < 64; m <<= 1) {
-    int o = __shfl_xor(F, m, 64);
-    F = o > F ? o : F;
+    int o = __shfl_xor(F0, m, 64);
+    F0 = o > F0 ? o : F0;
+    o = __shfl_xor(F1, m, 64);
+    F1 = o > F1 ? o : F1;
   }
-  if (F == -0x7FFFFFFF - 1) F = 0;
-  if (lane == 0) P.scale[line] = F;
+  if (F0 == kNone) F0 = 0;
+  if (F1 == kNone) F1 = 0;
+  if (lane == 0) {
+    P.scale0[line] = F0;
+    P.scale1[line] = F1;
+  }
   for (int64_t k = lane; k < lt; k += 64) {
     int part;
     int64_t kk;
     uint32_t ng;
     inner_map(P.mode, P.len, k, part, kk, ng);
     const arbgpu_arr &A = part_of(P.part, part);
-    const int64_t idx = P.off + line * P.line_stride + kk * P.elem_stride;
-    const int n = elem_n(A, idx);
-    double m = 0.0, r = 0.0;
-    if (n) m = ru_scale_down(mag_upper_mem(A, idx, n), A.exp[idx] - F);
-    if (A.rad_m) {
-      const double rr = A.rad_m[idx];
-      if (rr != 0.0) {
-        int ex;
-        const double rm = frexp(rr, &ex);
-        r = ru_scale_down(rm, A.rad_e[idx] + ex - F);
-      }
-    }
+    double m, r;
+    int e, re;
+    rad_elem(A, P.off + line * P.line_stride + kk * P.elem_stride, m, e, r, re);
     const int64_t o = (P.side == 0) ? line * lt + k : k * P.lines + line;
-    P.v0[o] = (P.side == 0) ? m : ru_add(m, r);
-    P.v1[o] = r;
+    P.v0[o] = (P.side == 0) ? rad_scaled(m, e - F0, P.tiny) : rad_scaled_sum(m, e - F0, r, re - F0, P.tiny);
+    P.v1[o] = rad_scaled(r, re - F1, P.tiny);
   }
 }
 
-// rho_in(i, j) = sum_k a_m[i][k] b_r[k][j] + a_r[i][k] b_mr[k][j], rounded up,
-// in the frame 2^(a_s[i] + b_s[j]).
+// rho_in(i, j) = sum_k a_m[i][k] b_r[k][j]    (frame 2^(a_s0[i] + b_s1[j]))
+//              + sum_k a_r[i][k] b_mr[k][j]   (frame 2^(a_s1[i] + b_s0[j])),
+// rounded up.  Skipped when a value was too small for its frame.
 __global__ __launch_bounds__(256) void rad_gemm_kernel(RadGemmParams P) {
   const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
   const int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (i >= P.M || j >= P.N) return;
-  double acc = 0.0;
+  if (i >= P.M || j >= P.N || *P.tiny) return;
+  double acc1 = 0.0, acc2 = 0.0;
   const double *am = P.a_m + i * P.Kt, *ar = P.a_r + i * P.Kt;
   for (int64_t k = 0; k < P.Kt; ++k) {
     const double x0 = am[k], x1 = ar[k];
     const double y0 = P.b_r[k * P.N + j], y1 = P.b_mr[k * P.N + j];
-    if (x0 != 0.0 && y0 != 0.0) acc = ru_add(acc, ru_mul(x0, y0));
-    if (x1 != 0.0 && y1 != 0.0) acc = ru_add(acc, ru_mul(x1, y1));
+    if (x0 != 0.0 && y0 != 0.0) acc1 = ru_add(acc1, ru_mul(x0, y0));
+    if (x1 != 0.0 && y1 != 0.0) acc2 = ru_add(acc2, ru_mul(x1, y1));
   }
+  double m1 = 0.0, m2 = 0.0;
+  int e1 = 0, e2 = 0, ex;
+  if (acc1 != 0.0) { m1 = frexp(acc1, &ex); e1 = P.a_s0[i] + P.b_s1[j] + ex; }
+  if (acc2 != 0.0) { m2 = frexp(acc2, &ex); e2 = P.a_s1[i] + P.b_s0[j] + ex; }
   double m = 0.0;
   int e = 0;
-  if (acc != 0.0) {
-    int ex;
-    m = frexp(acc, &ex);
-    e = P.a_s[i] + P.b_s[j] + ex;
-  }
+  if (m1 != 0.0 && m2 != 0.0) ru_add_ext(m1, e1, m2, e2, m, e);
+  else if (m1 != 0.0) { m = m1; e = e1; }
+  else if (m2 != 0.0) { m = m2; e = e2; }
   P.out_m[i * P.N + j] = m;
   P.out_e[i * P.N + j] = e;
+}
+
+// Radius of one entry with its own frame (the largest term bound), as in
+// the limb kernel: used when the per-line frames could not hold a value.
+__global__ __launch_bounds__(256) void rad_exact_kernel(RadExactParams P) {
+  const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= P.M || j >= P.N || !*P.tiny) return;
+  constexpr int kNone = -0x7FFFFFFF - 1;
+  int F = kNone;
+  for (int pass = 0; pass < 2; ++pass) {
+    double acc = 0.0;
+    for (int64_t k = 0; k < P.Kt; ++k) {
+      int pa, pb;
+      int64_t ka, kb;
+      uint32_t ng;
+      inner_map(P.a_mode, P.len, k, pa, ka, ng);
+      inner_map(P.b_mode, P.len, k, pb, kb, ng);
+      double am, ar, bm, br;
+      int ae, are, be, bre;
+      rad_elem(part_of(P.A, pa), P.a_off + i * P.a_rs + ka * P.a_cs, am, ae, ar, are);
+      rad_elem(part_of(P.B, pb), P.b_off + kb * P.b_rs + j * P.b_cs, bm, be, br, bre);
+      if (pass == 0) {
+        if (am != 0.0 && br != 0.0) F = ae + bre > F ? ae + bre : F;
+        if (ar != 0.0 && bm != 0.0) F = are + be > F ? are + be : F;
+        if (ar != 0.0 && br != 0.0) F = are + bre > F ? are + bre : F;
+      } else {
+        if (am != 0.0 && br != 0.0) acc = ru_add(acc, ru_scale_down(ru_mul(am, br), ae + bre - F));
+        if (ar != 0.0 && bm != 0.0) acc = ru_add(acc, ru_scale_down(ru_mul(ar, bm), are + be - F));
+        if (ar != 0.0 && br != 0.0) acc = ru_add(acc, ru_scale_down(ru_mul(ar, br), are + bre - F));
+      }
+    }
+    if (pass == 0 && F == kNone) break;
+    if (pass == 1) {
+      double m = 0.0;
+      int e = 0;
+      if (acc != 0.0) {
+        int ex;
+        m = frexp(acc, &ex);
+        e = F + ex;
+      }
+      P.out_m[i * P.N + j] = m;
+      P.out_e[i * P.N + j] = e;
+      return;
+    }
+  }
+  P.out_m[i * P.N + j] = 0.0;
+  P.out_e[i * P.N + j] = 0;
 }
 
 __global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n) {
@@ -644,6 +742,11 @@ hipError_t launch_rad_prep(const RadPrepParams &P, hipStream_t s) {
 hipError_t launch_rad_gemm(const RadGemmParams &P, hipStream_t s) {
   if (P.M == 0 || P.N == 0) return hipSuccess;
   hipLaunchKernelGGL(rad_gemm_kernel, dim3(nblk(P.N, 64), nblk(P.M, 4)), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_rad_exact(const RadExactParams &P, hipStream_t s) {
+  if (P.M == 0 || P.N == 0) return hipSuccess;
+  hipLaunchKernelGGL(rad_exact_kernel, dim3(nblk(P.N, 64), nblk(P.M, 4)), dim3(256), 0, s, P);
   return hipGetLastError();
 }
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {

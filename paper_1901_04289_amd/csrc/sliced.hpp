@@ -23,7 +23,8 @@ struct StatsParams {
   int64_t off, line_stride, elem_stride;
   int64_t k0;                // first inner index of the block
   LineStats out;
-  int32_t *gmax;             // [0] max height, [1] max precision, [2] erange flag
+  int32_t *gmax;             // [0] max height, [1] max precision, [2] erange flag,
+                             // [3] max |position| of a top or lowest set bit
 };
 
 // One operand of the block product, sliced into balanced base-256 digits.
@@ -75,20 +76,81 @@ struct RadPrepParams {
   arbgpu_arr part[2];
   int nparts;
   int64_t lines, len, off, line_stride, elem_stride;
-  int mode;                // as in SliceParams (inner index layout)
-  int side;                // 0: A side -> (|m|, r); 1: B side -> (|m| + r, r)
-  int32_t *scale;          // per-line exponent frame
-  double *v0, *v1;         // [lines][len_total] scaled upper bounds
+  int mode;                  // as in SliceParams (inner index layout)
+  int side;                  // 0: A side -> (|m|, r); 1: B side -> (|m| + r, r)
+  int32_t *scale0, *scale1;  // per-line exponent frames of v0 and v1
+  double *v0, *v1;           // [lines][len_total] scaled upper bounds
+  int32_t *tiny;             // set when a value fell too far below its frame
 };
 
 struct RadGemmParams {
   const double *a_m, *a_r;   // [M][Kt]: |A| and R_A, row-scaled
   const double *b_mr, *b_r;  // [N][Kt]: |B| + R_B and R_B, column-scaled
-  const int32_t *a_s, *b_s;  // row / column frames
+  const int32_t *a_s0, *a_s1, *b_s0, *b_s1;   // frames of a_m, a_r, b_mr, b_r
+  const int32_t *tiny;       // nonzero: the exact kernel writes the result
   int64_t M, N, Kt;
   double *out_m;             // [M*N]
   int32_t *out_e;
 };
+
+// Per-entry radius with per-entry frames (fallback of the radius product).
+struct RadExactParams {
+  arbgpu_arr A[2], B[2];
+  int a_mode, b_mode;        // inner layouts as in SliceParams
+  int64_t len, Kt, M, N;
+  int64_t a_off, a_rs, a_cs, b_off, b_rs, b_cs;
+  const int32_t *tiny;       // zero: nothing to do
+  double *out_m;
+  int32_t *out_e;
+};
+
+// Greedy block extraction (one workgroup).
+struct PlanParams {
+  arbgpu_arr A[2], B[2];
+  int nparts;
+  int64_t M, N, inner;
+  int64_t a_off, a_rs, a_cs, b_off, b_rs, b_cs;
+  int hmax;                 // largest admissible integer height (floor of h)
+  int basecase;             // shorter blocks become dot-product chunks
+  int32_t *rtop, *rlow, *ctop, *clow;   // per-line running state [M], [N]
+  int64_t *bounds;          // [2 * max_blocks]
+  int32_t *kinds;           // [max_blocks]: 0 block, 1 basecase
+  int64_t max_blocks;
+  int32_t *nblocks;
+};
+
+// Final per-entry sum over block results and basecase terms, rounded once.
+struct MergeParams {
+  arbgpu_arr T;             // exact block results, element (s, ij) at s * M * N + ij
+  int nS;
+  arbgpu_arr A[2], B[2];
+  int64_t a_off, a_rs, a_cs, b_off, b_rs, b_cs;
+  const int64_t *bk;        // inner indices of the basecase chunks
+  int64_t nbk;
+  CompTab ct;
+  int64_t M, N;
+  arbgpu_out C;
+  int64_t c_off, c_rs, c_cs;
+  int p;
+  int approx;
+  const double *rin_m;      // propagated radius per entry (nullable)
+  const int32_t *rin_e;
+};
+
+// One inner-index range of the partition: kind 0 is a scaled-integer block,
+// kind 1 a basecase chunk evaluated term by term.
+struct BlockSpan {
+  int64_t k0, k1;
+  int32_t kind;
+};
+
+// Greedy partition of the inner range under the integer height bound hmax
+// (synchronizes s to read the result back).
+int plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, bool cplx, int hmax, hipStream_t s,
+                std::vector<BlockSpan> &out);
+
+hipError_t launch_plan(const PlanParams &P, hipStream_t s);
+hipError_t launch_merge(const MergeParams &P, int ns, hipStream_t s);
 
 hipError_t launch_stats_rows(const StatsParams &P, hipStream_t s);
 hipError_t launch_stats_cols(const StatsParams &P, hipStream_t s);
@@ -97,6 +159,7 @@ hipError_t launch_mfma(const MfmaParams &P, hipStream_t s);
 hipError_t launch_recombine(const RecombParams &P, hipStream_t s);
 hipError_t launch_rad_prep(const RadPrepParams &P, hipStream_t s);
 hipError_t launch_rad_gemm(const RadGemmParams &P, hipStream_t s);
+hipError_t launch_rad_exact(const RadExactParams &P, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 
 }  // namespace arbgpu_impl

@@ -1,7 +1,7 @@
 // Host orchestration of the scaled-integer INT8-MFMA matrix product
-// (Algorithm 2, Johansson 2019, Section 4): statistics, block decision,
-// slicing, diagonal-group schedule, MFMA product, recombination and the
-// radius products.
+// (Algorithm 2, Johansson 2019, Section 4): statistics, block partition,
+// slicing, diagonal-group schedule, MFMA product, recombination, radius
+// products, and the exact merge when the inner range splits into blocks.
 #include <math.h>
 #include <string.h>
 
@@ -16,71 +16,77 @@ namespace {
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-}  // namespace
+struct Shape {
+  bool cplx, approx;
+  int nparts;
+  int64_t M, N, K;   // C is M x N, inner dimension K (per part)
+};
 
-int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p,
-                   uint32_t flags, hipStream_t s, bool forced) {
-  const bool cplx = flags & ARBGPU_COMPLEX;
-  const bool approx = flags & ARBGPU_APPROX;
-  const int nparts = cplx ? 2 : 1;
-  const int64_t M = A->rows, N = B->cols, K = A->cols;     // C is M x N, inner K
-  const int64_t Kt = cplx ? 2 * K : K;                     // inner length of the real products
-  // Basecase (Algorithm 2: blocks shorter than 30 use dot products).
-  if (!forced && K < 30) return kNotApplicable;
-  const int64_t Kp = round_up(std::max<int64_t>(Kt, 1), kKStep);
-  // int32 partial planes: P pairs of Kp terms of |d d'| <= 2^14 each
-  const int64_t pmax = ((int64_t)0x7FFFFFFF) / (Kp << 14);
-  if (pmax < 1) {
-    if (forced) return set_error(ctx, ARBGPU_EINVAL, "sliced product: inner length %lld too long", (long long)Kt);
-    return kNotApplicable;
-  }
+#define ARB_TRY(expr, what)                                                                          \
+  do {                                                                                               \
+    hipError_t e_ = (expr);                                                                          \
+    if (e_ != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "%s: %s", what, hipGetErrorString(e_)); \
+  } while (0)
 
-  // ---- statistics ---------------------------------------------------------
-  const int64_t Mp = round_up(std::max<int64_t>(M, 1), kTile), Np = round_up(std::max<int64_t>(N, 1), kTile);
-  size_t st_bytes = sizeof(int32_t) * (size_t)(2 * M + 2 * N + 8);
-  int32_t *st = (int32_t *)ws_get(ctx, WS_STATS, st_bytes);
-  if (!st) return ARBGPU_ENOMEM;
-  int32_t *rtop = st, *rv2 = st + M, *ctop = st + 2 * M, *cv2 = st + 2 * M + N;
-  int32_t *gA = st + 2 * M + 2 * N, *gB = gA + 4;
-  hipError_t e = launch_fill_i32(gA, 0, 8, s);
-  if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "fill: %s", hipGetErrorString(e));
+// Statistics workspace: rtop[M], rv2[M], ctop[N], cv2[N], gA[4], gB[4].
+int32_t *stats_ws(arbgpu_ctx *ctx, const Shape &sh) {
+  return (int32_t *)ws_get(ctx, WS_STATS, sizeof(int32_t) * (size_t)(2 * sh.M + 2 * sh.N + 8));
+}
+
+// Line statistics of A's rows and B's columns over the inner range [k0, k1):
+// per-line lowest set bit (left in the workspace for slicing) and the
+// global maxima g[0..3] (A) and g[4..7] (B) as described in StatsParams.
+// Synchronizes s to read the maxima back.
+int line_stats(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const Shape &sh, int64_t k0, int64_t k1,
+               int32_t *st, hipStream_t s, int32_t g[8]) {
+  int32_t *rtop = st, *rv2 = st + sh.M, *ctop = st + 2 * sh.M, *cv2 = st + 2 * sh.M + sh.N;
+  int32_t *gA = st + 2 * sh.M + 2 * sh.N, *gB = gA + 4;
+  ARB_TRY(launch_fill_i32(gA, 0, 8, s), "fill");
   StatsParams sp;
   memset(&sp, 0, sizeof sp);
   sp.part[0] = A->re;
-  sp.part[1] = cplx ? A->im : A->re;
-  sp.nparts = nparts;
-  sp.lines = M; sp.len = K; sp.off = A->off; sp.line_stride = A->rs; sp.elem_stride = A->cs; sp.k0 = 0;
+  sp.part[1] = sh.cplx ? A->im : A->re;
+  sp.nparts = sh.nparts;
+  sp.lines = sh.M; sp.len = k1 - k0; sp.off = A->off; sp.line_stride = A->rs; sp.elem_stride = A->cs; sp.k0 = k0;
   sp.out = LineStats{rtop, rv2};
   sp.gmax = gA;
   StatsParams sq = sp;
   sq.part[0] = B->re;
-  sq.part[1] = cplx ? B->im : B->re;
-  sq.lines = N; sq.len = K; sq.off = B->off; sq.line_stride = B->cs; sq.elem_stride = B->rs;
+  sq.part[1] = sh.cplx ? B->im : B->re;
+  sq.lines = sh.N; sq.off = B->off; sq.line_stride = B->cs; sq.elem_stride = B->rs;
   sq.out = LineStats{ctop, cv2};
   sq.gmax = gB;
   {
     KernelTimer t_stats(ctx, "stats", s);
-    if ((e = launch_stats_rows(sp, s)) == hipSuccess) e = launch_stats_cols(sq, s);
+    ARB_TRY(launch_stats_rows(sp, s), "stats");
+    ARB_TRY(launch_stats_cols(sq, s), "stats");
   }
-  if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "stats: %s", hipGetErrorString(e));
-  int32_t g[8];
-  if ((e = hipMemcpyAsync(g, gA, sizeof g, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-      (e = hipStreamSynchronize(s)) != hipSuccess)
-    return set_error(ctx, ARBGPU_EDEVICE, "stats readback: %s", hipGetErrorString(e));
-  const int HA = g[0], HB = g[4];
-  const int pA = g[1], pB = g[5];
-  if (g[2] || g[6]) return kNotApplicable;   // out-of-range exponents: flagged per entry by the limb kernel
-  // Height bound of Algorithm 2: h = 1.25 min(p, max(p_A, p_B)) + 192.  With
-  // every line below it the whole inner range is one block.
-  const double h = 1.25 * (double)std::min<int64_t>(p, std::max(pA, pB)) + 192.0;
-  if (!forced && (HA > h || HB > h)) return kNotApplicable;
-  const int LA = std::max(1, (HA + 1 + 7) / 8), LB = std::max(1, (HB + 1 + 7) / 8);
-  if (LA > kMaxSlices || LB > kMaxSlices) {
-    if (forced) return set_error(ctx, ARBGPU_EINVAL, "sliced product: integer height %d too large", std::max(HA, HB));
-    return kNotApplicable;
-  }
+  ARB_TRY(hipMemcpyAsync(g, gA, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s), "stats readback");
+  ARB_TRY(hipStreamSynchronize(s), "stats readback");
+  return ARBGPU_OK;
+}
 
-  // ---- diagonal-group schedule --------------------------------------------
+inline int slices_for(int height) { return std::max(1, (height + 1 + 7) / 8); }
+
+// Limbs of the exact block result T for the given digit-plane counts.
+inline int t_limbs(int LA, int LB) { return (LA + LB - 1 + 3) / 4 + 2; }
+
+// One scaled-integer block over the inner range [k0, k1) whose line
+// statistics are in `st`: slices, MFMA product and recombination into
+// out[q] (q = output part) truncated to p bits.
+int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const Shape &sh, int64_t k0, int64_t k1,
+                  const int32_t *st, int HA, int HB, const arbgpu_out *out, int64_t o_off, int64_t o_rs, int64_t o_cs,
+                  int p, bool out_approx, double *const rin_m[2], int32_t *const rin_e[2], hipStream_t s) {
+  const int32_t *rv2 = st + sh.M, *cv2 = st + 2 * sh.M + sh.N;
+  const int64_t Kb = k1 - k0;
+  const int64_t Kt = sh.cplx ? 2 * Kb : Kb;
+  const int64_t Kp = round_up(std::max<int64_t>(Kt, 1), kKStep);
+  // int32 partial planes: P pairs of Kp terms of |d d'| <= 2^14 each
+  const int64_t pmax = ((int64_t)0x7FFFFFFF) / (Kp << 14);
+  const int64_t Mp = round_up(std::max<int64_t>(sh.M, 1), kTile), Np = round_up(std::max<int64_t>(sh.N, 1), kTile);
+  const int LA = slices_for(HA), LB = slices_for(HB);
+
+  // diagonal groups of at most pmax slice pairs, each one exact int32 plane
   const int Lc = LA + LB - 1;
   std::vector<DiagGroup> groups;
   std::vector<int32_t> slot_of(Lc + 1, 0);
@@ -98,131 +104,360 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
                    [](const DiagGroup &x, const DiagGroup &y) { return (x.a1 - x.a0) > (y.a1 - y.a0); });
   const int ngroups_real = (int)groups.size();
   while (groups.size() % 8) groups.push_back(DiagGroup{0, 0, 0, -1});   // padding for the XCD mapping
-  const int nq = (Lc + 3) / 4, nT = nq + 2;
+  const int nT = t_limbs(LA, LB);
   {
-    const int64_t plan[8] = {LA, LB, nslots, ngroups_real, Kt, M, N, nparts};
+    const int64_t plan[8] = {LA, LB, nslots, ngroups_real, Kt, sh.M, sh.N, sh.nparts};
     memcpy(ctx->last_plan, plan, sizeof plan);
   }
 
-  // ---- workspace ------------------------------------------------------------
   const size_t bytesA = (size_t)LA * Mp * Kp, bytesB = (size_t)LB * Np * Kp;
   int8_t *planesA = (int8_t *)ws_get(ctx, WS_PLANES_A, bytesA);
   int8_t *planesB = (int8_t *)ws_get(ctx, WS_PLANES_B, bytesB);
-  int8_t *planesB2 = cplx ? (int8_t *)ws_get(ctx, WS_PLANES_B2, bytesB) : nullptr;
-  int32_t *D = (int32_t *)ws_get(ctx, WS_D, sizeof(int32_t) * (size_t)nslots * M * N);
-  uint32_t *T = (uint32_t *)ws_get(ctx, WS_T, sizeof(uint32_t) * (size_t)nT * M * N);
+  int8_t *planesB2 = sh.cplx ? (int8_t *)ws_get(ctx, WS_PLANES_B2, bytesB) : nullptr;
+  int32_t *D = (int32_t *)ws_get(ctx, WS_D, sizeof(int32_t) * (size_t)nslots * sh.M * sh.N);
+  uint32_t *T = (uint32_t *)ws_get(ctx, WS_T, sizeof(uint32_t) * (size_t)nT * sh.M * sh.N);
   const size_t tab_bytes = sizeof(DiagGroup) * groups.size() + sizeof(int32_t) * slot_of.size();
   char *tabs = (char *)ws_get(ctx, WS_TABLES, tab_bytes);
-  if (!planesA || !planesB || (cplx && !planesB2) || !D || !T || !tabs) return ARBGPU_ENOMEM;
+  if (!planesA || !planesB || (sh.cplx && !planesB2) || !D || !T || !tabs) return ARBGPU_ENOMEM;
   DiagGroup *dgroups = (DiagGroup *)tabs;
   int32_t *dslot = (int32_t *)(tabs + sizeof(DiagGroup) * groups.size());
-  if ((e = hipMemcpyAsync(dgroups, groups.data(), sizeof(DiagGroup) * groups.size(), hipMemcpyHostToDevice, s)) !=
-          hipSuccess ||
-      (e = hipMemcpyAsync(dslot, slot_of.data(), sizeof(int32_t) * slot_of.size(), hipMemcpyHostToDevice, s)) !=
-          hipSuccess)
-    return set_error(ctx, ARBGPU_EDEVICE, "table upload: %s", hipGetErrorString(e));
+  ARB_TRY(hipMemcpyAsync(dgroups, groups.data(), sizeof(DiagGroup) * groups.size(), hipMemcpyHostToDevice, s),
+          "table upload");
+  ARB_TRY(hipMemcpyAsync(dslot, slot_of.data(), sizeof(int32_t) * slot_of.size(), hipMemcpyHostToDevice, s),
+          "table upload");
+  // the host tables must outlive their asynchronous uploads
+  ARB_TRY(hipStreamSynchronize(s), "table upload");
 
-  // ---- radius products (ball inputs only) -----------------------------------
-  const bool radA = A->re.rad_m || (cplx && A->im.rad_m);
-  const bool radB = B->re.rad_m || (cplx && B->im.rad_m);
-  const bool want_rad = !approx && (radA || radB);
-  double *rad_out_m[2] = {nullptr, nullptr};
-  int32_t *rad_out_e[2] = {nullptr, nullptr};
-  if (want_rad) {
-    const size_t na = (size_t)M * Kt, nb = (size_t)N * Kt;
-    char *ra = (char *)ws_get(ctx, WS_RAD_A, 2 * sizeof(double) * na + sizeof(int32_t) * M);
-    char *rb = (char *)ws_get(ctx, WS_RAD_B, 2 * sizeof(double) * nb + sizeof(int32_t) * N);
-    char *ro = (char *)ws_get(ctx, WS_RAD_OUT, (size_t)nparts * (sizeof(double) + sizeof(int32_t)) * M * N);
-    if (!ra || !rb || !ro) return ARBGPU_ENOMEM;
-    RadPrepParams pa;
-    memset(&pa, 0, sizeof pa);
-    pa.part[0] = A->re;
-    pa.part[1] = cplx ? A->im : A->re;
-    pa.nparts = nparts;
-    pa.lines = M; pa.len = K; pa.off = A->off; pa.line_stride = A->rs; pa.elem_stride = A->cs;
-    pa.mode = cplx ? 3 : 0;
-    pa.side = 0;
-    pa.v0 = (double *)ra;
-    pa.v1 = (double *)ra + na;
-    pa.scale = (int32_t *)((double *)ra + 2 * na);
-    if ((e = launch_rad_prep(pa, s)) != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "rad prep: %s", hipGetErrorString(e));
-    for (int q = 0; q < nparts; ++q) {
-      RadPrepParams pb;
-      memset(&pb, 0, sizeof pb);
-      pb.part[0] = B->re;
-      pb.part[1] = cplx ? B->im : B->re;
-      pb.nparts = nparts;
-      pb.lines = N; pb.len = K; pb.off = B->off; pb.line_stride = B->cs; pb.elem_stride = B->rs;
-      pb.mode = !cplx ? 0 : (q == 0 ? 1 : 2);
-      pb.side = 1;
-      pb.v0 = (double *)rb;
-      pb.v1 = (double *)rb + nb;
-      pb.scale = (int32_t *)((double *)rb + 2 * nb);
-      if ((e = launch_rad_prep(pb, s)) != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "rad prep: %s", hipGetErrorString(e));
-      RadGemmParams rg;
-      rg.a_m = pa.v0; rg.a_r = pa.v1; rg.b_mr = pb.v0; rg.b_r = pb.v1;
-      rg.a_s = pa.scale; rg.b_s = pb.scale;
-      rg.M = M; rg.N = N; rg.Kt = Kt;
-      rad_out_m[q] = (double *)ro + (size_t)q * M * N;
-      rad_out_e[q] = (int32_t *)((double *)ro + (size_t)nparts * M * N) + (size_t)q * M * N;
-      rg.out_m = rad_out_m[q];
-      rg.out_e = rad_out_e[q];
-      KernelTimer tg(ctx, "rad_gemm", s);
-      if ((e = launch_rad_gemm(rg, s)) != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "rad gemm: %s", hipGetErrorString(e));
-    }
-  }
-
-  // ---- slicing ----------------------------------------------------------------
   SliceParams sa;
   memset(&sa, 0, sizeof sa);
   sa.part[0] = A->re;
-  sa.part[1] = cplx ? A->im : A->re;
-  sa.lines = M; sa.len = K; sa.off = A->off; sa.line_stride = A->rs; sa.elem_stride = A->cs; sa.k0 = 0;
-  sa.mode = cplx ? 3 : 0;
+  sa.part[1] = sh.cplx ? A->im : A->re;
+  sa.lines = sh.M; sa.len = Kb; sa.off = A->off; sa.line_stride = A->rs; sa.elem_stride = A->cs; sa.k0 = k0;
+  sa.mode = sh.cplx ? 3 : 0;
   sa.lines_pad = Mp; sa.k_pad = Kp; sa.L = LA; sa.v2 = rv2; sa.planes = planesA;
   {
     KernelTimer t_slice(ctx, "slice", s);
-    e = launch_slice(sa, s);
-    for (int q = 0; q < nparts && e == hipSuccess; ++q) {
+    ARB_TRY(launch_slice(sa, s), "slice");
+    for (int q = 0; q < sh.nparts; ++q) {
       SliceParams sb = sa;
       sb.part[0] = B->re;
-      sb.part[1] = cplx ? B->im : B->re;
-      sb.lines = N; sb.off = B->off; sb.line_stride = B->cs; sb.elem_stride = B->rs;
-      sb.mode = !cplx ? 0 : (q == 0 ? 1 : 2);
+      sb.part[1] = sh.cplx ? B->im : B->re;
+      sb.lines = sh.N; sb.off = B->off; sb.line_stride = B->cs; sb.elem_stride = B->rs;
+      sb.mode = !sh.cplx ? 0 : (q == 0 ? 1 : 2);
       sb.lines_pad = Np; sb.L = LB; sb.v2 = cv2; sb.planes = q == 0 ? planesB : planesB2;
-      e = launch_slice(sb, s);
+      ARB_TRY(launch_slice(sb, s), "slice");
     }
   }
-  if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "slice: %s", hipGetErrorString(e));
-
-  // ---- product and recombination per output part ------------------------------
-  const arbgpu_out *cparts[2] = {&C->re, &C->im};
-  for (int q = 0; q < nparts; ++q) {
+  for (int q = 0; q < sh.nparts; ++q) {
     MfmaParams mp;
     mp.A = planesA;
     mp.B = q == 0 ? planesB : planesB2;
     mp.D = D;
     mp.groups = dgroups;
-    mp.M = M; mp.N = N; mp.Mp = Mp; mp.Np = Np; mp.Kp = Kp;
+    mp.M = sh.M; mp.N = sh.N; mp.Mp = Mp; mp.Np = Np; mp.Kp = Kp;
     mp.ntm = (int)(Mp / kTile); mp.ntn = (int)(Np / kTile);
     mp.ngroups = (int)groups.size();
-    hipError_t em;
     {
       KernelTimer tm(ctx, "mfma", s);
-      em = launch_mfma(mp, s);
+      ARB_TRY(launch_mfma(mp, s), "mfma");
     }
-    if ((e = em) != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "mfma: %s", hipGetErrorString(e));
     RecombParams rp;
-    rp.D = D; rp.slot_of = dslot; rp.Lc = Lc; rp.M = M; rp.N = N; rp.T = T; rp.nT = nT;
+    rp.D = D; rp.slot_of = dslot; rp.Lc = Lc; rp.M = sh.M; rp.N = sh.N; rp.T = T; rp.nT = nT;
     rp.rowv2 = rv2; rp.colv2 = cv2;
-    rp.C = *cparts[q];
-    rp.c_off = C->off; rp.c_rs = C->rs; rp.c_cs = C->cs;
-    rp.p = (int)p;
-    rp.approx = approx;
-    rp.rin_m = rad_out_m[q];
-    rp.rin_e = rad_out_e[q];
+    rp.C = out[q];
+    rp.c_off = o_off; rp.c_rs = o_rs; rp.c_cs = o_cs;
+    rp.p = p;
+    rp.approx = out_approx;
+    rp.rin_m = rin_m[q];
+    rp.rin_e = rin_e[q];
     KernelTimer tr(ctx, "recombine", s);
-    if ((e = launch_recombine(rp, s)) != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "recombine: %s", hipGetErrorString(e));
+    ARB_TRY(launch_recombine(rp, s), "recombine");
+  }
+  return ARBGPU_OK;
+}
+
+// Radius products over the whole inner range (Section 4.1, last
+// paragraph): rho = |A| R_B + R_A (|B| + R_B), FP64 rounded upward, with a
+// per-entry fallback when a value does not fit its line's frame.
+int radius_products(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const Shape &sh, double *rin_m[2],
+                    int32_t *rin_e[2], hipStream_t s) {
+  const int64_t Kt = sh.cplx ? 2 * sh.K : sh.K;
+  const size_t na = (size_t)sh.M * Kt, nb = (size_t)sh.N * Kt, mn = (size_t)sh.M * sh.N;
+  char *ra = (char *)ws_get(ctx, WS_RAD_A, 2 * sizeof(double) * na + 2 * sizeof(int32_t) * sh.M);
+  char *rb = (char *)ws_get(ctx, WS_RAD_B, 2 * sizeof(double) * nb + 2 * sizeof(int32_t) * sh.N);
+  char *ro = (char *)ws_get(ctx, WS_RAD_OUT, (size_t)sh.nparts * (sizeof(double) + sizeof(int32_t)) * mn + 8);
+  if (!ra || !rb || !ro) return ARBGPU_ENOMEM;
+  int32_t *tiny = (int32_t *)((double *)ro + (size_t)sh.nparts * mn) + (size_t)sh.nparts * mn;
+  ARB_TRY(launch_fill_i32(tiny, 0, 1, s), "fill");
+  RadPrepParams pa;
+  memset(&pa, 0, sizeof pa);
+  pa.part[0] = A->re;
+  pa.part[1] = sh.cplx ? A->im : A->re;
+  pa.nparts = sh.nparts;
+  pa.lines = sh.M; pa.len = sh.K; pa.off = A->off; pa.line_stride = A->rs; pa.elem_stride = A->cs;
+  pa.mode = sh.cplx ? 3 : 0;
+  pa.side = 0;
+  pa.v0 = (double *)ra;
+  pa.v1 = (double *)ra + na;
+  pa.scale0 = (int32_t *)((double *)ra + 2 * na);
+  pa.scale1 = pa.scale0 + sh.M;
+  pa.tiny = tiny;
+  ARB_TRY(launch_rad_prep(pa, s), "rad prep");
+  for (int q = 0; q < sh.nparts; ++q) {
+    RadPrepParams pb;
+    memset(&pb, 0, sizeof pb);
+    pb.part[0] = B->re;
+    pb.part[1] = sh.cplx ? B->im : B->re;
+    pb.nparts = sh.nparts;
+    pb.lines = sh.N; pb.len = sh.K; pb.off = B->off; pb.line_stride = B->cs; pb.elem_stride = B->rs;
+    pb.mode = !sh.cplx ? 0 : (q == 0 ? 1 : 2);
+    pb.side = 1;
+    pb.v0 = (double *)rb;
+    pb.v1 = (double *)rb + nb;
+    pb.scale0 = (int32_t *)((double *)rb + 2 * nb);
+    pb.scale1 = pb.scale0 + sh.N;
+    pb.tiny = tiny;
+    ARB_TRY(launch_rad_prep(pb, s), "rad prep");
+    rin_m[q] = (double *)ro + (size_t)q * mn;
+    rin_e[q] = (int32_t *)((double *)ro + (size_t)sh.nparts * mn) + (size_t)q * mn;
+    RadGemmParams rg;
+    rg.a_m = pa.v0; rg.a_r = pa.v1; rg.b_mr = pb.v0; rg.b_r = pb.v1;
+    rg.a_s0 = pa.scale0; rg.a_s1 = pa.scale1; rg.b_s0 = pb.scale0; rg.b_s1 = pb.scale1;
+    rg.tiny = tiny;
+    rg.M = sh.M; rg.N = sh.N; rg.Kt = Kt;
+    rg.out_m = rin_m[q];
+    rg.out_e = rin_e[q];
+    RadExactParams rx;
+    memset(&rx, 0, sizeof rx);
+    rx.A[0] = A->re;
+    rx.A[1] = sh.cplx ? A->im : A->re;
+    rx.B[0] = B->re;
+    rx.B[1] = sh.cplx ? B->im : B->re;
+    rx.a_mode = pa.mode;
+    rx.b_mode = pb.mode;
+    rx.len = sh.K; rx.Kt = Kt; rx.M = sh.M; rx.N = sh.N;
+    rx.a_off = A->off; rx.a_rs = A->rs; rx.a_cs = A->cs;
+    rx.b_off = B->off; rx.b_rs = B->rs; rx.b_cs = B->cs;
+    rx.tiny = tiny;
+    rx.out_m = rin_m[q];
+    rx.out_e = rin_e[q];
+    KernelTimer tg(ctx, "rad_gemm", s);
+    ARB_TRY(launch_rad_gemm(rg, s), "rad gemm");
+    ARB_TRY(launch_rad_exact(rx, s), "rad exact");
+  }
+  return ARBGPU_OK;
+}
+
+// Height bound of Algorithm 2, h = 1.25 min(p, max(p_A, p_B)) + 192; block
+// heights are integers, so the admissible maximum is floor(h).
+int height_bound(int64_t p, int pA, int pB) {
+  const int64_t m = std::min<int64_t>(p, std::max(pA, pB));
+  return (int)((5 * m) / 4 + 192);
+}
+
+constexpr int kBasecase = 30;   // Algorithm 2: shorter ranges use dot products
+
+}  // namespace
+
+int plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, bool cplx, int hmax, hipStream_t s,
+                std::vector<BlockSpan> &out) {
+  const int64_t M = A->rows, N = B->cols, K = A->cols;
+  const int64_t maxb = K / kBasecase + 2;   // every block but the last has >= 30 indices or is basecase-extended
+  const int64_t nline = 2 * M + 2 * N + ((2 * M + 2 * N) & 1);
+  const size_t bytes = sizeof(int32_t) * (size_t)nline + sizeof(int64_t) * 2 * maxb + sizeof(int32_t) * (maxb + 1);
+  char *w = (char *)ws_get(ctx, WS_PLAN, bytes);
+  if (!w) return ARBGPU_ENOMEM;
+  PlanParams pp;
+  memset(&pp, 0, sizeof pp);
+  pp.A[0] = A->re;
+  pp.A[1] = cplx ? A->im : A->re;
+  pp.B[0] = B->re;
+  pp.B[1] = cplx ? B->im : B->re;
+  pp.nparts = cplx ? 2 : 1;
+  pp.M = M; pp.N = N; pp.inner = K;
+  pp.a_off = A->off; pp.a_rs = A->rs; pp.a_cs = A->cs;
+  pp.b_off = B->off; pp.b_rs = B->rs; pp.b_cs = B->cs;
+  pp.hmax = hmax;
+  pp.basecase = kBasecase;
+  int32_t *iw = (int32_t *)w;
+  pp.rtop = iw; pp.rlow = iw + M; pp.ctop = iw + 2 * M; pp.clow = iw + 2 * M + N;
+  pp.bounds = (int64_t *)(iw + nline);
+  pp.kinds = (int32_t *)(pp.bounds + 2 * maxb);
+  pp.max_blocks = maxb;
+  pp.nblocks = pp.kinds + maxb;
+  {
+    KernelTimer tp(ctx, "plan", s);
+    ARB_TRY(launch_plan(pp, s), "plan");
+  }
+  int32_t nb = 0;
+  ARB_TRY(hipMemcpyAsync(&nb, pp.nblocks, sizeof nb, hipMemcpyDeviceToHost, s), "plan readback");
+  ARB_TRY(hipStreamSynchronize(s), "plan readback");
+  if (nb < 0 || nb > maxb)
+    return set_error(ctx, ARBGPU_EDEVICE, "planner produced %d blocks (bound %lld)", nb, (long long)maxb);
+  std::vector<int64_t> b(2 * (size_t)nb + 2);
+  std::vector<int32_t> k((size_t)nb + 1);
+  if (nb) {
+    ARB_TRY(hipMemcpyAsync(b.data(), pp.bounds, sizeof(int64_t) * 2 * nb, hipMemcpyDeviceToHost, s), "plan readback");
+    ARB_TRY(hipMemcpyAsync(k.data(), pp.kinds, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s), "plan readback");
+    ARB_TRY(hipStreamSynchronize(s), "plan readback");
+  }
+  out.clear();
+  for (int i = 0; i < nb; ++i) out.push_back(BlockSpan{b[2 * i], b[2 * i + 1], k[i]});
+  return ARBGPU_OK;
+}
+
+int plan_partition(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags,
+                   hipStream_t s, int64_t *bounds, int32_t *kinds, int64_t max_blocks, int64_t *nblocks) {
+  Shape sh{(flags & ARBGPU_COMPLEX) != 0, false, (flags & ARBGPU_COMPLEX) ? 2 : 1, A->rows, B->cols, A->cols};
+  int32_t *st = stats_ws(ctx, sh);
+  if (!st) return ARBGPU_ENOMEM;
+  int32_t g[8];
+  int rc = line_stats(ctx, A, B, sh, 0, sh.K, st, s, g);
+  if (rc) return rc;
+  if (g[2] || g[6]) return set_error(ctx, ARBGPU_EINVAL, "an operand exponent is outside (-2^28, 2^28)");
+  std::vector<BlockSpan> blocks;
+  rc = plan_blocks(ctx, A, B, sh.cplx, height_bound(p, g[1], g[5]), s, blocks);
+  if (rc) return rc;
+  *nblocks = (int64_t)blocks.size();
+  for (int64_t i = 0; i < (int64_t)blocks.size() && i < max_blocks; ++i) {
+    bounds[2 * i] = blocks[i].k0;
+    bounds[2 * i + 1] = blocks[i].k1;
+    kinds[i] = blocks[i].kind;
+  }
+  return ARBGPU_OK;
+}
+
+int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p,
+                   uint32_t flags, hipStream_t s, bool forced) {
+  Shape sh{(flags & ARBGPU_COMPLEX) != 0, (flags & ARBGPU_APPROX) != 0, (flags & ARBGPU_COMPLEX) ? 2 : 1,
+           A->rows, B->cols, A->cols};
+  if (!forced && sh.K < kBasecase) return kNotApplicable;
+  const int64_t Kt = sh.cplx ? 2 * sh.K : sh.K;
+  if (((int64_t)0x7FFFFFFF) / (round_up(std::max<int64_t>(Kt, 1), kKStep) << 14) < 1) {
+    if (forced) return set_error(ctx, ARBGPU_EINVAL, "sliced product: inner length %lld too long", (long long)Kt);
+    return kNotApplicable;
+  }
+
+  // ---- statistics over the whole inner range --------------------------------
+  int32_t *st = stats_ws(ctx, sh);
+  if (!st) return ARBGPU_ENOMEM;
+  int32_t g[8];
+  int rc = line_stats(ctx, A, B, sh, 0, sh.K, st, s, g);
+  if (rc) return rc;
+  if (g[2] || g[6]) return kNotApplicable;   // out-of-range exponents: flagged per entry by the limb kernel
+  const int hmax = height_bound(p, g[1], g[5]);
+  const bool radA = A->re.rad_m || (sh.cplx && A->im.rad_m);
+  const bool radB = B->re.rad_m || (sh.cplx && B->im.rad_m);
+  const arbgpu_out outs[2] = {C->re, C->im};
+  double *rin_m[2] = {nullptr, nullptr};
+  int32_t *rin_e[2] = {nullptr, nullptr};
+  // The limb kernel takes over what this path does not cover, unless the
+  // caller asked for this path explicitly.
+  auto not_here = [&](const char *why) {
+    return forced ? set_error(ctx, ARBGPU_EINVAL, "sliced product: %s", why) : kNotApplicable;
+  };
+
+  if (g[0] <= hmax && g[4] <= hmax) {
+    // ---- the whole inner range is one block: its exact integer product
+    //      rounds straight to the output
+    if (slices_for(g[0]) > kMaxSlices || slices_for(g[4]) > kMaxSlices) return not_here("integer height too large");
+    if (!sh.approx && (radA || radB)) {
+      rc = radius_products(ctx, A, B, sh, rin_m, rin_e, s);
+      if (rc) return rc;
+    }
+    return block_product(ctx, A, B, sh, 0, sh.K, st, g[0], g[4], outs, C->off, C->rs, C->cs, (int)p, sh.approx,
+                         rin_m, rin_e, s);
+  }
+
+  // ---- several blocks (Algorithm 2's greedy partition) ----------------------
+  // Every block result T_s 2^(-e_i - f_j) is kept exactly and the merge adds
+  // them and the basecase products exactly before the one truncation.  The
+  // exact block values need exponents inside the operand format's range.
+  if (2 * (int64_t)std::max(g[3], g[7]) + 64 >= (int64_t)(1 << 28)) return not_here("exponents too large for blocks");
+  if (slices_for(hmax) > kMaxSlices) return not_here("height bound too large");
+  std::vector<BlockSpan> blocks;
+  rc = plan_blocks(ctx, A, B, sh.cplx, hmax, s, blocks);
+  if (rc) return rc;
+  std::vector<int64_t> bk;   // basecase inner indices
+  std::vector<int32_t> hts;  // (HA, HB) per scaled-integer block
+  int nS = 0, capT = 1;
+  for (const BlockSpan &b : blocks) {
+    if (b.kind == 1) {
+      for (int64_t k = b.k0; k < b.k1; ++k) bk.push_back(k);
+      continue;
+    }
+    rc = line_stats(ctx, A, B, sh, b.k0, b.k1, st, s, g);
+    if (rc) return rc;
+    hts.push_back(g[0]);
+    hts.push_back(g[4]);
+    capT = std::max(capT, t_limbs(slices_for(g[0]), slices_for(g[4])));
+    ++nS;
+  }
+  if (nS == 0 && !forced) return kNotApplicable;   // only dot products: the limb kernel
+  int cap = std::max(A->re.cap, B->re.cap);
+  if (sh.cplx) cap = std::max(cap, std::max(A->im.cap, B->im.cap));
+  LimbShape ls;
+  if (!limb_shape_for((int)p, nS + (int64_t)bk.size() * sh.nparts, cap, &ls)) return not_here("precision too large");
+  if (!sh.approx && (radA || radB)) {
+    rc = radius_products(ctx, A, B, sh, rin_m, rin_e, s);
+    if (rc) return rc;
+  }
+  const int64_t MN = sh.M * sh.N;
+  const size_t tcount = (size_t)sh.nparts * nS * MN;   // exact block values
+  const size_t tbytes = tcount * (sizeof(uint32_t) * capT + 2 * sizeof(int32_t));
+  char *tw = (char *)ws_get(ctx, WS_BLOCKS, round_up(tbytes, 8) + sizeof(int64_t) * (bk.size() + 1));
+  if (!tw) return ARBGPU_ENOMEM;
+  uint32_t *tl = (uint32_t *)tw;
+  int32_t *te = (int32_t *)(tl + tcount * capT);
+  int32_t *tn = te + tcount;
+  int64_t *dbk = (int64_t *)(tw + round_up(tbytes, 8));
+  if (!bk.empty()) {
+    ARB_TRY(hipMemcpyAsync(dbk, bk.data(), sizeof(int64_t) * bk.size(), hipMemcpyHostToDevice, s), "basecase upload");
+    ARB_TRY(hipStreamSynchronize(s), "basecase upload");
+  }
+  // part q, block si: limb plane k of entry ij at tl[q*nS*MN*capT + k*nS*MN + si*MN + ij]
+  const int64_t ldT = (int64_t)nS * MN;
+  int si = 0;
+  for (const BlockSpan &b : blocks) {
+    if (b.kind == 1) continue;
+    rc = line_stats(ctx, A, B, sh, b.k0, b.k1, st, s, g);
+    if (rc) return rc;
+    arbgpu_out tout[2];
+    for (int q = 0; q < sh.nparts; ++q) {
+      const size_t e0 = (size_t)q * nS * MN + (size_t)si * MN;
+      tout[q] = arbgpu_out{tl + (size_t)q * nS * MN * capT + (size_t)si * MN, ldT, capT, te + e0, tn + e0,
+                           nullptr, nullptr, nullptr};
+    }
+    double *no_m[2] = {nullptr, nullptr};
+    int32_t *no_e[2] = {nullptr, nullptr};
+    rc = block_product(ctx, A, B, sh, b.k0, b.k1, st, g[0], g[4], tout, 0, sh.N, 1, 32 * capT, true, no_m, no_e, s);
+    if (rc) return rc;
+    ++si;
+  }
+  for (int q = 0; q < sh.nparts; ++q) {
+    MergeParams mp;
+    memset(&mp, 0, sizeof mp);
+    mp.T = arbgpu_arr{tl + (size_t)q * nS * MN * capT, ldT, capT, te + (size_t)q * nS * MN,
+                      tn + (size_t)q * nS * MN, nullptr, nullptr};
+    mp.nS = nS;
+    mp.A[0] = A->re;
+    mp.A[1] = sh.cplx ? A->im : A->re;
+    mp.B[0] = B->re;
+    mp.B[1] = sh.cplx ? B->im : B->re;
+    mp.a_off = A->off; mp.a_rs = A->rs; mp.a_cs = A->cs;
+    mp.b_off = B->off; mp.b_rs = B->rs; mp.b_cs = B->cs;
+    mp.bk = dbk;
+    mp.nbk = (int64_t)bk.size();
+    mp.ct = !sh.cplx ? comp_real() : (q == 0 ? comp_re() : comp_im());
+    mp.M = sh.M; mp.N = sh.N;
+    mp.C = outs[q];
+    mp.c_off = C->off; mp.c_rs = C->rs; mp.c_cs = C->cs;
+    mp.p = (int)p;
+    mp.approx = sh.approx;
+    mp.rin_m = rin_m[q];
+    mp.rin_e = rin_e[q];
+    KernelTimer tmg(ctx, "merge", s);
+    ARB_TRY(launch_merge(mp, ls.ns, s), "merge");
   }
   return ARBGPU_OK;
 }

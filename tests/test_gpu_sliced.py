@@ -157,3 +157,24 @@ def test_config2_sliced_sampled(ctx):
     rows = {i: [gen.to_canonical(w.A, i * w.N + k) for k in range(w.N)] for i, _ in ent}
     cols = {j: [gen.to_canonical(w.B, k * w.K + j) for k in range(w.N)] for _, j in ent}
     check(out, st, lambda i, j: oracle.dot(rows[i], cols[j], w.p), ent, w.K)
+
+
+@pytest.mark.parametrize("seed,spread,bside", [(1, 700, False), (2, 300, True), (3, 1500, True)])
+def test_sliced_radius_wide_range(ctx, seed, spread, bside):
+    # radii spread over many binades inside one row (and column): the
+    # per-line FP64 frames cannot hold them all, so the per-entry radius
+    # kernel takes over; tiny radii next to large midpoints exercise the
+    # |b| + r_b bump
+    rng = gen.rng_for(23, seed)
+    M, N, K, p = 13, 70, 11, 150
+    A = gen.random_operands(rng, M * N, 150, -8, 8, radius_shift=140)
+    B = gen.random_operands(rng, N * K, 150, -8, 8, radius_shift=140 if bside else None)
+    A.rad_e[::2] -= spread
+    if bside:
+        B.rad_e[1::3] -= spread
+    say(f"sliced radius spread={spread} seed={seed}")
+    (out, st), _ = run(ctx, A, B, M, N, K, p, arbgpu.ALGO_SLICED)
+    Ac = gen.canonical_matrix(A, M, N, N, 1)
+    Bc = gen.canonical_matrix(B, N, K, K, 1)
+    C = oracle.mat_mul(Ac, Bc, p)
+    check(out, st, lambda i, j: C[i][j], [(i, j) for i in range(M) for j in range(K)], K)

@@ -94,6 +94,28 @@ def test_host_only_context_validates_matmul(hctx):
     assert hctx.mat_mul_raw(omat(0, 4), mat(0, 5), mat(5, 4), 100, check=False) == arbgpu.OK
 
 
+def test_host_only_context_validates_plan_blocks(hctx, lib):
+    def mat(rows, cols, ld=100):
+        return arbgpu.Mat(_arr(ld), _arr(ld), rows, cols, 0, cols, 1)
+
+    bounds = (ctypes.c_int64 * 8)()
+    kinds = (ctypes.c_int32 * 4)()
+    nb = ctypes.c_int64(-1)
+
+    def call(A, B, p=100, flags=0, b=bounds, k=kinds, cap=4, n=ctypes.byref(nb)):
+        return lib.arbgpu_plan_blocks(hctx.h, ctypes.byref(A), ctypes.byref(B), p, flags, b, k, cap, n, None)
+
+    assert call(mat(3, 5), mat(5, 4)) == arbgpu.EDEVICE
+    assert call(mat(3, 5), mat(6, 4)) == arbgpu.EINVAL          # inner dimensions
+    assert call(mat(3, 5), mat(5, 4), p=1) == arbgpu.EINVAL     # precision
+    assert call(mat(3, 5), mat(5, 4), flags=arbgpu.APPROX) == arbgpu.EINVAL
+    assert call(mat(3, 5), mat(5, 4), n=None) == arbgpu.EINVAL
+    assert call(mat(3, 5), mat(5, 4), b=None) == arbgpu.EINVAL
+    assert call(mat(30, 5), mat(5, 4)) == arbgpu.EINVAL         # A index range
+    # an empty inner range has no blocks, no device needed
+    assert call(mat(3, 0), mat(0, 4)) == arbgpu.OK and nb.value == 0
+
+
 def test_init_rejects_bad_device(lib):
     h = ctypes.c_void_p()
     assert lib.arbgpu_init(ctypes.byref(h), -2, 0, None) == arbgpu.EINVAL
