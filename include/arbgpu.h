@@ -161,11 +161,53 @@ int arbgpu_plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B
                        int64_t p, uint32_t flags, int64_t *bounds, int32_t *kinds,
                        int64_t max_blocks, int64_t *nblocks, arbgpu_stream stream);
 
+/* One dot product of a batch: the arguments of arbgpu_dot by value.
+ * Complex jobs (ARBGPU_COMPLEX in flags) use both entries of res, init, x
+ * and y as {real part, imaginary part}; real jobs use entry 0 only.
+ * init[0].limbs == NULL means no initial value.  flags: APPROX, COMPLEX,
+ * REDUCE_PREC. */
+typedef struct {
+  arbgpu_out res[2];
+  int64_t res_idx;
+  arbgpu_arr init[2];
+  int64_t init_idx;
+  arbgpu_arr x[2], y[2];
+  int64_t xoff, xstep, yoff, ystep, N, p;
+  uint32_t flags;
+  int32_t sub;
+} arbgpu_dot_job;
+
+/* A resident batch of dot products (the persistent batched launch): the
+ * jobs are validated, grouped by kernel shape (window and operand limbs,
+ * chosen from p, N and operand widths), ordered longest first, copied to
+ * device memory once, and bound into one HIP graph.  Each launch replays
+ * the graph on `stream`: one persistent kernel per shape whose waves take
+ * dots from a device work counter until the queue is empty.  The operand
+ * and output arrays the jobs name must stay valid while the batch is
+ * launched.  Waves per compute unit per shape come from the context's tune
+ * table (arbgpu_batch_tune), else a default.
+ * create: EINVAL on a bad job (its index in the message), ENOMEM, EDEVICE.
+ * launch: EDEVICE on HIP errors.  destroy waits for the device. */
+typedef struct arbgpu_batch arbgpu_batch;
+int arbgpu_batch_create(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs,
+                        arbgpu_batch **batch);
+int arbgpu_batch_launch(arbgpu_batch *batch, arbgpu_stream stream);
+/* Autotuner: times every shape of the batch alone at 1, 2, 4, 8 and 16
+ * waves per compute unit, keeps the fastest in the context's tune table
+ * (written back to the context's tune_cache file when one was given), and
+ * rebuilds the graph.  Synchronizes `stream`. */
+int arbgpu_batch_tune(arbgpu_batch *batch, arbgpu_stream stream);
+/* Writes up to n values {jobs, kernel tasks (one per output part), shapes,
+ * then per shape (NS, NA, tasks, waves per CU)} to out (host memory). */
+int arbgpu_batch_info(arbgpu_batch *batch, int64_t *out, int n);
+void arbgpu_batch_destroy(arbgpu_batch *batch);
+
 /* Per-kernel timing with HIP events recorded on the caller's stream around
  * each launch (for measurement; off by default).  arbgpu_timing(ctx, 1)
  * clears old records and starts recording, 0 stops.  arbgpu_timing_read
  * waits for the recorded launches of `kernel` ("mfma", "slice", "stats",
- * "recombine", "rad_gemm", "plan", "merge", "limb_mm", "limb_dot") and returns their total
+ * "recombine", "rad_gemm", "plan", "merge", "limb_mm", "limb_dot",
+ * "dot_batch") and returns their total
  * milliseconds and count.  EINVAL on NULL arguments. */
 int arbgpu_timing(arbgpu_ctx *ctx, int enable);
 

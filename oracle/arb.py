@@ -277,11 +277,13 @@ def dot(x: Sequence, y: Sequence, p: int, initial=None, sub: bool = False,
 
 
 def cdot(x: Sequence, y: Sequence, p: int, initial=None, sub: bool = False,
-         approx: bool = False) -> Tuple[DotResult, DotResult]:
+         approx: bool = False, reduce_prec: bool = False) -> Tuple[DotResult, DotResult]:
     """Complex dot over rectangular complex balls (Section 3.6): the real
     part is the real dot of the 2N terms a_i c_i and -(b_i d_i), the
     imaginary part that of a_i d_i and b_i c_i, each rounded once.  Each
-    operand is ((a, ra), (b, rb)) = [a +- ra] + [b +- rb] i."""
+    operand is ((a, ra), (b, rb)) = [a +- ra] + [b +- rb] i.  With
+    ``reduce_prec`` each part takes the precision cut of its own 2N-term
+    real dot (Section 3.3, step 7(a))."""
     if len(x) != len(y):
         raise ValueError("length mismatch")
     re_terms, im_terms = [], []
@@ -292,8 +294,8 @@ def cdot(x: Sequence, y: Sequence, p: int, initial=None, sub: bool = False,
         im_terms.append((0, b, c))
     ire = initial[0] if initial is not None else None
     iim = initial[1] if initial is not None else None
-    return (_real_dot(re_terms, p, ire, sub, approx),
-            _real_dot(im_terms, p, iim, sub, approx))
+    return (_real_dot(re_terms, p, ire, sub, approx, reduce_prec),
+            _real_dot(im_terms, p, iim, sub, approx, reduce_prec))
 
 
 # ---------------------------------------------------------------------------

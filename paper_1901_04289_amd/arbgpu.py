@@ -47,6 +47,13 @@ class OMat(ctypes.Structure):
                 ("rs", c_i64), ("cs", c_i64)]
 
 
+class DotJob(ctypes.Structure):
+    """One dot product of a batch (the arguments of arbgpu_dot by value)."""
+    _fields_ = [("res", Out * 2), ("res_idx", c_i64), ("init", Arr * 2), ("init_idx", c_i64),
+                ("x", Arr * 2), ("y", Arr * 2), ("xoff", c_i64), ("xstep", c_i64), ("yoff", c_i64),
+                ("ystep", c_i64), ("N", c_i64), ("p", c_i64), ("flags", c_u32), ("sub", c_i32)]
+
+
 class ArbgpuError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"arbgpu error {code}: {msg}")
@@ -67,6 +74,11 @@ EXPORTS = {
     "arbgpu_plan_blocks": (ctypes.c_int, [c_p, ctypes.POINTER(Mat), ctypes.POINTER(Mat), c_i64, c_u32,
                                           ctypes.POINTER(c_i64), ctypes.POINTER(ctypes.c_int32), c_i64,
                                           ctypes.POINTER(c_i64), c_p]),
+    "arbgpu_batch_create": (ctypes.c_int, [c_p, ctypes.POINTER(DotJob), c_i64, ctypes.POINTER(c_p)]),
+    "arbgpu_batch_launch": (ctypes.c_int, [c_p, c_p]),
+    "arbgpu_batch_tune": (ctypes.c_int, [c_p, c_p]),
+    "arbgpu_batch_info": (ctypes.c_int, [c_p, ctypes.POINTER(c_i64), ctypes.c_int]),
+    "arbgpu_batch_destroy": (None, [c_p]),
     "arbgpu_timing": (ctypes.c_int, [c_p, ctypes.c_int]),
     "arbgpu_plan_info": (ctypes.c_int, [c_p, ctypes.POINTER(c_i64), ctypes.c_int]),
     "arbgpu_timing_read": (ctypes.c_int, [c_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -282,3 +294,57 @@ class Context:
         if cplx and (Ai is None or Bi is None or Ci is None):
             raise ValueError("complex product needs imaginary parts")
         return self.mat_mul_raw(cm, am, bm, p, flags, stream)
+
+
+def dot_job(res: Sequence[Out], res_idx: int, x: Sequence[Arr], xoff: int, xstep: int, y: Sequence[Arr],
+            yoff: int, ystep: int, N: int, p: int, flags: int = 0, initial: Optional[Sequence[Arr]] = None,
+            init_idx: int = 0, sub: bool = False) -> DotJob:
+    """Pack one batch job; sequences hold one part (real) or two (complex)."""
+    j = DotJob()
+    for q in range(len(x)):
+        j.res[q] = res[q]
+        j.x[q] = x[q]
+        j.y[q] = y[q]
+        if initial is not None:
+            j.init[q] = initial[q]
+    j.res_idx, j.init_idx = res_idx, init_idx
+    j.xoff, j.xstep, j.yoff, j.ystep, j.N, j.p = xoff, xstep, yoff, ystep, N, p
+    j.flags, j.sub = flags, int(bool(sub))
+    return j
+
+
+class Batch:
+    """A resident batch of dot products replayed as one graph launch."""
+
+    def __init__(self, ctx: "Context", jobs: Sequence[DotJob]):
+        self.ctx = ctx
+        arr = (DotJob * max(1, len(jobs)))(*jobs)
+        h = c_p()
+        ctx._check(ctx.lib.arbgpu_batch_create(ctx.h, arr, len(jobs), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self, stream=None):
+        self.ctx._check(self.ctx.lib.arbgpu_batch_launch(self.h, _stream_handle(stream)))
+
+    def tune(self, stream=None):
+        self.ctx._check(self.ctx.lib.arbgpu_batch_tune(self.h, _stream_handle(stream)))
+
+    def info(self):
+        buf = (c_i64 * 256)()
+        self.ctx._check(self.ctx.lib.arbgpu_batch_info(self.h, buf, 256))
+        v = list(buf)
+        shapes = [dict(ns=v[3 + 4 * k], na=v[4 + 4 * k], tasks=v[5 + 4 * k], waves=v[6 + 4 * k])
+                  for k in range(min(v[2], 63))]
+        return dict(jobs=v[0], tasks=v[1], shapes=shapes)
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.arbgpu_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -7,6 +7,7 @@
 
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -65,6 +66,43 @@ void *ws_get(arbgpu_ctx *ctx, int slot, size_t bytes) {
   b.ptr = p;
   b.size = bytes;
   return p;
+}
+
+void tune_load(arbgpu_ctx *ctx) {
+  FILE *f = fopen(ctx->tune_path.c_str(), "r");
+  if (!f) return;
+  std::string txt;
+  char buf[4096];
+  size_t n;
+  while ((n = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+  fclose(f);
+  // "key": value pairs; anything else is skipped
+  size_t i = 0;
+  while ((i = txt.find('"', i)) != std::string::npos) {
+    const size_t j = txt.find('"', i + 1);
+    if (j == std::string::npos) break;
+    const std::string key = txt.substr(i + 1, j - i - 1);
+    size_t k = j + 1;
+    while (k < txt.size() && (txt[k] == ' ' || txt[k] == ':' || txt[k] == '\t')) ++k;
+    char *end = nullptr;
+    const long v = strtol(txt.c_str() + k, &end, 10);
+    if (end != txt.c_str() + k) ctx->tune[key] = (int)v;
+    i = j + 1;
+  }
+}
+
+void tune_save(arbgpu_ctx *ctx) {
+  if (ctx->tune_path.empty()) return;
+  FILE *f = fopen(ctx->tune_path.c_str(), "w");
+  if (!f) return;
+  fprintf(f, "{");
+  bool first = true;
+  for (auto &kv : ctx->tune) {
+    fprintf(f, "%s\n  \"%s\": %d", first ? "" : ",", kv.first.c_str(), kv.second);
+    first = false;
+  }
+  fprintf(f, "\n}\n");
+  fclose(f);
 }
 
 }  // namespace arbgpu_impl
@@ -133,10 +171,72 @@ int bind_device(arbgpu_ctx *ctx) {
 
 }  // namespace
 
+namespace arbgpu_impl {
+
+int dot_tasks(arbgpu_ctx *ctx, const arbgpu_dot_job &job, const char *who, DotParams prm[2], int *ntasks,
+              LimbShape *shape) {
+  const uint32_t flags = job.flags;
+  const bool approx = flags & ARBGPU_APPROX;
+  const bool cplx = flags & ARBGPU_COMPLEX;
+  const int nparts = cplx ? 2 : 1;
+  const bool has_init = job.init[0].limbs != nullptr;
+  const int64_t p = job.p, N = job.N;
+  if (flags & ~(ARBGPU_APPROX | ARBGPU_COMPLEX | ARBGPU_REDUCE_PREC))
+    return fail(ctx, ARBGPU_EINVAL, "%s: unknown flags 0x%x", who, flags);
+  if (p < 2 || p > (1 << 20)) return fail(ctx, ARBGPU_EINVAL, "%s: p=%lld out of range", who, (long long)p);
+  if (N < 0) return fail(ctx, ARBGPU_EINVAL, "%s: N < 0", who);
+  int cap = 1;
+  for (int q = 0; q < nparts; ++q) {
+    if (!out_ok(job.res[q], p, approx)) return fail(ctx, ARBGPU_EINVAL, "%s: bad result array (cap, pointers)", who);
+    if (job.res_idx < 0 || job.res_idx >= job.res[q].ld)
+      return fail(ctx, ARBGPU_EINVAL, "%s: res_idx out of range", who);
+    if (!arr_ok(job.x[q]) || !arr_ok(job.y[q])) return fail(ctx, ARBGPU_EINVAL, "%s: bad operand array", who);
+    int64_t lo, hi;
+    index_range(job.xoff, N, job.xstep, 0, 0, &lo, &hi);
+    if (N > 0 && !range_ok(lo, hi, job.x[q].ld)) return fail(ctx, ARBGPU_EINVAL, "%s: x index out of range", who);
+    index_range(job.yoff, N, job.ystep, 0, 0, &lo, &hi);
+    if (N > 0 && !range_ok(lo, hi, job.y[q].ld)) return fail(ctx, ARBGPU_EINVAL, "%s: y index out of range", who);
+    if (has_init) {
+      if (!arr_ok(job.init[q])) return fail(ctx, ARBGPU_EINVAL, "%s: bad initial array", who);
+      if (job.init_idx < 0 || job.init_idx >= job.init[q].ld)
+        return fail(ctx, ARBGPU_EINVAL, "%s: init_idx out of range", who);
+      cap = job.init[q].cap > cap ? job.init[q].cap : cap;
+    }
+    cap = job.x[q].cap > cap ? job.x[q].cap : cap;
+    cap = job.y[q].cap > cap ? job.y[q].cap : cap;
+  }
+  if (!limb_shape_for((int)p, N * nparts + 1, cap, shape))
+    return fail(ctx, ARBGPU_EINVAL, "%s: precision %lld above the limb kernel's window", who, (long long)p);
+  for (int q = 0; q < nparts; ++q) {
+    DotParams &d = prm[q];
+    memset(&d, 0, sizeof d);
+    for (int k = 0; k < 2; ++k) {
+      const int src = cplx ? k : 0;
+      d.X[k] = job.x[src];
+      d.Y[k] = job.y[src];
+      if (has_init) d.I[k] = job.init[src];
+    }
+    d.has_init = has_init;
+    d.init_idx = job.init_idx;
+    d.init_part = q;
+    d.R = job.res[q];
+    d.res_idx = job.res_idx;
+    d.xoff = job.xoff; d.xstep = job.xstep; d.yoff = job.yoff; d.ystep = job.ystep; d.N = N;
+    d.p = (int)p;
+    d.approx = approx;
+    d.sub = job.sub ? 1u : 0u;
+    d.reduce = (flags & ARBGPU_REDUCE_PREC) != 0;
+    d.ct = !cplx ? comp_real() : (q == 0 ? comp_re() : comp_im());
+  }
+  *ntasks = nparts;
+  return ARBGPU_OK;
+}
+
+}  // namespace arbgpu_impl
+
 extern "C" {
 
 int arbgpu_init(arbgpu_ctx **ctx, int device, size_t hbm_budget_bytes, const char *tune_cache) {
-  (void)tune_cache;
   if (!ctx) return ARBGPU_EINVAL;
   *ctx = nullptr;
   if (device < -1) return ARBGPU_EINVAL;
@@ -144,6 +244,10 @@ int arbgpu_init(arbgpu_ctx **ctx, int device, size_t hbm_budget_bytes, const cha
   if (!c) return ARBGPU_ENOMEM;
   c->device = device;
   c->budget = hbm_budget_bytes;
+  if (tune_cache && tune_cache[0]) {
+    c->tune_path = tune_cache;
+    tune_load(c);
+  }
   if (device >= 0) {
     int n = 0;
     hipError_t e = hipGetDeviceCount(&n);
@@ -218,63 +322,31 @@ int arbgpu_dot(arbgpu_ctx *ctx, const arbgpu_out *res, int64_t res_idx, const ar
                arbgpu_stream stream) {
   if (!ctx) return ARBGPU_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
-  const bool approx = flags & ARBGPU_APPROX;
-  const bool cplx = flags & ARBGPU_COMPLEX;
-  const int nparts = cplx ? 2 : 1;
-  if (flags & ~(ARBGPU_APPROX | ARBGPU_COMPLEX | ARBGPU_REDUCE_PREC))
-    return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: unknown flags 0x%x", flags);
-  if (flags & ARBGPU_REDUCE_PREC) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: REDUCE_PREC is not supported");
-  if (p < 2 || p > (1 << 20)) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: p=%lld out of range", (long long)p);
-  if (N < 0) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: N < 0");
   if (!res || !x || !y) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: NULL argument");
-  int cap = 1;
+  const int nparts = (flags & ARBGPU_COMPLEX) ? 2 : 1;
+  arbgpu_dot_job job;
+  memset(&job, 0, sizeof job);
   for (int q = 0; q < nparts; ++q) {
-    if (!out_ok(res[q], p, approx)) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: bad result array (cap, pointers)");
-    if (res_idx < 0 || res_idx >= res[q].ld) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: res_idx out of range");
-    if (!arr_ok(x[q]) || !arr_ok(y[q])) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: bad operand array");
-    int64_t lo, hi;
-    index_range(xoff, N, xstep, 0, 0, &lo, &hi);
-    if (N > 0 && !range_ok(lo, hi, x[q].ld)) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: x index out of range");
-    index_range(yoff, N, ystep, 0, 0, &lo, &hi);
-    if (N > 0 && !range_ok(lo, hi, y[q].ld)) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: y index out of range");
-    if (initial) {
-      if (!arr_ok(initial[q])) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: bad initial array");
-      if (init_idx < 0 || init_idx >= initial[q].ld) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: init_idx out of range");
-      cap = initial[q].cap > cap ? initial[q].cap : cap;
-    }
-    cap = x[q].cap > cap ? x[q].cap : cap;
-    cap = y[q].cap > cap ? y[q].cap : cap;
+    job.res[q] = res[q];
+    job.x[q] = x[q];
+    job.y[q] = y[q];
+    if (initial) job.init[q] = initial[q];
   }
+  job.res_idx = res_idx;
+  job.init_idx = init_idx;
+  job.xoff = xoff; job.xstep = xstep; job.yoff = yoff; job.ystep = ystep; job.N = N; job.p = p;
+  job.flags = flags;
+  job.sub = sub;
+  if (initial && !initial[0].limbs) return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: bad initial array");
+  DotParams prm[2];
+  int nt = 0;
   LimbShape sh;
-  if (!limb_shape_for((int)p, N * nparts + 1, cap, &sh))
-    return fail(ctx, ARBGPU_EINVAL, "arbgpu_dot: precision %lld above the limb kernel's window", (long long)p);
-  int rc = bind_device(ctx);
+  int rc = dot_tasks(ctx, job, "arbgpu_dot", prm, &nt, &sh);
   if (rc) return rc;
-  for (int q = 0; q < nparts; ++q) {
-    DotParams prm;
-    memset(&prm, 0, sizeof prm);
-    for (int k = 0; k < nparts; ++k) {
-      prm.X[k] = x[k];
-      prm.Y[k] = y[k];
-      if (initial) prm.I[k] = initial[k];
-    }
-    if (!cplx) {
-      prm.X[1] = x[0];
-      prm.Y[1] = y[0];
-      if (initial) prm.I[1] = initial[0];
-    }
-    prm.has_init = initial != nullptr;
-    prm.init_idx = init_idx;
-    prm.init_part = q;
-    prm.R = res[q];
-    prm.res_idx = res_idx;
-    prm.xoff = xoff; prm.xstep = xstep; prm.yoff = yoff; prm.ystep = ystep; prm.N = N;
-    prm.p = (int)p;
-    prm.approx = approx;
-    prm.sub = sub ? 1u : 0u;
-    prm.ct = !cplx ? comp_real() : (q == 0 ? comp_re() : comp_im());
+  if ((rc = bind_device(ctx))) return rc;
+  for (int q = 0; q < nt; ++q) {
     KernelTimer kt(ctx, "limb_dot", to_stream(stream));
-    hipError_t e = launch_limb_dot(prm, sh, to_stream(stream));
+    hipError_t e = launch_limb_dot(prm[q], sh, to_stream(stream));
     if (e != hipSuccess) return hip_fail(ctx, e, "arbgpu_dot launch");
   }
   return ARBGPU_OK;

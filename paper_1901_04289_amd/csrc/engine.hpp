@@ -481,6 +481,7 @@ struct DotOut {
   double rin_m;   // propagated radius rho_in = rin_m * 2^rin_e (upper bound)
   int rin_e;
   bool erange;
+  int p;          // precision of the midpoint (below the request after a cut)
 };
 
 // Reducer for a single lane per output (no cross-lane traffic).
@@ -501,8 +502,12 @@ struct SoloReducer {
 // `Op` is Opnd<NA> (limbs in registers) or SOpnd (limbs read in place).
 // Lane `Red::lane()` of `Red::group()` handles terms t = lane (mod group);
 // lane 0 also handles the initial term.
+// With `reduce`, the precision is first cut to
+// p' = max(2, min(p, e_max - e_rad + 30)) from the setup statistics
+// (Section 3.3, step 7(a)); e_max and e_rad bound the exponents of the
+// midpoint and radius products, and p' = 2 when every midpoint product is 0.
 template <int NS, class Op, class Red, class Src>
-ARB_HD void run_dot(const Src &src, int p, bool want_rad, DotOut<NS> &out) {
+ARB_HD void run_dot(const Src &src, int p, bool want_rad, DotOut<NS> &out, bool reduce = false) {
   const int lane = Red::lane(), group = Red::group();
   const int64_t nt = src.nterms();
   const bool hi = src.has_init() && lane == 0;
@@ -512,14 +517,20 @@ ARB_HD void run_dot(const Src &src, int p, bool want_rad, DotOut<NS> &out) {
     Op a, b;
     uint32_t neg;
     src.term(t, a, b, neg, false);
-    setup_term(S, a, b, want_rad);
+    setup_term(S, a, b, want_rad || reduce);
   }
   if (hi) {
     Op a, b;
     src.init(a, b, false);
-    setup_term(S, a, b, want_rad);
+    setup_term(S, a, b, want_rad || reduce);
   }
   Red::setup(S);
+  if (reduce) {
+    int64_t q = S.nnz ? p : 2;
+    if (S.nnz && S.any_rad && (int64_t)S.emax - S.F + 30 < q) q = (int64_t)S.emax - S.F + 30;
+    p = q < 2 ? 2 : (int)q;
+  }
+  out.p = p;
   out.erange = S.erange;
   out.rin_m = 0.0;
   out.rin_e = 0;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -32,6 +33,10 @@ struct arbgpu_ctx {
   // shape of the last scaled-integer product: digit planes of A and B,
   // partial planes, diagonal groups, inner length, rows, cols
   int64_t last_plan[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // autotuned launch parameters ("dot_batch:NSxNA" -> waves per CU), and
+  // the file they are loaded from and saved to (may be empty)
+  std::map<std::string, int> tune;
+  std::string tune_path;
   ~arbgpu_ctx();
 };
 
@@ -49,6 +54,10 @@ enum WsSlot {
 void *ws_get(arbgpu_ctx *ctx, int slot, size_t bytes);
 
 int set_error(arbgpu_ctx *ctx, int code, const char *fmt, ...);
+
+// Tune table file: a flat JSON object of string keys and integer values.
+void tune_load(arbgpu_ctx *ctx);
+void tune_save(arbgpu_ctx *ctx);
 
 // Records HIP events around one kernel launch on `s` when the context's
 // timing is enabled.
@@ -118,6 +127,7 @@ struct DotParams {
   int approx;
   uint32_t sub;
   int init_part;            // which part of the initial value feeds this output
+  int reduce;               // radius-driven precision cut (Section 3.3, step 7(a))
   CompTab ct;
 };
 
@@ -133,6 +143,22 @@ hipError_t launch_mm_shape(const MmParams &prm, hipStream_t s);
 template <int NS, int NA>
 hipError_t launch_dot_shape(const DotParams &prm, hipStream_t s);
 hipError_t launch_limb_mm(const MmParams &prm, LimbShape sh, hipStream_t s);
+
+// Persistent batched dot kernel of one shape.
+struct BatchShapeParams {
+  const DotParams *tasks;   // every task of the batch (device memory)
+  const int32_t *order;     // indices of this shape's tasks, longest first
+  int64_t count;
+  int32_t *counter;         // work counter, zero before the launch
+};
+template <int NS, int NA>
+const void *dot_batch_kernel_shape();
+const void *dot_batch_kernel(LimbShape sh);   // kernel taking (BatchShapeParams)
+
+// Validates one dot job and builds its kernel tasks (one per output part)
+// and kernel shape; sets the context error and returns EINVAL on a bad job.
+int dot_tasks(arbgpu_ctx *ctx, const arbgpu_dot_job &job, const char *who, DotParams prm[2], int *ntasks,
+              LimbShape *shape);
 hipError_t launch_limb_dot(const DotParams &prm, LimbShape sh, hipStream_t s);
 
 }  // namespace arbgpu_impl

@@ -42,6 +42,14 @@ hipError_t launch_limb_mm(const MmParams &prm, LimbShape sh, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+const void *dot_batch_kernel(LimbShape sh) {
+#define X(a, b) \
+  if (sh.ns == a && sh.na == b) return dot_batch_kernel_shape<a, b>();
+  ARB_LIMB_SHAPES(X)
+#undef X
+  return nullptr;
+}
+
 hipError_t launch_limb_dot(const DotParams &prm, LimbShape sh, hipStream_t s) {
 #define X(a, b) \
   if (sh.ns == a && sh.na == b) return launch_dot_shape<a, b>(prm, s);

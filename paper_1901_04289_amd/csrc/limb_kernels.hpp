@@ -198,7 +198,7 @@ __device__ __forceinline__ void store_out(const arbgpu_out &o, int64_t idx, cons
       rm = INFINITY;
       re = 0;
     } else {
-      total_radius(r, p, rm, re);
+      total_radius(r, r.p, rm, re);
     }
     o.rad_m[idx] = rm;
     o.rad_e[idx] = re;
@@ -238,14 +238,40 @@ template <int NS, int NA>
 __global__ __launch_bounds__(64) void limb_dot_kernel(DotParams prm) {
   DotOut<NS> out;
   DotSrc<Opnd<NA>> src{&prm};
-  run_dot<NS, Opnd<NA>, WaveReducer>(src, prm.p, !prm.approx, out);
+  run_dot<NS, Opnd<NA>, WaveReducer>(src, prm.p, !prm.approx, out, prm.reduce != 0);
   bool fell_back = false;
   if (out.st.bad) {   // uniform across the wave: every lane holds the same state
     DotSrc<SOpnd> s2{&prm};
-    run_dot<NS, SOpnd, WaveReducer>(s2, prm.p, !prm.approx, out);
+    run_dot<NS, SOpnd, WaveReducer>(s2, prm.p, !prm.approx, out, prm.reduce != 0);
     fell_back = true;
   }
   if (threadIdx.x == 0) store_out<NS>(prm.R, prm.res_idx, out, prm.p, prm.approx, status_of(out, fell_back));
+}
+
+// Persistent batch: waves take tasks from a work counter until the list
+// of this shape is exhausted; each task is one dot output as in
+// limb_dot_kernel.  Four independent waves per workgroup.
+template <int NS, int NA>
+__global__ __launch_bounds__(256) void limb_dot_batch_kernel(BatchShapeParams bp) {
+  const int lane = threadIdx.x & 63;
+  // the counter only grows, so a wave takes at most `count` tasks
+  for (int64_t iter = 0; iter <= bp.count; ++iter) {
+    int t = 0;
+    if (lane == 0) t = atomicAdd(bp.counter, 1);
+    t = __shfl(t, 0, 64);
+    if (t >= bp.count) break;   // uniform across the wave
+    const DotParams *prm = bp.tasks + bp.order[t];
+    DotOut<NS> out;
+    DotSrc<Opnd<NA>> src{prm};
+    run_dot<NS, Opnd<NA>, WaveReducer>(src, prm->p, !prm->approx, out, prm->reduce != 0);
+    bool fell_back = false;
+    if (out.st.bad) {
+      DotSrc<SOpnd> s2{prm};
+      run_dot<NS, SOpnd, WaveReducer>(s2, prm->p, !prm->approx, out, prm->reduce != 0);
+      fell_back = true;
+    }
+    if (lane == 0) store_out<NS>(prm->R, prm->res_idx, out, prm->p, prm->approx, status_of(out, fell_back));
+  }
 }
 
 }  // namespace arbgpu_impl

@@ -116,6 +116,23 @@ def test_host_only_context_validates_plan_blocks(hctx, lib):
     assert call(mat(3, 0), mat(0, 4)) == arbgpu.OK and nb.value == 0
 
 
+def test_host_only_context_validates_batch(hctx, lib):
+    ok = arbgpu.dot_job([_out()], 0, [_arr()], 0, 1, [_arr()], 0, 1, 5, 64)
+    bad = arbgpu.dot_job([_out()], 0, [_arr()], 0, 1, [_arr()], 0, 1, 5, 1)
+    h = ctypes.c_void_p()
+    jobs = (arbgpu.DotJob * 3)(ok, ok, bad)
+    assert lib.arbgpu_batch_create(hctx.h, jobs, 3, ctypes.byref(h)) == arbgpu.EINVAL
+    assert "job 2" in hctx.last_error()
+    # a valid list reaches the device step
+    assert lib.arbgpu_batch_create(hctx.h, jobs, 2, ctypes.byref(h)) == arbgpu.EDEVICE
+    assert not h.value
+    # the cut flag is accepted for dots; unknown flags are not
+    okr = arbgpu.dot_job([_out()], 0, [_arr()], 0, 1, [_arr()], 0, 1, 5, 64, flags=arbgpu.REDUCE_PREC)
+    assert lib.arbgpu_batch_create(hctx.h, (arbgpu.DotJob * 1)(okr), 1, ctypes.byref(h)) == arbgpu.EDEVICE
+    badf = arbgpu.dot_job([_out()], 0, [_arr()], 0, 1, [_arr()], 0, 1, 5, 64, flags=arbgpu.ALGO_LIMB)
+    assert lib.arbgpu_batch_create(hctx.h, (arbgpu.DotJob * 1)(badf), 1, ctypes.byref(h)) == arbgpu.EINVAL
+
+
 def test_init_rejects_bad_device(lib):
     h = ctypes.c_void_p()
     assert lib.arbgpu_init(ctypes.byref(h), -2, 0, None) == arbgpu.EINVAL

@@ -284,6 +284,29 @@ def test_reduced_precision_cut():
     assert fr(r.mid) == 1
 
 
+def test_reduced_precision_cut_complex():
+    # x = [1 +- 2^-40] + [3 +- 0] i, y = 1 + 1 i (exact): both parts are
+    # exact small integers, unchanged by any cut of at least 2 bits
+    one = (0, 1, 1)
+    three = (0, 3, 2)
+    x = [((one, (1, -40)), (three, None))]
+    y = [((one, None), (one, None))]
+    re, im = oracle.cdot(x, y, 500, reduce_prec=True)
+    assert fr(re.mid) == -2 and fr(im.mid) == 4
+    # an inexact case: a 200-bit mantissa near 2/3 with zero imaginary
+    # parts reduces to the real cut dot
+    m = (1 << 200) // 3 | 1
+    xm = (0, m, 1)
+    x2 = [((xm, (1, -40)), (oracle.ZERO, None))]
+    y2 = [((one, None), (oracle.ZERO, None))]
+    re2, im2 = oracle.cdot(x2, y2, 500, reduce_prec=True)
+    real = oracle.dot([(xm, (1, -40))], [(one, None)], 500, reduce_prec=True)
+    assert re2.mid == real.mid and re2.rad == real.rad
+    # the real dot is cut to 1 + 38 + 30 = 69 bits (e_max = 1 + 1 = 2, e_rad = 1 - 39 = -38)
+    assert oracle.fprec(re2.mid) <= 70 and re2.inexact
+    assert im2.mid == oracle.ZERO
+
+
 def test_badly_scaled_matrix_keeps_entrywise_accuracy():
     # The 3x3 example of Section 2 times the identity and times itself.
     ten = Fraction(10)
