@@ -202,6 +202,44 @@ int arbgpu_batch_tune(arbgpu_batch *batch, arbgpu_stream stream);
 int arbgpu_batch_info(arbgpu_batch *batch, int64_t *out, int n);
 void arbgpu_batch_destroy(arbgpu_batch *batch);
 
+/* Request loop (serving).  A job is a dot product or a matrix product over
+ * device-resident operands, described by value; submit copies the
+ * descriptors (never the operands), validates every job (nothing is queued
+ * when one is bad; EINVAL names its index), and admits the set only if its
+ * workspace footprint fits next to the work already in flight within the
+ * loop's HBM budget: EAGAIN (try again after polling) when it does not fit
+ * now, ENOMEM when it never can.  Worker slots, each with its own stream
+ * and workspace, run the queue in order; requests on different slots
+ * overlap on the device, and dot jobs found together at the head of the
+ * queue run as one persistent batch launch.  Results are the same as from
+ * arbgpu_dot / arbgpu_mat_mul.  Operands and outputs must stay valid until
+ * the job's ticket polls as done.  The loop starts at the first submit with
+ * 4 slots and half the context's budget unless configured before. */
+#define ARBGPU_JOB_DOT     1
+#define ARBGPU_JOB_MATMUL  2
+typedef struct {
+  int32_t kind;            /* ARBGPU_JOB_DOT or ARBGPU_JOB_MATMUL             */
+  arbgpu_dot_job dot;      /* kind == ARBGPU_JOB_DOT                          */
+  arbgpu_omat C;           /* kind == ARBGPU_JOB_MATMUL: C = A B at precision */
+  arbgpu_mat A, B;         /*   p with flags, as arbgpu_mat_mul               */
+  int64_t p;
+  uint32_t flags;
+} arbgpu_job;
+
+/* (Re)starts the loop with `slots` workers (1..16) and an HBM budget in
+ * bytes for the workspace of admitted jobs (0: half the context budget).
+ * EINVAL while requests are in flight. */
+int arbgpu_serve_config(arbgpu_ctx *ctx, int slots, size_t budget_bytes);
+/* Queues njobs jobs and writes their tickets (host array). */
+int arbgpu_submit(arbgpu_ctx *ctx, const arbgpu_job *jobs, int64_t njobs, uint64_t *tickets);
+/* Waits up to timeout_us (0: no wait) for a ticket: OK when its job is
+ * done, NOTREADY when not yet, the job's error code when it failed (text
+ * in arbgpu_last_error), EINVAL for an unknown ticket. */
+int arbgpu_poll(arbgpu_ctx *ctx, uint64_t ticket, int64_t timeout_us);
+/* Submit, start and completion times of a ticket in nanoseconds of a
+ * monotonic host clock (start and completion 0 until they happen). */
+int arbgpu_ticket_times(arbgpu_ctx *ctx, uint64_t ticket, int64_t times_ns[3]);
+
 /* Per-kernel timing with HIP events recorded on the caller's stream around
  * each launch (for measurement; off by default).  arbgpu_timing(ctx, 1)
  * clears old records and starts recording, 0 stops.  arbgpu_timing_read

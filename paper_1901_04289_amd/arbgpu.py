@@ -54,6 +54,15 @@ class DotJob(ctypes.Structure):
                 ("ystep", c_i64), ("N", c_i64), ("p", c_i64), ("flags", c_u32), ("sub", c_i32)]
 
 
+JOB_DOT, JOB_MATMUL = 1, 2
+
+
+class Job(ctypes.Structure):
+    """One request of the serving loop (a dot or a matrix product)."""
+    _fields_ = [("kind", c_i32), ("dot", DotJob), ("C", OMat), ("A", Mat), ("B", Mat), ("p", c_i64),
+                ("flags", c_u32)]
+
+
 class ArbgpuError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"arbgpu error {code}: {msg}")
@@ -79,6 +88,10 @@ EXPORTS = {
     "arbgpu_batch_tune": (ctypes.c_int, [c_p, c_p]),
     "arbgpu_batch_info": (ctypes.c_int, [c_p, ctypes.POINTER(c_i64), ctypes.c_int]),
     "arbgpu_batch_destroy": (None, [c_p]),
+    "arbgpu_serve_config": (ctypes.c_int, [c_p, ctypes.c_int, ctypes.c_size_t]),
+    "arbgpu_submit": (ctypes.c_int, [c_p, ctypes.POINTER(Job), c_i64, ctypes.POINTER(ctypes.c_uint64)]),
+    "arbgpu_poll": (ctypes.c_int, [c_p, ctypes.c_uint64, c_i64]),
+    "arbgpu_ticket_times": (ctypes.c_int, [c_p, ctypes.c_uint64, ctypes.POINTER(c_i64)]),
     "arbgpu_timing": (ctypes.c_int, [c_p, ctypes.c_int]),
     "arbgpu_plan_info": (ctypes.c_int, [c_p, ctypes.POINTER(c_i64), ctypes.c_int]),
     "arbgpu_timing_read": (ctypes.c_int, [c_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -275,6 +288,42 @@ class Context:
         n = min(nb.value, cap)
         return [(bounds[2 * i], bounds[2 * i + 1], kinds[i]) for i in range(n)]
 
+    # -- request loop ------------------------------------------------------
+    def serve_config(self, slots: int = 4, budget: int = 0):
+        self._check(self.lib.arbgpu_serve_config(self.h, slots, budget))
+
+    def submit(self, jobs: Sequence[Job], check: bool = True):
+        """Queue jobs; returns their tickets (or (rc, []) with check=False)."""
+        arr = (Job * max(1, len(jobs)))(*jobs)
+        t = (ctypes.c_uint64 * max(1, len(jobs)))()
+        rc = self.lib.arbgpu_submit(self.h, arr, len(jobs), t)
+        if not check:
+            return rc, list(t)[:len(jobs)] if rc == OK else []
+        self._check(rc)
+        return list(t)[:len(jobs)]
+
+    def poll(self, ticket: int, timeout_us: int = 0) -> int:
+        return self.lib.arbgpu_poll(self.h, ticket, timeout_us)
+
+    def wait(self, ticket: int, timeout_s: float = 120.0):
+        """Polls until done; raises on the job's error or after timeout_s."""
+        import time
+        end = time.monotonic() + timeout_s
+        while True:
+            rc = self.poll(ticket, 100000)
+            if rc == OK:
+                return
+            if rc != NOTREADY:
+                self._check(rc)
+            if time.monotonic() > end:
+                raise TimeoutError(f"ticket {ticket} not done after {timeout_s} s")
+
+    def ticket_times(self, ticket: int):
+        """(submit, start, end) in ns of a monotonic host clock."""
+        buf = (c_i64 * 3)()
+        self._check(self.lib.arbgpu_ticket_times(self.h, ticket, buf))
+        return tuple(buf)
+
     # -- convenience -------------------------------------------------------
     def plan_blocks(self, A: DeviceArray, B: DeviceArray, M: int, N: int, K: int, p: int, flags: int = 0,
                     Ai: Optional[DeviceArray] = None, Bi: Optional[DeviceArray] = None, stream=None):
@@ -347,4 +396,18 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def matmul_job(C: OMat, A: Mat, B: Mat, p: int, flags: int = 0) -> Job:
+    j = Job()
+    j.kind = JOB_MATMUL
+    j.C, j.A, j.B, j.p, j.flags = C, A, B, p, flags
+    return j
+
+
+def dot_request(job: DotJob) -> Job:
+    j = Job()
+    j.kind = JOB_DOT
+    j.dot = job
+    return j
 

@@ -18,6 +18,7 @@
 using namespace arbgpu_impl;
 
 arbgpu_ctx::~arbgpu_ctx() {
+  if (server) arbgpu_impl::server_delete(server);
   for (auto &t : timed) {
     (void)hipEventDestroy(t.start);
     (void)hipEventDestroy(t.stop);
@@ -366,10 +367,12 @@ static int validate_mat(arbgpu_ctx *ctx, const arbgpu_mat *m, int nparts, const 
   return ARBGPU_OK;
 }
 
-int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p,
-                   uint32_t flags, arbgpu_stream stream) {
-  if (!ctx) return ARBGPU_EINVAL;
-  std::lock_guard<std::mutex> lk(ctx->mu);
+}  // extern "C"
+
+namespace arbgpu_impl {
+
+int mat_mul_check(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p,
+                  uint32_t flags) {
   const bool approx = flags & ARBGPU_APPROX;
   const bool cplx = flags & ARBGPU_COMPLEX;
   const int nparts = cplx ? 2 : 1;
@@ -393,19 +396,39 @@ int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
     if (C->rows > 0 && C->cols > 0 && !range_ok(lo, hi, cparts[q]->ld))
       return fail(ctx, ARBGPU_EINVAL, "C: element index out of range");
   }
+  return ARBGPU_OK;
+}
+
+}  // namespace arbgpu_impl
+
+extern "C" {
+
+int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p,
+                   uint32_t flags, arbgpu_stream stream) {
+  if (!ctx) return ARBGPU_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  int rc = mat_mul_check(ctx, C, A, B, p, flags);
+  if (rc) return rc;
   if (C->rows == 0 || C->cols == 0) return ARBGPU_OK;
+  if ((rc = bind_device(ctx))) return rc;
+  const bool approx = flags & ARBGPU_APPROX;
+  const bool cplx = flags & ARBGPU_COMPLEX;
+  const int nparts = cplx ? 2 : 1;
+  const arbgpu_out *cparts[2] = {&C->re, &C->im};
   int cap = A->re.cap > B->re.cap ? A->re.cap : B->re.cap;
   if (cplx) {
     cap = A->im.cap > cap ? A->im.cap : cap;
     cap = B->im.cap > cap ? B->im.cap : cap;
   }
-  if ((rc = bind_device(ctx))) return rc;
+  LimbShape sh;
+  const bool limb_ok = limb_shape_for((int)p, A->cols * nparts, cap, &sh);
   if (!(flags & ARBGPU_ALGO_LIMB)) {
-    rc = sliced_mat_mul(ctx, C, A, B, p, flags, to_stream(stream), (flags & ARBGPU_ALGO_SLICED) != 0);
+    // the scaled-integer path, forced when asked for or when the limb
+    // kernel's window cannot hold the precision
+    rc = sliced_mat_mul(ctx, C, A, B, p, flags, to_stream(stream), (flags & ARBGPU_ALGO_SLICED) != 0 || !limb_ok);
     if (rc != kNotApplicable) return rc;
   }
-  LimbShape sh;
-  if (!limb_shape_for((int)p, A->cols * nparts, cap, &sh))
+  if (!limb_ok)
     return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul: precision %lld above the limb kernel's window", (long long)p);
   for (int q = 0; q < nparts; ++q) {
     MmParams prm;

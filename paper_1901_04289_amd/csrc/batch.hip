@@ -32,16 +32,112 @@ std::string tune_key(LimbShape sh) {
   return "dot_batch:" + std::to_string(sh.ns) + "x" + std::to_string(sh.na);
 }
 
+struct ShapeRun {
+  LimbShape sh;
+  int64_t begin, count;   // slice of the order array
+  int waves;              // per compute unit
+};
+
+// Validates the jobs and builds the tasks, their order (by shape, longest
+// first) and the per-shape runs; sets the context error on a bad job.
+int plan_batch(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, const char *who,
+               std::vector<DotParams> &tasks, std::vector<int32_t> &order, std::vector<ShapeRun> &runs) {
+  std::vector<LimbShape> shape_of;
+  std::vector<double> cost;
+  tasks.clear();
+  runs.clear();
+  tasks.reserve((size_t)njobs * 2);
+  for (int64_t i = 0; i < njobs; ++i) {
+    DotParams prm[2];
+    int nt = 0;
+    LimbShape sh;
+    const int rc = dot_tasks(ctx, jobs[i], who, prm, &nt, &sh);
+    if (rc) {
+      ctx->err = "job " + std::to_string(i) + ": " + ctx->err;
+      return rc;
+    }
+    int cap = 1;
+    for (int q = 0; q < nt; ++q) cap = std::max(cap, std::max(jobs[i].x[q].cap, jobs[i].y[q].cap));
+    const double w = (double)std::min(cap, sh.na);
+    for (int q = 0; q < nt; ++q) {
+      tasks.push_back(prm[q]);
+      shape_of.push_back(sh);
+      cost.push_back((double)(prm[q].N * prm[q].ct.ncomp + 1) * w * w);
+    }
+  }
+  order.resize(tasks.size());
+  for (size_t t = 0; t < tasks.size(); ++t) order[t] = (int32_t)t;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    const LimbShape &a = shape_of[x], &c = shape_of[y];
+    if (a.ns != c.ns) return a.ns > c.ns;
+    if (a.na != c.na) return a.na > c.na;
+    return cost[x] > cost[y];
+  });
+  for (size_t t = 0; t < order.size(); ++t) {
+    const LimbShape &sh = shape_of[order[t]];
+    if (runs.empty() || runs.back().sh.ns != sh.ns || runs.back().sh.na != sh.na) {
+      auto it = ctx->tune.find(tune_key(sh));
+      runs.push_back({sh, (int64_t)t, 0, it != ctx->tune.end() ? it->second : kDefaultWaves});
+    }
+    runs.back().count++;
+  }
+  return ARBGPU_OK;
+}
+
+unsigned blocks_for(int64_t count, int waves, int num_cu) {
+  const int64_t by_work = (count + 3) / 4;
+  const int64_t by_width = std::max<int64_t>(1, (int64_t)num_cu * waves / 4);
+  return (unsigned)std::max<int64_t>(1, std::min(by_work, by_width));
+}
+
+int device_cus(int device) {
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0) return ncu;
+  return 256;
+}
+
 }  // namespace
+
+namespace arbgpu_impl {
+
+int dot_batch_run(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, hipStream_t s) {
+  std::vector<DotParams> tasks;
+  std::vector<int32_t> order;
+  std::vector<ShapeRun> runs;
+  int rc = plan_batch(ctx, jobs, njobs, "dot batch", tasks, order, runs);
+  if (rc || tasks.empty()) return rc;
+  const size_t tb = sizeof(DotParams) * tasks.size(), ob = sizeof(int32_t) * order.size();
+  char *w = (char *)ws_get(ctx, WS_BATCH, tb + ob + sizeof(int32_t) * runs.size() + 64);
+  if (!w) return ARBGPU_ENOMEM;
+  DotParams *d_tasks = (DotParams *)w;
+  int32_t *d_order = (int32_t *)(w + tb);
+  int32_t *d_ctr = d_order + order.size();
+  hipError_t e = hipMemcpyAsync(d_tasks, tasks.data(), tb, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_order, order.data(), ob, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    int n = (int)runs.size();
+    void *rargs[] = {&d_ctr, &n};
+    e = hipLaunchKernel(reinterpret_cast<const void *>(&batch_reset_kernel), dim3((unsigned)((n + 255) / 256)),
+                        dim3(256), rargs, 0, s);
+  }
+  const int ncu = device_cus(ctx->device);
+  for (size_t k = 0; k < runs.size() && e == hipSuccess; ++k) {
+    BatchShapeParams bp{d_tasks, d_order + runs[k].begin, runs[k].count, d_ctr + k};
+    void *args[] = {&bp};
+    e = hipLaunchKernel(dot_batch_kernel(runs[k].sh), dim3(blocks_for(runs[k].count, runs[k].waves, ncu)),
+                        dim3(256), args, 0, s);
+  }
+  // the host task list must outlive its asynchronous upload
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "dot batch: %s", hipGetErrorString(e));
+  return ARBGPU_OK;
+}
+
+}  // namespace arbgpu_impl
 
 struct arbgpu_batch {
   arbgpu_ctx *ctx = nullptr;
   int64_t njobs = 0;
-  struct ShapeRun {
-    LimbShape sh;
-    int64_t begin, count;   // slice of the order array
-    int waves;              // per compute unit
-  };
   std::vector<ShapeRun> runs;
   int64_t ntasks = 0;
   DotParams *d_tasks = nullptr;
@@ -59,11 +155,7 @@ struct arbgpu_batch {
     if (d_counters) (void)hipFree(d_counters);
   }
 
-  unsigned blocks_for(const ShapeRun &r, int waves) const {
-    const int64_t by_work = (r.count + 3) / 4;
-    const int64_t by_width = std::max<int64_t>(1, (int64_t)num_cu * waves / 4);
-    return (unsigned)std::max<int64_t>(1, std::min(by_work, by_width));
-  }
+  unsigned blocks_for(const ShapeRun &r, int waves) const { return ::blocks_for(r.count, waves, num_cu); }
 
   BatchShapeParams params(size_t k) const {
     return BatchShapeParams{d_tasks, d_order + runs[k].begin, runs[k].count, d_counters + k};
@@ -116,27 +208,10 @@ int arbgpu_batch_create(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njo
   if (njobs < 0 || (njobs > 0 && !jobs)) return set_error(ctx, ARBGPU_EINVAL, "arbgpu_batch_create: bad job list");
   if (njobs > (int64_t)1 << 29) return set_error(ctx, ARBGPU_EINVAL, "arbgpu_batch_create: too many jobs");
   std::vector<DotParams> tasks;
-  std::vector<LimbShape> shape_of;
-  std::vector<double> cost;
-  tasks.reserve((size_t)njobs * 2);
-  for (int64_t i = 0; i < njobs; ++i) {
-    DotParams prm[2];
-    int nt = 0;
-    LimbShape sh;
-    const int rc = dot_tasks(ctx, jobs[i], "arbgpu_batch_create", prm, &nt, &sh);
-    if (rc) {
-      ctx->err = "job " + std::to_string(i) + ": " + ctx->err;
-      return rc;
-    }
-    int cap = 1;
-    for (int q = 0; q < nt; ++q) cap = std::max(cap, std::max(jobs[i].x[q].cap, jobs[i].y[q].cap));
-    const double w = (double)std::min(cap, sh.na);
-    for (int q = 0; q < nt; ++q) {
-      tasks.push_back(prm[q]);
-      shape_of.push_back(sh);
-      cost.push_back((double)(prm[q].N * prm[q].ct.ncomp + 1) * w * w);
-    }
-  }
+  std::vector<int32_t> order;
+  std::vector<ShapeRun> runs;
+  const int prc = plan_batch(ctx, jobs, njobs, "arbgpu_batch_create", tasks, order, runs);
+  if (prc) return prc;
   if (ctx->device < 0) return set_error(ctx, ARBGPU_EDEVICE, "host-only context cannot launch work");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
@@ -145,26 +220,8 @@ int arbgpu_batch_create(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njo
   b->ctx = ctx;
   b->njobs = njobs;
   b->ntasks = (int64_t)tasks.size();
-  int ncu = 0;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && ncu > 0)
-    b->num_cu = ncu;
-  // group by shape, longest first inside a shape
-  std::vector<int32_t> order(tasks.size());
-  for (size_t t = 0; t < tasks.size(); ++t) order[t] = (int32_t)t;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-    const LimbShape &a = shape_of[x], &c = shape_of[y];
-    if (a.ns != c.ns) return a.ns > c.ns;
-    if (a.na != c.na) return a.na > c.na;
-    return cost[x] > cost[y];
-  });
-  for (size_t t = 0; t < order.size(); ++t) {
-    const LimbShape &sh = shape_of[order[t]];
-    if (b->runs.empty() || b->runs.back().sh.ns != sh.ns || b->runs.back().sh.na != sh.na) {
-      auto it = ctx->tune.find(tune_key(sh));
-      b->runs.push_back({sh, (int64_t)t, 0, it != ctx->tune.end() ? it->second : kDefaultWaves});
-    }
-    b->runs.back().count++;
-  }
+  b->num_cu = device_cus(ctx->device);
+  b->runs = runs;
   const size_t tb = sizeof(DotParams) * std::max<size_t>(1, tasks.size());
   const size_t ob = sizeof(int32_t) * std::max<size_t>(1, order.size());
   const size_t cb = sizeof(int32_t) * std::max<size_t>(1, b->runs.size());

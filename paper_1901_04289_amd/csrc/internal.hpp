@@ -12,6 +12,11 @@
 
 #include "../../include/arbgpu.h"
 
+namespace arbgpu_impl {
+struct Server;                  // request loop (serve.hip)
+void server_delete(Server *s);
+}  // namespace arbgpu_impl
+
 // Context: one device, one error string, a grow-only device workspace.
 struct arbgpu_ctx {
   int device;            // -1: host-only
@@ -37,6 +42,7 @@ struct arbgpu_ctx {
   // the file they are loaded from and saved to (may be empty)
   std::map<std::string, int> tune;
   std::string tune_path;
+  arbgpu_impl::Server *server = nullptr;   // started by the first submit
   ~arbgpu_ctx();
 };
 
@@ -45,7 +51,7 @@ namespace arbgpu_impl {
 // Workspace slots (each holds one growing device buffer).
 enum WsSlot {
   WS_STATS = 0, WS_PLANES_A, WS_PLANES_B, WS_PLANES_B2, WS_D, WS_T, WS_TABLES,
-  WS_RAD_A, WS_RAD_B, WS_RAD_OUT, WS_PLAN, WS_BLOCKS, WS_COUNT
+  WS_RAD_A, WS_RAD_B, WS_RAD_OUT, WS_PLAN, WS_BLOCKS, WS_BATCH, WS_COUNT
 };
 
 // Device buffer of at least `bytes` in workspace slot `slot` (nullptr and
@@ -154,6 +160,19 @@ struct BatchShapeParams {
 template <int NS, int NA>
 const void *dot_batch_kernel_shape();
 const void *dot_batch_kernel(LimbShape sh);   // kernel taking (BatchShapeParams)
+
+// One-shot batch of dot jobs on stream s (validated here; the task list is
+// staged in the context workspace; synchronizes s).
+int dot_batch_run(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, hipStream_t s);
+
+// Validates the arguments of a matrix product (EINVAL with the context
+// error set on a bad argument).
+int mat_mul_check(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p,
+                  uint32_t flags);
+
+// Upper estimate of the workspace bytes a matrix product takes on the
+// scaled-integer path (for admission by HBM footprint).
+size_t mat_mul_footprint(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags);
 
 // Validates one dot job and builds its kernel tasks (one per output part)
 // and kernel shape; sets the context error and returns EINVAL on a bad job.

@@ -259,6 +259,26 @@ constexpr int kBasecase = 30;   // Algorithm 2: shorter ranges use dot products
 
 }  // namespace
 
+size_t mat_mul_footprint(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags) {
+  const bool cplx = flags & ARBGPU_COMPLEX;
+  const int64_t parts = cplx ? 2 : 1;
+  const int64_t M = A->rows, N = B->cols, K = A->cols;
+  const int64_t Kt = cplx ? 2 * K : K;
+  const int64_t Kp = round_up(std::max<int64_t>(Kt, 1), kKStep);
+  const int64_t Mp = round_up(std::max<int64_t>(M, 1), kTile), Np = round_up(std::max<int64_t>(N, 1), kTile);
+  int cap = std::max(A->re.cap, B->re.cap);
+  if (cplx) cap = std::max(cap, std::max(A->im.cap, B->im.cap));
+  const int64_t L = std::min<int64_t>(kMaxSlices, slices_for(height_bound(p, 32 * cap, 32 * cap)));
+  const int64_t pmax = std::max<int64_t>(1, ((int64_t)0x7FFFFFFF) / (Kp << 14));
+  const int64_t nslots = (2 * L - 1) + L * L / pmax;
+  const int64_t mn = M * N;
+  int64_t bytes = L * Mp * Kp + L * Np * Kp * parts;          // digit planes
+  bytes += 4 * nslots * mn + 4 * (int64_t)t_limbs((int)L, (int)L) * mn;   // partial planes, T
+  bytes += 4 * (2 * M + 2 * N + 8);                            // statistics
+  bytes += 16 * (M + N) * Kt + 8 * (M + N) + 12 * parts * mn;  // radius products
+  return (size_t)bytes + 65536;
+}
+
 int plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, bool cplx, int hmax, hipStream_t s,
                 std::vector<BlockSpan> &out) {
   const int64_t M = A->rows, N = B->cols, K = A->cols;

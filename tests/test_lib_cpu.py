@@ -133,6 +133,29 @@ def test_host_only_context_validates_batch(hctx, lib):
     assert lib.arbgpu_batch_create(hctx.h, (arbgpu.DotJob * 1)(badf), 1, ctypes.byref(h)) == arbgpu.EINVAL
 
 
+def test_host_only_context_validates_submit(hctx, lib):
+    def mat(rows, cols, ld=100):
+        return arbgpu.Mat(_arr(ld), _arr(ld), rows, cols, 0, cols, 1)
+
+    def omat(rows, cols, ld=100, cap=4, rad=True):
+        return arbgpu.OMat(_out(ld, cap, rad), _out(ld, cap, rad), rows, cols, 0, cols, 1)
+
+    good = arbgpu.matmul_job(omat(3, 4), mat(3, 5), mat(5, 4), 100)
+    bad = arbgpu.matmul_job(omat(3, 4), mat(3, 5), mat(6, 4), 100)
+    dot = arbgpu.dot_request(arbgpu.dot_job([_out()], 0, [_arr()], 0, 1, [_arr()], 0, 1, 5, 64))
+    weird = arbgpu.Job()
+    weird.kind = 9
+    rc, t = hctx.submit([good, dot, bad], check=False)
+    assert rc == arbgpu.EINVAL and "job 2" in hctx.last_error() and t == []
+    rc, _ = hctx.submit([weird], check=False)
+    assert rc == arbgpu.EINVAL
+    # valid jobs reach the loop start, which needs a device
+    rc, _ = hctx.submit([good, dot], check=False)
+    assert rc == arbgpu.EDEVICE
+    assert hctx.poll(1) == arbgpu.EINVAL
+    assert lib.arbgpu_serve_config(hctx.h, 0, 0) == arbgpu.EINVAL
+
+
 def test_init_rejects_bad_device(lib):
     h = ctypes.c_void_p()
     assert lib.arbgpu_init(ctypes.byref(h), -2, 0, None) == arbgpu.EINVAL
