@@ -9,6 +9,15 @@ oracle on the host cores.
 Prints one JSON line.  A step is one arbgpu_mat_mul call (statistics,
 slicing, MFMA product, recombination and rounding) with the operands
 already resident in device memory.
+
+Two more workloads are measured and reported beside the headline number:
+  dot_batch  10^4 complex ball dot products (lengths log-uniform in
+             [4, 4096], p log-uniform in [64, 1024], operand precisions in
+             [p/2, 2p]) as one resident graph launch after autotuning;
+  serving    a Poisson stream (200 requests/s) of complex ball matrix
+             products, N log-uniform in [16, 1024], p in {128, ..., 2048},
+             over device-resident operands through arbgpu_submit/poll:
+             p50/p99 latency from arrival to completion and throughput.
 """
 
 from __future__ import annotations
@@ -29,6 +38,21 @@ from paper_1901_04289_amd import gen  # noqa: E402
 
 METRIC = "p-bit MACs/s, sliced-MFMA vs plain limb kernel, N=2048 p=512; p99 latency"
 PEAK_INT8_TOPS = 5000.0   # MI355X dense INT8 MFMA, 5.0 POP/s
+
+# HBM bytes per launch of mfma_diag_kernel at N = 2048, p = 512, from the
+# FETCH_SIZE (x2, copy-calibrated) and WRITE_SIZE (x1) counter runs in
+# profiles/mfma_diag_kernel_matmul2048_p512.txt; valid only for the kernel
+# source they were taken on (sha256 prefix of csrc/sliced.hip).
+MFMA_TRAFFIC_BYTES = (27.87e6 * 2 + 2228224) * 1024
+MFMA_TRAFFIC_SRC = "6534c66661bc206f"
+
+
+def _mfma_traffic(n):
+    import hashlib
+    src = os.path.join(ROOT, "paper_1901_04289_amd", "csrc", "sliced.hip")
+    with open(src, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()[:16]
+    return MFMA_TRAFFIC_BYTES if (h == MFMA_TRAFFIC_SRC and n == 2048) else None
 
 
 # ---------------------------------------------------------------------------
@@ -87,6 +111,117 @@ def cpu_baseline(w, seconds: float, cores: int):
 # GPU
 # ---------------------------------------------------------------------------
 
+def bench_dot_batch(arbgpu, torch, log, launches: int):
+    """The 10^4-dot complex ball batch as one graph launch (tuned first)."""
+    t0 = time.time()
+    w = gen.config3()
+    terms = int(w.lengths.sum())
+    log(f"[bench] dot batch: {len(w.lengths)} dots, {terms} terms, generated in {time.time() - t0:.1f}s")
+    ctx = arbgpu.Context(0)
+    dev = [arbgpu.DeviceArray.from_host(o) for o in (w.x_re, w.x_im, w.y_re, w.y_im)]
+    del w.x_re, w.x_im, w.y_re, w.y_im
+    outs = [arbgpu.DeviceOut.empty(len(w.lengths), 1024), arbgpu.DeviceOut.empty(len(w.lengths), 1024)]
+    jobs = [arbgpu.dot_job([outs[0].out(), outs[1].out()], i, [dev[0].arr(), dev[1].arr()], int(w.offsets[i]), 1,
+                           [dev[2].arr(), dev[3].arr()], int(w.offsets[i]), 1, int(w.lengths[i]), int(w.precs[i]),
+                           arbgpu.COMPLEX) for i in range(len(w.lengths))]
+    b = arbgpu.Batch(ctx, jobs)
+    stream = torch.cuda.current_stream()
+    b.launch(stream)
+    torch.cuda.synchronize()
+    b.tune(stream)
+    b.launch(stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(launches):
+        b.launch(stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / launches
+    info = b.info()
+    b.close()
+    ctx.close()
+    cmacs = terms / (ms / 1e3)
+    log(f"[bench] dot batch {ms:.2f} ms/launch, {cmacs:.3e} complex MACs/s")
+    return {"dots": len(w.lengths), "terms": terms, "launches": launches, "ms_per_launch": ms,
+            "complex_macs_per_s": cmacs, "real_macs_per_s": 4 * cmacs,
+            "mean_p": float(np.mean(w.precs)), "shapes": info["shapes"]}
+
+
+def bench_serving(arbgpu, torch, log, nreq: int, rate: float, slots: int):
+    """Open-loop Poisson arrivals of complex ball matrix products; operands
+    are taken from resident 1024x1024 pools (the top-left n x n block, row
+    stride 1024), outputs from a ring of 8 buffers per precision."""
+    reqs = gen.config4_requests(count=nreq, rate=rate)
+    ps = sorted({r.p for r in reqs})
+    t0 = time.time()
+    pools, rings = {}, {}
+    for p in ps:
+        rng = gen.rng_for(4, 500 + p)
+        pools[p] = [arbgpu.DeviceArray.from_host(o) for o in gen.config4_operands(rng, 1024, p)]
+        rings[p] = [[arbgpu.DeviceOut.empty(1024 * 1024, p), arbgpu.DeviceOut.empty(1024 * 1024, p)]
+                    for _ in range(8)]
+    torch.cuda.synchronize()
+    log(f"[bench] serving: {nreq} requests at {rate}/s, pools ready in {time.time() - t0:.1f}s")
+    ctx = arbgpu.Context(0)
+    ctx.serve_config(slots=slots)
+    used = {p: 0 for p in ps}
+
+    def job(r):
+        P = pools[r.p]
+        ring = rings[r.p][used[r.p] % 8]
+        used[r.p] += 1
+        A = arbgpu.Mat(P[0].arr(), P[1].arr(), r.n, r.n, 0, 1024, 1)
+        B = arbgpu.Mat(P[2].arr(), P[3].arr(), r.n, r.n, 0, 1024, 1)
+        C = arbgpu.OMat(ring[0].out(), ring[1].out(), r.n, r.n, 0, 1024, 1)
+        return arbgpu.matmul_job(C, A, B, r.p, arbgpu.COMPLEX)
+
+    # warm the slots' workspaces and kernels with one request of each precision
+    warm = ctx.submit([job(gen.Request(0.0, 256, p)) for p in ps])
+    for t in warm:
+        ctx.wait(t, 600.0)
+    tickets, arrivals = [], []
+    start = time.monotonic_ns()
+    retries = 0
+    for k, r in enumerate(reqs):
+        due = start + int(r.arrival_s * 1e9)
+        now = time.monotonic_ns()
+        if due > now:
+            time.sleep((due - now) / 1e9)
+        jb = job(r)
+        while True:
+            rc, t = ctx.submit([jb], check=False)
+            if rc == arbgpu.OK:
+                break
+            if rc != arbgpu.EAGAIN:
+                raise RuntimeError(f"submit failed: {rc} {ctx.last_error()}")
+            retries += 1
+            time.sleep(0.001)
+        tickets.append(t[0])
+        arrivals.append(due)
+        if k % 100 == 99:
+            log(f"[bench] serving: {k + 1} submitted")
+    last_submit = time.monotonic_ns()
+    for k, t in enumerate(tickets):
+        ctx.wait(t, 1200.0)
+        if k % 100 == 99:
+            log(f"[bench] serving: {k + 1} done")
+    end = max(ctx.ticket_times(t)[2] for t in tickets)
+    lat = np.array([(ctx.ticket_times(t)[2] - a) / 1e6 for t, a in zip(tickets, arrivals)])
+    wait = np.array([(ctx.ticket_times(t)[1] - a) / 1e6 for t, a in zip(tickets, arrivals)])
+    ctx.close()
+    cmacs = float(sum(r.n ** 3 for r in reqs))
+    span = (end - start) / 1e9
+    log(f"[bench] serving p50 {np.percentile(lat, 50):.1f} ms, p99 {np.percentile(lat, 99):.1f} ms, "
+        f"span {span:.1f}s for {reqs[-1].arrival_s:.1f}s of arrivals")
+    return {"requests": nreq, "rate_per_s": rate, "slots": slots,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "max": float(lat.max())},
+            "queue_wait_ms": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))},
+            "complex_macs_per_s": cmacs / span, "real_macs_per_s": 4 * cmacs / span,
+            "arrival_span_s": reqs[-1].arrival_s, "completion_span_s": span,
+            "submit_span_s": (last_submit - start) / 1e9, "eagain_retries": retries}
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +232,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--batch-launches", type=int, default=5, help="0 skips the dot batch")
+    ap.add_argument("--serve-requests", type=int, default=600, help="0 skips the serving loop")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also copy a buffer of this many MiB once (reference kernel for HBM counters)")
     a = ap.parse_args()
@@ -180,7 +319,7 @@ def main():
         "kernels_ms_per_step": {k: v[0] / max(v[1], 1) * (v[1] / a.steps) for k, v in kern.items()},
         "slice_plan": plan,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_INT8_TOPS, "traffic": None,
+                     "frac": achieved / PEAK_INT8_TOPS, "traffic": _mfma_traffic(a.n),
                      "kernel": "mfma_diag_kernel", "ops_per_launch": int8_ops,
                      "avg_launch_ms": mfma_avg_s * 1e3},
         "cpu_baseline": cpu,
@@ -202,7 +341,17 @@ def main():
                              "steps": a.plain_steps, "bit_identical_midpoints": same}
         out["speedup_vs_plain"] = ms_plain / ms_step
         log(f"[bench] plain {ms_plain:.1f} ms/step, identical midpoints: {same}")
+        del Cl
     ctx.close()
+    del C, dA, dB
+    torch.cuda.empty_cache()
+    if a.batch_launches:
+        out["dot_batch"] = bench_dot_batch(arbgpu, torch, log, a.batch_launches)
+        torch.cuda.empty_cache()
+    if a.serve_requests:
+        out["serving"] = bench_serving(arbgpu, torch, log, a.serve_requests, a.serve_rate, a.serve_slots)
+        out["latency_ms"]["serving_p50"] = out["serving"]["latency_ms"]["p50"]
+        out["latency_ms"]["serving_p99"] = out["serving"]["latency_ms"]["p99"]
     print(json.dumps(out), flush=True)
 
 
