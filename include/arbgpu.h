@@ -198,7 +198,8 @@ int arbgpu_batch_launch(arbgpu_batch *batch, arbgpu_stream stream);
  * rebuilds the graph.  Synchronizes `stream`. */
 int arbgpu_batch_tune(arbgpu_batch *batch, arbgpu_stream stream);
 /* Writes up to n values {jobs, kernel tasks (one per output part), shapes,
- * then per shape (NS, NA, tasks, waves per CU)} to out (host memory). */
+ * then per shape (NS, NA, tasks, waves per CU, microseconds of the shape
+ * alone when tuned, else 0)} to out (host memory). */
 int arbgpu_batch_info(arbgpu_batch *batch, int64_t *out, int n);
 void arbgpu_batch_destroy(arbgpu_batch *batch);
 

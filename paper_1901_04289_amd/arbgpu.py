@@ -382,8 +382,8 @@ class Batch:
         buf = (c_i64 * 256)()
         self.ctx._check(self.ctx.lib.arbgpu_batch_info(self.h, buf, 256))
         v = list(buf)
-        shapes = [dict(ns=v[3 + 4 * k], na=v[4 + 4 * k], tasks=v[5 + 4 * k], waves=v[6 + 4 * k])
-                  for k in range(min(v[2], 63))]
+        shapes = [dict(ns=v[3 + 5 * k], na=v[4 + 5 * k], tasks=v[5 + 5 * k], waves=v[6 + 5 * k],
+                       tuned_us=v[7 + 5 * k]) for k in range(min(v[2], 50))]
         return dict(jobs=v[0], tasks=v[1], shapes=shapes)
 
     def close(self):

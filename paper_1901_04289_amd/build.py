@@ -39,8 +39,14 @@ def limb_shapes():
     return [(int(a), int(b)) for a, b in re.findall(r"X\((\d+),\s*(\d+)\)", txt)]
 
 
+# The limb kernels keep whole multi-limb products in registers: their fully
+# unrolled multiply chains exceed the default size limit of requested unrolls.
+LIMB_FLAGS = ["-mllvm", "-pragma-unroll-threshold=200000"]
+
+
 def _compile(src: str, obj: str, defines=()):
-    cmd = [HIPCC] + CFLAGS + [f"-D{d}" for d in defines] + ["-c", src, "-o", obj]
+    extra = LIMB_FLAGS if defines else []
+    cmd = [HIPCC] + CFLAGS + extra + [f"-D{d}" for d in defines] + ["-c", src, "-o", obj]
     t = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

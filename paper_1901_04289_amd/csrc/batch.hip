@@ -36,6 +36,7 @@ struct ShapeRun {
   LimbShape sh;
   int64_t begin, count;   // slice of the order array
   int waves;              // per compute unit
+  float tuned_ms;         // time of this shape alone at `waves` (0: not tuned)
 };
 
 // Validates the jobs and builds the tasks, their order (by shape, longest
@@ -77,7 +78,7 @@ int plan_batch(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, const
     const LimbShape &sh = shape_of[order[t]];
     if (runs.empty() || runs.back().sh.ns != sh.ns || runs.back().sh.na != sh.na) {
       auto it = ctx->tune.find(tune_key(sh));
-      runs.push_back({sh, (int64_t)t, 0, it != ctx->tune.end() ? it->second : kDefaultWaves});
+      runs.push_back({sh, (int64_t)t, 0, it != ctx->tune.end() ? it->second : kDefaultWaves, 0.f});
     }
     runs.back().count++;
   }
@@ -299,6 +300,7 @@ int arbgpu_batch_tune(arbgpu_batch *b, arbgpu_stream stream) {
       }
     }
     b->runs[k].waves = best_w;
+    b->runs[k].tuned_ms = best;
     ctx->tune[tune_key(b->runs[k].sh)] = best_w;
   }
   if (t0) (void)hipEventDestroy(t0);
@@ -316,6 +318,7 @@ int arbgpu_batch_info(arbgpu_batch *b, int64_t *out, int n) {
     v.push_back(r.sh.na);
     v.push_back(r.count);
     v.push_back(r.waves);
+    v.push_back((int64_t)(r.tuned_ms * 1000.f));
   }
   for (int i = 0; i < n; ++i) out[i] = i < (int)v.size() ? v[i] : 0;
   return ARBGPU_OK;

@@ -350,7 +350,7 @@ namespace arb {
 // An operand whose limbs stay in memory; any length.  Used by the exact
 // fallback, which must never truncate an operand.
 struct SOpnd {
-  const uint32_t *l;   // limb planes, most significant first
+  const ARB_GLOBAL uint32_t *l;   // limb planes, most significant first
   int64_t ld;          // plane distance
   int64_t idx;         // element index
   int n;

@@ -24,28 +24,39 @@ using namespace arb;
 
 namespace arbgpu_impl {
 
+// The arrays behind arbgpu_arr / arbgpu_out live in device global memory.
+template <class T>
+__device__ __forceinline__ const ARB_GLOBAL T *gp(const T *p) {
+  return (const ARB_GLOBAL T *)p;
+}
+template <class T>
+__device__ __forceinline__ ARB_GLOBAL T *gpw(T *p) {
+  return (ARB_GLOBAL T *)p;
+}
+
 template <int NA>
 __device__ __forceinline__ void load_op(const arbgpu_arr &A, int64_t idx, Opnd<NA> &o, bool limbs) {
-  const int32_t nl = A.nls[idx];
+  const int32_t nl = gp(A.nls)[idx];
   int n = nl & 0x7FFFFFFF;
   if (n > A.cap) n = A.cap;
   o.sign = (uint32_t)nl >> 31;
-  o.e = A.exp[idx];
+  o.e = gp(A.exp)[idx];
   const int nt = n < NA ? n : NA;
   o.trunc = n > NA;
   o.n = nt;
+  const ARB_GLOBAL uint32_t *L = gp(A.limbs);
 #pragma unroll
   for (int i = 0; i < NA; ++i)
-    o.l[i] = (limbs && i < nt) ? A.limbs[(int64_t)(nt - 1 - i) * A.ld + idx] : 0u;
+    o.l[i] = (limbs && i < nt) ? L[(int64_t)(nt - 1 - i) * A.ld + idx] : 0u;
   o.rm = 0.0;
   o.re = 0;
   if (A.rad_m) {
-    const double r = A.rad_m[idx];
+    const double r = gp(A.rad_m)[idx];
     if (r != 0.0) {
       if (r > 0.0 && r < INFINITY) {
         int ex;
         o.rm = frexp(r, &ex);
-        o.re = A.rad_e[idx] + ex;
+        o.re = gp(A.rad_e)[idx] + ex;
       } else {
         o.rm = 1.0;
         o.re = kExpLimit;   // reported as out of range
@@ -55,25 +66,25 @@ __device__ __forceinline__ void load_op(const arbgpu_arr &A, int64_t idx, Opnd<N
 }
 
 __device__ __forceinline__ void load_op(const arbgpu_arr &A, int64_t idx, SOpnd &o, bool) {
-  const int32_t nl = A.nls[idx];
+  const int32_t nl = gp(A.nls)[idx];
   int n = nl & 0x7FFFFFFF;
   if (n > A.cap) n = A.cap;
-  o.l = A.limbs;
+  o.l = gp(A.limbs);
   o.ld = A.ld;
   o.idx = idx;
   o.n = n;
   o.trunc = false;
   o.sign = (uint32_t)nl >> 31;
-  o.e = A.exp[idx];
+  o.e = gp(A.exp)[idx];
   o.rm = 0.0;
   o.re = 0;
   if (A.rad_m) {
-    const double r = A.rad_m[idx];
+    const double r = gp(A.rad_m)[idx];
     if (r != 0.0) {
       if (r > 0.0 && r < INFINITY) {
         int ex;
         o.rm = frexp(r, &ex);
-        o.re = A.rad_e[idx] + ex;
+        o.re = gp(A.rad_e)[idx] + ex;
       } else {
         o.rm = 1.0;
         o.re = kExpLimit;
@@ -82,7 +93,7 @@ __device__ __forceinline__ void load_op(const arbgpu_arr &A, int64_t idx, SOpnd 
   }
 }
 
-static __constant__ uint32_t kOneLimb[1] = {0x80000000u};
+static __device__ const uint32_t kOneLimb[1] = {0x80000000u};
 
 template <int NA>
 __device__ __forceinline__ void make_one(Opnd<NA> &o) {
@@ -92,11 +103,12 @@ __device__ __forceinline__ void make_one(Opnd<NA> &o) {
   o.n = 1; o.trunc = false; o.e = 1; o.sign = 0; o.rm = 0.0; o.re = 0;
 }
 __device__ __forceinline__ void make_one(SOpnd &o) {
-  o.l = kOneLimb; o.ld = 1; o.idx = 0;
+  o.l = gp(kOneLimb); o.ld = 1; o.idx = 0;
   o.n = 1; o.trunc = false; o.e = 1; o.sign = 0; o.rm = 0.0; o.re = 0;
 }
 
-__device__ __forceinline__ const arbgpu_arr &pick(const arbgpu_arr *arr, int i) { return i ? arr[1] : arr[0]; }
+template <class AP>
+__device__ __forceinline__ arbgpu_arr pick(const AP &arr, int i) { return i ? arr[1] : arr[0]; }
 
 // Terms of output (i, j) of a matrix product.
 template <class Op>
@@ -116,9 +128,9 @@ struct MmSrc {
 };
 
 // Terms of one dot product.
-template <class Op>
+template <class Op, class PP = const DotParams *>
 struct DotSrc {
-  const DotParams *P;
+  PP P;
   __device__ __forceinline__ int64_t nterms() const { return P->N * P->ct.ncomp; }
   __device__ __forceinline__ bool has_init() const { return P->has_init != 0; }
   __device__ __forceinline__ void term(int64_t t, Op &a, Op &b, uint32_t &neg, bool limbs) const {
@@ -185,12 +197,12 @@ __device__ __forceinline__ void store_out(const arbgpu_out &o, int64_t idx, cons
     const int k = NS - 1 - i;
     if (k < PL) {
       const uint32_t v = r.st.zero ? 0u : r.st.Y[i];
-      o.limbs[(int64_t)k * o.ld + idx] = v;
+      gpw(o.limbs)[(int64_t)k * o.ld + idx] = v;
       if (v) n = k + 1;
     }
   }
-  o.exp[idx] = r.st.zero ? 0 : r.st.r_exp;
-  o.nls[idx] = r.st.zero ? 0 : (int32_t)((uint32_t)n | (r.st.r_sign << 31));
+  gpw(o.exp)[idx] = r.st.zero ? 0 : r.st.r_exp;
+  gpw(o.nls)[idx] = r.st.zero ? 0 : (int32_t)((uint32_t)n | (r.st.r_sign << 31));
   if (!approx) {
     double rm;
     int re;
@@ -200,10 +212,10 @@ __device__ __forceinline__ void store_out(const arbgpu_out &o, int64_t idx, cons
     } else {
       total_radius(r, r.p, rm, re);
     }
-    o.rad_m[idx] = rm;
-    o.rad_e[idx] = re;
+    gpw(o.rad_m)[idx] = rm;
+    gpw(o.rad_e)[idx] = re;
   }
-  if (o.status) o.status[idx] = status;
+  if (o.status) gpw(o.status)[idx] = status;
 }
 
 template <int NS>
@@ -260,13 +272,15 @@ __global__ __launch_bounds__(256) void limb_dot_batch_kernel(BatchShapeParams bp
     if (lane == 0) t = atomicAdd(bp.counter, 1);
     t = __shfl(t, 0, 64);
     if (t >= bp.count) break;   // uniform across the wave
-    const DotParams *prm = bp.tasks + bp.order[t];
+    // uniform task index: the parameters are read with scalar loads
+    const int tu = __builtin_amdgcn_readfirstlane(t);
+    const ARB_GLOBAL DotParams *prm = gp(bp.tasks) + gp(bp.order)[tu];
     DotOut<NS> out;
-    DotSrc<Opnd<NA>> src{prm};
+    DotSrc<Opnd<NA>, const ARB_GLOBAL DotParams *> src{prm};
     run_dot<NS, Opnd<NA>, WaveReducer>(src, prm->p, !prm->approx, out, prm->reduce != 0);
     bool fell_back = false;
     if (out.st.bad) {
-      DotSrc<SOpnd> s2{prm};
+      DotSrc<SOpnd, const ARB_GLOBAL DotParams *> s2{prm};
       run_dot<NS, SOpnd, WaveReducer>(s2, prm->p, !prm->approx, out, prm->reduce != 0);
       fell_back = true;
     }

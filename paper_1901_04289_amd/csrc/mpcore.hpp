@@ -21,9 +21,18 @@
 #ifndef ARB_HD
 #include <hip/hip_runtime.h>
 #define ARB_HD __host__ __device__ __forceinline__
+// Pointers into device global memory: declaring the address space lets
+// the device compiler use global (not flat) memory instructions.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define ARB_GLOBAL __attribute__((address_space(1)))
+#endif
 #endif
 
 namespace arb {
+
+#ifndef ARB_GLOBAL
+#define ARB_GLOBAL
+#endif
 
 ARB_HD int bitlen32(uint32_t x) { return x ? 32 - __builtin_clz(x) : 0; }
 
@@ -174,23 +183,23 @@ ARB_HD void shl_var(uint32_t (&x)[L], uint32_t S) {
 template <int NA>
 ARB_HD void mul_limbs(const uint32_t (&a)[NA], int na, const uint32_t (&b)[NA], int nb,
                       uint32_t (&p)[2 * NA]) {
+  // Limbs of a and b at and above na / nb are zero, so only the rows of a
+  // are skipped; every row is a straight multiply-add chain (a[i] b[j] +
+  // p[i + j] + carry < 2^64), which the compiler unrolls into registers.
+  (void)nb;
 #pragma unroll
   for (int k = 0; k < 2 * NA; ++k) p[k] = 0;
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
     if (i < na) {
-      uint64_t c = 0;
+      uint32_t c = 0;
 #pragma unroll
       for (int j = 0; j < NA; ++j) {
-        uint64_t t;
-        if (j < nb)
-          t = (uint64_t)a[i] * b[j] + p[i + j] + c;
-        else
-          t = (uint64_t)p[i + j] + c;
+        const uint64_t t = (uint64_t)a[i] * b[j] + p[i + j] + c;
         p[i + j] = (uint32_t)t;
-        c = t >> 32;
+        c = (uint32_t)(t >> 32);
       }
-      p[i + NA] = (uint32_t)c;
+      p[i + NA] = c;
     }
   }
 }
