@@ -58,7 +58,11 @@ extern "C" {
                                      step 7(a)): p' = max(2, min(p,
                                      e_max - e_rad + 30)); changes the midpoint */
 #define ARBGPU_ALGO_LIMB    0x10u /* matmul: force the limb-window kernel       */
-#define ARBGPU_ALGO_SLICED  0x20u /* matmul: force the scaled-integer INT8 path */
+#define ARBGPU_ALGO_SLICED  0x20u /* matmul: force the scaled-integer INT8 path
+                                     with base-256 digit slices               */
+#define ARBGPU_ALGO_RNS     0x40u /* matmul: force the scaled-integer INT8 path
+                                     with residues modulo primes < 2^15
+                                     (multimodular, Section 4)             */
 
 /* Per-element status bytes. */
 #define ARBGPU_ST_OK       0   /* result written                                 */
@@ -137,8 +141,9 @@ int arbgpu_dot(arbgpu_ctx *ctx, const arbgpu_out *res, int64_t res_idx,
 /* Matrix product C = A B (Section 4): A is rows x inner, B is inner x cols,
  * C is rows x cols; every entry equals arbgpu_dot of its row and column.
  * ALGO flags choose the limb-window kernel (Algorithm 1 per entry) or the
- * scaled-integer block product on INT8 MFMA (Algorithm 2); neither changes
- * a single output bit.  EINVAL on shape mismatch, p < 2, output cap too
+ * scaled-integer block product on INT8 MFMA (Algorithm 2) with base-256
+ * slices or with residues modulo small primes; none changes a single
+ * output bit.  EINVAL on shape mismatch, p < 2, output cap too
  * small, NULL pointers. */
 int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A,
                    const arbgpu_mat *B, int64_t p, uint32_t flags,
@@ -252,8 +257,9 @@ int arbgpu_timing(arbgpu_ctx *ctx, int enable);
 
 /* Shape of the last scaled-integer product run on this context: writes up
  * to n of {digit planes of A, digit planes of B, int32 partial planes,
- * diagonal groups, inner length, rows, cols, parts} to out (host memory).
- * All zero before the first such product.  EINVAL on NULL. */
+ * diagonal groups, inner length, rows, cols, parts, primes (0 for base-256
+ * slices), digit-plane pairs multiplied} to out (host memory).  All zero
+ * before the first such product.  EINVAL on NULL. */
 int arbgpu_plan_info(arbgpu_ctx *ctx, int64_t *out, int n);
 int arbgpu_timing_read(arbgpu_ctx *ctx, const char *kernel, double *ms_total,
                        int64_t *launches);

@@ -18,7 +18,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libarbgpu.so")
 
 OK, NOTREADY, EINVAL, ERANGE, ENOMEM, EAGAIN, EDEVICE = 0, 1, -1, -2, -3, -4, -5
-APPROX, COMPLEX, REDUCE_PREC, ALGO_LIMB, ALGO_SLICED = 0x01, 0x02, 0x04, 0x10, 0x20
+APPROX, COMPLEX, REDUCE_PREC, ALGO_LIMB, ALGO_SLICED, ALGO_RNS = 0x01, 0x02, 0x04, 0x10, 0x20, 0x40
 ST_OK, ST_REFINED, ST_ERANGE = 0, 1, 2
 
 c_p = ctypes.c_void_p
@@ -244,9 +244,10 @@ class Context:
 
     def plan_info(self):
         """Shape of the last scaled-integer product (dict)."""
-        buf = (c_i64 * 8)()
-        self._check(self.lib.arbgpu_plan_info(self.h, buf, 8))
-        keys = ["slices_a", "slices_b", "partial_planes", "groups", "inner", "rows", "cols", "parts"]
+        buf = (c_i64 * 10)()
+        self._check(self.lib.arbgpu_plan_info(self.h, buf, 10))
+        keys = ["slices_a", "slices_b", "partial_planes", "groups", "inner", "rows", "cols", "parts", "primes",
+                "pairs"]
         return dict(zip(keys, list(buf)))
 
     def timing_read(self, kernel: str):

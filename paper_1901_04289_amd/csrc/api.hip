@@ -293,7 +293,7 @@ int arbgpu_timing(arbgpu_ctx *ctx, int enable) {
 int arbgpu_plan_info(arbgpu_ctx *ctx, int64_t *out, int n) {
   if (!ctx || !out || n < 0) return ARBGPU_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
-  for (int i = 0; i < n; ++i) out[i] = i < 8 ? ctx->last_plan[i] : 0;
+  for (int i = 0; i < n; ++i) out[i] = i < 10 ? ctx->last_plan[i] : 0;
   return ARBGPU_OK;
 }
 
@@ -376,10 +376,10 @@ int mat_mul_check(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, co
   const bool approx = flags & ARBGPU_APPROX;
   const bool cplx = flags & ARBGPU_COMPLEX;
   const int nparts = cplx ? 2 : 1;
-  if (flags & ~(ARBGPU_APPROX | ARBGPU_COMPLEX | ARBGPU_ALGO_LIMB | ARBGPU_ALGO_SLICED))
+  if (flags & ~(ARBGPU_APPROX | ARBGPU_COMPLEX | ARBGPU_ALGO_LIMB | ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS))
     return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul: unknown flags 0x%x", flags);
-  if ((flags & ARBGPU_ALGO_LIMB) && (flags & ARBGPU_ALGO_SLICED))
-    return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul: conflicting ALGO flags");
+  const uint32_t algo = flags & (ARBGPU_ALGO_LIMB | ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS);
+  if (algo & (algo - 1)) return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul: conflicting ALGO flags");
   if (p < 2 || p > (1 << 20)) return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul: p=%lld out of range", (long long)p);
   int rc;
   if ((rc = validate_mat(ctx, A, nparts, "A"))) return rc;
@@ -425,7 +425,8 @@ int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
   if (!(flags & ARBGPU_ALGO_LIMB)) {
     // the scaled-integer path, forced when asked for or when the limb
     // kernel's window cannot hold the precision
-    rc = sliced_mat_mul(ctx, C, A, B, p, flags, to_stream(stream), (flags & ARBGPU_ALGO_SLICED) != 0 || !limb_ok);
+    rc = sliced_mat_mul(ctx, C, A, B, p, flags, to_stream(stream),
+                        (flags & (ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS)) != 0 || !limb_ok);
     if (rc != kNotApplicable) return rc;
   }
   if (!limb_ok)

@@ -37,12 +37,15 @@ struct arbgpu_ctx {
   std::vector<TimedLaunch> timed;
   // shape of the last scaled-integer product: digit planes of A and B,
   // partial planes, diagonal groups, inner length, rows, cols
-  int64_t last_plan[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // {planes of A, planes of B, partial planes, diagonal groups, inner
+  // length, rows, cols, parts, primes (0: base-256 slices), digit pairs}
+  int64_t last_plan[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   // autotuned launch parameters ("dot_batch:NSxNA" -> waves per CU), and
   // the file they are loaded from and saved to (may be empty)
   std::map<std::string, int> tune;
   std::string tune_path;
   arbgpu_impl::Server *server = nullptr;   // started by the first submit
+  int64_t rns_key = -1;                    // residue tables in the workspace (primes, digit words)
   ~arbgpu_ctx();
 };
 
@@ -51,7 +54,7 @@ namespace arbgpu_impl {
 // Workspace slots (each holds one growing device buffer).
 enum WsSlot {
   WS_STATS = 0, WS_PLANES_A, WS_PLANES_B, WS_PLANES_B2, WS_D, WS_T, WS_TABLES,
-  WS_RAD_A, WS_RAD_B, WS_RAD_OUT, WS_PLAN, WS_BLOCKS, WS_BATCH, WS_COUNT
+  WS_RAD_A, WS_RAD_B, WS_RAD_OUT, WS_PLAN, WS_BLOCKS, WS_BATCH, WS_RNS, WS_COUNT
 };
 
 // Device buffer of at least `bytes` in workspace slot `slot` (nullptr and

@@ -19,6 +19,8 @@
 
 #include "engine.hpp"
 #include "sliced.hpp"
+#include "finish.hpp"
+#include "elements.hpp"
 
 using namespace arb;
 
@@ -26,39 +28,6 @@ namespace arbgpu_impl {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
-
-// ---------------------------------------------------------------------------
-// element access
-// ---------------------------------------------------------------------------
-
-// Part and sign of inner index k under an inner layout mode (see SliceParams).
-__device__ __forceinline__ void inner_map(int mode, int64_t len, int64_t k, int &part, int64_t &kk, uint32_t &neg) {
-  part = 0;
-  kk = k;
-  neg = 0;
-  if (mode == 0) return;
-  const bool second = k >= len;
-  kk = second ? k - len : k;
-  if (mode == 1) { part = second ? 1 : 0; neg = second ? 1u : 0u; }
-  else if (mode == 2) { part = second ? 0 : 1; }
-  else { part = second ? 1 : 0; }
-}
-
-__device__ __forceinline__ const arbgpu_arr &part_of(const arbgpu_arr *p, int i) { return i ? p[1] : p[0]; }
-
-// position of the lowest set bit of |m| (INT32_MAX for zero)
-__device__ __forceinline__ int low_bit(const arbgpu_arr &A, int64_t idx, int n, int e) {
-  for (int q = n - 1; q >= 0; --q) {
-    uint32_t v = A.limbs[(int64_t)q * A.ld + idx];
-    if (v) return e - 32 * (q + 1) + __builtin_ctz(v);
-  }
-  return 0x7FFFFFFF;
-}
-
-__device__ __forceinline__ int elem_n(const arbgpu_arr &A, int64_t idx) {
-  int n = A.nls[idx] & 0x7FFFFFFF;
-  return n > A.cap ? A.cap : n;
-}
 
 // ---------------------------------------------------------------------------
 // statistics: top exponent and lowest set bit per line
@@ -151,19 +120,6 @@ __global__ __launch_bounds__(256) void stats_height_kernel(LineStats S, int64_t 
 // ---------------------------------------------------------------------------
 // slicing into balanced base-256 digit planes
 // ---------------------------------------------------------------------------
-
-// Bits [32w - s, 32w - s + 32) of the limb integer M (least significant limb
-// is limb n-1 in memory), zero outside.
-__device__ __forceinline__ uint32_t mant_chunk(const arbgpu_arr &A, int64_t idx, int n, int64_t o) {
-  // o: bit offset into M (may be negative)
-  const int64_t li = o >= 0 ? (o >> 5) : -((31 - o) >> 5);
-  const uint32_t r = (uint32_t)(o - 32 * li);
-  auto get = [&](int64_t i) -> uint32_t {
-    return (i >= 0 && i < n) ? A.limbs[(int64_t)(n - 1 - i) * A.ld + idx] : 0u;
-  };
-  const uint32_t lo = get(li), hi = get(li + 1);
-  return r ? ((lo >> r) | (hi << (32u - r))) : lo;
-}
 
 __global__ __launch_bounds__(256) void slice_kernel(SliceParams P) {
   const int64_t kq = P.k_pad >> 2;
@@ -426,72 +382,11 @@ __global__ __launch_bounds__(256) void recombine_kernel(RecombParams P) {
   T[(int64_t)(nq + 1) * MN] = (uint32_t)((uint64_t)carry >> 32);
   const int nT = nq + 2;
 
-  // magnitude of the two's-complement integer, limb by limb
-  const bool neg = (T[(int64_t)(nT - 1) * MN] >> 31) != 0;
-  int z = nT;   // lowest nonzero limb
-  for (int q = 0; q < nT; ++q)
-    if (T[(int64_t)q * MN]) { z = q; break; }
-  auto mag = [&](int q) -> uint32_t {
-    if (q < 0 || q >= nT) return 0u;
-    const uint32_t v = T[(int64_t)q * MN];
-    if (!neg) return v;
-    return q > z ? ~v : (q == z ? (uint32_t)(0u - v) : 0u);
-  };
-  int qt = -1;
-  for (int q = nT - 1; q >= 0; --q)
-    if (mag(q)) { qt = q; break; }
-  const arbgpu_out &C = P.C;
-  const int64_t oidx = P.c_off + i * P.c_rs + j * P.c_cs;
-  const int PL = (P.p + 31) >> 5;
-  if (qt < 0) {
-    for (int k = 0; k < PL; ++k) C.limbs[(int64_t)k * C.ld + oidx] = 0u;
-    C.exp[oidx] = 0;
-    C.nls[oidx] = 0;
-    if (!P.approx) {
-      double rm = 0.0;
-      int re = 0;
-      if (P.rin_m) { rm = P.rin_m[ij]; re = P.rin_e[ij]; }
-      C.rad_m[oidx] = rm;
-      C.rad_e[oidx] = re;
-    }
-    if (C.status) C.status[oidx] = ARBGPU_ST_OK;
-    return;
-  }
-  const int64_t bl = 32 * (int64_t)qt + (32 - __builtin_clz(mag(qt)));
-  auto bits32 = [&](int64_t lo) -> uint32_t {   // bits [lo, lo + 32) of |T|
-    const int64_t q0 = lo >= 0 ? (lo >> 5) : -((31 - lo) >> 5);
-    const uint32_t r = (uint32_t)(lo - 32 * q0);
-    const uint32_t a = mag((int)q0), b = mag((int)q0 + 1);
-    return r ? ((a >> r) | (b << (32u - r))) : a;
-  };
-  int nout = 0;
-  for (int k = 0; k < PL; ++k) {
-    uint32_t v = bits32(bl - 32 * (int64_t)(k + 1));
-    if (k == PL - 1) v &= 0xFFFFFFFFu << (32 * PL - P.p);
-    C.limbs[(int64_t)k * C.ld + oidx] = v;
-    if (v) nout = k + 1;
-  }
-  // bits of |T| below position bl - p
-  const int64_t cut = bl - P.p;
-  bool inexact = false;
-  if (cut > 0) {
-    const int64_t qc = cut >> 5;
-    for (int64_t q = 0; q < qc && !inexact; ++q) inexact = mag((int)q) != 0;
-    const uint32_t rc = (uint32_t)(cut & 31);
-    if (!inexact && rc) inexact = (mag((int)qc) & ((1u << rc) - 1u)) != 0;
-  }
-  const int em = (int)(bl + P.rowv2[i] + P.colv2[j]);
-  C.exp[oidx] = em;
-  C.nls[oidx] = (int32_t)((uint32_t)nout | (neg ? 0x80000000u : 0u));
-  if (!P.approx) {
-    double rm = 0.0, m0 = 0.0;
-    int re = 0, e0 = 0;
-    if (P.rin_m) { m0 = P.rin_m[ij]; e0 = P.rin_e[ij]; }
-    ru_add_ext(m0, e0, inexact ? 0.5 : 0.0, em - P.p + 1, rm, re);
-    C.rad_m[oidx] = rm;
-    C.rad_e[oidx] = re;
-  }
-  if (C.status) C.status[oidx] = ARBGPU_ST_OK;
+  double m0 = 0.0;
+  int e0 = 0;
+  if (P.rin_m) { m0 = P.rin_m[ij]; e0 = P.rin_e[ij]; }
+  finish_entry([&](int q) { return T[(int64_t)q * MN]; }, nT, (int64_t)P.rowv2[i] + P.colv2[j], P.C,
+               P.c_off + i * P.c_rs + j * P.c_cs, P.p, P.approx, m0, e0);
 }
 
 // ---------------------------------------------------------------------------

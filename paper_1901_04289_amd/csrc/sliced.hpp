@@ -104,6 +104,48 @@ struct RadExactParams {
   int32_t *out_e;
 };
 
+// Multimodular form of the block product: residues of the scaled integers
+// modulo m odd primes below 2^15, each split into two balanced int8 digits
+// (planes 2j: low digit, 2j + 1: high digit of prime j).
+struct RnsTables {
+  const int32_t *prime;     // [m]
+  const uint32_t *mu;       // [m] floor(2^32 / p)
+  const int32_t *wlo, *whi; // [m][nw] packed int8 digits of 256^a mod p (balanced), a = 4w + b
+  const uint16_t *inv;      // [m][m]: inv[k][i] = p_i^-1 mod p_k (i < k)
+  int m;
+  int nw;                   // words of 4 base-256 digits per element
+};
+
+struct RnsSliceParams {
+  arbgpu_arr part[2];
+  int64_t lines, len;        // as SliceParams
+  int64_t off, line_stride, elem_stride;
+  int64_t k0;
+  int mode;
+  int64_t lines_pad, k_pad;
+  int L;                     // base-256 digits of the scaled integers
+  const int32_t *v2;
+  RnsTables tab;
+  int8_t *planes;            // [2m][lines_pad][k_pad]
+};
+
+struct RnsCrtParams {
+  const int32_t *D;          // [3m][M][N]: digit products of weight 1, 256, 65536 per prime
+  RnsTables tab;
+  int64_t M, N;
+  int W;                     // two's-complement limbs of T
+  const int32_t *rowv2, *colv2;
+  arbgpu_out C;
+  int64_t c_off, c_rs, c_cs;
+  int p;
+  int approx;
+  const double *rin_m;
+  const int32_t *rin_e;
+};
+
+hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s);
+hipError_t launch_rns_crt(const RnsCrtParams &P, hipStream_t s);
+
 // Greedy block extraction (one workgroup).
 struct PlanParams {
   arbgpu_arr A[2], B[2];

@@ -68,15 +68,133 @@ int line_stats(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const 
 
 inline int slices_for(int height) { return std::max(1, (height + 1 + 7) / 8); }
 
+// Odd primes between 2^14 and 2^15, largest first (residue moduli).
+const std::vector<int32_t> &rns_primes() {
+  static const std::vector<int32_t> v = [] {
+    std::vector<char> comp(1 << 15, 0);
+    std::vector<int32_t> out;
+    for (int i = 2; i < (1 << 15); ++i) {
+      if (comp[i]) continue;
+      for (int j = 2 * i; j < (1 << 15); j += i) comp[j] = 1;
+    }
+    for (int i = (1 << 15) - 1; i > (1 << 14); --i)
+      if (!comp[i]) out.push_back(i);
+    return out;
+  }();
+  return v;
+}
+
+// Number of primes whose product exceeds 2^bits.
+int rns_count(int64_t bits) {
+  const std::vector<int32_t> &pr = rns_primes();
+  double acc = 0.0;
+  for (size_t j = 0; j < pr.size(); ++j) {
+    acc += log2((double)pr[j]);
+    if (acc > (double)bits + 1.0) return (int)j + 1;
+  }
+  return -1;
+}
+
+int64_t modinv(int64_t a, int64_t p) {   // a^-1 mod p, gcd(a, p) = 1
+  int64_t t = 0, nt = 1, r = p, nr = ((a % p) + p) % p;
+  while (nr) {
+    const int64_t q = r / nr;
+    int64_t x = t - q * nt; t = nt; nt = x;
+    x = r - q * nr; r = nr; nr = x;
+  }
+  return t < 0 ? t + p : t;
+}
+
+// Residue tables for m primes and nw words of base-256 digits, uploaded to
+// the context workspace (kept while m and nw stay the same).
+int rns_tables(arbgpu_ctx *ctx, int m, int nw, hipStream_t s, RnsTables &tab) {
+  const std::vector<int32_t> &pr = rns_primes();
+  const size_t o_mu = 4 * (size_t)m, o_wlo = o_mu + 4 * (size_t)m, o_whi = o_wlo + 4 * (size_t)m * nw,
+               o_inv = o_whi + 4 * (size_t)m * nw, bytes = o_inv + 2 * (size_t)m * m;
+  char *d = (char *)ws_get(ctx, WS_RNS, bytes);
+  if (!d) return ARBGPU_ENOMEM;
+  tab.prime = (const int32_t *)d;
+  tab.mu = (const uint32_t *)(d + o_mu);
+  tab.wlo = (const int32_t *)(d + o_wlo);
+  tab.whi = (const int32_t *)(d + o_whi);
+  tab.inv = (const uint16_t *)(d + o_inv);
+  tab.m = m;
+  tab.nw = nw;
+  const int64_t key = ((int64_t)m << 32) | (int64_t)nw;
+  if (ctx->rns_key == key && ctx->ws[WS_RNS].ptr == d) return ARBGPU_OK;
+  std::vector<char> h(bytes, 0);
+  int32_t *hp = (int32_t *)h.data();
+  uint32_t *hmu = (uint32_t *)(h.data() + o_mu);
+  uint8_t *hlo = (uint8_t *)(h.data() + o_wlo), *hhi = (uint8_t *)(h.data() + o_whi);
+  uint16_t *hinv = (uint16_t *)(h.data() + o_inv);
+  for (int j = 0; j < m; ++j) {
+    const int64_t p = pr[j];
+    hp[j] = (int32_t)p;
+    hmu[j] = (uint32_t)((((uint64_t)1) << 32) / (uint64_t)p);
+    int64_t w = 1;   // 256^a mod p
+    for (int a = 0; a < 4 * nw; ++a) {
+      const int64_t bal = w > p / 2 ? w - p : w;
+      const int64_t lo = ((bal + 128) & 255) - 128;
+      const int64_t hi = (bal - lo) >> 8;
+      hlo[(size_t)j * 4 * nw + a] = (uint8_t)(int8_t)lo;   // word a/4, byte a%4
+      hhi[(size_t)j * 4 * nw + a] = (uint8_t)(int8_t)hi;
+      w = w * 256 % p;
+    }
+    for (int i = 0; i < j; ++i) hinv[(size_t)j * m + i] = (uint16_t)modinv(pr[i], p);
+  }
+  hipError_t e = hipMemcpyAsync(d, h.data(), bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "residue tables: %s", hipGetErrorString(e));
+  ctx->rns_key = key;
+  return ARBGPU_OK;
+}
+
+// Two's-complement bits of the exact block value: |T| < Kt 2^(HA + HB).
+int64_t t_bits(int HA, int HB, int64_t Kt) {
+  int lg = 0;
+  while (((int64_t)1 << lg) < std::max<int64_t>(Kt, 1)) ++lg;
+  return (int64_t)HA + HB + lg + 1;
+}
+
+// The residue form applies when its LDS staging fits and the int32 partial
+// planes of two digit pairs stay exact.
+bool rns_fits(int HA, int HB, int64_t Kt) {
+  const int64_t Kp = round_up(std::max<int64_t>(Kt, 1), kKStep);
+  if (((int64_t)0x7FFFFFFF) / (Kp << 14) < 2) return false;
+  const int m = rns_count(t_bits(HA, HB, Kt));
+  if (m < 1) return false;
+  const int W = (int)((t_bits(HA, HB, Kt) + 1 + 31) / 32) + 1;
+  const int nw = (std::max(slices_for(HA), slices_for(HB)) + 3) / 4;
+  return 2 * m + 4 * W <= 2048 && nw <= 256;
+}
+
+// MFMA work of the two forms (digit pairs): base-256 slices L_A L_B, the
+// residue form 4 m; the residue form also pays its conversions, about the
+// cost of 4 more pairs per prime at these shapes.
+bool rns_better(int HA, int HB, int64_t Kt) {
+  if (!rns_fits(HA, HB, Kt)) return false;
+  const int64_t m = rns_count(t_bits(HA, HB, Kt));
+  return 8 * m < (int64_t)slices_for(HA) * slices_for(HB);
+}
+
 // Limbs of the exact block result T for the given digit-plane counts.
 inline int t_limbs(int LA, int LB) { return (LA + LB - 1 + 3) / 4 + 2; }
 
 // One scaled-integer block over the inner range [k0, k1) whose line
 // statistics are in `st`: slices, MFMA product and recombination into
 // out[q] (q = output part) truncated to p bits.
+int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const Shape &sh, int64_t k0,
+                      int64_t k1, const int32_t *st, int HA, int HB, const arbgpu_out *out, int64_t o_off,
+                      int64_t o_rs, int64_t o_cs, int p, bool out_approx, double *const rin_m[2],
+                      int32_t *const rin_e[2], hipStream_t s);
+
 int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const Shape &sh, int64_t k0, int64_t k1,
                   const int32_t *st, int HA, int HB, const arbgpu_out *out, int64_t o_off, int64_t o_rs, int64_t o_cs,
-                  int p, bool out_approx, double *const rin_m[2], int32_t *const rin_e[2], hipStream_t s) {
+                  int p, bool out_approx, double *const rin_m[2], int32_t *const rin_e[2], hipStream_t s,
+                  bool rns) {
+  if (rns)
+    return rns_block_product(ctx, A, B, sh, k0, k1, st, HA, HB, out, o_off, o_rs, o_cs, p, out_approx, rin_m, rin_e,
+                             s);
   const int32_t *rv2 = st + sh.M, *cv2 = st + 2 * sh.M + sh.N;
   const int64_t Kb = k1 - k0;
   const int64_t Kt = sh.cplx ? 2 * Kb : Kb;
@@ -106,7 +224,7 @@ int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, con
   while (groups.size() % 8) groups.push_back(DiagGroup{0, 0, 0, -1});   // padding for the XCD mapping
   const int nT = t_limbs(LA, LB);
   {
-    const int64_t plan[8] = {LA, LB, nslots, ngroups_real, Kt, sh.M, sh.N, sh.nparts};
+    const int64_t plan[10] = {LA, LB, nslots, ngroups_real, Kt, sh.M, sh.N, sh.nparts, 0, (int64_t)LA * LB};
     memcpy(ctx->last_plan, plan, sizeof plan);
   }
 
@@ -172,6 +290,102 @@ int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, con
     rp.rin_e = rin_e[q];
     KernelTimer tr(ctx, "recombine", s);
     ARB_TRY(launch_recombine(rp, s), "recombine");
+  }
+  return ARBGPU_OK;
+}
+
+// The block product in residue form: slices of residues modulo m primes,
+// three int32 partial planes per prime from the MFMA kernel, Chinese
+// remainder reconstruction and rounding per entry.
+int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const Shape &sh, int64_t k0,
+                      int64_t k1, const int32_t *st, int HA, int HB, const arbgpu_out *out, int64_t o_off,
+                      int64_t o_rs, int64_t o_cs, int p, bool out_approx, double *const rin_m[2],
+                      int32_t *const rin_e[2], hipStream_t s) {
+  const int32_t *rv2 = st + sh.M, *cv2 = st + 2 * sh.M + sh.N;
+  const int64_t Kb = k1 - k0;
+  const int64_t Kt = sh.cplx ? 2 * Kb : Kb;
+  const int64_t Kp = round_up(std::max<int64_t>(Kt, 1), kKStep);
+  const int64_t Mp = round_up(std::max<int64_t>(sh.M, 1), kTile), Np = round_up(std::max<int64_t>(sh.N, 1), kTile);
+  const int64_t bits = t_bits(HA, HB, Kt);
+  const int m = rns_count(bits);
+  const int W = (int)((bits + 1 + 31) / 32) + 1;
+  const int LA = slices_for(HA), LB = slices_for(HB);
+  const int nw = (std::max(LA, LB) + 3) / 4;
+  if (m < 1) return set_error(ctx, ARBGPU_EINVAL, "residue form: %lld-bit block values", (long long)bits);
+  RnsTables tab;
+  int rc = rns_tables(ctx, m, nw, s, tab);
+  if (rc) return rc;
+  // per prime j: weight 1 (lo lo), 256 (lo hi + hi lo), 65536 (hi hi)
+  std::vector<DiagGroup> groups;
+  for (int j = 0; j < m; ++j) {
+    groups.push_back(DiagGroup{4 * j + 1, 2 * j, 2 * j + 2, 3 * j + 1});
+    groups.push_back(DiagGroup{4 * j, 2 * j, 2 * j + 1, 3 * j});
+    groups.push_back(DiagGroup{4 * j + 2, 2 * j + 1, 2 * j + 2, 3 * j + 2});
+  }
+  std::stable_sort(groups.begin(), groups.end(),
+                   [](const DiagGroup &x, const DiagGroup &y) { return (x.a1 - x.a0) > (y.a1 - y.a0); });
+  const int ngroups_real = (int)groups.size();
+  while (groups.size() % 8) groups.push_back(DiagGroup{0, 0, 0, -1});
+  {
+    const int64_t plan[10] = {2 * m, 2 * m, 3 * m, ngroups_real, Kt, sh.M, sh.N, sh.nparts, m, 4 * (int64_t)m};
+    memcpy(ctx->last_plan, plan, sizeof plan);
+  }
+  const size_t bytesA = (size_t)2 * m * Mp * Kp, bytesB = (size_t)2 * m * Np * Kp;
+  int8_t *planesA = (int8_t *)ws_get(ctx, WS_PLANES_A, bytesA);
+  int8_t *planesB = (int8_t *)ws_get(ctx, WS_PLANES_B, bytesB);
+  int8_t *planesB2 = sh.cplx ? (int8_t *)ws_get(ctx, WS_PLANES_B2, bytesB) : nullptr;
+  int32_t *D = (int32_t *)ws_get(ctx, WS_D, sizeof(int32_t) * (size_t)3 * m * sh.M * sh.N);
+  char *tabs = (char *)ws_get(ctx, WS_TABLES, sizeof(DiagGroup) * groups.size());
+  if (!planesA || !planesB || (sh.cplx && !planesB2) || !D || !tabs) return ARBGPU_ENOMEM;
+  DiagGroup *dgroups = (DiagGroup *)tabs;
+  ARB_TRY(hipMemcpyAsync(dgroups, groups.data(), sizeof(DiagGroup) * groups.size(), hipMemcpyHostToDevice, s),
+          "table upload");
+  ARB_TRY(hipStreamSynchronize(s), "table upload");
+
+  RnsSliceParams sa;
+  memset(&sa, 0, sizeof sa);
+  sa.part[0] = A->re;
+  sa.part[1] = sh.cplx ? A->im : A->re;
+  sa.lines = sh.M; sa.len = Kb; sa.off = A->off; sa.line_stride = A->rs; sa.elem_stride = A->cs; sa.k0 = k0;
+  sa.mode = sh.cplx ? 3 : 0;
+  sa.lines_pad = Mp; sa.k_pad = Kp; sa.L = LA; sa.v2 = rv2; sa.tab = tab; sa.planes = planesA;
+  {
+    KernelTimer t_slice(ctx, "slice", s);
+    ARB_TRY(launch_rns_slice(sa, s), "residue slice");
+    for (int q = 0; q < sh.nparts; ++q) {
+      RnsSliceParams sb = sa;
+      sb.part[0] = B->re;
+      sb.part[1] = sh.cplx ? B->im : B->re;
+      sb.lines = sh.N; sb.off = B->off; sb.line_stride = B->cs; sb.elem_stride = B->rs;
+      sb.mode = !sh.cplx ? 0 : (q == 0 ? 1 : 2);
+      sb.lines_pad = Np; sb.L = LB; sb.v2 = cv2; sb.planes = q == 0 ? planesB : planesB2;
+      ARB_TRY(launch_rns_slice(sb, s), "residue slice");
+    }
+  }
+  for (int q = 0; q < sh.nparts; ++q) {
+    MfmaParams mp;
+    mp.A = planesA;
+    mp.B = q == 0 ? planesB : planesB2;
+    mp.D = D;
+    mp.groups = dgroups;
+    mp.M = sh.M; mp.N = sh.N; mp.Mp = Mp; mp.Np = Np; mp.Kp = Kp;
+    mp.ntm = (int)(Mp / kTile); mp.ntn = (int)(Np / kTile);
+    mp.ngroups = (int)groups.size();
+    {
+      KernelTimer tm(ctx, "mfma", s);
+      ARB_TRY(launch_mfma(mp, s), "mfma");
+    }
+    RnsCrtParams cp;
+    cp.D = D; cp.tab = tab; cp.M = sh.M; cp.N = sh.N; cp.W = W;
+    cp.rowv2 = rv2; cp.colv2 = cv2;
+    cp.C = out[q];
+    cp.c_off = o_off; cp.c_rs = o_rs; cp.c_cs = o_cs;
+    cp.p = p;
+    cp.approx = out_approx;
+    cp.rin_m = rin_m[q];
+    cp.rin_e = rin_e[q];
+    KernelTimer tr(ctx, "recombine", s);
+    ARB_TRY(launch_rns_crt(cp, s), "residue reconstruction");
   }
   return ARBGPU_OK;
 }
@@ -376,17 +590,25 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
   auto not_here = [&](const char *why) {
     return forced ? set_error(ctx, ARBGPU_EINVAL, "sliced product: %s", why) : kNotApplicable;
   };
+  // residue form or base-256 slices for a block of heights (ha, hb)
+  auto use_rns = [&](int ha, int hb, int64_t kt) {
+    if (flags & ARBGPU_ALGO_RNS) return true;
+    if (flags & ARBGPU_ALGO_SLICED) return false;
+    return rns_better(ha, hb, kt);
+  };
 
   if (g[0] <= hmax && g[4] <= hmax) {
     // ---- the whole inner range is one block: its exact integer product
     //      rounds straight to the output
     if (slices_for(g[0]) > kMaxSlices || slices_for(g[4]) > kMaxSlices) return not_here("integer height too large");
+    const bool rns = use_rns(g[0], g[4], Kt);
+    if (rns && !rns_fits(g[0], g[4], Kt)) return not_here("residue form does not fit these heights");
     if (!sh.approx && (radA || radB)) {
       rc = radius_products(ctx, A, B, sh, rin_m, rin_e, s);
       if (rc) return rc;
     }
     return block_product(ctx, A, B, sh, 0, sh.K, st, g[0], g[4], outs, C->off, C->rs, C->cs, (int)p, sh.approx,
-                         rin_m, rin_e, s);
+                         rin_m, rin_e, s, rns);
   }
 
   // ---- several blocks (Algorithm 2's greedy partition) ----------------------
@@ -450,7 +672,10 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
     }
     double *no_m[2] = {nullptr, nullptr};
     int32_t *no_e[2] = {nullptr, nullptr};
-    rc = block_product(ctx, A, B, sh, b.k0, b.k1, st, g[0], g[4], tout, 0, sh.N, 1, 32 * capT, true, no_m, no_e, s);
+    const int64_t ktb = sh.cplx ? 2 * (b.k1 - b.k0) : b.k1 - b.k0;
+    const bool rns = use_rns(g[0], g[4], ktb) && rns_fits(g[0], g[4], ktb);
+    rc = block_product(ctx, A, B, sh, b.k0, b.k1, st, g[0], g[4], tout, 0, sh.N, 1, 32 * capT, true, no_m, no_e, s,
+                       rns);
     if (rc) return rc;
     ++si;
   }

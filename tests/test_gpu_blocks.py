@@ -147,12 +147,13 @@ def test_multiblock_pascal_matches_oracle_and_limb(ctx):
         assert compare_entry(gen.to_canonical(out.ops, i * n + j), want, int(out.status[i * n + j])) is None, (i, j)
 
 
+@pytest.mark.parametrize("algo", [0, arbgpu.ALGO_RNS])
 @pytest.mark.parametrize("seed,M,N,K,p,prec,rshift,approx", [
     (1, 19, 330, 23, 100, 100, 95, False),   # blocks, basecase chunks, balls, zeros
     (2, 33, 260, 2, 150, 180, None, False),  # wide operands, exact
     (3, 5, 200, 70, 90, 100, 80, True),      # midpoints only
 ])
-def test_multiblock_real_parity(ctx, seed, M, N, K, p, prec, rshift, approx):
+def test_multiblock_real_parity(ctx, seed, M, N, K, p, prec, rshift, approx, algo):
     rng = gen.rng_for(32, seed)
     A = gen.random_operands(rng, M * N, rng.integers(1, prec + 1, M * N), -4, 4, radius_shift=rshift,
                             zero_frac=0.1)
@@ -161,8 +162,8 @@ def test_multiblock_real_parity(ctx, seed, M, N, K, p, prec, rshift, approx):
     g = mixed_grading(N)
     grade(A, M, N, g, True)
     grade(B, N, K, [-x for x in g], False)
-    flags = arbgpu.APPROX if approx else 0
-    say(f"multi-block real seed={seed} {M}x{N}x{K} p={p}")
+    flags = (arbgpu.APPROX if approx else 0) | algo
+    say(f"multi-block real seed={seed} {M}x{N}x{K} p={p} algo={algo:#x}")
     out, _, merges = run(ctx, A, B, M, N, K, p, flags)
     assert merges == 1
     Ac = gen.canonical_matrix(A, M, N, N, 1)

@@ -48,10 +48,14 @@ def check(out, st, want, entries, K, approx=False):
     assert not bad, bad[:5]
 
 
-def test_sliced_config0_full(ctx):
+ALGOS = [arbgpu.ALGO_SLICED, arbgpu.ALGO_RNS]
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_sliced_config0_full(ctx, algo):
     w = gen.config0()
-    say("sliced config0 64x64x64 p=128")
-    (out, st), _ = run(ctx, w.A, w.B, w.M, w.N, w.K, w.p, arbgpu.ALGO_SLICED)
+    say(f"sliced config0 64x64x64 p=128 algo={algo:#x}")
+    (out, st), _ = run(ctx, w.A, w.B, w.M, w.N, w.K, w.p, algo)
     Ac = gen.canonical_matrix(w.A, w.M, w.N, w.N, 1)
     Bc = gen.canonical_matrix(w.B, w.N, w.K, w.K, 1)
     C = oracle.mat_mul(Ac, Bc, w.p)
@@ -59,13 +63,14 @@ def test_sliced_config0_full(ctx):
     assert (st == 0).all()
 
 
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("seed,M,N,K,p,prec,erange,rshift", [
     (1, 5, 37, 70, 100, 120, 20, 110),       # ragged everywhere, balls, zeros
     (2, 300, 130, 257, 64, 64, 3, None),     # several tiles, K not a multiple of 128
     (3, 17, 300, 9, 333, 400, 40, 300),      # long inner dimension, wide operands
     (4, 1, 31, 1, 2, 50, 2, None),           # p = 2
 ])
-def test_sliced_random_parity(ctx, seed, M, N, K, p, prec, erange, rshift):
+def test_sliced_random_parity(ctx, seed, M, N, K, p, prec, erange, rshift, algo):
     rng = gen.rng_for(20, seed)
     A = gen.random_operands(rng, M * N, rng.integers(1, prec + 1, M * N), -erange, erange,
                             radius_shift=rshift, zero_frac=0.1)
@@ -74,8 +79,8 @@ def test_sliced_random_parity(ctx, seed, M, N, K, p, prec, erange, rshift):
     if M > 2:
         A.limbs[:, N:2 * N] = 0
         A.nls[N:2 * N] = 0
-    say(f"sliced random seed={seed} {M}x{N}x{K} p={p}")
-    (out, st), _ = run(ctx, A, B, M, N, K, p, arbgpu.ALGO_SLICED)
+    say(f"sliced random seed={seed} {M}x{N}x{K} p={p} algo={algo:#x}")
+    (out, st), _ = run(ctx, A, B, M, N, K, p, algo)
     Ac = gen.canonical_matrix(A, M, N, N, 1)
     Bc = gen.canonical_matrix(B, N, K, K, 1)
     ent = [(i, j) for i in range(M) for j in range(K)]
@@ -89,7 +94,8 @@ def test_sliced_random_parity(ctx, seed, M, N, K, p, prec, erange, rshift):
     check(out, st, want, ent, K)
 
 
-def test_sliced_exact_T(ctx):
+@pytest.mark.parametrize("algo", ALGOS)
+def test_sliced_exact_T(ctx, algo):
     # p larger than every exact sum: the output mantissa is the whole integer
     # block product T, so this checks T bit for bit
     rng = gen.rng_for(21, 0)
@@ -97,8 +103,8 @@ def test_sliced_exact_T(ctx):
     A = gen.random_operands(rng, M * N, 200, -6, 6)
     B = gen.random_operands(rng, N * K, 160, -6, 6)
     p = 600
-    say("sliced exact T")
-    (out, st), _ = run(ctx, A, B, M, N, K, p, arbgpu.ALGO_SLICED)
+    say(f"sliced exact T algo={algo:#x}")
+    (out, st), _ = run(ctx, A, B, M, N, K, p, algo)
     Ac = gen.canonical_matrix(A, M, N, N, 1)
     Bc = gen.canonical_matrix(B, N, K, K, 1)
     e, f, T = oracle.block_product([[x[0] for x in r] for r in Ac], [[x[0] for x in r] for r in Bc],
@@ -112,13 +118,14 @@ def test_sliced_exact_T(ctx):
             assert got[1] is None
 
 
-def test_sliced_complex(ctx):
+@pytest.mark.parametrize("algo", ALGOS)
+def test_sliced_complex(ctx, algo):
     rng = gen.rng_for(22, 0)
     M, N, K, p = 6, 45, 5, 120
     parts = [gen.random_operands(rng, c, 130, -10, 10, radius_shift=125, zero_frac=0.05)
              for c in (M * N, M * N, N * K, N * K)]
-    say("sliced complex")
-    (out, st), (outi, sti) = run(ctx, parts[0], parts[2], M, N, K, p, arbgpu.COMPLEX | arbgpu.ALGO_SLICED,
+    say(f"sliced complex algo={algo:#x}")
+    (out, st), (outi, sti) = run(ctx, parts[0], parts[2], M, N, K, p, arbgpu.COMPLEX | algo,
                                  Ai=parts[1], Bi=parts[3])
     A = [[(gen.to_canonical(parts[0], i * N + k), gen.to_canonical(parts[1], i * N + k)) for k in range(N)]
          for i in range(M)]
@@ -132,10 +139,11 @@ def test_sliced_complex(ctx):
             assert compare_entry(gen.to_canonical(outi, i * K + j), im, int(sti[i * K + j])) is None
 
 
-def test_config1_sliced_equals_limb_and_oracle(ctx):
+@pytest.mark.parametrize("algo", ALGOS)
+def test_config1_sliced_equals_limb_and_oracle(ctx, algo):
     w = gen.config1()
-    say("config1 sliced vs limb 512^3 p=256")
-    (o1, s1), _ = run(ctx, w.A, w.B, w.M, w.N, w.K, w.p, arbgpu.ALGO_SLICED)
+    say(f"config1 sliced vs limb 512^3 p=256 algo={algo:#x}")
+    (o1, s1), _ = run(ctx, w.A, w.B, w.M, w.N, w.K, w.p, algo)
     (o2, s2), _ = run(ctx, w.A, w.B, w.M, w.N, w.K, w.p, arbgpu.ALGO_LIMB)
     # identical midpoints everywhere
     assert np.array_equal(o1.limbs, o2.limbs)
@@ -152,6 +160,10 @@ def test_config2_sliced_sampled(ctx):
     say("config2 sliced 2048^3 p=512")
     (out, st), _ = run(ctx, w.A, w.B, w.M, w.N, w.K, w.p, arbgpu.ALGO_SLICED)
     assert (st == 0).all()
+    # the residue form gives the same bits
+    (o2, s2), _ = run(ctx, w.A, w.B, w.M, w.N, w.K, w.p, arbgpu.ALGO_RNS)
+    assert np.array_equal(out.limbs, o2.limbs) and np.array_equal(out.exp, o2.exp)
+    assert np.array_equal(out.nls, o2.nls) and np.array_equal(out.rad_m, o2.rad_m) and np.array_equal(st, s2)
     r = random.Random(4)
     ent = [(r.randrange(w.M), r.randrange(w.K)) for _ in range(10)] + [(0, 0), (w.M - 1, w.K - 1)]
     rows = {i: [gen.to_canonical(w.A, i * w.N + k) for k in range(w.N)] for i, _ in ent}
