@@ -111,9 +111,13 @@ struct RnsTables {
   const int32_t *prime;     // [m]
   const uint32_t *mu;       // [m] floor(2^32 / p)
   const int32_t *wlo, *whi; // [m][nw] packed int8 digits of 256^a mod p (balanced), a = 4w + b
-  const uint16_t *inv;      // [m][m]: inv[k][i] = p_i^-1 mod p_k (i < k)
+  const uint32_t *q;        // [m][wq] limbs (least significant first) of P / p_j, P = prod p_j
+  const uint32_t *pp;       // [wq] limbs of P
+  const uint16_t *c;        // [m] (P / p_j)^-1 mod p_j
+  const double *rp;         // [m] 1 / p_j
   int m;
   int nw;                   // words of 4 base-256 digits per element
+  int wq;                   // limbs of P
 };
 
 struct RnsSliceParams {

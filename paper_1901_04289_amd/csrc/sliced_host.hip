@@ -106,31 +106,58 @@ int64_t modinv(int64_t a, int64_t p) {   // a^-1 mod p, gcd(a, p) = 1
 }
 
 // Residue tables for m primes and nw words of base-256 digits, uploaded to
-// the context workspace (kept while m and nw stay the same).
+// the context workspace (kept while m and nw stay the same): primes and
+// reduction constants, the digit weights 256^a mod p_j as balanced int8
+// pairs, and the Chinese remainder constants P / p_j, P, (P / p_j)^-1 mod p_j.
 int rns_tables(arbgpu_ctx *ctx, int m, int nw, hipStream_t s, RnsTables &tab) {
   const std::vector<int32_t> &pr = rns_primes();
+  // P = prod p_j and Q_j = P / p_j as little-endian limbs
+  std::vector<uint32_t> P(1, 1u);
+  for (int j = 0; j < m; ++j) {
+    uint64_t c = 0;
+    for (auto &l : P) {
+      const uint64_t t = (uint64_t)l * (uint32_t)pr[j] + c;
+      l = (uint32_t)t;
+      c = t >> 32;
+    }
+    if (c) P.push_back((uint32_t)c);
+  }
+  const int wq = (int)P.size();
   const size_t o_mu = 4 * (size_t)m, o_wlo = o_mu + 4 * (size_t)m, o_whi = o_wlo + 4 * (size_t)m * nw,
-               o_inv = o_whi + 4 * (size_t)m * nw, bytes = o_inv + 2 * (size_t)m * m;
-  char *d = (char *)ws_get(ctx, WS_RNS, bytes);
+               o_q = o_whi + 4 * (size_t)m * nw, o_pp = o_q + 4 * (size_t)m * wq, o_rp = o_pp + 4 * (size_t)wq,
+               o_c = o_rp + 8 * (size_t)m, bytes = o_c + 2 * (size_t)m;
+  const size_t o_rp8 = (o_rp + 7) & ~(size_t)7;
+  const size_t o_c8 = o_rp8 + 8 * (size_t)m, bytes8 = o_c8 + 2 * (size_t)m;
+  (void)o_c;
+  (void)bytes;
+  char *d = (char *)ws_get(ctx, WS_RNS, bytes8);
   if (!d) return ARBGPU_ENOMEM;
   tab.prime = (const int32_t *)d;
   tab.mu = (const uint32_t *)(d + o_mu);
   tab.wlo = (const int32_t *)(d + o_wlo);
   tab.whi = (const int32_t *)(d + o_whi);
-  tab.inv = (const uint16_t *)(d + o_inv);
+  tab.q = (const uint32_t *)(d + o_q);
+  tab.pp = (const uint32_t *)(d + o_pp);
+  tab.rp = (const double *)(d + o_rp8);
+  tab.c = (const uint16_t *)(d + o_c8);
   tab.m = m;
   tab.nw = nw;
+  tab.wq = wq;
   const int64_t key = ((int64_t)m << 32) | (int64_t)nw;
   if (ctx->rns_key == key && ctx->ws[WS_RNS].ptr == d) return ARBGPU_OK;
-  std::vector<char> h(bytes, 0);
+  std::vector<char> h(bytes8, 0);
   int32_t *hp = (int32_t *)h.data();
   uint32_t *hmu = (uint32_t *)(h.data() + o_mu);
   uint8_t *hlo = (uint8_t *)(h.data() + o_wlo), *hhi = (uint8_t *)(h.data() + o_whi);
-  uint16_t *hinv = (uint16_t *)(h.data() + o_inv);
+  uint32_t *hq = (uint32_t *)(h.data() + o_q), *hpp = (uint32_t *)(h.data() + o_pp);
+  double *hrp = (double *)(h.data() + o_rp8);
+  uint16_t *hc = (uint16_t *)(h.data() + o_c8);
+  for (int q = 0; q < wq; ++q) hpp[q] = P[q];
   for (int j = 0; j < m; ++j) {
     const int64_t p = pr[j];
     hp[j] = (int32_t)p;
     hmu[j] = (uint32_t)((((uint64_t)1) << 32) / (uint64_t)p);
+    hrp[j] = 1.0 / (double)p;
     int64_t w = 1;   // 256^a mod p
     for (int a = 0; a < 4 * nw; ++a) {
       const int64_t bal = w > p / 2 ? w - p : w;
@@ -140,9 +167,18 @@ int rns_tables(arbgpu_ctx *ctx, int m, int nw, hipStream_t s, RnsTables &tab) {
       hhi[(size_t)j * 4 * nw + a] = (uint8_t)(int8_t)hi;
       w = w * 256 % p;
     }
-    for (int i = 0; i < j; ++i) hinv[(size_t)j * m + i] = (uint16_t)modinv(pr[i], p);
+    // Q_j = P / p_j (exact), its residue mod p_j, and that residue's inverse
+    uint64_t rem = 0;
+    for (int q = wq - 1; q >= 0; --q) {
+      const uint64_t cur = (rem << 32) | P[q];
+      hq[(size_t)j * wq + q] = (uint32_t)(cur / (uint64_t)p);
+      rem = cur % (uint64_t)p;
+    }
+    uint64_t qm = 0;
+    for (int q = wq - 1; q >= 0; --q) qm = ((qm << 32) | hq[(size_t)j * wq + q]) % (uint64_t)p;
+    hc[j] = (uint16_t)modinv((int64_t)qm, p);
   }
-  hipError_t e = hipMemcpyAsync(d, h.data(), bytes, hipMemcpyHostToDevice, s);
+  hipError_t e = hipMemcpyAsync(d, h.data(), bytes8, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "residue tables: %s", hipGetErrorString(e));
   ctx->rns_key = key;
