@@ -279,33 +279,62 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # sliced INT8 MFMA path
-    for _ in range(a.warmup):
-        ctx.mat_mul(C, dA, dB, M, N, K, p, arbgpu.ALGO_SLICED)
-    torch.cuda.synchronize()
-    log("[bench] sliced warmup done")
-    ctx.timing(True)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for s in range(a.steps):
-        ev[s][0].record(stream)
-        ctx.mat_mul(C, dA, dB, M, N, K, p, arbgpu.ALGO_SLICED)
-        ev[s][1].record(stream)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    ms_step = (t2 - t1) * 1e3 / a.steps
-    lat = np.array([x.elapsed_time(y) for x, y in ev])
-    mfma_ms, mfma_n = ctx.timing_read("mfma")
-    kern = {k: ctx.timing_read(k) for k in ("stats", "slice", "mfma", "recombine")}
-    ctx.timing(False)
-    plan = ctx.plan_info()
-    log(f"[bench] sliced {ms_step:.2f} ms/step, mfma {mfma_ms / max(mfma_n, 1):.2f} ms/launch, plan {plan}")
     macs = float(M) * N * K
-    value = macs / (ms_step / 1e3)
-    int8_ops = 2.0 * plan["slices_a"] * plan["slices_b"] * M * K * N   # algorithmic slice-pair MACs x 2
-    mfma_avg_s = mfma_ms / max(mfma_n, 1) / 1e3
-    achieved = int8_ops / mfma_avg_s / 1e12
+    KERNELS = ("stats", "slice", "mfma", "recombine")
+
+    def measure(flags, steps, warmup):
+        """Steps of one scaled-integer form: wall time per step, HIP-event
+        latencies, per-kernel times and the MFMA roofline."""
+        for _ in range(warmup):
+            ctx.mat_mul(C, dA, dB, M, N, K, p, flags)
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(steps):
+            ev[k][0].record(stream)
+            ctx.mat_mul(C, dA, dB, M, N, K, p, flags)
+            ev[k][1].record(stream)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ms_step = (t2 - t1) * 1e3 / steps
+        lat = np.array([x.elapsed_time(y) for x, y in ev])
+        kern = {k: ctx.timing_read(k) for k in KERNELS}
+        ctx.timing(False)
+        plan = ctx.plan_info()
+        mfma_ms, mfma_n = kern["mfma"]
+        mfma_avg_s = mfma_ms / max(mfma_n, 1) / 1e3
+        int8_ops = 2.0 * plan["pairs"] * M * K * N   # digit-plane pairs x MACs x 2
+        achieved = int8_ops / mfma_avg_s / 1e12
+        return {"ms_per_step": ms_step, "value": macs / (ms_step / 1e3), "lat": lat,
+                "kernels_ms_per_step": {k: v[0] / steps for k, v in kern.items()},
+                "plan": plan, "mfma_avg_ms": mfma_avg_s * 1e3, "int8_ops": int8_ops,
+                "mfma_tops": achieved}
+
+    # the library's automatic choice (residues modulo small primes at this
+    # shape) is the headline; base-256 slices are measured beside it
+    main = measure(0, a.steps, a.warmup)
+    log(f"[bench] auto path {main['ms_per_step']:.2f} ms/step, kernels {main['kernels_ms_per_step']}, "
+        f"plan {main['plan']}")
+    C_main = (C.limbs.clone(), C.exp.clone(), C.nls.clone())
+    forms = {}
+    for name, flag in (("residues", arbgpu.ALGO_RNS), ("slices", arbgpu.ALGO_SLICED)):
+        r = measure(flag, max(2, a.steps // 4), 1)
+        forms[name] = {"ms_per_step": r["ms_per_step"], "value": r["value"], "unit": "p-bit MACs/s",
+                       "kernels_ms_per_step": r["kernels_ms_per_step"], "digit_pairs": r["plan"]["pairs"],
+                       "primes": r["plan"]["primes"], "mfma_avg_ms": r["mfma_avg_ms"],
+                       "mfma_frac_of_int8_peak": r["mfma_tops"] / PEAK_INT8_TOPS,
+                       "bit_identical_midpoints": bool(torch.equal(C.limbs, C_main[0])
+                                                       and torch.equal(C.exp, C_main[1])
+                                                       and torch.equal(C.nls, C_main[2]))}
+        log(f"[bench] {name} {r['ms_per_step']:.2f} ms/step, mfma {r['mfma_avg_ms']:.2f} ms "
+            f"({r['mfma_tops'] / PEAK_INT8_TOPS:.1%} of INT8 peak)")
+    ms_step, value, lat, plan = main["ms_per_step"], main["value"], main["lat"], main["plan"]
+    mfma_avg_s = main["mfma_avg_ms"] / 1e3
+    int8_ops = main["int8_ops"]
+    achieved = main["mfma_tops"]
+    digits_path = plan["primes"] == 0
 
     out = {
         "metric": METRIC, "value": value, "unit": "p-bit MACs/s", "n_gpus": 1, "steps": a.steps,
@@ -313,17 +342,24 @@ def main():
         "vs_baseline": None, "dtype": "i8", "data": "synthetic",
         "config": {"workload": "real matrix product 2048x2048 by 2048x2048, p=512, 512-bit mantissas, "
                                "exponents uniform in [-4,4], exact inputs (zero radius)",
-                   "N": a.n, "p": p, "path": "scaled-integer block product on INT8 MFMA"},
+                   "N": a.n, "p": p,
+                   "path": "scaled-integer block product on INT8 MFMA, " +
+                           ("base-256 digit slices" if digits_path else
+                            f"residues modulo {plan['primes']} primes below 2^15")},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
-        "kernels_ms_per_step": {k: v[0] / max(v[1], 1) * (v[1] / a.steps) for k, v in kern.items()},
+        "kernels_ms_per_step": main["kernels_ms_per_step"],
         "slice_plan": plan,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_INT8_TOPS, "traffic": _mfma_traffic(a.n),
+                     "frac": achieved / PEAK_INT8_TOPS,
+                     "traffic": _mfma_traffic(a.n) if digits_path else None,
                      "kernel": "mfma_diag_kernel", "ops_per_launch": int8_ops,
                      "avg_launch_ms": mfma_avg_s * 1e3},
+        "int8_forms": forms,
         "cpu_baseline": cpu,
     }
+    ctx.mat_mul(C, dA, dB, M, N, K, p, 0)
+    torch.cuda.synchronize()
 
     # plain limb-window kernel on the same product
     if not a.no_plain:
