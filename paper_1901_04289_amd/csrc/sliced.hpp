@@ -195,6 +195,16 @@ struct BlockSpan {
 int plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, bool cplx, int hmax, hipStream_t s,
                 std::vector<BlockSpan> &out);
 
+// Line-major copy (limbs, exponents, counts) of an operand block.
+struct GatherParams {
+  arbgpu_arr src;
+  int64_t off, line_stride, elem_stride, k0;
+  int64_t lines, len;
+  uint32_t *limbs;          // [cap][lines * len]
+  int32_t *exp, *nls;       // [lines * len]
+};
+hipError_t launch_gather(const GatherParams &P, hipStream_t s);
+
 hipError_t launch_plan(const PlanParams &P, hipStream_t s);
 hipError_t launch_merge(const MergeParams &P, int ns, hipStream_t s);
 

@@ -68,6 +68,43 @@ int line_stats(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const 
 
 inline int slices_for(int height) { return std::max(1, (height + 1 + 7) / 8); }
 
+// B's lines (columns) for slicing the inner range [k0, k1): when the inner
+// index is strided and the columns are not (row-major B), a line-major copy
+// of the block, else B in place.
+struct Lines {
+  arbgpu_arr part[2];
+  int64_t off, line_stride, elem_stride, k0;
+};
+
+int b_lines(arbgpu_ctx *ctx, const arbgpu_mat *B, bool cplx, int64_t k0, int64_t k1, hipStream_t s, Lines &L) {
+  L.part[0] = B->re;
+  L.part[1] = cplx ? B->im : B->re;
+  L.off = B->off; L.line_stride = B->cs; L.elem_stride = B->rs; L.k0 = k0;
+  const int64_t N = B->cols, Kb = k1 - k0;
+  if (!(B->cs == 1 && B->rs != 1) || N == 0 || Kb == 0) return ARBGPU_OK;
+  const int nparts = cplx ? 2 : 1;
+  const size_t elems = (size_t)N * Kb;
+  size_t bytes = 0;
+  for (int q = 0; q < nparts; ++q) bytes += 4 * elems * (size_t)(L.part[q].cap + 2);
+  char *w = (char *)ws_get(ctx, WS_GATHER, bytes);
+  if (!w) return ARBGPU_ENOMEM;
+  for (int q = 0; q < nparts; ++q) {
+    GatherParams gp;
+    gp.src = L.part[q];
+    gp.off = B->off; gp.line_stride = B->cs; gp.elem_stride = B->rs; gp.k0 = k0;
+    gp.lines = N; gp.len = Kb;
+    gp.limbs = (uint32_t *)w;
+    gp.exp = (int32_t *)(w + 4 * elems * (size_t)L.part[q].cap);
+    gp.nls = gp.exp + elems;
+    w += 4 * elems * (size_t)(L.part[q].cap + 2);
+    ARB_TRY(launch_gather(gp, s), "gather");
+    L.part[q] = arbgpu_arr{gp.limbs, (int64_t)elems, L.part[q].cap, gp.exp, gp.nls, nullptr, nullptr};
+  }
+  if (!cplx) L.part[1] = L.part[0];
+  L.off = 0; L.line_stride = Kb; L.elem_stride = 1; L.k0 = 0;
+  return ARBGPU_OK;
+}
+
 // Odd primes between 2^14 and 2^15, largest first (residue moduli).
 const std::vector<int32_t> &rns_primes() {
   static const std::vector<int32_t> v = [] {
@@ -289,14 +326,18 @@ int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, con
   sa.lines = sh.M; sa.len = Kb; sa.off = A->off; sa.line_stride = A->rs; sa.elem_stride = A->cs; sa.k0 = k0;
   sa.mode = sh.cplx ? 3 : 0;
   sa.lines_pad = Mp; sa.k_pad = Kp; sa.L = LA; sa.v2 = rv2; sa.planes = planesA;
+  Lines bl;
   {
     KernelTimer t_slice(ctx, "slice", s);
+    int rc = b_lines(ctx, B, sh.cplx, k0, k1, s, bl);
+    if (rc) return rc;
     ARB_TRY(launch_slice(sa, s), "slice");
     for (int q = 0; q < sh.nparts; ++q) {
       SliceParams sb = sa;
-      sb.part[0] = B->re;
-      sb.part[1] = sh.cplx ? B->im : B->re;
-      sb.lines = sh.N; sb.off = B->off; sb.line_stride = B->cs; sb.elem_stride = B->rs;
+      sb.part[0] = bl.part[0];
+      sb.part[1] = bl.part[1];
+      sb.lines = sh.N; sb.off = bl.off; sb.line_stride = bl.line_stride; sb.elem_stride = bl.elem_stride;
+      sb.k0 = bl.k0;
       sb.mode = !sh.cplx ? 0 : (q == 0 ? 1 : 2);
       sb.lines_pad = Np; sb.L = LB; sb.v2 = cv2; sb.planes = q == 0 ? planesB : planesB2;
       ARB_TRY(launch_slice(sb, s), "slice");
@@ -385,14 +426,18 @@ int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
   sa.lines = sh.M; sa.len = Kb; sa.off = A->off; sa.line_stride = A->rs; sa.elem_stride = A->cs; sa.k0 = k0;
   sa.mode = sh.cplx ? 3 : 0;
   sa.lines_pad = Mp; sa.k_pad = Kp; sa.L = LA; sa.v2 = rv2; sa.tab = tab; sa.planes = planesA;
+  Lines bl;
   {
     KernelTimer t_slice(ctx, "slice", s);
+    rc = b_lines(ctx, B, sh.cplx, k0, k1, s, bl);
+    if (rc) return rc;
     ARB_TRY(launch_rns_slice(sa, s), "residue slice");
     for (int q = 0; q < sh.nparts; ++q) {
       RnsSliceParams sb = sa;
-      sb.part[0] = B->re;
-      sb.part[1] = sh.cplx ? B->im : B->re;
-      sb.lines = sh.N; sb.off = B->off; sb.line_stride = B->cs; sb.elem_stride = B->rs;
+      sb.part[0] = bl.part[0];
+      sb.part[1] = bl.part[1];
+      sb.lines = sh.N; sb.off = bl.off; sb.line_stride = bl.line_stride; sb.elem_stride = bl.elem_stride;
+      sb.k0 = bl.k0;
       sb.mode = !sh.cplx ? 0 : (q == 0 ? 1 : 2);
       sb.lines_pad = Np; sb.L = LB; sb.v2 = cv2; sb.planes = q == 0 ? planesB : planesB2;
       ARB_TRY(launch_rns_slice(sb, s), "residue slice");
