@@ -39,20 +39,21 @@ from paper_1901_04289_amd import gen  # noqa: E402
 METRIC = "p-bit MACs/s, sliced-MFMA vs plain limb kernel, N=2048 p=512; p99 latency"
 PEAK_INT8_TOPS = 5000.0   # MI355X dense INT8 MFMA, 5.0 POP/s
 
-# HBM bytes per launch of mfma_diag_kernel at N = 2048, p = 512, from the
-# FETCH_SIZE (x2, copy-calibrated) and WRITE_SIZE (x1) counter runs in
-# profiles/mfma_diag_kernel_matmul2048_p512.txt; valid only for the kernel
-# source they were taken on (sha256 prefix of csrc/sliced.hip).
-MFMA_TRAFFIC_BYTES = (27.87e6 * 2 + 2228224) * 1024
-MFMA_TRAFFIC_SRC = "6534c66661bc206f"
+# HBM bytes per launch of mfma_diag_kernel at N = 2048, p = 512 for the two
+# INT8 forms, from the FETCH_SIZE (x2, copy-calibrated) and WRITE_SIZE (x1)
+# counter runs in profiles/mfma_diag_kernel_matmul2048_p512.txt; valid only
+# for the kernel source they were taken on (sha256 prefix of csrc/sliced.hip).
+MFMA_TRAFFIC_BYTES = {"residues": (1745131 * 2 + 3489792) * 1024.0,
+                      "slices": (28.14e6 * 2 + 2228224) * 1024.0}
+MFMA_TRAFFIC_SRC = "81596c5b98ad48fe"
 
 
-def _mfma_traffic(n):
+def _mfma_traffic(n, form):
     import hashlib
     src = os.path.join(ROOT, "paper_1901_04289_amd", "csrc", "sliced.hip")
     with open(src, "rb") as f:
         h = hashlib.sha256(f.read()).hexdigest()[:16]
-    return MFMA_TRAFFIC_BYTES if (h == MFMA_TRAFFIC_SRC and n == 2048) else None
+    return MFMA_TRAFFIC_BYTES[form] if (h == MFMA_TRAFFIC_SRC and n == 2048) else None
 
 
 # ---------------------------------------------------------------------------
@@ -325,6 +326,7 @@ def main():
                        "kernels_ms_per_step": r["kernels_ms_per_step"], "digit_pairs": r["plan"]["pairs"],
                        "primes": r["plan"]["primes"], "mfma_avg_ms": r["mfma_avg_ms"],
                        "mfma_frac_of_int8_peak": r["mfma_tops"] / PEAK_INT8_TOPS,
+                       "mfma_traffic_bytes": _mfma_traffic(a.n, name),
                        "bit_identical_midpoints": bool(torch.equal(C.limbs, C_main[0])
                                                        and torch.equal(C.exp, C_main[1])
                                                        and torch.equal(C.nls, C_main[2]))}
@@ -352,7 +354,7 @@ def main():
         "slice_plan": plan,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
                      "frac": achieved / PEAK_INT8_TOPS,
-                     "traffic": _mfma_traffic(a.n) if digits_path else None,
+                     "traffic": _mfma_traffic(a.n, "slices" if digits_path else "residues"),
                      "kernel": "mfma_diag_kernel", "ops_per_launch": int8_ops,
                      "avg_launch_ms": mfma_avg_s * 1e3},
         "int8_forms": forms,
