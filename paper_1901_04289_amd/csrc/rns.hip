@@ -9,14 +9,18 @@
 // the explicit Chinese remainder formula, exact whenever prod p_j > 4 |T|.
 // The MFMA work is 4 m digit products instead of L_A L_B base-256 slices.
 //
-// The tables (primes, digit weights, quotients P / p_j) are the same for
-// every thread and are read through the constant address space, so they
-// arrive by scalar loads.
+// The per-prime tables are the same for every thread and are read through
+// the constant address space, so they arrive by scalar loads; the digit
+// tables of the two matrix products (weights 256^a mod p_j, quotients
+// P / p_j) are MFMA operands.
 #include "elements.hpp"
 #include "finish.hpp"
 #include "sliced.hpp"
 
 namespace arbgpu_impl {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 
 namespace {
 
@@ -67,31 +71,58 @@ __device__ __forceinline__ SliceElem slice_elem(const RnsSliceParams &P, int64_t
   return e;
 }
 
-// Word w (4 balanced base-256 digits, int8 each) of Y: the digits of
-// Y + B, B = sum_{a<L} 128 * 256^a, are bytes; those of Y are the bytes
-// minus 128.  cy carries between words.
-__device__ __forceinline__ uint32_t digit_word(const RnsSliceParams &P, const SliceElem &e, int w, uint32_t &cy) {
-  const int nbytes = P.L - 4 * w;
-  const uint32_t bmask = nbytes >= 4 ? 0xFFFFFFFFu : (nbytes <= 0 ? 0u : ((1u << (8 * nbytes)) - 1u));
-  const uint32_t Bc = 0x80808080u & bmask;
-  uint32_t x = 0;
-  if (e.n) x = mant_chunk(part_of(P.part, e.part), e.idx, e.n, 32 * (int64_t)w - e.s);
-  uint64_t v;
-  if (!e.sg) {
-    v = (uint64_t)Bc + x + cy;
-    cy = (uint32_t)(v >> 32);
-  } else {
-    v = (uint64_t)Bc - x - cy;
-    cy = (uint32_t)((v >> 63) & 1u);
+// Words 4 g .. 4 g + 3 (4 balanced base-256 digits each, int8) of Y: the
+// digits of Y + B, B = sum_{a<L} 128 * 256^a, are bytes; those of Y are
+// the bytes minus 128.  cy carries between words.  The five limbs that
+// hold bits [128 g - s, 128 g - s + 128) of the mantissa are read first,
+// all at once.
+__device__ __forceinline__ void digit_words4(const RnsSliceParams &P, const SliceElem &e, int g, uint32_t &cy,
+                                             uint32_t (&x)[4]) {
+  uint32_t lim[5] = {0u, 0u, 0u, 0u, 0u};
+  const int64_t o = 128 * (int64_t)g - e.s;   // bit offset of word 4 g into M (may be negative)
+  const int64_t li = o >= 0 ? (o >> 5) : -((31 - o) >> 5);
+  const uint32_t r = (uint32_t)(o - 32 * li);
+  if (e.n) {
+    const arbgpu_arr &A = part_of(P.part, e.part);
+    uint32_t v[5];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+      // limb li + t counted from the least significant; clamped reads stay
+      // inside the element's limbs and are discarded outside
+      const int64_t i = li + t;
+      const int64_t ic = i < 0 ? 0 : (i >= e.n ? e.n - 1 : i);
+      v[t] = A.limbs[(int64_t)(e.n - 1 - ic) * A.ld + e.idx];
+    }
+    // the values are taken unconditionally, so the five reads are issued
+    // together rather than each behind its own range test
+#pragma unroll
+    for (int t = 0; t < 5; ++t) asm volatile("" : "+v"(v[t]));
+#pragma unroll
+    for (int t = 0; t < 5; ++t) lim[t] = (li + t >= 0 && li + t < e.n) ? v[t] : 0u;
   }
-  return (((uint32_t)v) ^ 0x80808080u) & bmask;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int w = 4 * g + u;
+    const int nbytes = P.L - 4 * w;
+    const uint32_t bmask = nbytes >= 4 ? 0xFFFFFFFFu : (nbytes <= 0 ? 0u : ((1u << (8 * nbytes)) - 1u));
+    const uint32_t Bc = 0x80808080u & bmask;
+    const uint32_t xv = r ? ((lim[u] >> r) | (lim[u + 1] << (32u - r))) : lim[u];
+    uint64_t v;
+    if (!e.sg) {
+      v = (uint64_t)Bc + xv + cy;
+      cy = (uint32_t)(v >> 32);
+    } else {
+      v = (uint64_t)Bc - xv - cy;
+      cy = (uint32_t)((v >> 63) & 1u);
+    }
+    x[u] = (((uint32_t)v) ^ 0x80808080u) & bmask;
+  }
 }
 
-// Residue of sum_a d_a 256^a modulo prime j from the two int8 dot-product
-// sums, balanced and split into int8 digits (lo, hi).
-__device__ __forceinline__ void store_residue(const RnsSliceParams &P, int j, int32_t slo, int32_t shi,
+// Residue of sum_a d_a 256^a modulo p from the two int8 dot-product sums,
+// balanced and split into int8 digits (lo, hi) of residue planes 2j, 2j+1.
+__device__ __forceinline__ void store_residue(int j, uint32_t p, uint32_t mu, int32_t slo, int32_t shi,
                                               int8_t *out, int64_t plane) {
-  const uint32_t p = (uint32_t)cp(P.tab.prime)[j], mu = cp(P.tab.mu)[j];
   // S = 256 shi + slo, |S| < 2^31 for L <= 512
   uint32_t r = mod_s32(shi, p, mu);
   r = mod_u32((r << 8) + mod_s32(slo, p, mu), p, mu);
@@ -102,188 +133,273 @@ __device__ __forceinline__ void store_residue(const RnsSliceParams &P, int j, in
   out[(2 * j + 1) * plane] = (int8_t)hi;
 }
 
+// acc += A B over nks steps of 32 inner bytes (fragments at a + 32 ks and
+// b + 32 ks): the loads of up to four steps are issued before their
+// products.
+__device__ __forceinline__ void mfma_run(v16i &acc, const int8_t *a, const uint8_t *b, int nks) {
+  for (int k0 = 0; k0 < nks; k0 += 4) {
+    v4i fa[4], fb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ks = k0 + u < nks ? k0 + u : k0;
+      fa[u] = *reinterpret_cast<const v4i *>(a + 32 * ks);
+      fb[u] = *reinterpret_cast<const v4i *>(b + 32 * ks);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k0 + u < nks) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[u], fb[u], acc, 0, 0, 0);
+  }
+}
+
 }  // namespace
 
-// One thread per element (line, k) of the padded plane: the balanced
-// base-256 digits of the scaled integer, then for every prime the residue
-// sum_a d_a (256^a mod p) by 4-way int8 dot products.  NW > 0: at most NW
-// digit words, held in registers; NW = 0: any number, staged in LDS.
-template <int NW>
+// Residues of the plane elements on INT8 MFMA: r_j = sum_a d_a (256^a mod
+// p_j) is an integer matrix product of the balanced base-256 digits d_a
+// of the scaled integers with the int8 digits (lo, hi) of the weights
+// 256^a mod p_j.  Workgroup: 256 threads, EL consecutive elements of the
+// padded plane.  Phase 1: one thread per element writes its digits into an
+// LDS row of kd bytes (+16 so that 8 consecutive rows fall in distinct
+// 16-byte bank groups).  Phase 2: each wave takes 32 elements; per tile of
+// 16 primes one 32 x 32 MFMA result, whose lane l holds the (lo, hi) sums
+// of 8 primes for element l % 32, reduced modulo p_j and stored as two
+// int8 residue digits.
+template <int EL>
 __global__ __launch_bounds__(256) void rns_slice_kernel(RnsSliceParams P) {
-  extern __shared__ uint32_t dig[];   // NW = 0: [nw][blockDim]
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int64_t gid = (int64_t)blockIdx.x * nt + tid;
+  extern __shared__ __attribute__((aligned(16))) uint8_t dl[];   // [EL][kd + 16]
+  const int tid = threadIdx.x;
+  const int nw = P.tab.nw, kd = P.tab.kd, S = kd + 16, m = P.tab.m;
   const int64_t total = P.lines_pad * P.k_pad;
-  if (gid >= total) return;
-  const int64_t line = gid / P.k_pad;
-  const int64_t k = gid - line * P.k_pad;
-  const SliceElem e = slice_elem(P, line, k);
-  const int nw = P.tab.nw;
-  int8_t *out = P.planes + line * P.k_pad + k;
-  uint32_t cy = 0;
-  if (NW > 0) {
-    uint32_t d[NW > 0 ? NW : 1];
-#pragma unroll
-    for (int w = 0; w < NW; ++w) d[w] = w < nw ? digit_word(P, e, w, cy) : 0u;
-    for (int j = 0; j < P.tab.m; ++j) {
-      const __attribute__((address_space(4))) int32_t *wl = cp(P.tab.wlo) + (int64_t)j * nw;
-      const __attribute__((address_space(4))) int32_t *wh = cp(P.tab.whi) + (int64_t)j * nw;
-      int32_t slo = 0, shi = 0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        if (w < nw) {
-          slo = __builtin_amdgcn_sdot4((int)d[w], wl[w], slo, false);
-          shi = __builtin_amdgcn_sdot4((int)d[w], wh[w], shi, false);
-        }
-      }
-      store_residue(P, j, slo, shi, out, total);
+  const int64_t g0 = (int64_t)blockIdx.x * EL;
+  if (tid < EL) {
+    const int64_t gid = g0 + tid;
+    SliceElem e;
+    if (gid < total) {
+      const int64_t line = gid / P.k_pad;
+      e = slice_elem(P, line, gid - line * P.k_pad);
     }
-  } else {
-    for (int w = 0; w < nw; ++w) dig[w * nt + tid] = digit_word(P, e, w, cy);
-    for (int j = 0; j < P.tab.m; ++j) {
-      const __attribute__((address_space(4))) int32_t *wl = cp(P.tab.wlo) + (int64_t)j * nw;
-      const __attribute__((address_space(4))) int32_t *wh = cp(P.tab.whi) + (int64_t)j * nw;
-      int32_t slo = 0, shi = 0;
-      for (int w = 0; w < nw; ++w) {
-        const int dw = (int)dig[w * nt + tid];
-        slo = __builtin_amdgcn_sdot4(dw, wl[w], slo, false);
-        shi = __builtin_amdgcn_sdot4(dw, wh[w], shi, false);
-      }
-      store_residue(P, j, slo, shi, out, total);
+    uint32_t cy = 0;
+    for (int w4 = 0; w4 < kd / 16; ++w4) {
+      uint32_t x[4] = {0u, 0u, 0u, 0u};
+      if (4 * w4 < nw) digit_words4(P, e, w4, cy, x);   // words past nw have no digits (bmask 0)
+      *reinterpret_cast<uint4 *>(dl + (size_t)tid * S + 16 * w4) = make_uint4(x[0], x[1], x[2], x[3]);
+    }
+  }
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6, h = lane >> 5;
+  for (int wv = wave; wv < EL / 32; wv += 4) {
+    const uint8_t *drow = dl + (size_t)(32 * wv + (lane & 31)) * S + 16 * h;
+    const int64_t gid = g0 + 32 * wv + (lane & 31);
+    int8_t *out = P.planes + gid;
+    for (int rt = 0; rt < (m + 15) / 16; ++rt) {
+      const int8_t *wrow = P.tab.wd + ((int64_t)rt * 32 + (lane & 31)) * kd + 16 * h;
+      v16i acc;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = 0;
+      mfma_run(acc, wrow, drow, kd / 32);
+      // register 4 G + 2 t (+1): lo (hi) sum of prime 16 rt + 8 h + 2 G + t;
+      // the constants of both lane halves come by scalar loads
+#pragma unroll
+      for (int G = 0; G < 4; ++G)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int j0 = 16 * rt + 2 * G + t, j1 = min(j0 + 8, m - 1);
+          if (j0 < m) {
+            const uint32_t p0 = (uint32_t)cp(P.tab.prime)[j0], mu0 = cp(P.tab.mu)[j0];
+            const uint32_t p1 = (uint32_t)cp(P.tab.prime)[j1], mu1 = cp(P.tab.mu)[j1];
+            const int j = j0 + 8 * h;
+            if (j < m && gid < total)
+              store_residue(j, h ? p1 : p0, h ? mu1 : mu0, acc[4 * G + 2 * t], acc[4 * G + 2 * t + 1], out, total);
+          }
+        }
     }
   }
 }
 
 namespace {
 
-// Residue r_j = T mod p_j of entry ij from the three digit-product planes.
-__device__ __forceinline__ uint32_t entry_residue(const RnsCrtParams &P, int j, int64_t ij, int64_t MN,
-                                                  uint32_t p, uint32_t mu) {
-  const uint32_t d0 = mod_s32(P.D[(int64_t)(3 * j) * MN + ij], p, mu);
-  const uint32_t d1 = mod_s32(P.D[(int64_t)(3 * j + 1) * MN + ij], p, mu);
-  const uint32_t d2 = mod_s32(P.D[(int64_t)(3 * j + 2) * MN + ij], p, mu);
-  return mod_u32((mod_u32((d2 << 8) + d1, p, mu) << 8) + d0, p, mu);
+// Residue mod p of d0 + 256 d1 + 65536 d2 (the three digit-product
+// partial sums of one prime).
+__device__ __forceinline__ uint32_t residue3(int32_t d0, int32_t d1, int32_t d2, uint32_t p, uint32_t mu) {
+  const uint32_t r0 = mod_s32(d0, p, mu), r1 = mod_s32(d1, p, mu), r2 = mod_s32(d2, p, mu);
+  return mod_u32((mod_u32((r2 << 8) + r1, p, mu) << 8) + r0, p, mu);
 }
 
 }  // namespace
 
-// One thread per output entry: the explicit Chinese remainder formula
-//   T = sum_j y_j (P / p_j) - k P,  y_j = r_j (P / p_j)^-1 mod p_j,
+// Explicit Chinese remainder formula per entry:
+//   T = sum_j y_j (P / p_j) - k P,  y_j = r_j (P / p_j)^-1 mod p_j (balanced),
 // with k the integer nearest to alpha = sum_j y_j / p_j (|T| < P / 4, so
 // alpha lies within 1/4 of an integer and its double-precision value
-// rounds to the right k).  The products y_j (P / p_j)[q] add up in 64-bit
-// carry-save columns.  WB > 0: the W <= 16 WB columns stay in registers;
-// WB = 0: any W, in blocks of 16 limbs with the y_j staged in LDS.  T, in
-// W two's-complement limbs (LDS), is then rounded to the output.
-template <int WB>
+// rounds to the right k).  The sum is an integer matrix product: the int8
+// digits (lo, hi) of every y_j and of -k against the balanced base-256
+// digits of P / p_j, 256 P / p_j, P and 256 P, on INT8 MFMA.
+//
+// Workgroup: 256 threads, EW entries.  Phase 1: 256 / EW threads per entry
+// compute the y_j digits from the three partial planes of each prime into
+// an LDS row of kc bytes (+16 so that 8 consecutive rows fall in distinct
+// 16-byte bank groups), and k.  Phase 2: each wave takes 32 entries and
+// walks the digit columns in chunks of 32 (8 limbs): one 32 x 32 MFMA
+// result per chunk, whose lane l holds limbs 4 (l / 32) .. +3 of entry
+// l % 32 as four groups of 4 digit sums; the limbs are formed in 64-bit
+// with the carry passed from the lower lane half to the upper and on to
+// the next chunk, and kept in LDS.  Phase 3: every entry is rounded.
+template <int EW>
 __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
-  extern __shared__ uint32_t sh[];
-  const int nt = blockDim.x, tid = threadIdx.x;
-  const int m = P.tab.m, wq = P.tab.wq, W = P.W;
-  uint32_t *T = sh + tid;                                      // T[q * nt]
-  uint16_t *y = reinterpret_cast<uint16_t *>(sh + (size_t)W * nt) + tid;   // WB = 0: y[j * nt]
+  extern __shared__ __attribute__((aligned(16))) uint8_t ylds[];   // [EW][kc + 16], then T
+  uint32_t *tl = reinterpret_cast<uint32_t *>(ylds + (size_t)EW * (P.tab.kc + 16));   // [W][EW]
+  __shared__ double apart[256];
+  constexpr int TPE = 256 / EW;
+  const int tid = threadIdx.x;
+  const int m = P.tab.m, kc = P.tab.kc, S = kc + 16, W = P.W;
   const int64_t MN = P.M * P.N;
-  const int64_t ij = (int64_t)blockIdx.x * nt + tid;
-  if (ij >= MN) return;
-  const __attribute__((address_space(4))) uint32_t *Qt = cp(P.tab.q);
-  const __attribute__((address_space(4))) uint32_t *PP = cp(P.tab.pp);
-  double alpha = 0.0;
-  constexpr int NC = WB > 0 ? 16 * WB : 16;
-  uint64_t col[NC];
+  const int64_t e0 = (int64_t)blockIdx.x * EW;
+
+  // phase 1: balanced y_j = lo + 256 hi as bytes 2j, 2j + 1 of the row
+  {
+    const int e = tid % EW;
+    // part is the same across a wave when EW >= 64: per-prime constants
+    // then come by scalar loads
+    const int part = EW >= 64 ? __builtin_amdgcn_readfirstlane(tid / EW) : tid / EW;
+    const int64_t ij = e0 + e;
+    const bool live = ij < MN;
+    double alpha = 0.0;
+    // lanes past the end read entry 0 (in bounds) and contribute nothing
+    const int32_t *Dij = P.D + (live ? ij : 0);
+    for (int g = part; g < kc / 16; g += TPE) {
+      // the 24 partial-plane reads of 8 primes are issued before any use
+      int32_t dv[8][3];
 #pragma unroll
-  for (int u = 0; u < NC; ++u) col[u] = 0;
-  for (int j = 0; j < m; ++j) {
-    const uint32_t p = (uint32_t)cp(P.tab.prime)[j], mu = cp(P.tab.mu)[j];
-    const uint32_t r = entry_residue(P, j, ij, MN, p, mu);
-    const uint32_t yj = mod_u32(r * (uint32_t)cp(P.tab.c)[j], p, mu);
-    alpha += (double)yj * cp(P.tab.rp)[j];
-    if (WB > 0) {
-      const __attribute__((address_space(4))) uint32_t *Q = Qt + (int64_t)j * wq;
+      for (int u = 0; u < 8; ++u) {
+        const int jj = min(8 * g + u, m - 1);
 #pragma unroll
-      for (int u = 0; u < NC; ++u)
-        if (u < wq) col[u] += (uint64_t)yj * Q[u];
-    } else {
-      y[j * nt] = (uint16_t)yj;
-    }
-  }
-  const uint32_t kq = (uint32_t)__double2int_rn(alpha);   // 0 <= k <= m
-  // S - k P in W limbs (two's complement modulo 2^(32 W))
-  uint64_t carry = 0, kcarry = 0, borrow = 0;
-  auto emit = [&](int q, uint64_t c) {
-    const uint64_t sv = c + carry;   // < 2^58
-    carry = sv >> 32;
-    const uint64_t kp = (uint64_t)(q < wq ? PP[q] : 0u) * kq + kcarry;
-    kcarry = kp >> 32;
-    const uint64_t dv = (uint64_t)(uint32_t)sv - (uint32_t)kp - borrow;
-    borrow = (dv >> 63) & 1u;
-    T[q * nt] = (uint32_t)dv;
-  };
-  if (WB > 0) {
-#pragma unroll
-    for (int u = 0; u < NC; ++u)
-      if (u < W) emit(u, col[u]);
-  } else {
-    for (int q0 = 0; q0 < W; q0 += 16) {
-#pragma unroll
-      for (int u = 0; u < 16; ++u) col[u] = 0;
-      for (int j = 0; j < m; ++j) {
-        const uint64_t yj = y[j * nt];
-        const __attribute__((address_space(4))) uint32_t *Q = Qt + (int64_t)j * wq + q0;
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-          if (q0 + u < wq) col[u] += yj * Q[u];
+        for (int c = 0; c < 3; ++c) dv[u][c] = Dij[(int64_t)(3 * jj + c) * P.ds];
       }
+      uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (q0 + u < W) emit(q0 + u, col[u]);
+      for (int u = 0; u < 8; ++u) {
+        const int j = 8 * g + u;
+        if (j < m) {
+          const uint32_t p = (uint32_t)cp(P.tab.prime)[j], mu = cp(P.tab.mu)[j];
+          const uint32_t r = residue3(dv[u][0], dv[u][1], dv[u][2], p, mu);
+          const uint32_t y = mod_u32(r * cp(P.tab.c)[j], p, mu);
+          int32_t yb = y > (p >> 1) ? (int32_t)y - (int32_t)p : (int32_t)y;
+          yb = live ? yb : 0;
+          alpha += (double)yb * cp(P.tab.rp)[j];
+          const int32_t lo = ((yb + 128) & 255) - 128;
+          const int32_t hi = (yb - lo) >> 8;
+          w[u >> 1] |= (((uint32_t)lo & 0xFFu) | (((uint32_t)hi & 0xFFu) << 8)) << (16 * (u & 1));
+        }
+      }
+      *reinterpret_cast<uint4 *>(ylds + (size_t)e * S + 16 * g) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    apart[tid] = alpha;
+    __syncthreads();
+    if (part == 0) {
+      double a = 0.0;
+#pragma unroll
+      for (int t = 0; t < TPE; ++t) a += apart[e + t * EW];
+      const int32_t nk = live ? -__double2int_rn(a) : 0;   // |k| <= m / 2 + 1
+      const int32_t lo = ((nk + 128) & 255) - 128;
+      ylds[(size_t)e * S + 2 * m] = (uint8_t)lo;
+      ylds[(size_t)e * S + 2 * m + 1] = (uint8_t)((nk - lo) >> 8);
+    }
+    __syncthreads();
+  }
+
+  // phase 2: digit sums on MFMA, limbs with carries
+  {
+    const int lane = tid & 63, wave = tid >> 6, h = lane >> 5;
+    for (int wv = wave; wv < EW / 32; wv += 4) {
+      const uint8_t *yrow = ylds + (size_t)(32 * wv + (lane & 31)) * S + 16 * h;
+      const int el = 32 * wv + (lane & 31);
+      int64_t carry = 0;
+      for (int cc = 0; cc < P.tab.ncc; ++cc) {
+        const int8_t *qrow = P.tab.qd + ((int64_t)cc * 32 + (lane & 31)) * kc + 16 * h;
+        v16i acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0;
+        mfma_run(acc, qrow, yrow, kc / 32);
+        int64_t L[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          L[g] = (int64_t)acc[4 * g] + ((int64_t)acc[4 * g + 1] << 8) + ((int64_t)acc[4 * g + 2] << 16) +
+                 ((int64_t)acc[4 * g + 3] << 24);
+        // lower half first (carry in from the previous chunk), then the
+        // upper half with the lower half's carry out
+        uint32_t limb[4];
+        int64_t v = h ? 0 : carry;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          v += L[g];
+          limb[g] = (uint32_t)v;
+          v >>= 32;
+        }
+        const int64_t vl = __shfl(v, lane & 31);
+        if (h) {
+          v = vl;
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            v += L[g];
+            limb[g] = (uint32_t)v;
+            v >>= 32;
+          }
+        }
+        carry = __shfl(v, (lane & 31) + 32);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int q = 8 * cc + 4 * h + g;
+          if (q < W) tl[q * EW + el] = limb[g];
+        }
+      }
     }
   }
-  const int64_t i = ij / P.N, jj = ij - i * P.N;
-  double m0 = 0.0;
-  int e0 = 0;
-  if (P.rin_m) { m0 = P.rin_m[ij]; e0 = P.rin_e[ij]; }
-  finish_entry([&](int q) { return T[q * nt]; }, W, (int64_t)P.rowv2[i] + P.colv2[jj], P.C,
-               P.c_off + i * P.c_rs + jj * P.c_cs, P.p, P.approx, m0, e0);
+  __syncthreads();
+
+  // phase 3: rounding of the entry to the output
+  if (tid < EW) {
+    const int64_t ij = e0 + tid;
+    if (ij >= MN) return;
+    const uint32_t *T = tl + tid;
+    const int64_t i = ij / P.N, jj = ij - i * P.N;
+    double m0 = 0.0;
+    int e0r = 0;
+    if (P.rin_m) { m0 = P.rin_m[ij]; e0r = P.rin_e[ij]; }
+    finish_entry([&](int q) { return T[q * EW]; }, W, (int64_t)P.rowv2[i] + P.colv2[jj], P.C,
+                 P.c_off + i * P.c_rs + jj * P.c_cs, P.p, P.approx, m0, e0r);
+  }
 }
 
 hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s) {
   const int64_t total = P.lines_pad * P.k_pad;
   if (total == 0) return hipSuccess;
-  const int nw = P.tab.nw;
-  const dim3 grid((unsigned)((total + 255) / 256));
-#define ARB_SLICE(nwmax)                                                                  \
-  if (nw <= nwmax) {                                                                      \
-    hipLaunchKernelGGL(rns_slice_kernel<nwmax>, grid, dim3(256), 0, s, P);                \
-    return hipGetLastError();                                                             \
-  }
-  ARB_SLICE(8) ARB_SLICE(16) ARB_SLICE(24) ARB_SLICE(32)
-#undef ARB_SLICE
-  const int nt = nw <= 64 ? 256 : 64;
-  const size_t lds = sizeof(uint32_t) * nt * (size_t)nw;
-  if (lds > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(rns_slice_kernel<0>, dim3((unsigned)((total + nt - 1) / nt)), dim3(nt), lds, s, P);
+  const size_t S = (size_t)P.tab.kd + 16;
+  if (32 * S > 65536 || 4 * P.tab.nw > P.tab.kd) return hipErrorInvalidValue;
+  int el = 256;
+  while (el > 32 && (size_t)el * S > 65536) el >>= 1;
+  const dim3 grid((unsigned)((total + el - 1) / el));
+  const size_t lds = (size_t)el * S;
+  if (el == 256) hipLaunchKernelGGL(rns_slice_kernel<256>, grid, dim3(256), lds, s, P);
+  else if (el == 128) hipLaunchKernelGGL(rns_slice_kernel<128>, grid, dim3(256), lds, s, P);
+  else if (el == 64) hipLaunchKernelGGL(rns_slice_kernel<64>, grid, dim3(256), lds, s, P);
+  else hipLaunchKernelGGL(rns_slice_kernel<32>, grid, dim3(256), lds, s, P);
   return hipGetLastError();
 }
+
+size_t rns_crt_lds(int ew, int kc, int W) { return (size_t)ew * ((size_t)kc + 16 + 4 * (size_t)W); }
 
 hipError_t launch_rns_crt(const RnsCrtParams &P, hipStream_t s) {
   const int64_t MN = P.M * P.N;
   if (MN == 0) return hipSuccess;
-  const int W = P.W;
-  auto blocks = [&](int nt) { return dim3((unsigned)((MN + nt - 1) / nt)); };
-#define ARB_CRT(wb)                                                                       \
-  if (W <= 16 * wb) {                                                                     \
-    hipLaunchKernelGGL(rns_crt_kernel<wb>, blocks(256), dim3(256), 4 * (size_t)W * 256, s, P); \
-    return hipGetLastError();                                                             \
-  }
-  ARB_CRT(1) ARB_CRT(2) ARB_CRT(3) ARB_CRT(4)
-#undef ARB_CRT
-  // per entry: W limbs and m 16-bit digits in LDS; at most 64 KiB a block
-  const size_t per = 4 * (size_t)W + 2 * (size_t)P.tab.m;
-  int nt = 256;
-  while (nt > 32 && per * nt + 4 > 65536) nt >>= 1;
-  const size_t lds = per * nt + 4;
-  if (lds > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(rns_crt_kernel<0>, blocks(nt), dim3(nt), lds, s, P);
+  if (rns_crt_lds(32, P.tab.kc, P.W) > kRnsCrtLds || P.tab.ncc * 8 < P.W) return hipErrorInvalidValue;
+  // widest entry tile that fits the LDS budget, narrower while the launch
+  // would leave compute units idle
+  int ew = 128;
+  while (ew > 32 && (rns_crt_lds(ew, P.tab.kc, P.W) > kRnsCrtLds || (MN + ew - 1) / ew < 1024)) ew >>= 1;
+  const dim3 grid((unsigned)((MN + ew - 1) / ew));
+  const size_t lds = rns_crt_lds(ew, P.tab.kc, P.W);
+  if (ew == 128) hipLaunchKernelGGL(rns_crt_kernel<128>, grid, dim3(256), lds, s, P);
+  else if (ew == 64) hipLaunchKernelGGL(rns_crt_kernel<64>, grid, dim3(256), lds, s, P);
+  else hipLaunchKernelGGL(rns_crt_kernel<32>, grid, dim3(256), lds, s, P);
   return hipGetLastError();
 }
 

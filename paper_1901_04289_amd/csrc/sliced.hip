@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   }
 
   // epilogue: int32 partial plane of this diagonal group
-  int32_t *D = P.D + (int64_t)G.slot * P.M * P.N;
+  int32_t *D = P.D + (int64_t)G.slot * P.ds;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(256) void recombine_kernel(RecombParams P) {
       const int c = 4 * w + b;
       if (c < P.Lc) {
         int64_t s = 0;
-        for (int sl = P.slot_of[c]; sl < P.slot_of[c + 1]; ++sl) s += P.D[(int64_t)sl * MN + ij];
+        for (int sl = P.slot_of[c]; sl < P.slot_of[c + 1]; ++sl) s += P.D[(int64_t)sl * P.ds + ij];
         carry += s;
       }
       limb |= ((uint32_t)carry & 0xFFu) << (8 * b);

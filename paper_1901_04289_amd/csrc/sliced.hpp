@@ -49,15 +49,17 @@ struct DiagGroup {
 struct MfmaParams {
   const int8_t *A;       // [LA][Mp][Kp]
   const int8_t *B;       // [LB][Np][Kp]
-  int32_t *D;            // [nslots][M][N]
+  int32_t *D;            // [nslots][ds]: entry (i, j) of plane s at s ds + i N + j
   const DiagGroup *groups;
   int64_t M, N, Mp, Np, Kp;
+  int64_t ds;            // plane stride in entries (>= M N)
   int ntm, ntn;          // tiles along M and N
   int ngroups;
 };
 
 struct RecombParams {
-  const int32_t *D;        // [nslots][M][N]
+  const int32_t *D;        // [nslots][ds]
+  int64_t ds;              // plane stride in entries
   const int32_t *slot_of;  // [Lc + 1]: slots of diagonal c are slot_of[c] .. slot_of[c+1]-1
   int Lc;                  // number of diagonals (LA + LB - 1)
   int64_t M, N;
@@ -110,14 +112,25 @@ struct RadExactParams {
 struct RnsTables {
   const int32_t *prime;     // [m]
   const uint32_t *mu;       // [m] floor(2^32 / p)
-  const int32_t *wlo, *whi; // [m][nw] packed int8 digits of 256^a mod p (balanced), a = 4w + b
-  const uint32_t *q;        // [m][wq] limbs (least significant first) of P / p_j, P = prod p_j
-  const uint32_t *pp;       // [wq] limbs of P
-  const uint16_t *c;        // [m] (P / p_j)^-1 mod p_j
+  // [nrt][32][kd] int8 digits (lo, hi) of the balanced 256^a mod p_j,
+  // inner index a < 4 nw (zero beyond); row r of tile rt holds prime
+  // 16 rt + 8 ((r / 4) % 2) + 2 (r / 8) + (r / 2) % 2, lo for even r and hi
+  // for odd r (lane half h of a 32 x 32 MFMA result then holds the (lo, hi)
+  // pairs of primes 16 rt + 8 h .. + 7), nrt = ceil(m / 16)
+  const int8_t *wd;
+  const uint32_t *c;        // [m] (P / p_j)^-1 mod p_j, P = prod p_j
   const double *rp;         // [m] 1 / p_j
+  // [ncc][32][kc] balanced base-256 digits of the reconstruction weights:
+  // inner index 2j -> P / p_j, 2j + 1 -> 256 P / p_j, 2m -> P, 2m + 1 ->
+  // 256 P, zero beyond; digit column 32 cc + sigma(r) in row r, sigma(r) =
+  // 16 ((r / 4) % 2) + 4 (r / 8) + r % 4 (lane half h of a 32 x 32 MFMA
+  // result then holds digits 16 h .. 16 h + 15 of its column in order)
+  const int8_t *qd;
   int m;
   int nw;                   // words of 4 base-256 digits per element
-  int wq;                   // limbs of P
+  int kd;                   // inner length of wd: 4 nw rounded up to 32
+  int kc;                   // inner length of qd: 2m + 2 rounded up to 32
+  int ncc;                  // 32-digit column chunks: ceil(W / 8)
 };
 
 struct RnsSliceParams {
@@ -134,7 +147,8 @@ struct RnsSliceParams {
 };
 
 struct RnsCrtParams {
-  const int32_t *D;          // [3m][M][N]: digit products of weight 1, 256, 65536 per prime
+  const int32_t *D;          // [3m][ds]: digit products of weight 1, 256, 65536 per prime
+  int64_t ds;                // plane stride in entries
   RnsTables tab;
   int64_t M, N;
   int W;                     // two's-complement limbs of T
@@ -149,6 +163,9 @@ struct RnsCrtParams {
 
 hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s);
 hipError_t launch_rns_crt(const RnsCrtParams &P, hipStream_t s);
+// dynamic LDS of the reconstruction kernel for ew entries per workgroup
+size_t rns_crt_lds(int ew, int kc, int W);
+constexpr size_t kRnsCrtLds = 65536;
 
 // Greedy block extraction (one workgroup).
 struct PlanParams {
@@ -212,6 +229,10 @@ hipError_t launch_stats_rows(const StatsParams &P, hipStream_t s);
 hipError_t launch_stats_cols(const StatsParams &P, hipStream_t s);
 hipError_t launch_slice(const SliceParams &P, hipStream_t s);
 hipError_t launch_mfma(const MfmaParams &P, hipStream_t s);
+
+// Stride of the int32 partial planes: the entry count rounded up to 64,
+// which keeps every plane 256-byte aligned.
+inline int64_t plane_stride(int64_t mn) { return (mn + 63) / 64 * 64; }
 hipError_t launch_recombine(const RecombParams &P, hipStream_t s);
 hipError_t launch_rad_prep(const RadPrepParams &P, hipStream_t s);
 hipError_t launch_rad_gemm(const RadGemmParams &P, hipStream_t s);

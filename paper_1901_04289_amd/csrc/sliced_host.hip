@@ -142,12 +142,48 @@ int64_t modinv(int64_t a, int64_t p) {   // a^-1 mod p, gcd(a, p) = 1
   return t < 0 ? t + p : t;
 }
 
-// Residue tables for m primes and nw words of base-256 digits, uploaded to
-// the context workspace (kept while m and nw stay the same): primes and
-// reduction constants, the digit weights 256^a mod p_j as balanced int8
-// pairs, and the Chinese remainder constants P / p_j, P, (P / p_j)^-1 mod p_j.
-int rns_tables(arbgpu_ctx *ctx, int m, int nw, hipStream_t s, RnsTables &tab) {
+// Balanced base-256 digits d_0 .. d_{n-1} (each in [-128, 128)) of X mod
+// 256^n, X given as little-endian limbs.
+void balanced_digits(const std::vector<uint32_t> &X, int n, int8_t *d) {
+  int c = 0;
+  for (int i = 0; i < n; ++i) {
+    const int q = i >> 2;
+    const int byte = q < (int)X.size() ? (int)((X[q] >> (8 * (i & 3))) & 0xFFu) : 0;
+    const int v = byte + c;
+    c = v >= 128;
+    d[i] = (int8_t)(v - 256 * c);
+  }
+}
+
+// Residue tables for m primes, nw words of base-256 digits and W limbs of
+// T, uploaded to the context workspace (kept while m, nw and W stay the
+// same): primes and reduction constants, the digit weights 256^a mod p_j
+// as balanced int8 pairs, and the Chinese remainder constants
+// (P / p_j)^-1 mod p_j and the digits of P / p_j and P.
+int rns_tables(arbgpu_ctx *ctx, int m, int nw, int W, hipStream_t s, RnsTables &tab) {
   const std::vector<int32_t> &pr = rns_primes();
+  const int kc = (int)round_up(2 * (int64_t)m + 2, 32);
+  const int ncc = (W + 7) / 8;
+  const int kd = (int)round_up(4 * (int64_t)nw, 32);
+  const int nrt = (m + 15) / 16;
+  const size_t o_mu = 4 * (size_t)m, o_rp = (o_mu + 4 * (size_t)m + 7) & ~(size_t)7, o_c = o_rp + 8 * (size_t)m,
+               o_wd = (o_c + 4 * (size_t)m + 15) & ~(size_t)15, o_qd = o_wd + (size_t)nrt * 32 * kd,
+               bytes = o_qd + (size_t)ncc * 32 * kc;
+  char *d = (char *)ws_get(ctx, WS_RNS, bytes);
+  if (!d) return ARBGPU_ENOMEM;
+  tab.prime = (const int32_t *)d;
+  tab.mu = (const uint32_t *)(d + o_mu);
+  tab.wd = (const int8_t *)(d + o_wd);
+  tab.rp = (const double *)(d + o_rp);
+  tab.c = (const uint32_t *)(d + o_c);
+  tab.qd = (const int8_t *)(d + o_qd);
+  tab.m = m;
+  tab.nw = nw;
+  tab.kd = kd;
+  tab.kc = kc;
+  tab.ncc = ncc;
+  const int64_t key = (int64_t)m | ((int64_t)nw << 16) | ((int64_t)W << 32);
+  if (ctx->rns_key == key && ctx->ws[WS_RNS].ptr == d) return ARBGPU_OK;
   // P = prod p_j and Q_j = P / p_j as little-endian limbs
   std::vector<uint32_t> P(1, 1u);
   for (int j = 0; j < m; ++j) {
@@ -159,63 +195,58 @@ int rns_tables(arbgpu_ctx *ctx, int m, int nw, hipStream_t s, RnsTables &tab) {
     }
     if (c) P.push_back((uint32_t)c);
   }
-  const int wq = (int)P.size();
-  const size_t o_mu = 4 * (size_t)m, o_wlo = o_mu + 4 * (size_t)m, o_whi = o_wlo + 4 * (size_t)m * nw,
-               o_q = o_whi + 4 * (size_t)m * nw, o_pp = o_q + 4 * (size_t)m * wq, o_rp = o_pp + 4 * (size_t)wq,
-               o_c = o_rp + 8 * (size_t)m, bytes = o_c + 2 * (size_t)m;
-  const size_t o_rp8 = (o_rp + 7) & ~(size_t)7;
-  const size_t o_c8 = o_rp8 + 8 * (size_t)m, bytes8 = o_c8 + 2 * (size_t)m;
-  (void)o_c;
-  (void)bytes;
-  char *d = (char *)ws_get(ctx, WS_RNS, bytes8);
-  if (!d) return ARBGPU_ENOMEM;
-  tab.prime = (const int32_t *)d;
-  tab.mu = (const uint32_t *)(d + o_mu);
-  tab.wlo = (const int32_t *)(d + o_wlo);
-  tab.whi = (const int32_t *)(d + o_whi);
-  tab.q = (const uint32_t *)(d + o_q);
-  tab.pp = (const uint32_t *)(d + o_pp);
-  tab.rp = (const double *)(d + o_rp8);
-  tab.c = (const uint16_t *)(d + o_c8);
-  tab.m = m;
-  tab.nw = nw;
-  tab.wq = wq;
-  const int64_t key = ((int64_t)m << 32) | (int64_t)nw;
-  if (ctx->rns_key == key && ctx->ws[WS_RNS].ptr == d) return ARBGPU_OK;
-  std::vector<char> h(bytes8, 0);
+  std::vector<char> h(bytes, 0);
   int32_t *hp = (int32_t *)h.data();
   uint32_t *hmu = (uint32_t *)(h.data() + o_mu);
-  uint8_t *hlo = (uint8_t *)(h.data() + o_wlo), *hhi = (uint8_t *)(h.data() + o_whi);
-  uint32_t *hq = (uint32_t *)(h.data() + o_q), *hpp = (uint32_t *)(h.data() + o_pp);
-  double *hrp = (double *)(h.data() + o_rp8);
-  uint16_t *hc = (uint16_t *)(h.data() + o_c8);
-  for (int q = 0; q < wq; ++q) hpp[q] = P[q];
+  int8_t *hwd = (int8_t *)(h.data() + o_wd);
+  double *hrp = (double *)(h.data() + o_rp);
+  uint32_t *hc = (uint32_t *)(h.data() + o_c);
+  int8_t *hqd = (int8_t *)(h.data() + o_qd);
+  const int nd = 32 * ncc;                 // digit columns
+  std::vector<int8_t> dig((size_t)nd + 1);
+  // digits of X and of 256 X into inner rows 2i, 2i + 1 of the permuted table
+  auto put = [&](int row2, const std::vector<uint32_t> &X) {
+    balanced_digits(X, nd, dig.data());
+    for (int cc = 0; cc < ncc; ++cc)
+      for (int r = 0; r < 32; ++r) {
+        const int col = 32 * cc + 16 * ((r >> 2) & 1) + 4 * (r >> 3) + (r & 3);
+        int8_t *t = hqd + ((size_t)cc * 32 + r) * kc;
+        t[row2] = dig[col];
+        t[row2 + 1] = col > 0 ? dig[col - 1] : (int8_t)0;
+      }
+  };
+  std::vector<uint32_t> Q(P.size());
   for (int j = 0; j < m; ++j) {
     const int64_t p = pr[j];
     hp[j] = (int32_t)p;
     hmu[j] = (uint32_t)((((uint64_t)1) << 32) / (uint64_t)p);
     hrp[j] = 1.0 / (double)p;
+    // weight digits of prime j: tile j / 16, rows r with lo at even r
+    const int jt = j % 16;
+    const int rlo = 4 * ((jt >> 3) & 1) + 8 * ((jt >> 1) & 3) + 2 * (jt & 1);
+    int8_t *wlo = hwd + ((size_t)(j / 16) * 32 + rlo) * kd, *whi = wlo + kd;
     int64_t w = 1;   // 256^a mod p
     for (int a = 0; a < 4 * nw; ++a) {
       const int64_t bal = w > p / 2 ? w - p : w;
       const int64_t lo = ((bal + 128) & 255) - 128;
-      const int64_t hi = (bal - lo) >> 8;
-      hlo[(size_t)j * 4 * nw + a] = (uint8_t)(int8_t)lo;   // word a/4, byte a%4
-      hhi[(size_t)j * 4 * nw + a] = (uint8_t)(int8_t)hi;
+      wlo[a] = (int8_t)lo;
+      whi[a] = (int8_t)((bal - lo) >> 8);
       w = w * 256 % p;
     }
     // Q_j = P / p_j (exact), its residue mod p_j, and that residue's inverse
     uint64_t rem = 0;
-    for (int q = wq - 1; q >= 0; --q) {
+    for (int q = (int)P.size() - 1; q >= 0; --q) {
       const uint64_t cur = (rem << 32) | P[q];
-      hq[(size_t)j * wq + q] = (uint32_t)(cur / (uint64_t)p);
+      Q[q] = (uint32_t)(cur / (uint64_t)p);
       rem = cur % (uint64_t)p;
     }
     uint64_t qm = 0;
-    for (int q = wq - 1; q >= 0; --q) qm = ((qm << 32) | hq[(size_t)j * wq + q]) % (uint64_t)p;
-    hc[j] = (uint16_t)modinv((int64_t)qm, p);
+    for (int q = (int)P.size() - 1; q >= 0; --q) qm = ((qm << 32) | Q[q]) % (uint64_t)p;
+    hc[j] = (uint32_t)modinv((int64_t)qm, p);
+    put(2 * j, Q);
   }
-  hipError_t e = hipMemcpyAsync(d, h.data(), bytes8, hipMemcpyHostToDevice, s);
+  put(2 * m, P);
+  hipError_t e = hipMemcpyAsync(d, h.data(), bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "residue tables: %s", hipGetErrorString(e));
   ctx->rns_key = key;
@@ -238,7 +269,8 @@ bool rns_fits(int HA, int HB, int64_t Kt) {
   if (m < 1) return false;
   const int W = (int)((t_bits(HA, HB, Kt) + 1 + 31) / 32) + 1;
   const int nw = (std::max(slices_for(HA), slices_for(HB)) + 3) / 4;
-  return 2 * m + 4 * W <= 2048 && nw <= 256;
+  // the reconstruction kernel keeps 32 entries' digit rows and limbs in LDS
+  return rns_crt_lds(32, (int)round_up(2 * (int64_t)m + 2, 32), W) <= kRnsCrtLds && nw <= 256;
 }
 
 // MFMA work of the two forms (digit pairs): base-256 slices L_A L_B, the
@@ -305,7 +337,8 @@ int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, con
   int8_t *planesA = (int8_t *)ws_get(ctx, WS_PLANES_A, bytesA);
   int8_t *planesB = (int8_t *)ws_get(ctx, WS_PLANES_B, bytesB);
   int8_t *planesB2 = sh.cplx ? (int8_t *)ws_get(ctx, WS_PLANES_B2, bytesB) : nullptr;
-  int32_t *D = (int32_t *)ws_get(ctx, WS_D, sizeof(int32_t) * (size_t)nslots * sh.M * sh.N);
+  const int64_t ds = plane_stride(sh.M * sh.N);
+  int32_t *D = (int32_t *)ws_get(ctx, WS_D, sizeof(int32_t) * (size_t)nslots * ds);
   uint32_t *T = (uint32_t *)ws_get(ctx, WS_T, sizeof(uint32_t) * (size_t)nT * sh.M * sh.N);
   const size_t tab_bytes = sizeof(DiagGroup) * groups.size() + sizeof(int32_t) * slot_of.size();
   char *tabs = (char *)ws_get(ctx, WS_TABLES, tab_bytes);
@@ -348,6 +381,7 @@ int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, con
     mp.A = planesA;
     mp.B = q == 0 ? planesB : planesB2;
     mp.D = D;
+    mp.ds = ds;
     mp.groups = dgroups;
     mp.M = sh.M; mp.N = sh.N; mp.Mp = Mp; mp.Np = Np; mp.Kp = Kp;
     mp.ntm = (int)(Mp / kTile); mp.ntn = (int)(Np / kTile);
@@ -357,7 +391,7 @@ int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, con
       ARB_TRY(launch_mfma(mp, s), "mfma");
     }
     RecombParams rp;
-    rp.D = D; rp.slot_of = dslot; rp.Lc = Lc; rp.M = sh.M; rp.N = sh.N; rp.T = T; rp.nT = nT;
+    rp.D = D; rp.ds = ds; rp.slot_of = dslot; rp.Lc = Lc; rp.M = sh.M; rp.N = sh.N; rp.T = T; rp.nT = nT;
     rp.rowv2 = rv2; rp.colv2 = cv2;
     rp.C = out[q];
     rp.c_off = o_off; rp.c_rs = o_rs; rp.c_cs = o_cs;
@@ -390,7 +424,7 @@ int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
   const int nw = (std::max(LA, LB) + 3) / 4;
   if (m < 1) return set_error(ctx, ARBGPU_EINVAL, "residue form: %lld-bit block values", (long long)bits);
   RnsTables tab;
-  int rc = rns_tables(ctx, m, nw, s, tab);
+  int rc = rns_tables(ctx, m, nw, W, s, tab);
   if (rc) return rc;
   // per prime j: weight 1 (lo lo), 256 (lo hi + hi lo), 65536 (hi hi)
   std::vector<DiagGroup> groups;
@@ -411,7 +445,8 @@ int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
   int8_t *planesA = (int8_t *)ws_get(ctx, WS_PLANES_A, bytesA);
   int8_t *planesB = (int8_t *)ws_get(ctx, WS_PLANES_B, bytesB);
   int8_t *planesB2 = sh.cplx ? (int8_t *)ws_get(ctx, WS_PLANES_B2, bytesB) : nullptr;
-  int32_t *D = (int32_t *)ws_get(ctx, WS_D, sizeof(int32_t) * (size_t)3 * m * sh.M * sh.N);
+  const int64_t ds = plane_stride(sh.M * sh.N);
+  int32_t *D = (int32_t *)ws_get(ctx, WS_D, sizeof(int32_t) * (size_t)3 * m * ds);
   char *tabs = (char *)ws_get(ctx, WS_TABLES, sizeof(DiagGroup) * groups.size());
   if (!planesA || !planesB || (sh.cplx && !planesB2) || !D || !tabs) return ARBGPU_ENOMEM;
   DiagGroup *dgroups = (DiagGroup *)tabs;
@@ -448,6 +483,7 @@ int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
     mp.A = planesA;
     mp.B = q == 0 ? planesB : planesB2;
     mp.D = D;
+    mp.ds = ds;
     mp.groups = dgroups;
     mp.M = sh.M; mp.N = sh.N; mp.Mp = Mp; mp.Np = Np; mp.Kp = Kp;
     mp.ntm = (int)(Mp / kTile); mp.ntn = (int)(Np / kTile);
@@ -457,7 +493,7 @@ int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
       ARB_TRY(launch_mfma(mp, s), "mfma");
     }
     RnsCrtParams cp;
-    cp.D = D; cp.tab = tab; cp.M = sh.M; cp.N = sh.N; cp.W = W;
+    cp.D = D; cp.ds = ds; cp.tab = tab; cp.M = sh.M; cp.N = sh.N; cp.W = W;
     cp.rowv2 = rv2; cp.colv2 = cv2;
     cp.C = out[q];
     cp.c_off = o_off; cp.c_rs = o_rs; cp.c_cs = o_cs;
@@ -568,7 +604,7 @@ size_t mat_mul_footprint(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, ui
   const int64_t nslots = (2 * L - 1) + L * L / pmax;
   const int64_t mn = M * N;
   int64_t bytes = L * Mp * Kp + L * Np * Kp * parts;          // digit planes
-  bytes += 4 * nslots * mn + 4 * (int64_t)t_limbs((int)L, (int)L) * mn;   // partial planes, T
+  bytes += 4 * nslots * plane_stride(mn) + 4 * (int64_t)t_limbs((int)L, (int)L) * mn;   // partial planes, T
   bytes += 4 * (2 * M + 2 * N + 8);                            // statistics
   bytes += 16 * (M + N) * Kt + 8 * (M + N) + 12 * parts * mn;  // radius products
   return (size_t)bytes + 65536;
