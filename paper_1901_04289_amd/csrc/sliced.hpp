@@ -87,7 +87,7 @@ struct RadPrepParams {
 
 struct RadGemmParams {
   const double *a_m, *a_r;   // [M][Kt]: |A| and R_A, row-scaled
-  const double *b_mr, *b_r;  // [N][Kt]: |B| + R_B and R_B, column-scaled
+  const double *b_mr, *b_r;  // [Kt][N]: |B| + R_B and R_B, column-scaled
   const int32_t *a_s0, *a_s1, *b_s0, *b_s1;   // frames of a_m, a_r, b_mr, b_r
   const int32_t *tiny;       // nonzero: the exact kernel writes the result
   int64_t M, N, Kt;
