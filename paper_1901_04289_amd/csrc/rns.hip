@@ -29,13 +29,12 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *cp(const T
   return (const __attribute__((address_space(4))) T *)p;
 }
 
-// x mod p for 0 <= x < 2^32 (Barrett with mu = floor(2^32 / p)).
+// x mod p for 0 <= x < 2^32 (Barrett with mu = floor(2^32 / p): the
+// quotient estimate is short by at most one, so one correction suffices).
 __device__ __forceinline__ uint32_t mod_u32(uint32_t x, uint32_t p, uint32_t mu) {
   const uint32_t q = __umulhi(x, mu);
-  uint32_t r = x - q * p;
-  r = r >= p ? r - p : r;
-  r = r >= p ? r - p : r;
-  return r;
+  const uint32_t r = x - q * p;
+  return r >= p ? r - p : r;
 }
 
 // x mod p in [0, p) for signed x.
@@ -119,18 +118,18 @@ __device__ __forceinline__ void digit_words4(const RnsSliceParams &P, const Slic
   }
 }
 
-// Residue of sum_a d_a 256^a modulo p from the two int8 dot-product sums,
-// balanced and split into int8 digits (lo, hi) of residue planes 2j, 2j+1.
-__device__ __forceinline__ void store_residue(int j, uint32_t p, uint32_t mu, int32_t slo, int32_t shi,
+// Residue of S = 256 shi + slo = sum_a d_a 256^a modulo p, balanced and
+// split into the int8 digits (lo, hi) stored at out[0] and out[plane].
+// |S| < 2^30 (4 nw <= 508 digits of |d_a| <= 128 against weight digits of
+// magnitude <= 128 and <= 64), so S + kp, kp = p ceil(2^30 / p), lies in
+// [0, 2^32).
+__device__ __forceinline__ void store_residue(uint32_t p, uint32_t mu, uint32_t kp, int32_t slo, int32_t shi,
                                               int8_t *out, int64_t plane) {
-  // S = 256 shi + slo, |S| < 2^31 for L <= 512
-  uint32_t r = mod_s32(shi, p, mu);
-  r = mod_u32((r << 8) + mod_s32(slo, p, mu), p, mu);
+  const uint32_t r = mod_u32((uint32_t)((shi << 8) + slo) + kp, p, mu);
   const int32_t rb = r > (p >> 1) ? (int32_t)r - (int32_t)p : (int32_t)r;   // balanced, |rb| < 2^14
   const int32_t lo = ((rb + 128) & 255) - 128;
-  const int32_t hi = (rb - lo) >> 8;
-  out[(2 * j) * plane] = (int8_t)lo;
-  out[(2 * j + 1) * plane] = (int8_t)hi;
+  out[0] = (int8_t)lo;
+  out[plane] = (int8_t)((rb - lo) >> 8);
 }
 
 // acc += A B over nks steps of 32 inner bytes (fragments at a + 32 ks and
@@ -189,7 +188,9 @@ __global__ __launch_bounds__(256) void rns_slice_kernel(RnsSliceParams P) {
   for (int wv = wave; wv < EL / 32; wv += 4) {
     const uint8_t *drow = dl + (size_t)(32 * wv + (lane & 31)) * S + 16 * h;
     const int64_t gid = g0 + 32 * wv + (lane & 31);
-    int8_t *out = P.planes + gid;
+    // planes 2j, 2j + 1 of prime j = 16 rt + 8 h + 2 G + t: the lane half
+    // goes into the base, the rest is the same for every lane
+    int8_t *out = P.planes + gid + (int64_t)(16 * h) * total;
     for (int rt = 0; rt < (m + 15) / 16; ++rt) {
       const int8_t *wrow = P.tab.wd + ((int64_t)rt * 32 + (lane & 31)) * kd + 16 * h;
       v16i acc;
@@ -204,11 +205,11 @@ __global__ __launch_bounds__(256) void rns_slice_kernel(RnsSliceParams P) {
         for (int t = 0; t < 2; ++t) {
           const int j0 = 16 * rt + 2 * G + t, j1 = min(j0 + 8, m - 1);
           if (j0 < m) {
-            const uint32_t p0 = (uint32_t)cp(P.tab.prime)[j0], mu0 = cp(P.tab.mu)[j0];
-            const uint32_t p1 = (uint32_t)cp(P.tab.prime)[j1], mu1 = cp(P.tab.mu)[j1];
-            const int j = j0 + 8 * h;
-            if (j < m && gid < total)
-              store_residue(j, h ? p1 : p0, h ? mu1 : mu0, acc[4 * G + 2 * t], acc[4 * G + 2 * t + 1], out, total);
+            const uint32_t p0 = (uint32_t)cp(P.tab.prime)[j0], mu0 = cp(P.tab.mu)[j0], k0 = cp(P.tab.kp)[j0];
+            const uint32_t p1 = (uint32_t)cp(P.tab.prime)[j1], mu1 = cp(P.tab.mu)[j1], k1 = cp(P.tab.kp)[j1];
+            if (j0 + 8 * h < m && gid < total)
+              store_residue(h ? p1 : p0, h ? mu1 : mu0, h ? k1 : k0, acc[4 * G + 2 * t], acc[4 * G + 2 * t + 1],
+                            out + (int64_t)(2 * j0) * total, total);
           }
         }
     }
@@ -218,10 +219,14 @@ __global__ __launch_bounds__(256) void rns_slice_kernel(RnsSliceParams P) {
 namespace {
 
 // Residue mod p of d0 + 256 d1 + 65536 d2 (the three digit-product
-// partial sums of one prime).
-__device__ __forceinline__ uint32_t residue3(int32_t d0, int32_t d1, int32_t d2, uint32_t p, uint32_t mu) {
-  const uint32_t r0 = mod_s32(d0, p, mu), r1 = mod_s32(d1, p, mu), r2 = mod_s32(d2, p, mu);
-  return mod_u32((mod_u32((r2 << 8) + r1, p, mu) << 8) + r0, p, mu);
+// partial sums of one prime), Horner's rule from d2 down; every |d| < 2^30
+// (int32 planes of at most two pairs with 2 Kp 2^14 < 2^31), so each step
+// adds kp = p ceil(2^30 / p) to stay in [0, 2^32).
+__device__ __forceinline__ uint32_t residue3(int32_t d0, int32_t d1, int32_t d2, uint32_t p, uint32_t mu,
+                                             uint32_t kp) {
+  uint32_t r = mod_u32((uint32_t)d2 + kp, p, mu);
+  r = mod_u32((r << 8) + (uint32_t)d1 + kp, p, mu);
+  return mod_u32((r << 8) + (uint32_t)d0 + kp, p, mu);
 }
 
 }  // namespace
@@ -280,7 +285,7 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
         const int j = 8 * g + u;
         if (j < m) {
           const uint32_t p = (uint32_t)cp(P.tab.prime)[j], mu = cp(P.tab.mu)[j];
-          const uint32_t r = residue3(dv[u][0], dv[u][1], dv[u][2], p, mu);
+          const uint32_t r = residue3(dv[u][0], dv[u][1], dv[u][2], p, mu, cp(P.tab.kp)[j]);
           const uint32_t y = mod_u32(r * cp(P.tab.c)[j], p, mu);
           int32_t yb = y > (p >> 1) ? (int32_t)y - (int32_t)p : (int32_t)y;
           yb = live ? yb : 0;

@@ -112,6 +112,7 @@ struct RadExactParams {
 struct RnsTables {
   const int32_t *prime;     // [m]
   const uint32_t *mu;       // [m] floor(2^32 / p)
+  const uint32_t *kp;       // [m] p ceil(2^30 / p): makes values above -2^30 nonnegative
   // [nrt][32][kd] int8 digits (lo, hi) of the balanced 256^a mod p_j,
   // inner index a < 4 nw (zero beyond); row r of tile rt holds prime
   // 16 rt + 8 ((r / 4) % 2) + 2 (r / 8) + (r / 2) % 2, lo for even r and hi

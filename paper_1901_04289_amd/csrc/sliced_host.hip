@@ -166,13 +166,15 @@ int rns_tables(arbgpu_ctx *ctx, int m, int nw, int W, hipStream_t s, RnsTables &
   const int ncc = (W + 7) / 8;
   const int kd = (int)round_up(4 * (int64_t)nw, 32);
   const int nrt = (m + 15) / 16;
-  const size_t o_mu = 4 * (size_t)m, o_rp = (o_mu + 4 * (size_t)m + 7) & ~(size_t)7, o_c = o_rp + 8 * (size_t)m,
+  const size_t o_mu = 4 * (size_t)m, o_kp = o_mu + 4 * (size_t)m, o_rp = (o_kp + 4 * (size_t)m + 7) & ~(size_t)7,
+               o_c = o_rp + 8 * (size_t)m,
                o_wd = (o_c + 4 * (size_t)m + 15) & ~(size_t)15, o_qd = o_wd + (size_t)nrt * 32 * kd,
                bytes = o_qd + (size_t)ncc * 32 * kc;
   char *d = (char *)ws_get(ctx, WS_RNS, bytes);
   if (!d) return ARBGPU_ENOMEM;
   tab.prime = (const int32_t *)d;
   tab.mu = (const uint32_t *)(d + o_mu);
+  tab.kp = (const uint32_t *)(d + o_kp);
   tab.wd = (const int8_t *)(d + o_wd);
   tab.rp = (const double *)(d + o_rp);
   tab.c = (const uint32_t *)(d + o_c);
@@ -198,6 +200,7 @@ int rns_tables(arbgpu_ctx *ctx, int m, int nw, int W, hipStream_t s, RnsTables &
   std::vector<char> h(bytes, 0);
   int32_t *hp = (int32_t *)h.data();
   uint32_t *hmu = (uint32_t *)(h.data() + o_mu);
+  uint32_t *hkp = (uint32_t *)(h.data() + o_kp);
   int8_t *hwd = (int8_t *)(h.data() + o_wd);
   double *hrp = (double *)(h.data() + o_rp);
   uint32_t *hc = (uint32_t *)(h.data() + o_c);
@@ -220,6 +223,7 @@ int rns_tables(arbgpu_ctx *ctx, int m, int nw, int W, hipStream_t s, RnsTables &
     const int64_t p = pr[j];
     hp[j] = (int32_t)p;
     hmu[j] = (uint32_t)((((uint64_t)1) << 32) / (uint64_t)p);
+    hkp[j] = (uint32_t)((((int64_t)1 << 30) + p - 1) / p * p);
     hrp[j] = 1.0 / (double)p;
     // weight digits of prime j: tile j / 16, rows r with lo at even r
     const int jt = j % 16;
@@ -269,8 +273,9 @@ bool rns_fits(int HA, int HB, int64_t Kt) {
   if (m < 1) return false;
   const int W = (int)((t_bits(HA, HB, Kt) + 1 + 31) / 32) + 1;
   const int nw = (std::max(slices_for(HA), slices_for(HB)) + 3) / 4;
-  // the reconstruction kernel keeps 32 entries' digit rows and limbs in LDS
-  return rns_crt_lds(32, (int)round_up(2 * (int64_t)m + 2, 32), W) <= kRnsCrtLds && nw <= 256;
+  // the reconstruction kernel keeps 32 entries' digit rows and limbs in LDS;
+  // the residue sums of at most 4 nw <= 508 digits stay below 2^30
+  return rns_crt_lds(32, (int)round_up(2 * (int64_t)m + 2, 32), W) <= kRnsCrtLds && nw <= 127;
 }
 
 // MFMA work of the two forms (digit pairs): base-256 slices L_A L_B, the
