@@ -37,13 +37,6 @@ __device__ __forceinline__ uint32_t mod_u32(uint32_t x, uint32_t p, uint32_t mu)
   return r >= p ? r - p : r;
 }
 
-// x mod p in [0, p) for signed x.
-__device__ __forceinline__ uint32_t mod_s32(int32_t x, uint32_t p, uint32_t mu) {
-  const uint32_t ax = x < 0 ? (uint32_t)0 - (uint32_t)x : (uint32_t)x;
-  const uint32_t r = mod_u32(ax, p, mu);
-  return (x < 0 && r) ? p - r : r;
-}
-
 // Scaled integer of one plane element: its limbs, shift and sign.
 struct SliceElem {
   int n = 0, part = 0;

@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   const int ntiles = P.ntm * P.ntn;
   // Workgroups are handed to the 8 XCDs round-robin by id.  Work item
   // (group, tile) for XCD x = id % 8, slot = id / 8: groups x, x + 8, ...
-  // (the host sorted groups by size, so every XCD gets a similar share),
+  // (the host orders the groups so that every XCD gets a similar share),
   // tiles of one group in order, so the workgroups resident on one XCD
   // share A row blocks and B column blocks in that XCD's L2.
   const int bid = blockIdx.x;

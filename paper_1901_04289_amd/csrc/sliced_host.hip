@@ -438,8 +438,9 @@ int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
     groups.push_back(DiagGroup{4 * j, 2 * j, 2 * j + 1, 3 * j});
     groups.push_back(DiagGroup{4 * j + 2, 2 * j + 1, 2 * j + 2, 3 * j + 2});
   }
-  std::stable_sort(groups.begin(), groups.end(),
-                   [](const DiagGroup &x, const DiagGroup &y) { return (x.a1 - x.a0) > (y.a1 - y.a0); });
+  // sizes 2, 1, 1 repeat along the table, so every XCD (groups x, x + 8,
+  // ...) gets a similar share, and work items of both lengths run side by
+  // side instead of all finishing (and storing their planes) together
   const int ngroups_real = (int)groups.size();
   while (groups.size() % 8) groups.push_back(DiagGroup{0, 0, 0, -1});
   {
