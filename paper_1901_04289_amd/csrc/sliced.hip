@@ -208,7 +208,9 @@ __device__ __forceinline__ int swz(int row, int chunk) { return row * kKStep + (
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void mfma_diag_kernel(MfmaParams P) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[2][2][kTile * kKStep];  // [buf][A/B]
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  // the wave index is the same across a wave: say so, so that addresses
+  // built from it stay in scalar registers
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 1, wn = wave & 1;
   const int ntiles = P.ntm * P.ntn;
   // Workgroups are handed to the 8 XCDs round-robin by id.  Work item
@@ -337,18 +339,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     ks = nks;
   }
 
-  // epilogue: int32 partial plane of this diagonal group
-  int32_t *D = P.D + (int64_t)G.slot * P.ds;
+  // epilogue: int32 partial plane of this diagonal group.  Addresses are a
+  // wave base (the quarter's corner, scalar) plus a 32-bit byte offset: a
+  // lane part and a row part that is the same for every lane (the host
+  // keeps N < 2^22, so 128 rows of the plane span fewer than 2^31 bytes).
+  const int64_t r0 = (int64_t)tm * kTile + wm * 128, c0 = (int64_t)tn * kTile + wn * 128;
+  char *D = reinterpret_cast<char *>(P.D + (int64_t)G.slot * P.ds + r0 * P.N + c0);
+  const uint32_t rowb = 4u * (uint32_t)P.N;
+  const uint32_t loff = (uint32_t)(lane >> 5) * 4u * rowb + 4u * (uint32_t)(lane & 31);
+  auto put = [&](uint32_t dr, int j, int32_t v) {
+    *reinterpret_cast<int32_t *>(D + (loff + (dr * rowb + 128u * (uint32_t)j))) = v;
+  };
+  if (r0 + 128 <= P.M && c0 + 128 <= P.N) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t row = (int64_t)tm * kTile + wm * 128 + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        const int64_t col = (int64_t)tn * kTile + wn * 128 + j * 32 + (lane & 31);
-        if (row < P.M && col < P.N) D[row * P.N + col] = acc[i][j][r];
-      }
+        for (int r = 0; r < 16; ++r) put(i * 32 + (r >> 2) * 8 + (r & 3), j, acc[i][j][r]);
+  } else {
+    // edge quarter: rows below rlim and columns below clim are inside
+    const int rlim = (int)min<int64_t>(P.M - r0, 128) - (lane >> 5) * 4;
+    const int clim = (int)min<int64_t>(P.N - c0, 128) - (lane & 31);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int dr = i * 32 + (r >> 2) * 8 + (r & 3);
+          if (dr < rlim && j * 32 < clim) put((uint32_t)dr, j, acc[i][j][r]);
+        }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -691,7 +713,7 @@ hipError_t launch_slice(const SliceParams &P, hipStream_t s) {
 hipError_t launch_mfma(const MfmaParams &P, hipStream_t s) {
   // the group table is padded to a multiple of 8 (see the kernel's mapping)
   const int64_t n = (int64_t)P.ngroups * P.ntm * P.ntn;
-  if (P.ngroups % 8 != 0) return hipErrorInvalidValue;
+  if (P.ngroups % 8 != 0 || P.N >= ((int64_t)1 << 22)) return hipErrorInvalidValue;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(mfma_diag_kernel, dim3((unsigned)n), dim3(256), 0, s, P);
   return hipGetLastError();
