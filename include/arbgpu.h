@@ -131,7 +131,9 @@ const char *arbgpu_last_error(const arbgpu_ctx *ctx);
  * {real part, imaginary part} and the real and imaginary results are each
  * the exact sum of their 2N real terms, rounded once (Section 3.6).
  * EINVAL: p < 2, N < 0, NULL operand, cap of res < ceil(p/32), radius
- * output NULL without APPROX. */
+ * output NULL without APPROX, or p too large for the widest compiled
+ * window (38 limbs: p + bitlength(t + 1) + 41 <= 1216 with t = N + 1
+ * terms, 2N + 1 for complex). */
 int arbgpu_dot(arbgpu_ctx *ctx, const arbgpu_out *res, int64_t res_idx,
                const arbgpu_arr *initial, int64_t init_idx, int sub,
                const arbgpu_arr *x, int64_t xoff, int64_t xstep,
@@ -144,7 +146,11 @@ int arbgpu_dot(arbgpu_ctx *ctx, const arbgpu_out *res, int64_t res_idx,
  * scaled-integer block product on INT8 MFMA (Algorithm 2) with base-256
  * slices or with residues modulo small primes; none changes a single
  * output bit.  EINVAL on shape mismatch, p < 2, output cap too
- * small, NULL pointers. */
+ * small, NULL pointers, or when the chosen (or, without an ALGO flag,
+ * every) path cannot hold the operands: the limb kernel's window as for
+ * arbgpu_dot; base-256 slices up to integer heights below 4095 bits per
+ * block; residues while the exact block values stay within about 7800
+ * bits (the reconstruction's LDS rows). */
 int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A,
                    const arbgpu_mat *B, int64_t p, uint32_t flags,
                    arbgpu_stream stream);
