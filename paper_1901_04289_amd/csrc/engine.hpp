@@ -96,16 +96,24 @@ ARB_HD void add_term(Window<NS> &W, int lo, const Opnd<NA> &a, const Opnd<NA> &b
   uint32_t z[L];
 #pragma unroll
   for (int i = 0; i < NS; ++i) z[i] = 0;
+  // products of limb index sum below kc are left out: they sum below
+  // kc 2^(32 kc + 32) (1 + 2^-31) 2^base < 2^(lo - 8 + log2 kc) <= 2^lo for
+  // kc <= 2 NA <= 80, i.e. below one window unit
+  const int kc = (lo - base - 40) >> 5;
+  bool skipped;
   {
     uint32_t p[2 * NA];
-    mul_limbs<NA>(a.l, a.n, b.l, b.n, p);
+    mul_limbs<NA>(a.l, a.n, b.l, p, kc < 0 ? 0 : kc, skipped);
 #pragma unroll
     for (int i = 0; i < 2 * NA; ++i) z[NS + i] = p[i];
   }
   uint32_t x[NS];
   uint32_t sticky = 0;
   shr_sticky<L, NS>(z, (uint32_t)(top - base), x, sticky);
-  if (sticky) e_inc += 1;
+  // the window takes floor(P' 2^(base - lo)); the exact term lies within
+  // one unit above it, or two when products were left out
+  if (skipped) e_inc += 2;
+  else if (sticky) e_inc += 1;
   if (e_inc) W.pt += 1;
   W.err += e_inc;
   const uint32_t inv = neg ? 0xFFFFFFFFu : 0u;

@@ -177,16 +177,22 @@ ARB_HD void shl_var(uint32_t (&x)[L], uint32_t S) {
   }
 }
 
-// Schoolbook product of LS-first limb arrays: p = a * b (a has na <= NA
-// nonzero-position limbs, b has nb).  Rows and columns beyond na / nb are
-// skipped (the branches are uniform when the operands share a length).
+// Schoolbook product of LS-first limb arrays, p = a * b, with the low
+// products left out (the "mulhigh" of Section 3.4): in every row i < na a
+// leading run of BLK-column blocks whose pairs all have i + j < kc is
+// skipped and the rest of the row is an exact multiply-add chain (a[i]
+// b[j] + p[i + j] + carry < 2^64) from the first kept block.  The left-out
+// pairs sum below sum_{s<kc} (s+1) 2^(64 + 32 s) < kc 2^(32 kc + 32)
+// (1 + 2^-31) units of p's lowest limb.  `skipped` tells whether a pair was
+// left out.  Limbs of a at and above na are not read; rows are skipped
+// uniformly when the operands of a wave share a length, blocks when their
+// exponents put the same products below the window.
 template <int NA>
-ARB_HD void mul_limbs(const uint32_t (&a)[NA], int na, const uint32_t (&b)[NA], int nb,
-                      uint32_t (&p)[2 * NA]) {
-  // Limbs of a and b at and above na / nb are zero, so only the rows of a
-  // are skipped; every row is a straight multiply-add chain (a[i] b[j] +
-  // p[i + j] + carry < 2^64), which the compiler unrolls into registers.
-  (void)nb;
+ARB_HD void mul_limbs(const uint32_t (&a)[NA], int na, const uint32_t (&b)[NA], uint32_t (&p)[2 * NA], int kc,
+                      bool &skipped) {
+  constexpr int BLK = NA >= 24 ? 8 : 4;
+  static_assert(NA % BLK == 0, "operand limbs in whole blocks");
+  skipped = na > 0 && kc >= BLK;
 #pragma unroll
   for (int k = 0; k < 2 * NA; ++k) p[k] = 0;
 #pragma unroll
@@ -194,10 +200,15 @@ ARB_HD void mul_limbs(const uint32_t (&a)[NA], int na, const uint32_t (&b)[NA], 
     if (i < na) {
       uint32_t c = 0;
 #pragma unroll
-      for (int j = 0; j < NA; ++j) {
-        const uint64_t t = (uint64_t)a[i] * b[j] + p[i + j] + c;
-        p[i + j] = (uint32_t)t;
-        c = (uint32_t)(t >> 32);
+      for (int jb = 0; jb < NA; jb += BLK) {
+        if (i + jb + BLK - 1 >= kc) {
+#pragma unroll
+          for (int j = jb; j < jb + BLK; ++j) {
+            const uint64_t t = (uint64_t)a[i] * b[j] + p[i + j] + c;
+            p[i + j] = (uint32_t)t;
+            c = (uint32_t)(t >> 32);
+          }
+        }
       }
       p[i + NA] = c;
     }
