@@ -48,11 +48,11 @@ class Pool:
 
 def random_jobs(seed, njobs, cplx_frac=0.5):
     """A mix of real and complex jobs over shared operand pools: lengths
-    0..300, p 2..1100, narrow and wide operands, strides of both signs,
+    0..2100, p 2..1100, narrow and wide operands, strides of both signs,
     initial values, sub, approx and the precision cut."""
     r = random.Random(seed)
     rng = gen.rng_for(40, seed)
-    L = 6000
+    L = 8000   # the longest job (N = 2100, stride 3) reads up to index ~6400
     pools = {}
     for name, prec, rs in (("n", 100, 90), ("w", 2200, 700)):
         parts = [Pool(gen.random_operands(rng, L, rng.integers(1, prec + 1, L), -20, 20,
@@ -62,7 +62,7 @@ def random_jobs(seed, njobs, cplx_frac=0.5):
     inits = [Pool(gen.random_operands(rng, 64, 120, -4, 4, radius_shift=100)) for _ in range(2)]
     specs = []
     for i in range(njobs):
-        N = r.choice([0, 1, 2, 5, 17, 64, 100, 300])
+        N = r.choice([0, 1, 2, 5, 17, 64, 100, 300, 1500, 2100])
         p = r.choice([2, 30, 64, 100, 128, 200, 512, 700, 1100])
         pool = pools[r.choice("nw")]
         cplx = r.random() < cplx_frac
@@ -243,4 +243,38 @@ def test_config3_full_batch_sampled(ctx):
         for (ops, st), want in zip(host, (wre, wim)):
             e = compare_entry(gen.to_canonical(ops, i), want, int(st[i]))
             assert e is None, (i, n, int(w.precs[i]), e)
+    b.close()
+
+
+def test_batch_long_dots_that_cancel(ctx):
+    # long dots of 2n + 1 terms whose first 2n cancel exactly: the first
+    # window level cannot decide, so the wave refines over all terms; the
+    # results are exact
+    r = random.Random(41)
+    # ~1100-bit operands at p ~ 1000: the widest shape
+    outs = arbgpu.DeviceOut.empty(4, 1100)
+    jobs, want, keep = [], [], []
+    for k, (n, p) in enumerate([(1600, 1000), (700, 1100), (3000, 960), (1200, 1000)]):
+        xs, ys = [], []
+        for _ in range(n):
+            xs.append(((r.randrange(2), r.getrandbits(1100) | 1 | (1 << 1099), r.randrange(-10, 11)), None))
+            ys.append(((r.randrange(2), r.getrandbits(1000) | 1 | (1 << 999), r.randrange(-10, 11)), None))
+        tiny = ((k % 2, 1, -400 - k), None)
+        one = ((0, 1, 1), None)
+        X = xs + xs + [tiny]
+        Y = ys + [((1 - s, M, e), rad) for (s, M, e), rad in ys] + [one]
+        dX = arbgpu.DeviceArray.from_host(gen.from_canonical(X))
+        dY = arbgpu.DeviceArray.from_host(gen.from_canonical(Y))
+        keep += [dX, dY]
+        jobs.append(arbgpu.dot_job([outs.out()], k, [dX.arr()], 0, 1, [dY.arr()], 0, 1, 2 * n + 1, p))
+        want.append(oracle.dot(X, Y, p))
+    say("batch long dots that cancel")
+    b = arbgpu.Batch(ctx, jobs)
+    b.launch()
+    _sync()
+    host, st = outs.to_host()
+    for k, w in enumerate(want):
+        assert compare_entry(gen.to_canonical(host, k), w, int(st[k])) is None, k
+        m, rad = gen.to_canonical(host, k)
+        assert m[1] == 1 and rad is None   # exactly the tiny term, zero radius
     b.close()
