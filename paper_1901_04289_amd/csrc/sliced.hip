@@ -240,20 +240,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   // global -> register staging: thread covers chunk (tid & 7) of rows
   // (tid >> 3) + 32 u, u = 0..7, for A and for B; the loads for step s + 1
   // are issued at the start of step s and stored to LDS at its end.
+  // (addresses: a scalar base per step plus a 32-bit lane offset; 256 rows
+  // of K_pad bytes stay below 2^31 bytes)
   const int srow = tid >> 3, schunk = tid & 7;
-  const int8_t *baseA = P.A + ((int64_t)tm * kTile + srow) * P.Kp + schunk * 16;
-  const int8_t *baseB = P.B + ((int64_t)tn * kTile + srow) * P.Kp + schunk * 16;
-  const int64_t rowstep = 32 * P.Kp;
+  const char *tileA = reinterpret_cast<const char *>(P.A) + (int64_t)tm * kTile * P.Kp;
+  const char *tileB = reinterpret_cast<const char *>(P.B) + (int64_t)tn * kTile * P.Kp;
+  const uint32_t goff = (uint32_t)srow * (uint32_t)P.Kp + (uint32_t)schunk * 16u;
+  const uint32_t rowstep = 32u * (uint32_t)P.Kp;
   v4i stA[8], stB[8];
   auto gload = [&](v4i (&sa)[8], v4i (&sb)[8], int pr, int ks) {
     const int a = G.a0 + pr;
     const int b = G.c - a;
-    const int8_t *pa = baseA + a * planeA + ks * kKStep;
-    const int8_t *pb = baseB + b * planeB + ks * kKStep;
+    const char *pa = tileA + a * planeA + ks * kKStep;
+    const char *pb = tileB + b * planeB + ks * kKStep;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      sa[u] = *reinterpret_cast<const v4i *>(pa + u * rowstep);
-      sb[u] = *reinterpret_cast<const v4i *>(pb + u * rowstep);
+      sa[u] = *reinterpret_cast<const v4i *>(pa + (goff + u * rowstep));
+      sb[u] = *reinterpret_cast<const v4i *>(pb + (goff + u * rowstep));
     }
   };
   auto lstore = [&](const v4i (&sa)[8], const v4i (&sb)[8], int buf) {
@@ -713,7 +716,7 @@ hipError_t launch_slice(const SliceParams &P, hipStream_t s) {
 hipError_t launch_mfma(const MfmaParams &P, hipStream_t s) {
   // the group table is padded to a multiple of 8 (see the kernel's mapping)
   const int64_t n = (int64_t)P.ngroups * P.ntm * P.ntn;
-  if (P.ngroups % 8 != 0 || P.N >= ((int64_t)1 << 22)) return hipErrorInvalidValue;
+  if (P.ngroups % 8 != 0 || P.N >= ((int64_t)1 << 22) || P.Kp >= ((int64_t)1 << 23)) return hipErrorInvalidValue;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(mfma_diag_kernel, dim3((unsigned)n), dim3(256), 0, s, P);
   return hipGetLastError();
