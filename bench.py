@@ -43,9 +43,9 @@ PEAK_INT8_TOPS = 5000.0   # MI355X dense INT8 MFMA, 5.0 POP/s
 # INT8 forms, from the FETCH_SIZE (x2, copy-calibrated) and WRITE_SIZE (x1)
 # counter runs in profiles/mfma_diag_kernel_matmul2048_p512.txt; valid only
 # for the kernel source they were taken on (sha256 prefix of csrc/sliced.hip).
-MFMA_TRAFFIC_BYTES = {"residues": (1745132 * 2 + 3489792) * 1024.0,
-                      "slices": (28.33e6 * 2 + 2228224) * 1024.0}
-MFMA_TRAFFIC_SRC = "74d0e883e0c8e1d7"
+MFMA_TRAFFIC_BYTES = {"residues": (1800637 * 2 + 3489792) * 1024.0,
+                      "slices": (37918505 * 2 + 2228224) * 1024.0}
+MFMA_TRAFFIC_SRC = "649d049405eb4858"
 
 
 def _mfma_traffic(n, form):
