@@ -237,6 +237,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=600, help="0 skips the serving loop")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--no-peaks", action="store_true", help="skip the machine-limit microbenchmarks")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also copy a buffer of this many MiB once (reference kernel for HBM counters)")
     a = ap.parse_args()
@@ -279,6 +280,14 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    peaks = None
+    if not a.no_peaks:
+        scratch = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
+        peaks = ctx.probe_peaks(scratch, stream)
+        del scratch
+        torch.cuda.empty_cache()
+        log(f"[bench] measured limits {peaks}")
 
     macs = float(M) * N * K
     KERNELS = ("stats", "slice", "mfma", "recombine")
@@ -360,6 +369,10 @@ def main():
         "int8_forms": forms,
         "cpu_baseline": cpu,
     }
+    if peaks is not None:
+        out["measured_peaks"] = peaks
+        out["roofline"]["measured_peak"] = peaks["int8_mfma_tops"]
+        out["roofline"]["frac_of_measured_peak"] = achieved / peaks["int8_mfma_tops"]
     ctx.mat_mul(C, dA, dB, M, N, K, p, 0)
     torch.cuda.synchronize()
 

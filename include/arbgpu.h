@@ -260,6 +260,8 @@ int arbgpu_ticket_times(arbgpu_ctx *ctx, uint64_t ticket, int64_t times_ns[3]);
  * "dot_batch") and returns their total
  * milliseconds and count.  EINVAL on NULL arguments. */
 int arbgpu_timing(arbgpu_ctx *ctx, int enable);
+int arbgpu_timing_read(arbgpu_ctx *ctx, const char *kernel, double *ms_total,
+                       int64_t *launches);
 
 /* Shape of the last scaled-integer product run on this context: writes up
  * to n of {digit planes of A, digit planes of B, int32 partial planes,
@@ -267,8 +269,32 @@ int arbgpu_timing(arbgpu_ctx *ctx, int enable);
  * slices), digit-plane pairs multiplied} to out (host memory).  All zero
  * before the first such product.  EINVAL on NULL. */
 int arbgpu_plan_info(arbgpu_ctx *ctx, int64_t *out, int n);
-int arbgpu_timing_read(arbgpu_ctx *ctx, const char *kernel, double *ms_total,
-                       int64_t *launches);
+
+/* Machine limits measured on the context's device, the denominators the
+ * kernels' roofline fractions are read against (the published figures are
+ * for a 2.4 GHz clock the chip need not hold under load).  Runs six
+ * microbenchmark kernels on `stream`, each once untimed and then five times
+ * between HIP events, and waits for them; takes about a second.  Writes up
+ * to n of these to out (host memory):
+ *   [0] dense INT8 matrix-core throughput, TOP/s (32x32x32 int8 MFMA,
+ *       operands in registers, 8 independent accumulators per wave)
+ *   [1] dense FP64 matrix-core throughput, TFLOP/s (16x16x4 f64 MFMA)
+ *   [2] HBM copy bandwidth, GB/s counting bytes read plus bytes written
+ *   [3] HBM read bandwidth, GB/s
+ *   [4] vector 32x32+64 -> 64-bit integer multiply-adds (v_mad_u64_u32),
+ *       G lane-operations/s
+ *   [5] vector high-half 32x32 multiplies (v_mul_hi_u32), G lane-ops/s
+ *   [6] mean shader clock during the INT8 probe, MHz (cycle counter over
+ *       the constant-rate wall clock)
+ *   [7] compute units
+ * and zeros past 7.  `buf` is caller-owned device scratch of `bytes` bytes,
+ * 256-byte aligned, at least 136 MiB (8 MiB of sinks and clock records plus
+ * two streamed halves of a multiple of 64 MiB; give 2 GiB or more so the
+ * halves exceed the on-package cache); its contents are overwritten and
+ * need no initialisation.  EINVAL on NULL, misalignment or a short buffer,
+ * EDEVICE on a host-only context or a HIP error.  Not for graph capture. */
+int arbgpu_probe_peaks(arbgpu_ctx *ctx, void *buf, size_t bytes, arbgpu_stream stream,
+                       double *out, int n);
 
 #ifdef __cplusplus
 }

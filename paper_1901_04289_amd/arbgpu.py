@@ -96,7 +96,12 @@ EXPORTS = {
     "arbgpu_plan_info": (ctypes.c_int, [c_p, ctypes.POINTER(c_i64), ctypes.c_int]),
     "arbgpu_timing_read": (ctypes.c_int, [c_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(c_i64)]),
+    "arbgpu_probe_peaks": (ctypes.c_int, [c_p, c_p, ctypes.c_size_t, c_p, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.c_int]),
 }
+
+PEAK_KEYS = ["int8_mfma_tops", "fp64_mfma_tflops", "hbm_copy_gbs", "hbm_read_gbs", "mad_u64_u32_gops",
+             "mul_hi_u32_gops", "clock_mhz", "compute_units"]
 
 
 def load(path: str = LIB_PATH):
@@ -256,6 +261,14 @@ class Context:
         n = c_i64()
         self._check(self.lib.arbgpu_timing_read(self.h, kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def probe_peaks(self, buf, stream=None):
+        """Measured machine limits (dict keyed by PEAK_KEYS); `buf` is a
+        device tensor of at least 136 MiB used as scratch."""
+        out = (ctypes.c_double * 8)()
+        self._check(self.lib.arbgpu_probe_peaks(self.h, ctypes.c_void_p(buf.data_ptr()),
+                                                buf.numel() * buf.element_size(), _stream_handle(stream), out, 8))
+        return dict(zip(PEAK_KEYS, list(out)))
 
     # -- raw entry points (ctypes structs) --------------------------------
     def dot_raw(self, res: Sequence[Out], res_idx: int, initial: Optional[Sequence[Arr]], init_idx: int,

@@ -44,8 +44,14 @@ def limb_shapes():
 LIMB_FLAGS = ["-mllvm", "-pragma-unroll-threshold=200000"]
 
 
+# The machine-limit probes keep FP64 matrix-core accumulators in ordinary
+# vector registers; without this the loop-carried accumulators are copied
+# to and from the accumulation registers around every multiply.
+FILE_FLAGS = {"peaks.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src: str, obj: str, defines=()):
-    extra = LIMB_FLAGS if defines else []
+    extra = (LIMB_FLAGS if defines else []) + FILE_FLAGS.get(os.path.basename(src), [])
     cmd = [HIPCC] + CFLAGS + extra + [f"-D{d}" for d in defines] + ["-c", src, "-o", obj]
     t = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)

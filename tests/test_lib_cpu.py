@@ -156,6 +156,18 @@ def test_host_only_context_validates_submit(hctx, lib):
     assert lib.arbgpu_serve_config(hctx.h, 0, 0) == arbgpu.EINVAL
 
 
+def test_host_only_context_validates_probe_peaks(hctx, lib):
+    out = (ctypes.c_double * 8)()
+    fake = ctypes.c_void_p(1 << 20)     # never dereferenced: every call below fails validation
+    need = (8 << 20) + (128 << 20)
+    assert lib.arbgpu_probe_peaks(hctx.h, None, need, None, out, 8) == arbgpu.EINVAL
+    assert lib.arbgpu_probe_peaks(hctx.h, fake, need, None, None, 8) == arbgpu.EINVAL
+    assert lib.arbgpu_probe_peaks(hctx.h, ctypes.c_void_p((1 << 20) + 64), need, None, out, 8) == arbgpu.EINVAL
+    assert lib.arbgpu_probe_peaks(hctx.h, fake, need - 1, None, out, 8) == arbgpu.EINVAL
+    assert "need at least" in hctx.last_error()
+    assert lib.arbgpu_probe_peaks(hctx.h, fake, need, None, out, 8) == arbgpu.EDEVICE
+
+
 def test_init_rejects_bad_device(lib):
     h = ctypes.c_void_p()
     assert lib.arbgpu_init(ctypes.byref(h), -2, 0, None) == arbgpu.EINVAL
