@@ -149,8 +149,9 @@ int arbgpu_dot(arbgpu_ctx *ctx, const arbgpu_out *res, int64_t res_idx,
  * small, NULL pointers, or when the chosen (or, without an ALGO flag,
  * every) path cannot hold the operands: the limb kernel's window as for
  * arbgpu_dot; base-256 slices up to integer heights below 4095 bits per
- * block; residues while the exact block values stay within about 7800
- * bits (the reconstruction's LDS rows). */
+ * block; residues up to heights of about 4060 bits (127 words of four
+ * base-256 digits, so that the residue sums stay below 2^30) while the
+ * exact block values fit the reconstruction's LDS rows (about 8000 bits). */
 int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A,
                    const arbgpu_mat *B, int64_t p, uint32_t flags,
                    arbgpu_stream stream);
@@ -288,8 +289,8 @@ int arbgpu_plan_info(arbgpu_ctx *ctx, int64_t *out, int n);
  *       the constant-rate wall clock)
  *   [7] compute units
  * and zeros past 7.  `buf` is caller-owned device scratch of `bytes` bytes,
- * 256-byte aligned, at least 136 MiB (8 MiB of sinks and clock records plus
- * two streamed halves of a multiple of 64 MiB; give 2 GiB or more so the
+ * 256-byte aligned, at least 264 MiB (8 MiB of sinks and clock records plus
+ * two streamed halves of a multiple of 128 MiB; give 2 GiB or more so the
  * halves exceed the on-package cache); its contents are overwritten and
  * need no initialisation.  EINVAL on NULL, misalignment or a short buffer,
  * EDEVICE on a host-only context or a HIP error.  Not for graph capture. */

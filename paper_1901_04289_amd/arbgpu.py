@@ -264,7 +264,7 @@ class Context:
 
     def probe_peaks(self, buf, stream=None):
         """Measured machine limits (dict keyed by PEAK_KEYS); `buf` is a
-        device tensor of at least 136 MiB used as scratch."""
+        device tensor of at least 264 MiB used as scratch."""
         out = (ctypes.c_double * 8)()
         self._check(self.lib.arbgpu_probe_peaks(self.h, ctypes.c_void_p(buf.data_ptr()),
                                                 buf.numel() * buf.element_size(), _stream_handle(stream), out, 8))

@@ -235,16 +235,19 @@ __device__ __forceinline__ uint32_t residue3(int32_t d0, int32_t d1, int32_t d2,
 // Workgroup: 256 threads, EW entries.  Phase 1: 256 / EW threads per entry
 // compute the y_j digits from the three partial planes of each prime into
 // an LDS row of kc bytes (+16 so that 8 consecutive rows fall in distinct
-// 16-byte bank groups), and k.  Phase 2: each wave takes 32 entries and
-// walks the digit columns in chunks of 32 (8 limbs): one 32 x 32 MFMA
-// result per chunk, whose lane l holds limbs 4 (l / 32) .. +3 of entry
-// l % 32 as four groups of 4 digit sums; the limbs are formed in 64-bit
-// with the carry passed from the lower lane half to the upper and on to
-// the next chunk, and kept in LDS.  Phase 3: every entry is rounded.
+// 16-byte bank groups), and k.  Phase 2: the waves split the blocks of 32
+// entries and (for a single block) its chunks of 32 digit columns (8
+// limbs) into runs of consecutive chunks: one 32 x 32 MFMA result per
+// chunk, whose lane l holds limbs 4 (l / 32) .. +3 of entry l % 32 as four
+// groups of 4 digit sums; the limbs are formed in 64-bit with the carry
+// passed from the lower lane half to the upper and on along the run, and
+// kept in LDS with the run's signed carry out.  Phase 3: every entry adds
+// the runs' carries in limb order and is rounded.
 template <int EW>
 __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
   extern __shared__ __attribute__((aligned(16))) uint8_t ylds[];   // [EW][kc + 16], then T
   uint32_t *tl = reinterpret_cast<uint32_t *>(ylds + (size_t)EW * (P.tab.kc + 16));   // [W][EW]
+  int32_t *cyl = reinterpret_cast<int32_t *>(tl + (size_t)P.W * EW);                  // [ncc][EW], EW = 32
   __shared__ double apart[256];
   constexpr int TPE = 256 / EW;
   const int tid = threadIdx.x;
@@ -304,50 +307,61 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
     __syncthreads();
   }
 
-  // phase 2: digit sums on MFMA, limbs with carries
+  // phase 2: digit sums on MFMA; each wave walks a run of consecutive limb
+  // chunks of one entry block, passing the carry along the run, and
+  // stores each chunk's 8 limbs and, at the end of its run, the signed
+  // carry out (zero for the other chunks)
   {
     const int lane = tid & 63, wave = tid >> 6, h = lane >> 5;
-    for (int wv = wave; wv < EW / 32; wv += 4) {
-      const uint8_t *yrow = ylds + (size_t)(32 * wv + (lane & 31)) * S + 16 * h;
-      const int el = 32 * wv + (lane & 31);
-      int64_t carry = 0;
-      for (int cc = 0; cc < P.tab.ncc; ++cc) {
-        const int8_t *qrow = P.tab.qd + ((int64_t)cc * 32 + (lane & 31)) * kc + 16 * h;
-        v16i acc;
+    // entry blocks; runs per block: with 64 entries two waves walk all
+    // chunks of a block each (splitting them further measured slower, the
+    // carry pass below costing more than the shorter walks gain), with 32
+    // entries the four waves share the one block
+    constexpr int NB = EW / 32, RB = EW == 32 ? 4 : 1;
+    const int ncc = P.tab.ncc, rl = (ncc + RB - 1) / RB;
+    const int wv = wave % NB, c0 = (wave / NB) * rl, c1 = min(c0 + rl, ncc);
+    const uint8_t *yrow = ylds + (size_t)(32 * wv + (lane & 31)) * S + 16 * h;
+    const int el = 32 * wv + (lane & 31);
+    int64_t carry = 0;
+    for (int cc = c0; cc < c1; ++cc) {
+      const int8_t *qrow = P.tab.qd + ((int64_t)cc * 32 + (lane & 31)) * kc + 16 * h;
+      v16i acc;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] = 0;
-        mfma_run(acc, qrow, yrow, kc / 32);
-        int64_t L[4];
+      for (int r = 0; r < 16; ++r) acc[r] = 0;
+      mfma_run(acc, qrow, yrow, kc / 32);
+      int64_t L[4];
 #pragma unroll
-        for (int g = 0; g < 4; ++g)
-          L[g] = (int64_t)acc[4 * g] + ((int64_t)acc[4 * g + 1] << 8) + ((int64_t)acc[4 * g + 2] << 16) +
-                 ((int64_t)acc[4 * g + 3] << 24);
-        // lower half first (carry in from the previous chunk), then the
-        // upper half with the lower half's carry out
-        uint32_t limb[4];
-        int64_t v = h ? 0 : carry;
+      for (int g = 0; g < 4; ++g)
+        L[g] = (int64_t)acc[4 * g] + ((int64_t)acc[4 * g + 1] << 8) + ((int64_t)acc[4 * g + 2] << 16) +
+               ((int64_t)acc[4 * g + 3] << 24);
+      // lower half first (carry in from the previous chunk of the run),
+      // then the upper half with the lower half's carry out; the carry out
+      // of a run is below 2^22 in magnitude (every column sum is below
+      // kc 2^14 < 2^25)
+      uint32_t limb[4];
+      int64_t v = h ? 0 : carry;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        v += L[g];
+        limb[g] = (uint32_t)v;
+        v >>= 32;
+      }
+      const int64_t vl = __shfl(v, lane & 31);
+      if (h) {
+        v = vl;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
           v += L[g];
           limb[g] = (uint32_t)v;
           v >>= 32;
         }
-        const int64_t vl = __shfl(v, lane & 31);
-        if (h) {
-          v = vl;
+      }
+      carry = __shfl(v, (lane & 31) + 32);
+      if (RB > 1 && h) cyl[cc * EW + el] = cc + 1 == c1 ? (int32_t)carry : 0;
 #pragma unroll
-          for (int g = 0; g < 4; ++g) {
-            v += L[g];
-            limb[g] = (uint32_t)v;
-            v >>= 32;
-          }
-        }
-        carry = __shfl(v, (lane & 31) + 32);
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const int q = 8 * cc + 4 * h + g;
-          if (q < W) tl[q * EW + el] = limb[g];
-        }
+      for (int g = 0; g < 4; ++g) {
+        const int q = 8 * cc + 4 * h + g;
+        if (q < W) tl[q * EW + el] = limb[g];
       }
     }
   }
@@ -357,7 +371,23 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
   if (tid < EW) {
     const int64_t ij = e0 + tid;
     if (ij >= MN) return;
-    const uint32_t *T = tl + tid;
+    uint32_t *T = tl + tid;
+    // the runs' carries, added in limb order (a chunk's 8 limbs are read
+    // together)
+    int64_t c = 0;
+    for (int cc = 0; EW == 32 && cc < P.tab.ncc; ++cc) {
+      uint32_t t[8];
+#pragma unroll
+      for (int g = 0; g < 8; ++g) t[g] = 8 * cc + g < W ? T[(8 * cc + g) * EW] : 0u;
+      const int32_t co = cyl[cc * EW + tid];
+#pragma unroll
+      for (int g = 0; g < 8; ++g) {
+        const int64_t v = (int64_t)t[g] + c;
+        if (8 * cc + g < W) T[(8 * cc + g) * EW] = (uint32_t)v;
+        c = v >> 32;
+      }
+      c += co;
+    }
     const int64_t i = ij / P.N, jj = ij - i * P.N;
     double m0 = 0.0;
     int e0r = 0;
@@ -383,20 +413,22 @@ hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s) {
   return hipGetLastError();
 }
 
-size_t rns_crt_lds(int ew, int kc, int W) { return (size_t)ew * ((size_t)kc + 16 + 4 * (size_t)W); }
+size_t rns_crt_lds(int ew, int kc, int W) {
+  return (size_t)ew * ((size_t)kc + 16 + 4 * (size_t)W + (ew == 32 ? 4 * (size_t)((W + 7) / 8) : 0));
+}
 
 hipError_t launch_rns_crt(const RnsCrtParams &P, hipStream_t s) {
   const int64_t MN = P.M * P.N;
   if (MN == 0) return hipSuccess;
-  if (rns_crt_lds(32, P.tab.kc, P.W) > kRnsCrtLds || P.tab.ncc * 8 < P.W) return hipErrorInvalidValue;
-  // widest entry tile that fits the LDS budget, narrower while the launch
-  // would leave compute units idle
-  int ew = 128;
-  while (ew > 32 && (rns_crt_lds(ew, P.tab.kc, P.W) > kRnsCrtLds || (MN + ew - 1) / ew < 1024)) ew >>= 1;
+  if (rns_crt_lds(32, P.tab.kc, P.W) > kRnsCrtLds || P.tab.ncc * 8 < P.W || P.tab.ncc != (P.W + 7) / 8)
+    return hipErrorInvalidValue;
+  // 64 entries per workgroup (four threads per entry in phase 1) measured
+  // faster than 128 and than fewer threads; 32 when that tile would take
+  // more than 64 KiB of LDS or the launch would leave compute units idle
+  const int ew = rns_crt_lds(64, P.tab.kc, P.W) <= 65536 && (MN + 63) / 64 >= 1024 ? 64 : 32;
   const dim3 grid((unsigned)((MN + ew - 1) / ew));
   const size_t lds = rns_crt_lds(ew, P.tab.kc, P.W);
-  if (ew == 128) hipLaunchKernelGGL(rns_crt_kernel<128>, grid, dim3(256), lds, s, P);
-  else if (ew == 64) hipLaunchKernelGGL(rns_crt_kernel<64>, grid, dim3(256), lds, s, P);
+  if (ew == 64) hipLaunchKernelGGL(rns_crt_kernel<64>, grid, dim3(256), lds, s, P);
   else hipLaunchKernelGGL(rns_crt_kernel<32>, grid, dim3(256), lds, s, P);
   return hipGetLastError();
 }

@@ -166,7 +166,10 @@ hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s);
 hipError_t launch_rns_crt(const RnsCrtParams &P, hipStream_t s);
 // dynamic LDS of the reconstruction kernel for ew entries per workgroup
 size_t rns_crt_lds(int ew, int kc, int W);
-constexpr size_t kRnsCrtLds = 65536;
+// its budget: 64 KiB of digit rows and limbs plus the chunk carries, at
+// most 32 entries x 64 chunks x 4 bytes (a gfx950 workgroup may hold up to
+// 160 KiB)
+constexpr size_t kRnsCrtLds = 65536 + 8192;
 
 // Greedy block extraction (one workgroup).
 struct PlanParams {

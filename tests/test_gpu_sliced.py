@@ -194,21 +194,22 @@ def test_sliced_radius_wide_range(ctx, seed, spread, bside):
 
 @pytest.mark.parametrize("cplx", [False, True])
 def test_rns_widest_shapes(ctx, cplx):
-    # operands near 3700 bits: ~500 primes, ~235 limbs of T, 122 digit words;
-    # the residue slicer runs with 64 elements per workgroup and the
-    # reconstruction with 32 entries per workgroup at its largest LDS rows
+    # operands near 4000 bits: ~540 primes, ~252 limbs of T, 126 digit
+    # words (the residue sums allow 127); the residue slicer runs with 64
+    # elements per workgroup and the reconstruction with 32 entries per
+    # workgroup in about 70 KiB of LDS
     rng = gen.rng_for(24, int(cplx))
-    M, N, K, p = 4, 9, 3, 3700
-    prec = rng.integers(3500, 3701, 4 * M * N)
-    A = gen.random_operands(rng, M * N, prec[:M * N], -6, 6, radius_shift=3690, zero_frac=0.05)
-    B = gen.random_operands(rng, N * K, prec[M * N:M * N + N * K], -6, 6, zero_frac=0.05)
-    Ai = gen.random_operands(rng, M * N, prec[2 * M * N:3 * M * N], -6, 6, radius_shift=3690) if cplx else None
-    Bi = gen.random_operands(rng, N * K, prec[3 * M * N:3 * M * N + N * K], -6, 6) if cplx else None
+    M, N, K, p = 4, 9, 3, 4000
+    prec = rng.integers(3800, 4001, 4 * M * N)
+    A = gen.random_operands(rng, M * N, prec[:M * N], -3, 3, radius_shift=3990, zero_frac=0.05)
+    B = gen.random_operands(rng, N * K, prec[M * N:M * N + N * K], -3, 3, zero_frac=0.05)
+    Ai = gen.random_operands(rng, M * N, prec[2 * M * N:3 * M * N], -3, 3, radius_shift=3990) if cplx else None
+    Bi = gen.random_operands(rng, N * K, prec[3 * M * N:3 * M * N + N * K], -3, 3) if cplx else None
     flags = arbgpu.COMPLEX if cplx else 0
     say(f"residue form widest shapes complex={cplx}")
     (out, st), im = run(ctx, A, B, M, N, K, p, flags | arbgpu.ALGO_RNS, Ai=Ai, Bi=Bi)
     plan = ctx.plan_info()
-    assert plan["primes"] > 450, plan
+    assert plan["primes"] > 500, plan
     # the base-256 slices give the same bits
     (o2, s2), im2 = run(ctx, A, B, M, N, K, p, flags | arbgpu.ALGO_SLICED, Ai=Ai, Bi=Bi)
     assert np.array_equal(out.limbs, o2.limbs) and np.array_equal(out.exp, o2.exp)
@@ -231,13 +232,13 @@ def test_rns_widest_shapes(ctx, cplx):
 
 
 def test_rns_beyond_its_limits(ctx):
-    # 4000-bit operands: T needs ~8000 bits, more than the residue form's
-    # LDS rows hold, so a forced residue product is refused and the
-    # automatic choice takes the base-256 slices (heights < 4095 bits)
+    # 4070-bit operands: 128 digit words, more than the residue sums allow
+    # (127), so a forced residue product is refused and the automatic
+    # choice takes the base-256 slices (heights < 4095 bits)
     rng = gen.rng_for(25, 0)
-    M, N, K, p = 2, 5, 2, 4000
-    A = gen.random_operands(rng, M * N, 4000, -3, 3)
-    B = gen.random_operands(rng, N * K, 4000, -3, 3)
+    M, N, K, p = 2, 5, 2, 4070
+    A = gen.random_operands(rng, M * N, 4070, -3, 3)
+    B = gen.random_operands(rng, N * K, 4070, -3, 3)
     with pytest.raises(arbgpu.ArbgpuError, match="residue form does not fit"):
         run(ctx, A, B, M, N, K, p, arbgpu.ALGO_RNS)
     (out, st), _ = run(ctx, A, B, M, N, K, p, 0)

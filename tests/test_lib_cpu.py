@@ -159,7 +159,7 @@ def test_host_only_context_validates_submit(hctx, lib):
 def test_host_only_context_validates_probe_peaks(hctx, lib):
     out = (ctypes.c_double * 8)()
     fake = ctypes.c_void_p(1 << 20)     # never dereferenced: every call below fails validation
-    need = (8 << 20) + (128 << 20)
+    need = (8 << 20) + (256 << 20)
     assert lib.arbgpu_probe_peaks(hctx.h, None, need, None, out, 8) == arbgpu.EINVAL
     assert lib.arbgpu_probe_peaks(hctx.h, fake, need, None, None, 8) == arbgpu.EINVAL
     assert lib.arbgpu_probe_peaks(hctx.h, ctypes.c_void_p((1 << 20) + 64), need, None, out, 8) == arbgpu.EINVAL
