@@ -112,17 +112,16 @@ __device__ __forceinline__ void digit_words4(const RnsSliceParams &P, const Slic
 }
 
 // Residue of S = 256 shi + slo = sum_a d_a 256^a modulo p, balanced and
-// split into the int8 digits (lo, hi) stored at out[0] and out[plane].
+// split into its int8 digits (lo, hi), returned as the bytes lo | hi << 8.
 // |S| < 2^30 (4 nw <= 508 digits of |d_a| <= 128 against weight digits of
 // magnitude <= 128 and <= 64), so S + kp, kp = p ceil(2^30 / p), lies in
 // [0, 2^32).
-__device__ __forceinline__ void store_residue(uint32_t p, uint32_t mu, uint32_t kp, int32_t slo, int32_t shi,
-                                              int8_t *out, int64_t plane) {
+__device__ __forceinline__ uint32_t residue_digits(uint32_t p, uint32_t mu, uint32_t kp, int32_t slo,
+                                                   int32_t shi) {
   const uint32_t r = mod_u32((uint32_t)((shi << 8) + slo) + kp, p, mu);
   const int32_t rb = r > (p >> 1) ? (int32_t)r - (int32_t)p : (int32_t)r;   // balanced, |rb| < 2^14
   const int32_t lo = ((rb + 128) & 255) - 128;
-  out[0] = (int8_t)lo;
-  out[plane] = (int8_t)((rb - lo) >> 8);
+  return ((uint32_t)lo & 0xFFu) | ((((uint32_t)(rb - lo) >> 8) & 0xFFu) << 8);
 }
 
 // acc += A B over nks steps of 32 inner bytes (fragments at a + 32 ks and
@@ -153,8 +152,11 @@ __device__ __forceinline__ void mfma_run(v16i &acc, const int8_t *a, const uint8
 // LDS row of kd bytes (+16 so that 8 consecutive rows fall in distinct
 // 16-byte bank groups).  Phase 2: each wave takes 32 elements; per tile of
 // 16 primes one 32 x 32 MFMA result, whose lane l holds the (lo, hi) sums
-// of 8 primes for element l % 32, reduced modulo p_j and stored as two
-// int8 residue digits.
+// of 8 primes for element l % 32, reduced modulo p_j to two int8 residue
+// digits; a byte transpose within quads of lanes turns each lane's 4
+// digits of one element into 4 elements' digits of one plane, stored as
+// one word (the padded plane holds whole blocks of 32 elements and starts
+// 16-byte aligned).
 template <int EL>
 __global__ __launch_bounds__(256) void rns_slice_kernel(RnsSliceParams P) {
   extern __shared__ __attribute__((aligned(16))) uint8_t dl[];   // [EL][kd + 16]
@@ -177,34 +179,49 @@ __global__ __launch_bounds__(256) void rns_slice_kernel(RnsSliceParams P) {
     }
   }
   __syncthreads();
-  const int lane = tid & 63, wave = tid >> 6, h = lane >> 5;
+  const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, q = lane & 3;
+  // byte selectors of the two transpose steps (quad partners at lane
+  // distance 2, then 1)
+  const uint32_t sel1 = q < 2 ? 0x05040100u : 0x03020706u;
+  const uint32_t sel2 = (q & 1) ? 0x03070105u : 0x06020400u;
   for (int wv = wave; wv < EL / 32; wv += 4) {
     const uint8_t *drow = dl + (size_t)(32 * wv + (lane & 31)) * S + 16 * h;
-    const int64_t gid = g0 + 32 * wv + (lane & 31);
-    // planes 2j, 2j + 1 of prime j = 16 rt + 8 h + 2 G + t: the lane half
-    // goes into the base, the rest is the same for every lane
-    int8_t *out = P.planes + gid + (int64_t)(16 * h) * total;
+    // this lane stores elements 4 e' .. 4 e' + 3 (e' = (lane % 32) / 4) of
+    // its planes
+    int8_t *out = P.planes + g0 + 32 * wv + (lane & 28);
+    const bool inside = g0 + 32 * wv < total;
     for (int rt = 0; rt < (m + 15) / 16; ++rt) {
       const int8_t *wrow = P.tab.wd + ((int64_t)rt * 32 + (lane & 31)) * kd + 16 * h;
       v16i acc;
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[r] = 0;
       mfma_run(acc, wrow, drow, kd / 32);
-      // register 4 G + 2 t (+1): lo (hi) sum of prime 16 rt + 8 h + 2 G + t;
-      // the constants of both lane halves come by scalar loads
+      // register 4 G + 2 t (+1): lo (hi) sum of prime 16 rt + 8 h + 2 G + t,
+      // whose digits are planes 2 (8 h + 2 G + t) (+1) of the tile; the
+      // constants of both lane halves come by scalar loads
+      uint32_t wd[4];
 #pragma unroll
-      for (int G = 0; G < 4; ++G)
+      for (int G = 0; G < 4; ++G) {
+        wd[G] = 0u;
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          const int j0 = 16 * rt + 2 * G + t, j1 = min(j0 + 8, m - 1);
-          if (j0 < m) {
-            const uint32_t p0 = (uint32_t)cp(P.tab.prime)[j0], mu0 = cp(P.tab.mu)[j0], k0 = cp(P.tab.kp)[j0];
-            const uint32_t p1 = (uint32_t)cp(P.tab.prime)[j1], mu1 = cp(P.tab.mu)[j1], k1 = cp(P.tab.kp)[j1];
-            if (j0 + 8 * h < m && gid < total)
-              store_residue(h ? p1 : p0, h ? mu1 : mu0, h ? k1 : k0, acc[4 * G + 2 * t], acc[4 * G + 2 * t + 1],
-                            out + (int64_t)(2 * j0) * total, total);
-          }
+          const int j0 = min(16 * rt + 2 * G + t, m - 1), j1 = min(j0 + 8, m - 1);
+          const uint32_t p0 = (uint32_t)cp(P.tab.prime)[j0], mu0 = cp(P.tab.mu)[j0], k0 = cp(P.tab.kp)[j0];
+          const uint32_t p1 = (uint32_t)cp(P.tab.prime)[j1], mu1 = cp(P.tab.mu)[j1], k1 = cp(P.tab.kp)[j1];
+          wd[G] |= residue_digits(h ? p1 : p0, h ? mu1 : mu0, h ? k1 : k0, acc[4 * G + 2 * t],
+                                  acc[4 * G + 2 * t + 1]) << (16 * t);
         }
+      }
+      // 4 x 4 byte transpose within each quad of lanes: lane 4 e' + q then
+      // holds plane 32 rt + 16 h + 4 G + q of elements 4 e' .. 4 e' + 3
+#pragma unroll
+      for (int G = 0; G < 4; ++G) {
+        const uint32_t x = __builtin_amdgcn_perm((uint32_t)__builtin_amdgcn_mov_dpp((int)wd[G], 0x4E, 0xF, 0xF, false),
+                                                 wd[G], sel1);
+        wd[G] = __builtin_amdgcn_perm((uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false), x, sel2);
+        const int plane = 32 * rt + 16 * h + 4 * G + q;
+        if (plane < 2 * m && inside) *reinterpret_cast<uint32_t *>(out + (int64_t)plane * total) = wd[G];
+      }
     }
   }
 }
@@ -402,6 +419,8 @@ hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s) {
   if (total == 0) return hipSuccess;
   const size_t S = (size_t)P.tab.kd + 16;
   if (32 * S > 65536 || 4 * P.tab.nw > P.tab.kd) return hipErrorInvalidValue;
+  // whole blocks of 32 elements, 16-byte aligned plane rows
+  if ((total & 31) != 0 || ((uintptr_t)P.planes & 15) != 0) return hipErrorInvalidValue;
   int el = 256;
   while (el > 32 && (size_t)el * S > 65536) el >>= 1;
   const dim3 grid((unsigned)((total + el - 1) / el));
