@@ -124,16 +124,32 @@ __device__ __forceinline__ uint32_t residue_digits(uint32_t p, uint32_t mu, uint
   return ((uint32_t)lo & 0xFFu) | ((((uint32_t)(rb - lo) >> 8) & 0xFFu) << 8);
 }
 
+// Fragments of steps k0 .. k0 + 3 of a run of 32-byte steps (at a + 32 ks;
+// steps past nks repeat step k0 and are not used).
+__device__ __forceinline__ void frag_load4(v4i (&f)[4], const int8_t *a, int k0, int nks) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int ks = k0 + u < nks ? k0 + u : k0;
+    f[u] = *reinterpret_cast<const v4i *>(a + 32 * ks);
+  }
+}
+
 // acc += A B over nks steps of 32 inner bytes (fragments at a + 32 ks and
-// b + 32 ks): the loads of up to four steps are issued before their
-// products.
-__device__ __forceinline__ void mfma_run(v16i &acc, const int8_t *a, const uint8_t *b, int nks) {
+// b + 32 ks), the A fragments of the first four steps already in fa0: the
+// loads of up to four steps are issued before their products.
+__device__ __forceinline__ void mfma_run(v16i &acc, const v4i (&fa0)[4], const int8_t *a, const uint8_t *b,
+                                         int nks) {
   for (int k0 = 0; k0 < nks; k0 += 4) {
     v4i fa[4], fb[4];
+    if (k0 == 0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) fa[u] = fa0[u];
+    } else {
+      frag_load4(fa, a, k0, nks);
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int ks = k0 + u < nks ? k0 + u : k0;
-      fa[u] = *reinterpret_cast<const v4i *>(a + 32 * ks);
       fb[u] = *reinterpret_cast<const v4i *>(b + 32 * ks);
     }
 #pragma unroll
@@ -190,12 +206,22 @@ __global__ __launch_bounds__(256) void rns_slice_kernel(RnsSliceParams P) {
     // its planes
     int8_t *out = P.planes + g0 + 32 * wv + (lane & 28);
     const bool inside = g0 + 32 * wv < total;
-    for (int rt = 0; rt < (m + 15) / 16; ++rt) {
-      const int8_t *wrow = P.tab.wd + ((int64_t)rt * 32 + (lane & 31)) * kd + 16 * h;
+    const int nrt = (m + 15) / 16;
+    const int8_t *wbase = P.tab.wd + (int64_t)(lane & 31) * kd + 16 * h;
+    v4i fnext[4];
+    frag_load4(fnext, wbase, 0, kd / 32);
+    for (int rt = 0; rt < nrt; ++rt) {
+      const int8_t *wrow = wbase + (int64_t)rt * 32 * kd;
+      // the next tile's first weight fragments load during this tile's
+      // products and residue arithmetic
+      v4i fcur[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) fcur[u] = fnext[u];
+      frag_load4(fnext, rt + 1 < nrt ? wrow + 32 * kd : wbase, 0, kd / 32);
       v16i acc;
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[r] = 0;
-      mfma_run(acc, wrow, drow, kd / 32);
+      mfma_run(acc, fcur, wrow, drow, kd / 32);
       // register 4 G + 2 t (+1): lo (hi) sum of prime 16 rt + 8 h + 2 G + t,
       // whose digits are planes 2 (8 h + 2 G + t) (+1) of the tile; the
       // constants of both lane halves come by scalar loads
@@ -342,10 +368,12 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
     int64_t carry = 0;
     for (int cc = c0; cc < c1; ++cc) {
       const int8_t *qrow = P.tab.qd + ((int64_t)cc * 32 + (lane & 31)) * kc + 16 * h;
+      v4i f0[4];
+      frag_load4(f0, qrow, 0, kc / 32);
       v16i acc;
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[r] = 0;
-      mfma_run(acc, qrow, yrow, kc / 32);
+      mfma_run(acc, f0, qrow, yrow, kc / 32);
       int64_t L[4];
 #pragma unroll
       for (int g = 0; g < 4; ++g)
