@@ -53,13 +53,31 @@ __device__ __forceinline__ void stats_elem(const StatsParams &P, int64_t line, i
   }
 }
 
-// One wave per row: lanes stride the inner index (coalesced for row-major A).
+// Atomic max / min that first reads the stored value and skips the atomic
+// when it cannot change it (the stored value only moves one way, so a
+// stale read costs at most a needless atomic): most partial results of a
+// line or of the whole product lose, and atomics on one address serialize.
+__device__ __forceinline__ void max_into(int32_t *p, int v) {
+  if (v > *reinterpret_cast<volatile int32_t *>(p)) atomicMax(p, v);
+}
+__device__ __forceinline__ void min_into(int32_t *p, int v) {
+  if (v < *reinterpret_cast<volatile int32_t *>(p)) atomicMin(p, v);
+}
+
+// Rows: one wave per (row, chunk of kRowChunk inner indices), lanes along
+// the inner index (coalesced for row-major A); partial results merge with
+// atomics.  Chunks keep enough waves in flight to hide the dependent
+// count, exponent and low-limb loads of each element.
+constexpr int kRowChunk = 256;
 __global__ __launch_bounds__(256) void stats_rows_kernel(StatsParams P) {
-  const int64_t line = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nch = (P.len + kRowChunk - 1) / kRowChunk;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t line = w / nch, k0 = (w - line * nch) * kRowChunk;
   const int lane = threadIdx.x & 63;
   if (line >= P.lines) return;
+  const int64_t k1 = k0 + kRowChunk < P.len ? k0 + kRowChunk : P.len;
   int top = -0x7FFFFFFF - 1, v2 = 0x7FFFFFFF, prec = 0, bad = 0, amax = 0;
-  for (int64_t k = lane; k < P.len; k += 64) stats_elem(P, line, k, top, v2, prec, bad, amax);
+  for (int64_t k = k0 + lane; k < k1; k += 64) stats_elem(P, line, k, top, v2, prec, bad, amax);
 #pragma unroll
   for (int m = 1; m < 64; m <<= 1) {
     int t = __shfl_xor(top, m, 64); top = t > top ? t : top;
@@ -69,31 +87,43 @@ __global__ __launch_bounds__(256) void stats_rows_kernel(StatsParams P) {
     int a = __shfl_xor(amax, m, 64); amax = a > amax ? a : amax;
   }
   if (lane == 0) {
-    atomicMax(&P.out.top[line], top);
-    atomicMin(&P.out.v2[line], v2);
-    atomicMax(&P.gmax[1], prec);
-    if (bad) atomicMax(&P.gmax[2], 1);
-    if (amax) atomicMax(&P.gmax[3], amax);
+    if (top != -0x7FFFFFFF - 1) max_into(&P.out.top[line], top);
+    if (v2 != 0x7FFFFFFF) min_into(&P.out.v2[line], v2);
+    if (prec) max_into(&P.gmax[1], prec);
+    if (bad) max_into(&P.gmax[2], 1);
+    if (amax) max_into(&P.gmax[3], amax);
   }
 }
 
 // Columns: lane = column (coalesced for row-major B), one wave per chunk of
-// 64 inner indices; partial results merge with atomics.
+// kColChunk inner indices; partial results merge with atomics.
+constexpr int kColChunk = 16;
 __global__ __launch_bounds__(256) void stats_cols_kernel(StatsParams P) {
   const int64_t nct = (P.lines + 63) >> 6;
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t ct = w % nct, kc = w / nct;
   const int64_t line = ct * 64 + (threadIdx.x & 63);
-  const int64_t k0 = kc * 64;
-  if (line >= P.lines || k0 >= P.len) return;
-  const int64_t k1 = k0 + 64 < P.len ? k0 + 64 : P.len;
+  const int64_t k0 = kc * kColChunk;
+  if (k0 >= P.len) return;   // uniform across the wave
+  const int64_t k1 = k0 + kColChunk < P.len ? k0 + kColChunk : P.len;
   int top = -0x7FFFFFFF - 1, v2 = 0x7FFFFFFF, prec = 0, bad = 0, amax = 0;
-  for (int64_t k = k0; k < k1; ++k) stats_elem(P, line, k, top, v2, prec, bad, amax);
-  if (top != -0x7FFFFFFF - 1) atomicMax(&P.out.top[line], top);
-  if (v2 != 0x7FFFFFFF) atomicMin(&P.out.v2[line], v2);
-  if (prec) atomicMax(&P.gmax[1], prec);
-  if (bad) atomicMax(&P.gmax[2], 1);
-  if (amax) atomicMax(&P.gmax[3], amax);
+  if (line < P.lines) {
+    for (int64_t k = k0; k < k1; ++k) stats_elem(P, line, k, top, v2, prec, bad, amax);
+    if (top != -0x7FFFFFFF - 1) max_into(&P.out.top[line], top);
+    if (v2 != 0x7FFFFFFF) min_into(&P.out.v2[line], v2);
+  }
+  // the whole-product maxima: one atomic (at most) per wave
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    int q = __shfl_xor(prec, m, 64); prec = q > prec ? q : prec;
+    bad |= __shfl_xor(bad, m, 64);
+    int a = __shfl_xor(amax, m, 64); amax = a > amax ? a : amax;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (prec) max_into(&P.gmax[1], prec);
+    if (bad) max_into(&P.gmax[2], 1);
+    if (amax) max_into(&P.gmax[3], amax);
+  }
 }
 
 __global__ __launch_bounds__(256) void stats_init_kernel(LineStats S, int64_t lines) {
@@ -693,7 +723,10 @@ static inline unsigned nblk(int64_t n, int64_t per) { return (unsigned)((n + per
 hipError_t launch_stats_rows(const StatsParams &P, hipStream_t s) {
   if (P.lines == 0) return hipSuccess;
   hipLaunchKernelGGL(stats_init_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P.out, P.lines);
-  hipLaunchKernelGGL(stats_rows_kernel, dim3(nblk(P.lines, 4)), dim3(256), 0, s, P);
+  if (P.len > 0) {
+    const int64_t waves = P.lines * ((P.len + kRowChunk - 1) / kRowChunk);
+    hipLaunchKernelGGL(stats_rows_kernel, dim3(nblk(waves, 4)), dim3(256), 0, s, P);
+  }
   hipLaunchKernelGGL(stats_height_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P.out, P.lines, P.gmax);
   return hipGetLastError();
 }
@@ -701,7 +734,7 @@ hipError_t launch_stats_cols(const StatsParams &P, hipStream_t s) {
   if (P.lines == 0) return hipSuccess;
   hipLaunchKernelGGL(stats_init_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P.out, P.lines);
   if (P.len > 0) {
-    const int64_t waves = ((P.lines + 63) / 64) * ((P.len + 63) / 64);
+    const int64_t waves = ((P.lines + 63) / 64) * ((P.len + kColChunk - 1) / kColChunk);
     hipLaunchKernelGGL(stats_cols_kernel, dim3(nblk(waves, 4)), dim3(256), 0, s, P);
   }
   hipLaunchKernelGGL(stats_height_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P.out, P.lines, P.gmax);
