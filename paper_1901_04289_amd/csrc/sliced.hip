@@ -448,11 +448,16 @@ __global__ __launch_bounds__(256) void recombine_kernel(RecombParams P) {
 // radius matrices (FP64, rounded up, per-line exponent frames)
 // ---------------------------------------------------------------------------
 
+// Upper bound of |m| (mantissa in [0.5, 1]): the top 64 bits rounded up to
+// 53 bits, with a sticky bit for the limbs below them.  The lowest limb is
+// read first: when it is nonzero (operands of full precision) it settles
+// the sticky bit without a pass over the middle limbs.
 __device__ __forceinline__ double mag_upper_mem(const arbgpu_arr &A, int64_t idx, int n) {
   const uint32_t top = A.limbs[idx];
   const uint32_t second = n > 1 ? A.limbs[A.ld + idx] : 0u;
-  uint32_t rest = 0;
-  for (int q = 2; q < n; ++q) rest |= A.limbs[(int64_t)q * A.ld + idx];
+  uint32_t rest = n > 2 ? A.limbs[(int64_t)(n - 1) * A.ld + idx] : 0u;
+  if (rest == 0)
+    for (int q = 2; q < n - 1; ++q) rest |= A.limbs[(int64_t)q * A.ld + idx];
   const uint64_t v = ((uint64_t)top << 32) | second;
   const uint64_t m53 = (v >> 11) + (((v & 0x7FFull) != 0 || rest != 0) ? 1 : 0);
   return (double)m53 * 0x1p-53;
@@ -504,34 +509,52 @@ __device__ __forceinline__ void rad_elem(const arbgpu_arr &A, int64_t idx, doubl
   }
 }
 
-// One wave per line: two exponent frames per line, one for each value
-// array (A side: |a| and r_a; B side: |b| + r_b and r_b), then the scaled
-// upper bounds.  A side writes [line][k]; B side writes [k][line].
-__global__ __launch_bounds__(256) void rad_prep_kernel(RadPrepParams P) {
-  const int64_t line = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+// Exponent frames per line, one for each value array (A side: |a| and
+// r_a; B side: |b| + r_b, bounded by 2^(max(e, re) + 1), and r_b), then
+// the values scaled into their frames (A side writes [line][k], B side
+// [k][line]).  The frames are maxima over a line, merged from chunks with
+// atomics into arrays preset to kNoFrame; lines without a value get frame
+// 0 afterwards.
+constexpr int kNoFrame = -0x7FFFFFFF - 1;
+
+__device__ __forceinline__ void rad_frame_elem(const RadPrepParams &P, int64_t line, int64_t k, int &F0,
+                                               int &F1) {
+  int part;
+  int64_t kk;
+  uint32_t ng;
+  inner_map(P.mode, P.len, k, part, kk, ng);
+  const arbgpu_arr &A = part_of(P.part, part);
+  const int64_t idx = P.off + line * P.line_stride + kk * P.elem_stride;
+  int f0 = elem_n(A, idx) ? A.exp[idx] : kNoFrame;
+  int f1 = kNoFrame;
+  if (A.rad_m) {
+    const double rr = A.rad_m[idx];
+    if (rr != 0.0) {
+      int ex;
+      (void)frexp(rr, &ex);
+      f1 = A.rad_e[idx] + ex;
+    }
+  }
+  if (P.side == 1) {
+    f0 = f1 > f0 ? f1 : f0;
+    if (f0 != kNoFrame) f0 += 1;
+  }
+  F0 = f0 > F0 ? f0 : F0;
+  F1 = f1 > F1 ? f1 : F1;
+}
+
+// A side: one wave per (line, chunk of kRowChunk inner indices), lanes
+// along the inner index.
+__global__ __launch_bounds__(256) void rad_frames_rows_kernel(RadPrepParams P) {
+  const int64_t lt = (P.mode == 0) ? P.len : 2 * P.len;
+  const int64_t nch = (lt + kRowChunk - 1) / kRowChunk;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t line = w / nch, k0 = (w - line * nch) * kRowChunk;
   const int lane = threadIdx.x & 63;
   if (line >= P.lines) return;
-  const int64_t lt = (P.mode == 0) ? P.len : 2 * P.len;
-  constexpr int kNone = -0x7FFFFFFF - 1;
-  int F0 = kNone, F1 = kNone;
-  for (int64_t k = lane; k < lt; k += 64) {
-    int part;
-    int64_t kk;
-    uint32_t ng;
-    inner_map(P.mode, P.len, k, part, kk, ng);
-    const arbgpu_arr &A = part_of(P.part, part);
-    double m, r;
-    int e, re;
-    rad_elem(A, P.off + line * P.line_stride + kk * P.elem_stride, m, e, r, re);
-    int f0 = m != 0.0 ? e : kNone;
-    const int f1 = r != 0.0 ? re : kNone;
-    if (P.side == 1) {   // |b| + r_b < 2^(max(e, re) + 1)
-      f0 = f1 > f0 ? f1 : f0;
-      if (f0 != kNone) f0 += 1;
-    }
-    F0 = f0 > F0 ? f0 : F0;
-    F1 = f1 > F1 ? f1 : F1;
-  }
+  const int64_t k1 = k0 + kRowChunk < lt ? k0 + kRowChunk : lt;
+  int F0 = kNoFrame, F1 = kNoFrame;
+  for (int64_t k = k0 + lane; k < k1; k += 64) rad_frame_elem(P, line, k, F0, F1);
 #pragma unroll
   for (int m = 1; m < 64; m <<= 1) {
     int o = __shfl_xor(F0, m, 64);
@@ -539,25 +562,65 @@ __global__ __launch_bounds__(256) void rad_prep_kernel(RadPrepParams P) {
     o = __shfl_xor(F1, m, 64);
     F1 = o > F1 ? o : F1;
   }
-  if (F0 == kNone) F0 = 0;
-  if (F1 == kNone) F1 = 0;
   if (lane == 0) {
-    P.scale0[line] = F0;
-    P.scale1[line] = F1;
+    if (F0 != kNoFrame) max_into(&P.scale0[line], F0);
+    if (F1 != kNoFrame) max_into(&P.scale1[line], F1);
   }
-  for (int64_t k = lane; k < lt; k += 64) {
-    int part;
-    int64_t kk;
-    uint32_t ng;
-    inner_map(P.mode, P.len, k, part, kk, ng);
-    const arbgpu_arr &A = part_of(P.part, part);
-    double m, r;
-    int e, re;
-    rad_elem(A, P.off + line * P.line_stride + kk * P.elem_stride, m, e, r, re);
-    const int64_t o = (P.side == 0) ? line * lt + k : k * P.lines + line;
-    P.v0[o] = (P.side == 0) ? rad_scaled(m, e - F0, P.tiny) : rad_scaled_sum(m, e - F0, r, re - F0, P.tiny);
-    P.v1[o] = rad_scaled(r, re - F1, P.tiny);
+}
+
+// B side: lane = line (consecutive in a row-major B), one wave per chunk of
+// kColChunk inner indices.
+__global__ __launch_bounds__(256) void rad_frames_cols_kernel(RadPrepParams P) {
+  const int64_t lt = (P.mode == 0) ? P.len : 2 * P.len;
+  const int64_t nct = (P.lines + 63) >> 6;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t ct = w % nct, kc = w / nct;
+  const int64_t line = ct * 64 + (threadIdx.x & 63);
+  const int64_t k0 = kc * kColChunk;
+  if (line >= P.lines || k0 >= lt) return;
+  const int64_t k1 = k0 + kColChunk < lt ? k0 + kColChunk : lt;
+  int F0 = kNoFrame, F1 = kNoFrame;
+  for (int64_t k = k0; k < k1; ++k) rad_frame_elem(P, line, k, F0, F1);
+  if (F0 != kNoFrame) max_into(&P.scale0[line], F0);
+  if (F1 != kNoFrame) max_into(&P.scale1[line], F1);
+}
+
+// One thread per value: consecutive threads along the inner index (A side)
+// or along the lines (B side), the direction its output is contiguous in.
+template <int SIDE>
+__global__ __launch_bounds__(256) void rad_values_kernel(RadPrepParams P) {
+  const int64_t lt = (P.mode == 0) ? P.len : 2 * P.len;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= P.lines * lt) return;
+  int64_t line, k;
+  if (SIDE == 0) {
+    line = t / lt;
+    k = t - line * lt;
+  } else {
+    k = t / P.lines;
+    line = t - k * P.lines;
   }
+  int F0 = P.scale0[line], F1 = P.scale1[line];
+  F0 = F0 == kNoFrame ? 0 : F0;
+  F1 = F1 == kNoFrame ? 0 : F1;
+  int part;
+  int64_t kk;
+  uint32_t ng;
+  inner_map(P.mode, P.len, k, part, kk, ng);
+  const arbgpu_arr &A = part_of(P.part, part);
+  double m, r;
+  int e, re;
+  rad_elem(A, P.off + line * P.line_stride + kk * P.elem_stride, m, e, r, re);
+  // t is the output index: [line][k] on the A side, [k][line] on the B side
+  P.v0[t] = (SIDE == 0) ? rad_scaled(m, e - F0, P.tiny) : rad_scaled_sum(m, e - F0, r, re - F0, P.tiny);
+  P.v1[t] = rad_scaled(r, re - F1, P.tiny);
+}
+
+__global__ __launch_bounds__(256) void rad_frames_finish_kernel(RadPrepParams P) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= P.lines) return;
+  if (P.scale0[i] == kNoFrame) P.scale0[i] = 0;
+  if (P.scale1[i] == kNoFrame) P.scale1[i] = 0;
 }
 
 // rho_in(i, j) = sum_k a_m[i][k] b_r[k][j]    (frame 2^(a_s0[i] + b_s1[j]))
@@ -762,7 +825,21 @@ hipError_t launch_recombine(const RecombParams &P, hipStream_t s) {
 }
 hipError_t launch_rad_prep(const RadPrepParams &P, hipStream_t s) {
   if (P.lines == 0) return hipSuccess;
-  hipLaunchKernelGGL(rad_prep_kernel, dim3(nblk(P.lines, 4)), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P.scale0, kNoFrame, P.lines);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P.scale1, kNoFrame, P.lines);
+  const int64_t lt = (P.mode == 0) ? P.len : 2 * P.len;
+  if (lt > 0) {
+    if (P.side == 0) {
+      const int64_t waves = P.lines * ((lt + kRowChunk - 1) / kRowChunk);
+      hipLaunchKernelGGL(rad_frames_rows_kernel, dim3(nblk(waves, 4)), dim3(256), 0, s, P);
+      hipLaunchKernelGGL(rad_values_kernel<0>, dim3(nblk(P.lines * lt, 256)), dim3(256), 0, s, P);
+    } else {
+      const int64_t waves = ((P.lines + 63) / 64) * ((lt + kColChunk - 1) / kColChunk);
+      hipLaunchKernelGGL(rad_frames_cols_kernel, dim3(nblk(waves, 4)), dim3(256), 0, s, P);
+      hipLaunchKernelGGL(rad_values_kernel<1>, dim3(nblk(P.lines * lt, 256)), dim3(256), 0, s, P);
+    }
+  }
+  hipLaunchKernelGGL(rad_frames_finish_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P);
   return hipGetLastError();
 }
 hipError_t launch_rad_gemm(const RadGemmParams &P, hipStream_t s) {
