@@ -44,10 +44,12 @@ def limb_shapes():
 LIMB_FLAGS = ["-mllvm", "-pragma-unroll-threshold=200000"]
 
 
-# The machine-limit probes keep FP64 matrix-core accumulators in ordinary
-# vector registers; without this the loop-carried accumulators are copied
-# to and from the accumulation registers around every multiply.
-FILE_FLAGS = {"peaks.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# The FP64 matrix-core loops (radius products, machine-limit probes) keep
+# their accumulators in ordinary vector registers; without this the
+# loop-carried accumulators are copied to and from the accumulation
+# registers around every multiply.
+FILE_FLAGS = {"peaks.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+              "radius.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src: str, obj: str, defines=()):

@@ -64,18 +64,34 @@ __device__ __forceinline__ void min_into(int32_t *p, int v) {
   if (v < *reinterpret_cast<volatile int32_t *>(p)) atomicMin(p, v);
 }
 
-// Rows: one wave per (row, chunk of kRowChunk inner indices), lanes along
+// Rows: one wave per (row, chunk of row_chunk inner indices), lanes along
 // the inner index (coalesced for row-major A); partial results merge with
 // atomics.  Chunks keep enough waves in flight to hide the dependent
 // count, exponent and low-limb loads of each element.
 constexpr int kRowChunk = 256;
+constexpr int kColChunk = 16;
+
+// Inner indices per wave of the row (column) kernels: kRowChunk
+// (kColChunk), halved while the product is too small to give about 2048
+// waves, down to one index per lane (per wave).
+__host__ __device__ inline int64_t row_chunk(int64_t lines, int64_t lt) {
+  int64_t c = kRowChunk;
+  while (c > 64 && lines * ((lt + c - 1) / c) < 2048) c >>= 1;
+  return c;
+}
+__host__ __device__ inline int64_t col_chunk(int64_t lines, int64_t lt) {
+  const int64_t tiles = (lines + 63) / 64;
+  int64_t c = kColChunk;
+  while (c > 1 && tiles * ((lt + c - 1) / c) < 2048) c >>= 1;
+  return c;
+}
 __global__ __launch_bounds__(256) void stats_rows_kernel(StatsParams P) {
-  const int64_t nch = (P.len + kRowChunk - 1) / kRowChunk;
+  const int64_t ch = row_chunk(P.lines, P.len), nch = (P.len + ch - 1) / ch;
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t line = w / nch, k0 = (w - line * nch) * kRowChunk;
+  const int64_t line = w / nch, k0 = (w - line * nch) * ch;
   const int lane = threadIdx.x & 63;
   if (line >= P.lines) return;
-  const int64_t k1 = k0 + kRowChunk < P.len ? k0 + kRowChunk : P.len;
+  const int64_t k1 = k0 + ch < P.len ? k0 + ch : P.len;
   int top = -0x7FFFFFFF - 1, v2 = 0x7FFFFFFF, prec = 0, bad = 0, amax = 0;
   for (int64_t k = k0 + lane; k < k1; k += 64) stats_elem(P, line, k, top, v2, prec, bad, amax);
 #pragma unroll
@@ -96,16 +112,15 @@ __global__ __launch_bounds__(256) void stats_rows_kernel(StatsParams P) {
 }
 
 // Columns: lane = column (coalesced for row-major B), one wave per chunk of
-// kColChunk inner indices; partial results merge with atomics.
-constexpr int kColChunk = 16;
+// col_chunk inner indices; partial results merge with atomics.
 __global__ __launch_bounds__(256) void stats_cols_kernel(StatsParams P) {
   const int64_t nct = (P.lines + 63) >> 6;
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t ct = w % nct, kc = w / nct;
   const int64_t line = ct * 64 + (threadIdx.x & 63);
-  const int64_t k0 = kc * kColChunk;
+  const int64_t ch = col_chunk(P.lines, P.len), k0 = kc * ch;
   if (k0 >= P.len) return;   // uniform across the wave
-  const int64_t k1 = k0 + kColChunk < P.len ? k0 + kColChunk : P.len;
+  const int64_t k1 = k0 + ch < P.len ? k0 + ch : P.len;
   int top = -0x7FFFFFFF - 1, v2 = 0x7FFFFFFF, prec = 0, bad = 0, amax = 0;
   if (line < P.lines) {
     for (int64_t k = k0; k < k1; ++k) stats_elem(P, line, k, top, v2, prec, bad, amax);
@@ -543,16 +558,16 @@ __device__ __forceinline__ void rad_frame_elem(const RadPrepParams &P, int64_t l
   F1 = f1 > F1 ? f1 : F1;
 }
 
-// A side: one wave per (line, chunk of kRowChunk inner indices), lanes
+// A side: one wave per (line, chunk of row_chunk inner indices), lanes
 // along the inner index.
 __global__ __launch_bounds__(256) void rad_frames_rows_kernel(RadPrepParams P) {
   const int64_t lt = (P.mode == 0) ? P.len : 2 * P.len;
-  const int64_t nch = (lt + kRowChunk - 1) / kRowChunk;
+  const int64_t ch = row_chunk(P.lines, lt), nch = (lt + ch - 1) / ch;
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t line = w / nch, k0 = (w - line * nch) * kRowChunk;
+  const int64_t line = w / nch, k0 = (w - line * nch) * ch;
   const int lane = threadIdx.x & 63;
   if (line >= P.lines) return;
-  const int64_t k1 = k0 + kRowChunk < lt ? k0 + kRowChunk : lt;
+  const int64_t k1 = k0 + ch < lt ? k0 + ch : lt;
   int F0 = kNoFrame, F1 = kNoFrame;
   for (int64_t k = k0 + lane; k < k1; k += 64) rad_frame_elem(P, line, k, F0, F1);
 #pragma unroll
@@ -569,16 +584,16 @@ __global__ __launch_bounds__(256) void rad_frames_rows_kernel(RadPrepParams P) {
 }
 
 // B side: lane = line (consecutive in a row-major B), one wave per chunk of
-// kColChunk inner indices.
+// col_chunk inner indices.
 __global__ __launch_bounds__(256) void rad_frames_cols_kernel(RadPrepParams P) {
   const int64_t lt = (P.mode == 0) ? P.len : 2 * P.len;
   const int64_t nct = (P.lines + 63) >> 6;
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t ct = w % nct, kc = w / nct;
   const int64_t line = ct * 64 + (threadIdx.x & 63);
-  const int64_t k0 = kc * kColChunk;
+  const int64_t ch = col_chunk(P.lines, lt), k0 = kc * ch;
   if (line >= P.lines || k0 >= lt) return;
-  const int64_t k1 = k0 + kColChunk < lt ? k0 + kColChunk : lt;
+  const int64_t k1 = k0 + ch < lt ? k0 + ch : lt;
   int F0 = kNoFrame, F1 = kNoFrame;
   for (int64_t k = k0; k < k1; ++k) rad_frame_elem(P, line, k, F0, F1);
   if (F0 != kNoFrame) max_into(&P.scale0[line], F0);
@@ -621,107 +636,6 @@ __global__ __launch_bounds__(256) void rad_frames_finish_kernel(RadPrepParams P)
   if (i >= P.lines) return;
   if (P.scale0[i] == kNoFrame) P.scale0[i] = 0;
   if (P.scale1[i] == kNoFrame) P.scale1[i] = 0;
-}
-
-// rho_in(i, j) = sum_k a_m[i][k] b_r[k][j]    (frame 2^(a_s0[i] + b_s1[j]))
-//              + sum_k a_r[i][k] b_mr[k][j]   (frame 2^(a_s1[i] + b_s0[j])),
-// rounded up.  Skipped when a value was too small for its frame.
-//
-// The two sums run on FP64 MFMA in round-to-nearest and are then raised to
-// upper bounds: every term is a nonnegative product of scaled values in
-// [2^-481, 1] (or zero), so no subnormal arises, and each term passes
-// through at most Kt + 1 roundings of relative error below 2^-52.  The
-// computed sum s' therefore satisfies s <= s' (1 - 2^-52)^-(Kt+1) <=
-// s' (1 + (Kt + 2) 2^-50), which is applied with upward rounding.
-//
-// Workgroup: 256 threads, 64 x 64 output tile, inner chunks of 16 staged
-// in LDS k-major ([16][64] for every operand, so the 16 rows or columns of
-// a fragment are consecutive doubles).  Wave w computes the 32 x 32
-// quarter (w / 2, w % 2) as 2 x 2 blocks of v_mfma_f64_16x16x4_f64 per
-// sum: operand lane l holds row (column) l % 16 at inner index l / 16;
-// result lane l, register r holds row l / 16 + 4 r, column l % 16.
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-__global__ __launch_bounds__(256) void rad_gemm_kernel(RadGemmParams P) {
-  constexpr int T = 64, KC = 16;
-  __shared__ double sa[2][KC][T], sb[2][KC][T];   // [a_m | a_r], [b_r | b_mr]
-  if (*P.tiny) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t i0 = (int64_t)blockIdx.y * T, j0 = (int64_t)blockIdx.x * T;
-  const int wm = wave >> 1, wn = wave & 1;
-  v4d acc[2][2][2];   // [sum][row block][column block]
-#pragma unroll
-  for (int q = 0; q < 2; ++q)
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) acc[q][bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
-  // staging: A rows (i0 + r, r = tid / 4) at inner offsets 4 (tid % 4) .. +3;
-  // B inner row k0 + tid / 16 at columns 4 (tid % 16) .. +3
-  const int ar = tid >> 2, ak = 4 * (tid & 3);
-  const int bk = tid >> 4, bc = 4 * (tid & 15);
-  const int64_t ai = i0 + ar;
-  for (int64_t k0 = 0; k0 < P.Kt; k0 += KC) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t k = k0 + ak + u;
-      const bool ok = ai < P.M && k < P.Kt;
-      sa[0][ak + u][ar] = ok ? P.a_m[ai * P.Kt + k] : 0.0;
-      sa[1][ak + u][ar] = ok ? P.a_r[ai * P.Kt + k] : 0.0;
-    }
-    {
-      const int64_t k = k0 + bk;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t j = j0 + bc + u;
-        const bool ok = k < P.Kt && j < P.N;
-        sb[0][bk][bc + u] = ok ? P.b_r[k * P.N + j] : 0.0;
-        sb[1][bk][bc + u] = ok ? P.b_mr[k * P.N + j] : 0.0;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < KC / 4; ++ks) {
-      const int kk = 4 * ks + (lane >> 4);
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        double fa[2], fb[2];
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi) fa[bi] = sa[q][kk][wm * 32 + bi * 16 + (lane & 15)];
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) fb[bj] = sb[q][kk][wn * 32 + bj * 16 + (lane & 15)];
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj)
-            acc[q][bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[bi], fb[bj], acc[q][bi][bj], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-  }
-  const double infl = 1.0 + ldexp((double)(P.Kt + 2), -50);
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + wm * 32 + bi * 16 + (lane >> 4) + 4 * r;
-        const int64_t j = j0 + wn * 32 + bj * 16 + (lane & 15);
-        if (i >= P.M || j >= P.N) continue;
-        const double s1 = acc[0][bi][bj][r], s2 = acc[1][bi][bj][r];
-        double m1 = 0.0, m2 = 0.0;
-        int e1 = 0, e2 = 0, ex;
-        if (s1 != 0.0) { m1 = frexp(ru_mul(s1, infl), &ex); e1 = P.a_s0[i] + P.b_s1[j] + ex; }
-        if (s2 != 0.0) { m2 = frexp(ru_mul(s2, infl), &ex); e2 = P.a_s1[i] + P.b_s0[j] + ex; }
-        double m = 0.0;
-        int e = 0;
-        if (m1 != 0.0 && m2 != 0.0) ru_add_ext(m1, e1, m2, e2, m, e);
-        else if (m1 != 0.0) { m = m1; e = e1; }
-        else if (m2 != 0.0) { m = m2; e = e2; }
-        P.out_m[i * P.N + j] = m;
-        P.out_e[i * P.N + j] = e;
-      }
 }
 
 // Radius of one entry with its own frame (the largest term bound), as in
@@ -787,7 +701,7 @@ hipError_t launch_stats_rows(const StatsParams &P, hipStream_t s) {
   if (P.lines == 0) return hipSuccess;
   hipLaunchKernelGGL(stats_init_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P.out, P.lines);
   if (P.len > 0) {
-    const int64_t waves = P.lines * ((P.len + kRowChunk - 1) / kRowChunk);
+    const int64_t ch = row_chunk(P.lines, P.len), waves = P.lines * ((P.len + ch - 1) / ch);
     hipLaunchKernelGGL(stats_rows_kernel, dim3(nblk(waves, 4)), dim3(256), 0, s, P);
   }
   hipLaunchKernelGGL(stats_height_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P.out, P.lines, P.gmax);
@@ -797,7 +711,7 @@ hipError_t launch_stats_cols(const StatsParams &P, hipStream_t s) {
   if (P.lines == 0) return hipSuccess;
   hipLaunchKernelGGL(stats_init_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P.out, P.lines);
   if (P.len > 0) {
-    const int64_t waves = ((P.lines + 63) / 64) * ((P.len + kColChunk - 1) / kColChunk);
+    const int64_t ch = col_chunk(P.lines, P.len), waves = ((P.lines + 63) / 64) * ((P.len + ch - 1) / ch);
     hipLaunchKernelGGL(stats_cols_kernel, dim3(nblk(waves, 4)), dim3(256), 0, s, P);
   }
   hipLaunchKernelGGL(stats_height_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P.out, P.lines, P.gmax);
@@ -830,21 +744,16 @@ hipError_t launch_rad_prep(const RadPrepParams &P, hipStream_t s) {
   const int64_t lt = (P.mode == 0) ? P.len : 2 * P.len;
   if (lt > 0) {
     if (P.side == 0) {
-      const int64_t waves = P.lines * ((lt + kRowChunk - 1) / kRowChunk);
+      const int64_t ch = row_chunk(P.lines, lt), waves = P.lines * ((lt + ch - 1) / ch);
       hipLaunchKernelGGL(rad_frames_rows_kernel, dim3(nblk(waves, 4)), dim3(256), 0, s, P);
       hipLaunchKernelGGL(rad_values_kernel<0>, dim3(nblk(P.lines * lt, 256)), dim3(256), 0, s, P);
     } else {
-      const int64_t waves = ((P.lines + 63) / 64) * ((lt + kColChunk - 1) / kColChunk);
+      const int64_t ch = col_chunk(P.lines, lt), waves = ((P.lines + 63) / 64) * ((lt + ch - 1) / ch);
       hipLaunchKernelGGL(rad_frames_cols_kernel, dim3(nblk(waves, 4)), dim3(256), 0, s, P);
       hipLaunchKernelGGL(rad_values_kernel<1>, dim3(nblk(P.lines * lt, 256)), dim3(256), 0, s, P);
     }
   }
   hipLaunchKernelGGL(rad_frames_finish_kernel, dim3(nblk(P.lines, 256)), dim3(256), 0, s, P);
-  return hipGetLastError();
-}
-hipError_t launch_rad_gemm(const RadGemmParams &P, hipStream_t s) {
-  if (P.M == 0 || P.N == 0) return hipSuccess;
-  hipLaunchKernelGGL(rad_gemm_kernel, dim3(nblk(P.N, 64), nblk(P.M, 64)), dim3(256), 0, s, P);
   return hipGetLastError();
 }
 hipError_t launch_rad_exact(const RadExactParams &P, hipStream_t s) {
