@@ -42,15 +42,15 @@ PEAK_INT8_TOPS = 5000.0   # MI355X dense INT8 MFMA, 5.0 POP/s
 # HBM bytes per launch of mfma_diag_kernel at N = 2048, p = 512 for the two
 # INT8 forms, from the FETCH_SIZE (x2, copy-calibrated) and WRITE_SIZE (x1)
 # counter runs in profiles/mfma_diag_kernel_matmul2048_p512.txt; valid only
-# for the kernel source they were taken on (sha256 prefix of csrc/sliced.hip).
-MFMA_TRAFFIC_BYTES = {"residues": (1800637 * 2 + 3489792) * 1024.0,
-                      "slices": (37918505 * 2 + 2228224) * 1024.0}
-MFMA_TRAFFIC_SRC = "649d049405eb4858"
+# for the kernel source they were taken on (sha256 prefix of csrc/mfma.hip).
+MFMA_TRAFFIC_BYTES = {"residues": (1786559 * 2 + 3489792) * 1024.0,
+                      "slices": (42483191 * 2 + 2228224) * 1024.0}
+MFMA_TRAFFIC_SRC = "cf974db54726e0ee"
 
 
 def _mfma_traffic(n, form):
     import hashlib
-    src = os.path.join(ROOT, "paper_1901_04289_amd", "csrc", "sliced.hip")
+    src = os.path.join(ROOT, "paper_1901_04289_amd", "csrc", "mfma.hip")
     with open(src, "rb") as f:
         h = hashlib.sha256(f.read()).hexdigest()[:16]
     return MFMA_TRAFFIC_BYTES[form] if (h == MFMA_TRAFFIC_SRC and n == 2048) else None
