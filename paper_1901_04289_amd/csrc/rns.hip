@@ -166,10 +166,11 @@ __device__ __forceinline__ void mfma_run(v16i &acc, const v4i (&fa0)[4], const i
 // 256^a mod p_j.  Workgroup: 256 threads, EL consecutive elements of the
 // padded plane.  Phase 1: one thread per element writes its digits into an
 // LDS row of kd bytes (+16 so that 8 consecutive rows fall in distinct
-// 16-byte bank groups).  Phase 2: each wave takes 32 elements; per tile of
-// 16 primes one 32 x 32 MFMA result, whose lane l holds the (lo, hi) sums
-// of 8 primes for element l % 32, reduced modulo p_j to two int8 residue
-// digits; a byte transpose within quads of lanes turns each lane's 4
+// 16-byte bank groups).  Phase 2: each wave takes one or two blocks of 32
+// elements and loads each tile of 16 primes' weight fragments once for
+// them; per block and tile one 32 x 32 MFMA result, whose lane l holds the
+// (lo, hi) sums of 8 primes for element l % 32, reduced modulo p_j to two
+// int8 residue digits; a byte transpose within quads of lanes turns each lane's 4
 // digits of one element into 4 elements' digits of one plane, stored as
 // one word (the padded plane holds whole blocks of 32 elements and starts
 // 16-byte aligned).
@@ -200,28 +201,59 @@ __global__ __launch_bounds__(256) void rns_slice_kernel(RnsSliceParams P) {
   // distance 2, then 1)
   const uint32_t sel1 = q < 2 ? 0x05040100u : 0x03020706u;
   const uint32_t sel2 = (q & 1) ? 0x03070105u : 0x06020400u;
-  for (int wv = wave; wv < EL / 32; wv += 4) {
-    const uint8_t *drow = dl + (size_t)(32 * wv + (lane & 31)) * S + 16 * h;
+  // blocks of 32 elements per wave (waves past EL / 32 have none); the
+  // weight fragments of a prime tile are loaded once for all of them
+  constexpr int NBW = EL >= 128 ? EL / 128 : 1;
+  if (wave >= EL / 32) return;
+  const uint8_t *drow[NBW];
+  int8_t *out[NBW];
+  bool inside[NBW];
+#pragma unroll
+  for (int b = 0; b < NBW; ++b) {
+    const int wv = wave + 4 * b;
+    drow[b] = dl + (size_t)(32 * wv + (lane & 31)) * S + 16 * h;
     // this lane stores elements 4 e' .. 4 e' + 3 (e' = (lane % 32) / 4) of
     // its planes
-    int8_t *out = P.planes + g0 + 32 * wv + (lane & 28);
-    const bool inside = g0 + 32 * wv < total;
-    const int nrt = (m + 15) / 16;
-    const int8_t *wbase = P.tab.wd + (int64_t)(lane & 31) * kd + 16 * h;
-    v4i fnext[4];
-    frag_load4(fnext, wbase, 0, kd / 32);
-    for (int rt = 0; rt < nrt; ++rt) {
-      const int8_t *wrow = wbase + (int64_t)rt * 32 * kd;
-      // the next tile's first weight fragments load during this tile's
-      // products and residue arithmetic
-      v4i fcur[4];
+    out[b] = P.planes + g0 + 32 * wv + (lane & 28);
+    inside[b] = g0 + 32 * wv < total;
+  }
+  const int nrt = (m + 15) / 16, nks = kd / 32;
+  const int8_t *wbase = P.tab.wd + (int64_t)(lane & 31) * kd + 16 * h;
+  v4i fnext[4];
+  frag_load4(fnext, wbase, 0, nks);
+  for (int rt = 0; rt < nrt; ++rt) {
+    const int8_t *wrow = wbase + (int64_t)rt * 32 * kd;
+    v16i acc[NBW];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) fcur[u] = fnext[u];
-      frag_load4(fnext, rt + 1 < nrt ? wrow + 32 * kd : wbase, 0, kd / 32);
-      v16i acc;
+    for (int b = 0; b < NBW; ++b)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] = 0;
-      mfma_run(acc, fcur, wrow, drow, kd / 32);
+      for (int r = 0; r < 16; ++r) acc[b][r] = 0;
+    for (int k0 = 0; k0 < nks; k0 += 4) {
+      v4i fa[4];
+      if (k0 == 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) fa[u] = fnext[u];
+        // the next tile's first weight fragments load during this tile's
+        // products and residue arithmetic
+        frag_load4(fnext, rt + 1 < nrt ? wrow + 32 * kd : wbase, 0, nks);
+      } else {
+        frag_load4(fa, wrow, k0, nks);
+      }
+#pragma unroll
+      for (int b = 0; b < NBW; ++b) {
+        v4i fb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ks = k0 + u < nks ? k0 + u : k0;
+          fb[u] = *reinterpret_cast<const v4i *>(drow[b] + 32 * ks);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (k0 + u < nks) acc[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[u], fb[u], acc[b], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NBW; ++b) {
       // register 4 G + 2 t (+1): lo (hi) sum of prime 16 rt + 8 h + 2 G + t,
       // whose digits are planes 2 (8 h + 2 G + t) (+1) of the tile; the
       // constants of both lane halves come by scalar loads
@@ -234,8 +266,8 @@ __global__ __launch_bounds__(256) void rns_slice_kernel(RnsSliceParams P) {
           const int j0 = min(16 * rt + 2 * G + t, m - 1), j1 = min(j0 + 8, m - 1);
           const uint32_t p0 = (uint32_t)cp(P.tab.prime)[j0], mu0 = cp(P.tab.mu)[j0], k0 = cp(P.tab.kp)[j0];
           const uint32_t p1 = (uint32_t)cp(P.tab.prime)[j1], mu1 = cp(P.tab.mu)[j1], k1 = cp(P.tab.kp)[j1];
-          wd[G] |= residue_digits(h ? p1 : p0, h ? mu1 : mu0, h ? k1 : k0, acc[4 * G + 2 * t],
-                                  acc[4 * G + 2 * t + 1]) << (16 * t);
+          wd[G] |= residue_digits(h ? p1 : p0, h ? mu1 : mu0, h ? k1 : k0, acc[b][4 * G + 2 * t],
+                                  acc[b][4 * G + 2 * t + 1]) << (16 * t);
         }
       }
       // 4 x 4 byte transpose within each quad of lanes: lane 4 e' + q then
@@ -246,7 +278,7 @@ __global__ __launch_bounds__(256) void rns_slice_kernel(RnsSliceParams P) {
                                                  wd[G], sel1);
         wd[G] = __builtin_amdgcn_perm((uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false), x, sel2);
         const int plane = 32 * rt + 16 * h + 4 * G + q;
-        if (plane < 2 * m && inside) *reinterpret_cast<uint32_t *>(out + (int64_t)plane * total) = wd[G];
+        if (plane < 2 * m && inside[b]) *reinterpret_cast<uint32_t *>(out[b] + (int64_t)plane * total) = wd[G];
       }
     }
   }
