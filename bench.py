@@ -234,8 +234,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--batch-launches", type=int, default=5, help="0 skips the dot batch")
-    ap.add_argument("--serve-requests", type=int, default=600, help="0 skips the serving loop")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="0 skips the serving loop")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-sweep", default="50,100",
+                    help="further arrival rates (req/s), 3 s of arrivals each; empty skips")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--no-peaks", action="store_true", help="skip the machine-limit microbenchmarks")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -403,6 +405,13 @@ def main():
         out["serving"] = bench_serving(arbgpu, torch, log, a.serve_requests, a.serve_rate, a.serve_slots)
         out["latency_ms"]["serving_p50"] = out["serving"]["latency_ms"]["p50"]
         out["latency_ms"]["serving_p99"] = out["serving"]["latency_ms"]["p99"]
+        sweep = []
+        for rate in [float(x) for x in a.serve_sweep.split(",") if x.strip()]:
+            r = bench_serving(arbgpu, torch, log, max(1, int(round(3.0 * rate))), rate, a.serve_slots)
+            sweep.append({"rate_per_s": rate, "requests": r["requests"], "latency_ms": r["latency_ms"],
+                          "complex_macs_per_s": r["complex_macs_per_s"], "eagain_retries": r["eagain_retries"]})
+        if sweep:
+            out["serving_sweep"] = sweep
     print(json.dumps(out), flush=True)
 
 
