@@ -474,6 +474,75 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
   }
 }
 
+// Residue planes of the inner layout [B_im; B_re] of a complex product's
+// imaginary part from those of [B_re; -B_im], its real part (Section 3.6:
+// Re = A_re B_re - A_im B_im, Im = A_re B_im + A_im B_re over the inner
+// index 0 .. 2K): position k < K takes the negated residue at k + K,
+// position K <= k < 2K the residue at k - K, the padding stays zero.  The
+// primes are odd, so a balanced residue r = lo + 256 hi negates within
+// range: (-lo, -hi), or (-128, 1 - hi) when lo = -128.  Thread: one prime
+// and line, 4 consecutive inner positions.
+__global__ __launch_bounds__(256) void rns_swap_neg_kernel(const int8_t *src, int8_t *dst, int m, int64_t lines_pad,
+                                                           int64_t k_pad, int64_t K) {
+  const int64_t words = k_pad >> 2;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)m * lines_pad * words) return;
+  const int64_t w = t % words, r = t / words;
+  const int64_t line = r % lines_pad, j = r / lines_pad;
+  const int64_t plane = lines_pad * k_pad, o = line * k_pad;
+  const int8_t *slo = src + 2 * j * plane + o, *shi = slo + plane;
+  const int64_t k0 = 4 * w;
+  uint32_t lo4 = 0u, hi4 = 0u;
+  // the 4 source bytes at k0 + d (d = K or -K), from the two aligned words
+  // holding them (both inside the line's row: 0 <= k0 + d and k0 + d + 3 < 2 K)
+  auto word_at = [&](const int8_t *row, int64_t b) -> uint32_t {
+    const int64_t a = b & ~(int64_t)3;
+    const uint32_t x = *reinterpret_cast<const uint32_t *>(row + a);
+    const uint32_t y = (b & 3) ? *reinterpret_cast<const uint32_t *>(row + a + 4) : 0u;
+    return __builtin_amdgcn_alignbyte(y, x, (uint32_t)(b & 3));
+  };
+  if (k0 + 3 < K) {
+    const uint32_t a = word_at(slo, k0 + K), b = word_at(shi, k0 + K);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t l = (int8_t)(a >> (8 * u)), hv = (int8_t)(b >> (8 * u));
+      lo4 |= ((uint32_t)(l == -128 ? -128 : -l) & 0xFFu) << (8 * u);
+      hi4 |= ((uint32_t)(l == -128 ? 1 - hv : -hv) & 0xFFu) << (8 * u);
+    }
+  } else if (k0 >= K && k0 + 3 < 2 * K) {
+    lo4 = word_at(slo, k0 - K);
+    hi4 = word_at(shi, k0 - K);
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = k0 + u;
+      int32_t lo = 0, hi = 0;
+      if (k < K) {
+        const int32_t a = slo[k + K], b = shi[k + K];
+        lo = a == -128 ? -128 : -a;
+        hi = a == -128 ? 1 - b : -b;
+      } else if (k < 2 * K) {
+        lo = slo[k - K];
+        hi = shi[k - K];
+      }
+      lo4 |= ((uint32_t)lo & 0xFFu) << (8 * u);
+      hi4 |= ((uint32_t)hi & 0xFFu) << (8 * u);
+    }
+  }
+  *reinterpret_cast<uint32_t *>(dst + 2 * j * plane + o + 4 * w) = lo4;
+  *reinterpret_cast<uint32_t *>(dst + (2 * j + 1) * plane + o + 4 * w) = hi4;
+}
+
+hipError_t launch_rns_swap_neg(const int8_t *src, int8_t *dst, int m, int64_t lines_pad, int64_t k_pad, int64_t K,
+                               hipStream_t s) {
+  if ((k_pad & 3) != 0 || 2 * K > k_pad || ((uintptr_t)dst & 3) != 0) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)m * lines_pad * (k_pad >> 2);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(rns_swap_neg_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, m, lines_pad,
+                     k_pad, K);
+  return hipGetLastError();
+}
+
 hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s) {
   const int64_t total = P.lines_pad * P.k_pad;
   if (total == 0) return hipSuccess;

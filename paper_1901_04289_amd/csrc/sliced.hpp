@@ -163,6 +163,10 @@ struct RnsCrtParams {
 };
 
 hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s);
+// residue planes of a complex product's [B_im; B_re] inner layout from
+// those of [B_re; -B_im] (inner length K per part, 2 K <= k_pad)
+hipError_t launch_rns_swap_neg(const int8_t *src, int8_t *dst, int m, int64_t lines_pad, int64_t k_pad, int64_t K,
+                               hipStream_t s);
 hipError_t launch_rns_crt(const RnsCrtParams &P, hipStream_t s);
 // dynamic LDS of the reconstruction kernel for ew entries per workgroup
 size_t rns_crt_lds(int ew, int kc, int W);

@@ -474,6 +474,10 @@ int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
     if (rc) return rc;
     ARB_TRY(launch_rns_slice(sa, s), "residue slice");
     for (int q = 0; q < sh.nparts; ++q) {
+      if (q == 1) {   // [B_im; B_re] from [B_re; -B_im] by moving and negating residues
+        ARB_TRY(launch_rns_swap_neg(planesB, planesB2, m, Np, Kp, Kb, s), "residue swap");
+        continue;
+      }
       RnsSliceParams sb = sa;
       sb.part[0] = bl.part[0];
       sb.part[1] = bl.part[1];
