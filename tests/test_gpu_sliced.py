@@ -139,6 +139,31 @@ def test_sliced_complex(ctx, algo):
             assert compare_entry(gen.to_canonical(outi, i * K + j), im, int(sti[i * K + j])) is None
 
 
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 6, 131])
+def test_rns_complex_short_and_ragged_inner(ctx, N):
+    # the imaginary part's residue planes come from the real part's by
+    # moving residues K positions and negating them: inner lengths below 4,
+    # not a multiple of 4, and one whose doubled length crosses a 128-byte
+    # step, with residues of both signs (negative and zero entries)
+    rng = gen.rng_for(26, N)
+    M, K, p = 7, 5, 150
+    parts = [gen.random_operands(rng, c, rng.integers(1, 200, c), -12, 12, radius_shift=140, zero_frac=0.1)
+             for c in (M * N, M * N, N * K, N * K)]
+    say(f"residue form complex inner N={N}")
+    (out, st), (outi, sti) = run(ctx, parts[0], parts[2], M, N, K, p, arbgpu.COMPLEX | arbgpu.ALGO_RNS,
+                                 Ai=parts[1], Bi=parts[3])
+    A = [[(gen.to_canonical(parts[0], i * N + k), gen.to_canonical(parts[1], i * N + k)) for k in range(N)]
+         for i in range(M)]
+    B = [[(gen.to_canonical(parts[2], k * K + j), gen.to_canonical(parts[3], k * K + j)) for j in range(K)]
+         for k in range(N)]
+    C = oracle.cmat_mul(A, B, p)
+    for i in range(M):
+        for j in range(K):
+            re, im = C[i][j]
+            assert compare_entry(gen.to_canonical(out, i * K + j), re, int(st[i * K + j])) is None
+            assert compare_entry(gen.to_canonical(outi, i * K + j), im, int(sti[i * K + j])) is None
+
+
 @pytest.mark.parametrize("algo", ALGOS)
 def test_config1_sliced_equals_limb_and_oracle(ctx, algo):
     w = gen.config1()
