@@ -15,6 +15,11 @@
 //
 // Radii (Section 4.1, last paragraph): |A| R_B + R_A (|B| + R_B) in FP64
 // with upward rounding, each row and column scaled into the double range.
+//
+// This unit holds the line statistics, the base-256 slicer, the carry
+// recombination and the radius frames; the INT8 MFMA product is in
+// mfma.hip, the FP64 radius product in radius.hip, the residue form in
+// rns.hip.
 #include <math.h>
 
 #include "engine.hpp"
