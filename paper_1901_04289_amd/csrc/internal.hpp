@@ -54,7 +54,7 @@ namespace arbgpu_impl {
 // Workspace slots (each holds one growing device buffer).
 enum WsSlot {
   WS_STATS = 0, WS_PLANES_A, WS_PLANES_B, WS_PLANES_B2, WS_D, WS_T, WS_TABLES,
-  WS_RAD_A, WS_RAD_B, WS_RAD_OUT, WS_PLAN, WS_BLOCKS, WS_BATCH, WS_RNS, WS_GATHER, WS_COUNT
+  WS_RAD_A, WS_RAD_B, WS_RAD_OUT, WS_PLAN, WS_BLOCKS, WS_BATCH, WS_RNS, WS_GATHER, WS_RAD_PART, WS_COUNT
 };
 
 // Device buffer of at least `bytes` in workspace slot `slot` (nullptr and

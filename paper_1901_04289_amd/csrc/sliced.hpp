@@ -93,7 +93,17 @@ struct RadGemmParams {
   int64_t M, N, Kt;
   double *out_m;             // [M*N]
   int32_t *out_e;
+  // inner dimension split over the third grid dimension: splits ranges of
+  // kchunk (a multiple of 16) indices, whose two partial sums per entry go
+  // to part[split][sum][M*N] and are added by rad_gemm_finish; splits = 1
+  // writes the result directly (part unused)
+  int splits;
+  int64_t kchunk;
+  double *part;
 };
+// Inner-dimension splits of the radius product of an M x N result over Kt
+// (enough workgroups to fill the device, each split at least 64 long).
+int rad_gemm_splits(int64_t M, int64_t N, int64_t Kt);
 
 // Per-entry radius with per-entry frames (fallback of the radius product).
 struct RadExactParams {

@@ -568,6 +568,13 @@ int radius_products(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, c
     rg.M = sh.M; rg.N = sh.N; rg.Kt = Kt;
     rg.out_m = rin_m[q];
     rg.out_e = rin_e[q];
+    rg.splits = rad_gemm_splits(sh.M, sh.N, Kt);
+    rg.kchunk = round_up((Kt + rg.splits - 1) / rg.splits, 16);
+    rg.part = nullptr;
+    if (rg.splits > 1) {
+      rg.part = (double *)ws_get(ctx, WS_RAD_PART, sizeof(double) * 2 * (size_t)rg.splits * mn);
+      if (!rg.part) return ARBGPU_ENOMEM;
+    }
     RadExactParams rx;
     memset(&rx, 0, sizeof rx);
     rx.A[0] = A->re;
@@ -617,6 +624,8 @@ size_t mat_mul_footprint(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, ui
   bytes += 4 * nslots * plane_stride(mn) + 4 * (int64_t)t_limbs((int)L, (int)L) * mn;   // partial planes, T
   bytes += 4 * (2 * M + 2 * N + 8);                            // statistics
   bytes += 16 * (M + N) * Kt + 8 * (M + N) + 12 * parts * mn;  // radius products
+  const int sp = rad_gemm_splits(M, N, Kt);
+  if (sp > 1) bytes += 16 * (int64_t)sp * mn;                  // their split partials
   return (size_t)bytes + 65536;
 }
 
