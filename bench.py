@@ -223,6 +223,32 @@ def bench_serving(arbgpu, torch, log, nreq: int, rate: float, slots: int):
             "arrival_span_s": reqs[-1].arrival_s, "completion_span_s": span,
             "submit_span_s": (last_submit - start) / 1e9, "eagain_retries": retries}
 
+def bench_largest(arbgpu, torch, log, n: int = 1024, p: int = 2048, reps: int = 5):
+    """The largest serving request alone: a complex n x n ball product at
+    precision p (operands as in the serving pools), wall time per call and
+    per-kernel HIP-event times."""
+    rng = gen.rng_for(4, 900 + p)
+    dev = [arbgpu.DeviceArray.from_host(o) for o in gen.config4_operands(rng, n, p)]
+    C, Ci = arbgpu.DeviceOut.empty(n * n, p, radius=True), arbgpu.DeviceOut.empty(n * n, p, radius=True)
+    ctx = arbgpu.Context(0)
+    call = lambda: ctx.mat_mul(C, dev[0], dev[2], n, n, n, p, arbgpu.COMPLEX, Ci=Ci, Ai=dev[1], Bi=dev[3])
+    call()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    t = time.perf_counter()
+    for _ in range(reps):
+        call()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / reps
+    kern = {k: ctx.timing_read(k)[0] / reps for k in ("stats", "slice", "mfma", "recombine", "rad_gemm")}
+    ctx.timing(False)
+    plan = ctx.plan_info()
+    ctx.close()
+    log(f"[bench] largest request n={n} p={p} complex: {ms:.2f} ms, kernels {kern}")
+    return {"n": n, "p": p, "complex": True, "ms": ms, "reps": reps, "kernels_ms": kern,
+            "primes": plan["primes"], "digit_pairs_per_part": plan["pairs"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +264,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-sweep", default="50,100",
                     help="further arrival rates (req/s), 3 s of arrivals each; empty skips")
+    ap.add_argument("--no-largest", action="store_true", help="skip timing the largest serving request alone")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--no-peaks", action="store_true", help="skip the machine-limit microbenchmarks")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -400,6 +427,9 @@ def main():
     torch.cuda.empty_cache()
     if a.batch_launches:
         out["dot_batch"] = bench_dot_batch(arbgpu, torch, log, a.batch_launches)
+        torch.cuda.empty_cache()
+    if not a.no_largest:
+        out["largest_request"] = bench_largest(arbgpu, torch, log)
         torch.cuda.empty_cache()
     if a.serve_requests:
         out["serving"] = bench_serving(arbgpu, torch, log, a.serve_requests, a.serve_rate, a.serve_slots)
