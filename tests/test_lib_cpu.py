@@ -171,3 +171,17 @@ def test_host_only_context_validates_probe_peaks(hctx, lib):
 def test_init_rejects_bad_device(lib):
     h = ctypes.c_void_p()
     assert lib.arbgpu_init(ctypes.byref(h), -2, 0, None) == arbgpu.EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark runs on one GPU only; asking for more is refused before
+    # any device work
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
