@@ -17,6 +17,10 @@
 #include "finish.hpp"
 #include "sliced.hpp"
 
+#ifndef CRT_PAIR
+#define CRT_PAIR 1
+#endif
+
 namespace arbgpu_impl {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -131,30 +135,6 @@ __device__ __forceinline__ void frag_load4(v4i (&f)[4], const int8_t *a, int k0,
   for (int u = 0; u < 4; ++u) {
     const int ks = k0 + u < nks ? k0 + u : k0;
     f[u] = *reinterpret_cast<const v4i *>(a + 32 * ks);
-  }
-}
-
-// acc += A B over nks steps of 32 inner bytes (fragments at a + 32 ks and
-// b + 32 ks), the A fragments of the first four steps already in fa0: the
-// loads of up to four steps are issued before their products.
-__device__ __forceinline__ void mfma_run(v16i &acc, const v4i (&fa0)[4], const int8_t *a, const uint8_t *b,
-                                         int nks) {
-  for (int k0 = 0; k0 < nks; k0 += 4) {
-    v4i fa[4], fb[4];
-    if (k0 == 0) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) fa[u] = fa0[u];
-    } else {
-      frag_load4(fa, a, k0, nks);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int ks = k0 + u < nks ? k0 + u : k0;
-      fb[u] = *reinterpret_cast<const v4i *>(b + 32 * ks);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (k0 + u < nks) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[u], fb[u], acc, 0, 0, 0);
   }
 }
 
@@ -311,18 +291,19 @@ __device__ __forceinline__ uint32_t residue3(int32_t d0, int32_t d1, int32_t d2,
 // compute the y_j digits from the three partial planes of each prime into
 // an LDS row of kc bytes (+16 so that 8 consecutive rows fall in distinct
 // 16-byte bank groups), and k.  Phase 2: the waves split the blocks of 32
-// entries and (for a single block) its chunks of 32 digit columns (8
-// limbs) into runs of consecutive chunks: one 32 x 32 MFMA result per
+// entries and (for a single block, or for both blocks together when the
+// limb count is large) their chunks of 32 digit columns (8 limbs) into
+// runs of consecutive chunks: one 32 x 32 MFMA result per
 // chunk, whose lane l holds limbs 4 (l / 32) .. +3 of entry l % 32 as four
 // groups of 4 digit sums; the limbs are formed in 64-bit with the carry
 // passed from the lower lane half to the upper and on along the run, and
 // kept in LDS with the run's signed carry out.  Phase 3: every entry adds
 // the runs' carries in limb order and is rounded.
-template <int EW>
+template <int EW, bool PAIR>
 __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
   extern __shared__ __attribute__((aligned(16))) uint8_t ylds[];   // [EW][kc + 16], then T
   uint32_t *tl = reinterpret_cast<uint32_t *>(ylds + (size_t)EW * (P.tab.kc + 16));   // [W][EW]
-  int32_t *cyl = reinterpret_cast<int32_t *>(tl + (size_t)P.W * EW);                  // [ncc][EW], EW = 32
+  int32_t *cyl = reinterpret_cast<int32_t *>(tl + (size_t)P.W * EW);                  // [ncc][EW], with runs
   __shared__ double apart[256];
   constexpr int TPE = 256 / EW;
   const int tid = threadIdx.x;
@@ -383,62 +364,90 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
   }
 
   // phase 2: digit sums on MFMA; each wave walks a run of consecutive limb
-  // chunks of one entry block, passing the carry along the run, and
-  // stores each chunk's 8 limbs and, at the end of its run, the signed
+  // chunks of one or two entry blocks, passing the carries along the run,
+  // and stores each chunk's 8 limbs and, at the end of its run, the signed
   // carry out (zero for the other chunks)
   {
     const int lane = tid & 63, wave = tid >> 6, h = lane >> 5;
     // entry blocks; runs per block: with 64 entries two waves walk all
     // chunks of a block each (splitting them further measured slower, the
-    // carry pass below costing more than the shorter walks gain), with 32
+    // carry pass below costing more than the shorter walks gain), unless
+    // PAIR: then each wave takes a quarter of the chunks of both blocks,
+    // and every weight fragment feeds the products of both (for long
+    // limb counts, where those fragments' traffic dominates); with 32
     // entries the four waves share the one block
-    constexpr int NB = EW / 32, RB = EW == 32 ? 4 : 1;
-    const int ncc = P.tab.ncc, rl = (ncc + RB - 1) / RB;
-    const int wv = wave % NB, c0 = (wave / NB) * rl, c1 = min(c0 + rl, ncc);
-    const uint8_t *yrow = ylds + (size_t)(32 * wv + (lane & 31)) * S + 16 * h;
-    const int el = 32 * wv + (lane & 31);
-    int64_t carry = 0;
+    constexpr int NB = EW / 32, RB = (EW == 32 || PAIR) ? 4 : 1, NBW = PAIR ? 2 : 1;
+    const int ncc = P.tab.ncc, rl = (ncc + RB - 1) / RB, nks = kc / 32;
+    const int wv0 = PAIR ? 0 : wave % NB, run = PAIR ? wave : wave / NB;
+    const int c0 = run * rl, c1 = min(c0 + rl, ncc);
+    const uint8_t *yrow[NBW];
+    int el[NBW];
+    int64_t carry[NBW];
+#pragma unroll
+    for (int b = 0; b < NBW; ++b) {
+      el[b] = 32 * (wv0 + b) + (lane & 31);
+      yrow[b] = ylds + (size_t)el[b] * S + 16 * h;
+      carry[b] = 0;
+    }
     for (int cc = c0; cc < c1; ++cc) {
       const int8_t *qrow = P.tab.qd + ((int64_t)cc * 32 + (lane & 31)) * kc + 16 * h;
-      v4i f0[4];
-      frag_load4(f0, qrow, 0, kc / 32);
-      v16i acc;
+      v16i acc[NBW];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] = 0;
-      mfma_run(acc, f0, qrow, yrow, kc / 32);
-      int64_t L[4];
+      for (int b = 0; b < NBW; ++b)
 #pragma unroll
-      for (int g = 0; g < 4; ++g)
-        L[g] = (int64_t)acc[4 * g] + ((int64_t)acc[4 * g + 1] << 8) + ((int64_t)acc[4 * g + 2] << 16) +
-               ((int64_t)acc[4 * g + 3] << 24);
-      // lower half first (carry in from the previous chunk of the run),
-      // then the upper half with the lower half's carry out; the carry out
-      // of a run is below 2^22 in magnitude (every column sum is below
-      // kc 2^14 < 2^25)
-      uint32_t limb[4];
-      int64_t v = h ? 0 : carry;
+        for (int r = 0; r < 16; ++r) acc[b][r] = 0;
+      for (int k0 = 0; k0 < nks; k0 += 4) {
+        v4i fa[4];
+        frag_load4(fa, qrow, k0, nks);
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        v += L[g];
-        limb[g] = (uint32_t)v;
-        v >>= 32;
+        for (int b = 0; b < NBW; ++b) {
+          v4i fb[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int ks = k0 + u < nks ? k0 + u : k0;
+            fb[u] = *reinterpret_cast<const v4i *>(yrow[b] + 32 * ks);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (k0 + u < nks) acc[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[u], fb[u], acc[b], 0, 0, 0);
+        }
       }
-      const int64_t vl = __shfl(v, lane & 31);
-      if (h) {
-        v = vl;
+#pragma unroll
+      for (int b = 0; b < NBW; ++b) {
+        int64_t L[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          L[g] = (int64_t)acc[b][4 * g] + ((int64_t)acc[b][4 * g + 1] << 8) + ((int64_t)acc[b][4 * g + 2] << 16) +
+                 ((int64_t)acc[b][4 * g + 3] << 24);
+        // lower half first (carry in from the previous chunk of the run),
+        // then the upper half with the lower half's carry out; the carry
+        // out of a run is below 2^22 in magnitude (every column sum is
+        // below kc 2^14 < 2^25)
+        uint32_t limb[4];
+        int64_t v = h ? 0 : carry[b];
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
           v += L[g];
           limb[g] = (uint32_t)v;
           v >>= 32;
         }
-      }
-      carry = __shfl(v, (lane & 31) + 32);
-      if (RB > 1 && h) cyl[cc * EW + el] = cc + 1 == c1 ? (int32_t)carry : 0;
+        const int64_t vl = __shfl(v, lane & 31);
+        if (h) {
+          v = vl;
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int q = 8 * cc + 4 * h + g;
-        if (q < W) tl[q * EW + el] = limb[g];
+          for (int g = 0; g < 4; ++g) {
+            v += L[g];
+            limb[g] = (uint32_t)v;
+            v >>= 32;
+          }
+        }
+        carry[b] = __shfl(v, (lane & 31) + 32);
+        if (RB > 1 && h) cyl[cc * EW + el[b]] = cc + 1 == c1 ? (int32_t)carry[b] : 0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int q = 8 * cc + 4 * h + g;
+          if (q < W) tl[q * EW + el[b]] = limb[g];
+        }
       }
     }
   }
@@ -452,7 +461,7 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
     // the runs' carries, added in limb order (a chunk's 8 limbs are read
     // together)
     int64_t c = 0;
-    for (int cc = 0; EW == 32 && cc < P.tab.ncc; ++cc) {
+    for (int cc = 0; (EW == 32 || PAIR) && cc < P.tab.ncc; ++cc) {
       uint32_t t[8];
 #pragma unroll
       for (int g = 0; g < 8; ++g) t[g] = 8 * cc + g < W ? T[(8 * cc + g) * EW] : 0u;
@@ -561,8 +570,10 @@ hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s) {
   return hipGetLastError();
 }
 
-size_t rns_crt_lds(int ew, int kc, int W) {
-  return (size_t)ew * ((size_t)kc + 16 + 4 * (size_t)W + (ew == 32 ? 4 * (size_t)((W + 7) / 8) : 0));
+size_t rns_crt_lds(int ew, int kc, int W) { return rns_crt_lds(ew, kc, W, ew == 32); }
+
+size_t rns_crt_lds(int ew, int kc, int W, bool runs) {
+  return (size_t)ew * ((size_t)kc + 16 + 4 * (size_t)W + (runs ? 4 * (size_t)((W + 7) / 8) : 0));
 }
 
 hipError_t launch_rns_crt(const RnsCrtParams &P, hipStream_t s) {
@@ -571,13 +582,22 @@ hipError_t launch_rns_crt(const RnsCrtParams &P, hipStream_t s) {
   if (rns_crt_lds(32, P.tab.kc, P.W) > kRnsCrtLds || P.tab.ncc * 8 < P.W || P.tab.ncc != (P.W + 7) / 8)
     return hipErrorInvalidValue;
   // 64 entries per workgroup (four threads per entry in phase 1) measured
-  // faster than 128 and than fewer threads; 32 when that tile would take
-  // more than 64 KiB of LDS or the launch would leave compute units idle
-  const int ew = rns_crt_lds(64, P.tab.kc, P.W) <= 65536 && (MN + 63) / 64 >= 1024 ? 64 : 32;
-  const dim3 grid((unsigned)((MN + ew - 1) / ew));
-  const size_t lds = rns_crt_lds(ew, P.tab.kc, P.W);
-  if (ew == 64) hipLaunchKernelGGL(rns_crt_kernel<64>, grid, dim3(256), lds, s, P);
-  else hipLaunchKernelGGL(rns_crt_kernel<32>, grid, dim3(256), lds, s, P);
+  // faster than 128 and than fewer threads while its tile takes at most
+  // 64 KiB of LDS; beyond that, 64 entries with the waves pairing the two
+  // blocks (up to 80 KiB), else 32; 32 also when the launch would leave
+  // compute units idle
+  const bool many = (MN + 63) / 64 >= 1024;
+  const int kc = P.tab.kc, W = P.W;
+  if (many && rns_crt_lds(64, kc, W, false) <= 65536) {
+    hipLaunchKernelGGL((rns_crt_kernel<64, false>), dim3((unsigned)((MN + 63) / 64)), dim3(256),
+                       rns_crt_lds(64, kc, W, false), s, P);
+  } else if (many && CRT_PAIR && rns_crt_lds(64, kc, W, true) <= 81920) {
+    hipLaunchKernelGGL((rns_crt_kernel<64, true>), dim3((unsigned)((MN + 63) / 64)), dim3(256),
+                       rns_crt_lds(64, kc, W, true), s, P);
+  } else {
+    hipLaunchKernelGGL((rns_crt_kernel<32, false>), dim3((unsigned)((MN + 31) / 32)), dim3(256),
+                       rns_crt_lds(32, kc, W, true), s, P);
+  }
   return hipGetLastError();
 }
 

@@ -180,6 +180,8 @@ hipError_t launch_rns_swap_neg(const int8_t *src, int8_t *dst, int m, int64_t li
 hipError_t launch_rns_crt(const RnsCrtParams &P, hipStream_t s);
 // dynamic LDS of the reconstruction kernel for ew entries per workgroup
 size_t rns_crt_lds(int ew, int kc, int W);
+// the same with or without the per-chunk carry words of the runs
+size_t rns_crt_lds(int ew, int kc, int W, bool runs);
 // its budget: 64 KiB of digit rows and limbs plus the chunk carries, at
 // most 32 entries x 64 chunks x 4 bytes (a gfx950 workgroup may hold up to
 // 160 KiB)

@@ -164,6 +164,38 @@ def test_rns_complex_short_and_ragged_inner(ctx, N):
             assert compare_entry(gen.to_canonical(outi, i * K + j), im, int(sti[i * K + j])) is None
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_rns_paired_reconstruction(ctx, cplx):
+    # 2048-bit operands over 65536 entries: the reconstruction's 64-entry
+    # tile needs more than 64 KiB of LDS, so its waves take runs of limb
+    # chunks of both 32-entry blocks together (every weight fragment feeding
+    # two products) and the runs' carries are added per entry
+    rng = gen.rng_for(27, int(cplx))
+    M, N, K, p = 256, 40, 256, 2048
+    prec = rng.integers(1900, 2049, 4 * M * N)
+    A = gen.random_operands(rng, M * N, prec[:M * N], -8, 8, radius_shift=2040, zero_frac=0.05)
+    B = gen.random_operands(rng, N * K, prec[M * N:M * N + N * K], -8, 8, zero_frac=0.05)
+    Ai = gen.random_operands(rng, M * N, prec[2 * M * N:3 * M * N], -8, 8) if cplx else None
+    Bi = gen.random_operands(rng, N * K, prec[3 * M * N:3 * M * N + N * K], -8, 8, radius_shift=2040) if cplx else None
+    flags = (arbgpu.COMPLEX if cplx else 0) | arbgpu.ALGO_RNS
+    say(f"residue form paired reconstruction complex={cplx}")
+    (out, st), im = run(ctx, A, B, M, N, K, p, flags, Ai=Ai, Bi=Bi)
+    r = random.Random(27)
+    ent = [(r.randrange(M), r.randrange(K)) for _ in range(24)] + [(0, 0), (M - 1, K - 1), (63, 31), (64, 32)]
+    if not cplx:
+        Ac = gen.canonical_matrix(A, M, N, N, 1)
+        Bc = gen.canonical_matrix(B, N, K, K, 1)
+        check(out, st, lambda i, j: oracle.dot(Ac[i], [Bc[k][j] for k in range(N)], p), ent, K)
+    else:
+        (oi, si) = im
+        for i, j in ent:
+            x = [(gen.to_canonical(A, i * N + k), gen.to_canonical(Ai, i * N + k)) for k in range(N)]
+            y = [(gen.to_canonical(B, k * K + j), gen.to_canonical(Bi, k * K + j)) for k in range(N)]
+            re, imv = oracle.cdot(x, y, p)
+            assert compare_entry(gen.to_canonical(out, i * K + j), re, int(st[i * K + j])) is None
+            assert compare_entry(gen.to_canonical(oi, i * K + j), imv, int(si[i * K + j])) is None
+
+
 @pytest.mark.parametrize("algo", ALGOS)
 def test_config1_sliced_equals_limb_and_oracle(ctx, algo):
     w = gen.config1()
