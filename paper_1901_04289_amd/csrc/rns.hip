@@ -17,10 +17,6 @@
 #include "finish.hpp"
 #include "sliced.hpp"
 
-#ifndef CRT_PAIR
-#define CRT_PAIR 1
-#endif
-
 namespace arbgpu_impl {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -582,18 +578,20 @@ hipError_t launch_rns_crt(const RnsCrtParams &P, hipStream_t s) {
   if (rns_crt_lds(32, P.tab.kc, P.W) > kRnsCrtLds || P.tab.ncc * 8 < P.W || P.tab.ncc != (P.W + 7) / 8)
     return hipErrorInvalidValue;
   // 64 entries per workgroup (four threads per entry in phase 1) measured
-  // faster than 128 and than fewer threads while its tile takes at most
-  // 64 KiB of LDS; beyond that, 64 entries with the waves pairing the two
-  // blocks (up to 80 KiB), else 32; 32 also when the launch would leave
-  // compute units idle
+  // faster than 128 and than fewer threads.  From 8 limb chunks on, the
+  // waves pair the two 32-entry blocks (up to 80 KiB of LDS; with 9 chunks
+  // 1.49 -> 1.38 ms at 1024^2 complex p = 1024, with 5 slower, 1.12 ->
+  // 1.25 ms at 2048^2 p = 512); below, two waves walk a block each (up to
+  // 64 KiB); else 32 entries, also when the launch would leave compute
+  // units idle
   const bool many = (MN + 63) / 64 >= 1024;
   const int kc = P.tab.kc, W = P.W;
-  if (many && rns_crt_lds(64, kc, W, false) <= 65536) {
-    hipLaunchKernelGGL((rns_crt_kernel<64, false>), dim3((unsigned)((MN + 63) / 64)), dim3(256),
-                       rns_crt_lds(64, kc, W, false), s, P);
-  } else if (many && CRT_PAIR && rns_crt_lds(64, kc, W, true) <= 81920) {
+  if (many && P.tab.ncc >= 8 && rns_crt_lds(64, kc, W, true) <= 81920) {
     hipLaunchKernelGGL((rns_crt_kernel<64, true>), dim3((unsigned)((MN + 63) / 64)), dim3(256),
                        rns_crt_lds(64, kc, W, true), s, P);
+  } else if (many && rns_crt_lds(64, kc, W, false) <= 65536) {
+    hipLaunchKernelGGL((rns_crt_kernel<64, false>), dim3((unsigned)((MN + 63) / 64)), dim3(256),
+                       rns_crt_lds(64, kc, W, false), s, P);
   } else {
     hipLaunchKernelGGL((rns_crt_kernel<32, false>), dim3((unsigned)((MN + 31) / 32)), dim3(256),
                        rns_crt_lds(32, kc, W, true), s, P);
