@@ -43,9 +43,9 @@ PEAK_INT8_TOPS = 5000.0   # MI355X dense INT8 MFMA, 5.0 POP/s
 # INT8 forms, from the FETCH_SIZE (x2, copy-calibrated) and WRITE_SIZE (x1)
 # counter runs in profiles/mfma_diag_kernel_matmul2048_p512.txt; valid only
 # for the kernel source they were taken on (sha256 prefix of csrc/mfma.hip).
-MFMA_TRAFFIC_BYTES = {"residues": (1786559 * 2 + 3489792) * 1024.0,
-                      "slices": (42483191 * 2 + 2228224) * 1024.0}
-MFMA_TRAFFIC_SRC = "cf974db54726e0ee"
+MFMA_TRAFFIC_BYTES = {"residues": (1761777 * 2 + 3489792) * 1024.0,
+                      "slices": (30267872 * 2 + 2228224) * 1024.0}
+MFMA_TRAFFIC_SRC = "ef1395843d68b766"
 
 
 def _mfma_traffic(n, form):
