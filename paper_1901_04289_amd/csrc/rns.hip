@@ -300,7 +300,10 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
   extern __shared__ __attribute__((aligned(16))) uint8_t ylds[];   // [EW][kc + 16], then T
   uint32_t *tl = reinterpret_cast<uint32_t *>(ylds + (size_t)EW * (P.tab.kc + 16));   // [W][EW]
   int32_t *cyl = reinterpret_cast<int32_t *>(tl + (size_t)P.W * EW);                  // [ncc][EW], with runs
-  __shared__ double apart[256];
+  // phase 1's partial sums of alpha share the limbs' space: the limbs are
+  // written only after the last read of the partials (and the host sizes
+  // that space to hold at least 256 doubles)
+  double *apart = reinterpret_cast<double *>(tl);
   constexpr int TPE = 256 / EW;
   const int tid = threadIdx.x;
   const int m = P.tab.m, kc = P.tab.kc, S = kc + 16, W = P.W;
@@ -569,7 +572,9 @@ hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s) {
 size_t rns_crt_lds(int ew, int kc, int W) { return rns_crt_lds(ew, kc, W, ew == 32); }
 
 size_t rns_crt_lds(int ew, int kc, int W, bool runs) {
-  return (size_t)ew * ((size_t)kc + 16 + 4 * (size_t)W + (runs ? 4 * (size_t)((W + 7) / 8) : 0));
+  const size_t rows = (size_t)ew * ((size_t)kc + 16);
+  const size_t rest = (size_t)ew * (4 * (size_t)W + (runs ? 4 * (size_t)((W + 7) / 8) : 0));
+  return rows + std::max<size_t>(rest, 256 * sizeof(double));
 }
 
 hipError_t launch_rns_crt(const RnsCrtParams &P, hipStream_t s) {
