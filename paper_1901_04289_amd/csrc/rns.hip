@@ -150,8 +150,13 @@ __device__ __forceinline__ void frag_load4(v4i (&f)[4], const int8_t *a, int k0,
 // digits of one element into 4 elements' digits of one plane, stored as
 // one word (the padded plane holds whole blocks of 32 elements and starts
 // 16-byte aligned).
+//
+// Registers are capped for five waves per SIMD (four otherwise): at 2048^2
+// p = 512 the two operands' slicing took 1.24 -> 1.20 ms with that, despite
+// an 8-byte spill in the 256-element form; six waves spilled 76 bytes and
+// took 1.76 ms.
 template <int EL>
-__global__ __launch_bounds__(256) void rns_slice_kernel(RnsSliceParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void rns_slice_kernel(RnsSliceParams P) {
   extern __shared__ __attribute__((aligned(16))) uint8_t dl[];   // [EL][kd + 16]
   const int tid = threadIdx.x;
   const int nw = P.tab.nw, kd = P.tab.kd, S = kd + 16, m = P.tab.m;
