@@ -148,7 +148,7 @@ int arbgpu_dot(arbgpu_ctx *ctx, const arbgpu_out *res, int64_t res_idx,
  * output bit.  EINVAL on shape mismatch, p < 2, output cap too
  * small, NULL pointers, or when the chosen (or, without an ALGO flag,
  * every) path cannot hold the operands: the limb kernel's window as for
- * arbgpu_dot; base-256 slices up to integer heights below 4095 bits per
+ * arbgpu_dot; base-256 slices up to integer heights of 4094 bits per
  * block; residues up to heights of about 4060 bits (127 words of four
  * base-256 digits, so that the residue sums stay below 2^30) while the
  * exact block values fit the reconstruction's LDS rows (about 8000 bits). */

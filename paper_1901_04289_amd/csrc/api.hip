@@ -51,6 +51,7 @@ void *ws_get(arbgpu_ctx *ctx, int slot, size_t bytes) {
     (void)hipFree(b.ptr);
     b.ptr = nullptr;
     b.size = 0;
+    if (slot == WS_RNS) ctx->rns_key = -1;
   }
   size_t total = bytes;
   for (int i = 0; i < (int)ctx->ws.size(); ++i) total += ctx->ws[i].size;

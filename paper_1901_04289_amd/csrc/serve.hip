@@ -112,6 +112,7 @@ struct Server {
             b.ptr = nullptr;
             b.size = 0;
           }
+          c->rns_key = -1;   // the residue tables went with the workspace
         }
       }
       {

@@ -8,7 +8,7 @@ namespace arbgpu_impl {
 
 constexpr int kTile = 256;       // output tile edge of the MFMA kernel
 constexpr int kKStep = 128;      // inner bytes per pipeline step
-constexpr int kMaxSlices = 512;  // digit planes per operand (height < 4095 bits)
+constexpr int kMaxSlices = 512;  // digit planes per operand (heights up to 4094 bits)
 
 // Per-row / per-column statistics over the inner index range of a block.
 struct LineStats {

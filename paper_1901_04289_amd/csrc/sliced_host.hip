@@ -66,7 +66,13 @@ int line_stats(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const 
   return ARBGPU_OK;
 }
 
-inline int slices_for(int height) { return std::max(1, (height + 1 + 7) / 8); }
+// Balanced base-256 digits (each in [-128, 127]) for the scaled integers of
+// a line of the given height, |Y| <= 2^height - 1.  L digits reach
+// 127 (256^L - 1) / 255 above zero, a little under 256^L / 2, so they hold
+// 2^h - 1 exactly when 8 L >= h + 2; the single digit of heights up to 7
+// holds 127 = 2^7 - 1.  (8 L = h + 1 would turn Y = 2^h - 1 into
+// Y - 256^L for every h = 8 L - 1 >= 15.)
+inline int slices_for(int height) { return height <= 7 ? 1 : (height + 2 + 7) / 8; }
 
 // B's lines (columns) for slicing the inner range [k0, k1): when the inner
 // index is strided and the columns are not (row-major B), a line-major copy

@@ -221,11 +221,67 @@ def test_config2_sliced_sampled(ctx):
     (o2, s2), _ = run(ctx, w.A, w.B, w.M, w.N, w.K, w.p, arbgpu.ALGO_RNS)
     assert np.array_equal(out.limbs, o2.limbs) and np.array_equal(out.exp, o2.exp)
     assert np.array_equal(out.nls, o2.nls) and np.array_equal(out.rad_m, o2.rad_m) and np.array_equal(st, s2)
+    # an independent check of whole rows: the first 64 rows of the product
+    # from the limb-window kernel (no slicing, no residues, no MFMA) are the
+    # same bits as the INT8 product's
+    R = 64
+    Ab = gen.Operands(w.A.limbs[:, :R * w.N].copy(), w.A.exp[:R * w.N].copy(), w.A.nls[:R * w.N].copy(), None, None)
+    say("config2 limb-kernel row block 64x2048x2048 p=512")
+    (o3, s3), _ = run(ctx, Ab, w.B, R, w.N, w.K, w.p, arbgpu.ALGO_LIMB)
+    n = R * w.K
+    assert np.array_equal(o3.limbs, out.limbs[:, :n]) and np.array_equal(o3.exp, out.exp[:n])
+    assert np.array_equal(o3.nls, out.nls[:n])
     r = random.Random(4)
     ent = [(r.randrange(w.M), r.randrange(w.K)) for _ in range(10)] + [(0, 0), (w.M - 1, w.K - 1)]
     rows = {i: [gen.to_canonical(w.A, i * w.N + k) for k in range(w.N)] for i, _ in ent}
     cols = {j: [gen.to_canonical(w.B, k * w.K + j) for k in range(w.N)] for _, j in ent}
     check(out, st, lambda i, j: oracle.dot(rows[i], cols[j], w.p), ent, w.K)
+
+
+def full_height_operands(rng, count, h, exp_lo, exp_hi):
+    """Operands whose mantissas have exactly h significant bits, a quarter of
+    them all ones (the scaled integer 2^h - 1 when the line's exponents
+    agree), both signs."""
+    ops = gen.random_operands(rng, count, h, exp_lo, exp_hi)
+    ones = rng.random(count) < 0.25
+    balls = []
+    for i in range(count):
+        m, r = gen.to_canonical(ops, i)
+        if ones[i] and m[1]:
+            m = oracle.fmake(m[0], (1 << h) - 1, m[2])
+        balls.append((m, r))
+    return gen.from_canonical(balls, cap=ops.cap)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("h", [7, 8, 15, 23, 31, 63, 64, 127, 255, 519, 520])
+def test_digit_count_at_every_height_class(ctx, algo, h):
+    # rows of A and columns of B of integer height exactly h (one exponent
+    # per line, mantissas of h bits, entries up to 2^h - 1 in magnitude):
+    # heights 8 L - 1 need L + 1 balanced base-256 digits, the largest
+    # values the most.  The exact block product T is compared with the
+    # oracle's integer product, and the midpoints with the limb kernel
+    rng = gen.rng_for(28, h)
+    M, N, K = 9, 6, 7
+    A = full_height_operands(rng, M * N, h, 0, 0)
+    B = full_height_operands(rng, N * K, h, 0, 0)
+    A.exp[:] = np.repeat(rng.integers(-5, 6, M), N).astype(np.int32) * (A.nls != 0)
+    B.exp[:] = np.tile(rng.integers(-5, 6, K), N).astype(np.int32) * (B.nls != 0)
+    p = 2 * h + 16
+    say(f"digit count h={h} algo={algo:#x}")
+    (out, st), _ = run(ctx, A, B, M, N, K, p, algo)
+    Ac = gen.canonical_matrix(A, M, N, N, 1)
+    Bc = gen.canonical_matrix(B, N, K, K, 1)
+    e, f, T = oracle.block_product([[x[0] for x in r] for r in Ac], [[x[0] for x in r] for r in Bc],
+                                   list(range(N)))
+    assert max(abs(x) for row in T for x in row) > 0
+    for i in range(M):
+        for j in range(K):
+            want = oracle.truncate(T[i][j], -e[i] - f[j], p)
+            assert not want[1]
+            assert gen.to_canonical(out, i * K + j)[0] == want[0], (i, j)
+    (o2, s2), _ = run(ctx, A, B, M, N, K, p, arbgpu.ALGO_LIMB)
+    assert np.array_equal(out.limbs, o2.limbs) and np.array_equal(out.nls, o2.nls)
 
 
 @pytest.mark.parametrize("seed,spread,bside", [(1, 700, False), (2, 300, True), (3, 1500, True)])

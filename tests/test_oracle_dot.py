@@ -348,3 +348,117 @@ def test_badly_scaled_matrix_keeps_entrywise_accuracy():
     assert rfr(C2[2][2].rad) < Fraction(1, 10 ** 40)
     # (2,3) entry = 2.34*3.45 + 3.45*4.56e-100: radius reflects 1e-20 and 1e-50 inputs
     assert rfr(C2[1][2].rad) < Fraction(1, 10 ** 19)
+
+
+# ------------------------------------------------- approx variants (Section 3)
+
+
+@settings(max_examples=150, deadline=None)
+@given(st.lists(st.tuples(balls, balls), min_size=0, max_size=8),
+       st.integers(2, 140), st.booleans(), st.one_of(st.none(), balls))
+def test_approx_dot_is_the_truncated_sum_without_radius(pairs, p, sub, initial):
+    # the approx variants return only a midpoint: the same truncation of the
+    # exact sum (checked against Fraction arithmetic and mpmath's round-down,
+    # independently of the full call), no radius, and the same inexact flag
+    x = [a for a, _ in pairs]
+    y = [b for _, b in pairs]
+    res = oracle.dot(x, y, p, initial=initial, sub=sub, approx=True)
+    S = sum((fr(a[0]) * fr(b[0]) for a, b in pairs), Fraction(0))
+    if sub:
+        S = -S
+    if initial is not None:
+        S += fr(initial[0])
+    want = trunc_fraction(S, p)
+    assert res.rad is None
+    assert fr(res.mid) == want
+    assert res.inexact == (want != S)
+    full = oracle.dot(x, y, p, initial=initial, sub=sub)
+    assert res.mid == full.mid and res.inexact == full.inexact
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_approx_cdot_against_fraction_definition(seed):
+    rng = random.Random(500 + seed)
+    n = 10
+    x = [(b1, b2) for b1, b2 in zip(_rand_balls(rng, n), _rand_balls(rng, n))]
+    y = [(b1, b2) for b1, b2 in zip(_rand_balls(rng, n), _rand_balls(rng, n))]
+    re, im = oracle.cdot(x, y, 61, approx=True)
+    Sre = sum((fr(a[0]) * fr(c[0]) - fr(b[0]) * fr(d[0]) for (a, b), (c, d) in zip(x, y)), Fraction(0))
+    Sim = sum((fr(a[0]) * fr(d[0]) + fr(b[0]) * fr(c[0]) for (a, b), (c, d) in zip(x, y)), Fraction(0))
+    assert re.rad is None and im.rad is None
+    assert fr(re.mid) == trunc_fraction(Sre, 61) and re.inexact == (fr(re.mid) != Sre)
+    assert fr(im.mid) == trunc_fraction(Sim, 61) and im.inexact == (fr(im.mid) != Sim)
+    fre, fim = oracle.cdot(x, y, 61)
+    assert (re.mid, re.inexact) == (fre.mid, fre.inexact)
+    assert (im.mid, im.inexact) == (fim.mid, fim.inexact)
+
+
+# ------------------------------------------- complex matrix product (Section 4.3)
+
+
+def _rand_cmat(rng, rows, cols, bits=90, erange=25):
+    return [[(b1, b2) for b1, b2 in zip(_rand_balls(rng, cols, bits, erange), _rand_balls(rng, cols, bits, erange))]
+            for _ in range(rows)]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_cmat_mul_against_fraction_definition(seed):
+    # C_ij = sum_k (a + b i)(c + d i) over exact rationals, each part
+    # truncated once toward zero (mpmath round-down), with the enclosure
+    # radius of Section 2 summed over the part's 2N real products
+    rng = random.Random(600 + seed)
+    M, N, K, p = 3, 7, 4, 70
+    A, B = _rand_cmat(rng, M, N), _rand_cmat(rng, N, K)
+    C = oracle.cmat_mul(A, B, p)
+    for i in range(M):
+        for j in range(K):
+            terms = [(A[i][k], B[k][j]) for k in range(N)]
+            Sre = sum((fr(a[0]) * fr(c[0]) - fr(b[0]) * fr(d[0]) for (a, b), (c, d) in terms), Fraction(0))
+            Sim = sum((fr(a[0]) * fr(d[0]) + fr(b[0]) * fr(c[0]) for (a, b), (c, d) in terms), Fraction(0))
+
+            def prad(u, v):
+                return abs(fr(u[0])) * rfr(v[1]) + abs(fr(v[0])) * rfr(u[1]) + rfr(u[1]) * rfr(v[1])
+
+            rho_re = sum((prad(a, c) + prad(b, d) for (a, b), (c, d) in terms), Fraction(0))
+            rho_im = sum((prad(a, d) + prad(b, c) for (a, b), (c, d) in terms), Fraction(0))
+            re, im = C[i][j]
+            for part, S, rho in ((re, Sre, rho_re), (im, Sim, rho_im)):
+                m = fr(part.mid)
+                assert m == trunc_fraction(S, p)
+                assert part.inexact == (m != S)
+                if part.inexact:
+                    rho += Fraction(2) ** (part.mid[2] - p)
+                assert rfr(part.rad) == rho
+                assert abs(S - m) <= rfr(part.rad)
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_cmat_mul_with_zero_imaginary_parts_is_mat_mul(seed):
+    rng = random.Random(700 + seed)
+    M, N, K, p = 4, 6, 3, 55
+    A = [_rand_balls(rng, N) for _ in range(M)]
+    B = [_rand_balls(rng, K) for _ in range(N)]
+    z = (oracle.ZERO, None)
+    C = oracle.cmat_mul([[(a, z) for a in row] for row in A], [[(b, z) for b in row] for row in B], p)
+    R = oracle.mat_mul(A, B, p)
+    for i in range(M):
+        for j in range(K):
+            re, im = C[i][j]
+            assert re == R[i][j]
+            assert im.mid == oracle.ZERO and im.rad == (0, 0) and not im.inexact
+
+
+@pytest.mark.parametrize("approx", [False, True])
+def test_cmat_mul_entry_is_cdot_of_row_and_column(approx):
+    rng = random.Random(800 + approx)
+    M, N, K = 2, 5, 3
+    A, B = _rand_cmat(rng, M, N), _rand_cmat(rng, N, K)
+    C = oracle.cmat_mul(A, B, 40, approx=approx)
+    R = oracle.mat_mul([[a for a, _ in row] for row in A], [[b for b, _ in row] for row in B], 40, approx=approx)
+    for i in range(M):
+        for j in range(K):
+            assert C[i][j] == oracle.cdot(A[i], [B[k][j] for k in range(N)], 40, approx=approx)
+            assert R[i][j] == oracle.dot([a for a, _ in A[i]], [B[k][j][0] for k in range(N)], 40,
+                                         approx=approx)
+            if approx:
+                assert C[i][j][0].rad is None and R[i][j].rad is None
