@@ -63,6 +63,12 @@ extern "C" {
 #define ARBGPU_ALGO_RNS     0x40u /* matmul: force the scaled-integer INT8 path
                                      with residues modulo primes < 2^15
                                      (multimodular, Section 4)             */
+#define ARBGPU_COMPLEX_4M   0x80u /* complex matmul on the residue path: four
+                                     real block products AC, BD, AD, BC
+                                     instead of the three of eq. (2)
+                                     (Section 3.6, Section 4.3), AC, BD and
+                                     (A+B)(C+D); both are exact, so no
+                                     output bit changes                    */
 
 /* Per-element status bytes. */
 #define ARBGPU_ST_OK       0   /* result written                                 */
@@ -156,6 +162,55 @@ int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A,
                    const arbgpu_mat *B, int64_t p, uint32_t flags,
                    arbgpu_stream stream);
 
+/* The exact integer block product of Algorithm 2 (Section 4.1) with the
+ * whole inner range taken as one block, midpoints only (radii are not
+ * read): with v_i the lowest set-bit position over the nonzero entries of
+ * row i of A and w_j that of column j of B (both parts together with
+ * ARBGPU_COMPLEX; 0 for a line without nonzero entries), the scaled
+ * integers a_ik 2^-v_i and b_kj 2^-w_j, and
+ *     T_ij = sum_k (a_ik 2^-v_i)(b_kj 2^-w_j),  so  (A B)_ij = T_ij 2^(v_i + w_j)
+ * (the paper's E_s = diag(2^e_i) is e_i = -v_i).  Complex: T_re from
+ * Re(A)Re(B) - Im(A)Im(B) and T_im from Re(A)Im(B) + Im(A)Re(B).  Writes
+ * T as capT two's-complement 32-bit limbs, least significant first, limb
+ * k of entry (i, j) at T_re[k*ldT + i*cols + j] (and T_im with
+ * ARBGPU_COMPLEX; T_im is not read otherwise), and v, w to row_v2[rows],
+ * col_v2[cols]; all DEVICE memory owned by the caller.  Flags: COMPLEX,
+ * ALGO_SLICED or ALGO_RNS (neither: the automatic choice), COMPLEX_4M.
+ * A debugging and verification entry point of the INT8 path; it
+ * synchronizes `stream` once to read the line statistics.  EINVAL: NULL
+ * pointers, shape mismatch, ldT < rows*cols, an integer height above the
+ * chosen form's limit, or capT below the limbs T needs (the needed count
+ * is in arbgpu_last_error); ERANGE: an exponent outside (-2^28, 2^28). */
+int arbgpu_mat_mul_exact_t(arbgpu_ctx *ctx, uint32_t *T_re, uint32_t *T_im, int64_t ldT,
+                           int32_t capT, int32_t *row_v2, int32_t *col_v2,
+                           const arbgpu_mat *A, const arbgpu_mat *B, uint32_t flags,
+                           arbgpu_stream stream);
+
+/* Workspace.  Each context keeps device workspace buffers that grow to
+ * the largest call made so far (never beyond its HBM budget) and are
+ * reused by later calls; growing one waits for the work the context has
+ * enqueued (on every stream it used), not for the whole device.
+ * arbgpu_reserve grows them ahead of time to what a matrix product of the
+ * given shape, precision and flags can take (an upper bound over the limb
+ * kernel and both INT8 forms when its inner range is one block; a product
+ * that splits into several blocks also holds its exact block values), so
+ * that calls on shapes within it allocate no device memory.  Reads only
+ * the shapes, caps and radius pointers of A and B.  EINVAL on bad
+ * arguments, ENOMEM over the budget, EDEVICE on a host-only context. */
+int arbgpu_reserve(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
+                   int64_t p, uint32_t flags);
+/* Workspace bookkeeping of the context and its request loop's slots:
+ * *allocs = device allocations made so far (workspace growth and batch
+ * creation; a warmed call sequence that allocates nothing leaves it
+ * unchanged), *bytes = workspace bytes held now.  Either pointer may be
+ * NULL.  EINVAL on a NULL context. */
+int arbgpu_workspace_info(arbgpu_ctx *ctx, int64_t *allocs, int64_t *bytes);
+/* The footprint arbgpu_submit admits a matrix product with: the sum over
+ * the workspace buffers of what arbgpu_reserve would grow them to, written
+ * to *bytes.  Host-only contexts may call it.  EINVAL on bad arguments. */
+int arbgpu_mat_mul_footprint(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
+                             int64_t p, uint32_t flags, size_t *bytes);
+
 /* Block partition of Algorithm 2 (Section 4.1) for the product A B at
  * precision p: the inner index range is cut greedily, from index 0 upward,
  * into ranges over which every row of A and every column of B keeps integer
@@ -221,8 +276,9 @@ void arbgpu_batch_destroy(arbgpu_batch *batch);
  * when one is bad; EINVAL names its index), and admits the set only if its
  * workspace footprint fits next to the work already in flight within the
  * loop's HBM budget: EAGAIN (try again after polling) when it does not fit
- * now, ENOMEM when it never can.  Worker slots, each with its own stream
- * and workspace, run the queue in order; requests on different slots
+ * now, ENOMEM when it never can (a job larger than one slot's share of the
+ * budget).  Worker slots, each with its own stream and workspace (kept
+ * between requests), run the queue in order; requests on different slots
  * overlap on the device, and dot jobs found together at the head of the
  * queue run as one persistent batch launch.  Results are the same as from
  * arbgpu_dot / arbgpu_mat_mul.  Operands and outputs must stay valid until
@@ -243,6 +299,13 @@ typedef struct {
  * bytes for the workspace of admitted jobs (0: half the context budget).
  * EINVAL while requests are in flight. */
 int arbgpu_serve_config(arbgpu_ctx *ctx, int slots, size_t budget_bytes);
+/* Reserves, in every slot of the loop (starting it with the defaults when
+ * needed), the workspace the largest of these jobs takes (arbgpu_reserve
+ * per matrix product; a dot job reserves a full batch of dot tasks), so
+ * that requests no larger allocate nothing.  Each slot holds at most the
+ * loop's budget divided by the slot count.  EINVAL on a bad job, ENOMEM
+ * when a slot's share is too small. */
+int arbgpu_serve_reserve(arbgpu_ctx *ctx, const arbgpu_job *jobs, int64_t njobs);
 /* Queues njobs jobs and writes their tickets (host array). */
 int arbgpu_submit(arbgpu_ctx *ctx, const arbgpu_job *jobs, int64_t njobs, uint64_t *tickets);
 /* Waits up to timeout_us (0: no wait) for a ticket: OK when its job is

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libarbgpu.so")
 
 OK, NOTREADY, EINVAL, ERANGE, ENOMEM, EAGAIN, EDEVICE = 0, 1, -1, -2, -3, -4, -5
 APPROX, COMPLEX, REDUCE_PREC, ALGO_LIMB, ALGO_SLICED, ALGO_RNS = 0x01, 0x02, 0x04, 0x10, 0x20, 0x40
+COMPLEX_4M = 0x80
 ST_OK, ST_REFINED, ST_ERANGE = 0, 1, 2
 
 c_p = ctypes.c_void_p
@@ -80,6 +81,13 @@ EXPORTS = {
                                   c_i64, c_i64, c_u32, c_p]),
     "arbgpu_mat_mul": (ctypes.c_int, [c_p, ctypes.POINTER(OMat), ctypes.POINTER(Mat), ctypes.POINTER(Mat),
                                       c_i64, c_u32, c_p]),
+    "arbgpu_mat_mul_exact_t": (ctypes.c_int, [c_p, c_p, c_p, c_i64, c_i32, c_p, c_p, ctypes.POINTER(Mat),
+                                              ctypes.POINTER(Mat), c_u32, c_p]),
+    "arbgpu_reserve": (ctypes.c_int, [c_p, ctypes.POINTER(Mat), ctypes.POINTER(Mat), c_i64, c_u32]),
+    "arbgpu_workspace_info": (ctypes.c_int, [c_p, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
+    "arbgpu_mat_mul_footprint": (ctypes.c_int, [c_p, ctypes.POINTER(Mat), ctypes.POINTER(Mat), c_i64, c_u32,
+                                                ctypes.POINTER(ctypes.c_size_t)]),
+    "arbgpu_serve_reserve": (ctypes.c_int, [c_p, ctypes.c_void_p, c_i64]),
     "arbgpu_plan_blocks": (ctypes.c_int, [c_p, ctypes.POINTER(Mat), ctypes.POINTER(Mat), c_i64, c_u32,
                                           ctypes.POINTER(c_i64), ctypes.POINTER(ctypes.c_int32), c_i64,
                                           ctypes.POINTER(c_i64), c_p]),
@@ -289,6 +297,18 @@ class Context:
                                      _stream_handle(stream) if self.device >= 0 else None)
         return self._check(rc) if check else rc
 
+    def mat_mul_exact_t_raw(self, T_re, T_im, ldT: int, capT: int, row_v2, col_v2, A: Mat, B: Mat,
+                            flags: int = 0, stream=None, check: bool = True) -> int:
+        """Exact block integer T into device tensors (int32 [capT, ldT]) and
+        the line scalings into int32 tensors [rows], [cols]."""
+        rc = self.lib.arbgpu_mat_mul_exact_t(self.h, ctypes.c_void_p(T_re.data_ptr()),
+                                             ctypes.c_void_p(T_im.data_ptr()) if T_im is not None else None,
+                                             ldT, capT, ctypes.c_void_p(row_v2.data_ptr()),
+                                             ctypes.c_void_p(col_v2.data_ptr()), ctypes.byref(A),
+                                             ctypes.byref(B), flags,
+                                             _stream_handle(stream) if self.device >= 0 else None)
+        return self._check(rc) if check else rc
+
     def plan_blocks_raw(self, A: Mat, B: Mat, p: int, flags: int = 0, stream=None):
         """Block partition of the inner range: list of (k0, k1, kind), kind 0
         a scaled-integer block, 1 a basecase chunk."""
@@ -302,9 +322,36 @@ class Context:
         n = min(nb.value, cap)
         return [(bounds[2 * i], bounds[2 * i + 1], kinds[i]) for i in range(n)]
 
+    def reserve_raw(self, A: Mat, B: Mat, p: int, flags: int = 0, check: bool = True) -> int:
+        """Grow the workspace for products of this shape (no allocation later)."""
+        rc = self.lib.arbgpu_reserve(self.h, ctypes.byref(A), ctypes.byref(B), p, flags)
+        return self._check(rc) if check else rc
+
+    def workspace_info(self):
+        """(device allocations made, workspace bytes held) by the context
+        and its serving slots."""
+        n, b = c_i64(), c_i64()
+        self._check(self.lib.arbgpu_workspace_info(self.h, ctypes.byref(n), ctypes.byref(b)))
+        return n.value, b.value
+
+    def alloc_count(self) -> int:
+        return self.workspace_info()[0]
+
+    def footprint_raw(self, A: Mat, B: Mat, p: int, flags: int = 0) -> int:
+        """Admission footprint of a matrix product, bytes."""
+        n = ctypes.c_size_t()
+        self._check(self.lib.arbgpu_mat_mul_footprint(self.h, ctypes.byref(A), ctypes.byref(B), p, flags,
+                                                      ctypes.byref(n)))
+        return n.value
+
     # -- request loop ------------------------------------------------------
     def serve_config(self, slots: int = 4, budget: int = 0):
         self._check(self.lib.arbgpu_serve_config(self.h, slots, budget))
+
+    def serve_reserve(self, jobs: Sequence[Job]):
+        """Reserve every slot's workspace for the largest of these jobs."""
+        arr = (Job * max(1, len(jobs)))(*jobs)
+        self._check(self.lib.arbgpu_serve_reserve(self.h, ctypes.cast(arr, ctypes.c_void_p), len(jobs)))
 
     def submit(self, jobs: Sequence[Job], check: bool = True):
         """Queue jobs; returns their tickets (or (rc, []) with check=False)."""

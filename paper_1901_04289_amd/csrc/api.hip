@@ -24,7 +24,7 @@ arbgpu_ctx::~arbgpu_ctx() {
     (void)hipEventDestroy(t.stop);
   }
   for (auto &b : ws)
-    if (b.ptr) (void)hipFree(b.ptr);
+    if (b.ptr && b.owned) (void)hipFree(b.ptr);
 }
 
 namespace arbgpu_impl {
@@ -41,33 +41,75 @@ int set_error(arbgpu_ctx *ctx, int code, const char *fmt, ...) {
   return code;
 }
 
-void *ws_get(arbgpu_ctx *ctx, int slot, size_t bytes) {
-  if ((int)ctx->ws.size() < WS_COUNT) ctx->ws.resize(WS_COUNT);
+namespace {
+
+// Waits for the work this context enqueued (on every stream it used) so
+// that a workspace buffer can be freed; other contexts' work is not waited
+// for.
+void ctx_drain(arbgpu_ctx *ctx) {
+  for (hipStream_t st : ctx->streams_seen) (void)hipStreamSynchronize(st);
+  ctx->streams_seen.clear();
+}
+
+bool ws_grow(arbgpu_ctx *ctx, int slot, size_t bytes) {
   arbgpu_ctx::Buf &b = ctx->ws[slot];
-  if (bytes == 0) bytes = 256;
-  if (b.size >= bytes) return b.ptr;
+  size_t total = bytes;
+  for (int i = 0; i < (int)ctx->ws.size(); ++i)
+    if (i != slot && ctx->ws[i].owned) total += ctx->ws[i].size;
+  if (ctx->budget && total > ctx->budget) {
+    set_error(ctx, ARBGPU_ENOMEM, "workspace of %zu bytes exceeds the HBM budget %zu", total, ctx->budget);
+    return false;
+  }
   if (b.ptr) {
-    (void)hipDeviceSynchronize();
-    (void)hipFree(b.ptr);
+    ctx_drain(ctx);
+    if (b.owned) (void)hipFree(b.ptr);
     b.ptr = nullptr;
     b.size = 0;
     if (slot == WS_RNS) ctx->rns_key = -1;
-  }
-  size_t total = bytes;
-  for (int i = 0; i < (int)ctx->ws.size(); ++i) total += ctx->ws[i].size;
-  if (ctx->budget && total > ctx->budget) {
-    set_error(ctx, ARBGPU_ENOMEM, "workspace of %zu bytes exceeds the HBM budget %zu", total, ctx->budget);
-    return nullptr;
   }
   void *p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
     set_error(ctx, ARBGPU_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
-    return nullptr;
+    return false;
   }
+  ++ctx->allocs;
   b.ptr = p;
   b.size = bytes;
-  return p;
+  b.owned = true;
+  return true;
+}
+
+}  // namespace
+
+void *ws_get(arbgpu_ctx *ctx, int slot, size_t bytes) {
+  if ((int)ctx->ws.size() < WS_COUNT) ctx->ws.resize(WS_COUNT);
+  arbgpu_ctx::Buf &b = ctx->ws[slot];
+  if (bytes == 0) bytes = 256;
+  if (b.size >= bytes) return b.ptr;
+  if (ctx->ws_fixed) {
+    set_error(ctx, ARBGPU_ENOMEM, "workspace slot %d holds %zu bytes, the call needs %zu (fixed workspace)", slot,
+              b.size, bytes);
+    return nullptr;
+  }
+  return ws_grow(ctx, slot, bytes) ? b.ptr : nullptr;
+}
+
+int ws_reserve(arbgpu_ctx *ctx, const size_t sizes[WS_COUNT]) {
+  if ((int)ctx->ws.size() < WS_COUNT) ctx->ws.resize(WS_COUNT);
+  for (int k = 0; k < WS_COUNT; ++k)
+    if (sizes[k] > ctx->ws[k].size) {
+      if (ctx->ws_fixed)
+        return set_error(ctx, ARBGPU_ENOMEM, "workspace slot %d is fixed at %zu bytes", k, ctx->ws[k].size);
+      if (!ws_grow(ctx, k, sizes[k])) return ARBGPU_ENOMEM;
+    }
+  return ARBGPU_OK;
+}
+
+void ctx_use_stream(arbgpu_ctx *ctx, hipStream_t s) {
+  for (hipStream_t t : ctx->streams_seen)
+    if (t == s) return;
+  ctx->streams_seen.push_back(s);
 }
 
 void tune_load(arbgpu_ctx *ctx) {
@@ -164,10 +206,11 @@ bool range_ok(int64_t lo, int64_t hi, int64_t ld) { return lo >= 0 && hi < ld; }
 
 hipStream_t to_stream(arbgpu_stream s) { return reinterpret_cast<hipStream_t>(s); }
 
-int bind_device(arbgpu_ctx *ctx) {
+int bind_device(arbgpu_ctx *ctx, arbgpu_stream s) {
   if (ctx->device < 0) return fail(ctx, ARBGPU_EDEVICE, "host-only context cannot launch work");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  ctx_use_stream(ctx, to_stream(s));
   return ARBGPU_OK;
 }
 
@@ -345,7 +388,7 @@ int arbgpu_dot(arbgpu_ctx *ctx, const arbgpu_out *res, int64_t res_idx, const ar
   LimbShape sh;
   int rc = dot_tasks(ctx, job, "arbgpu_dot", prm, &nt, &sh);
   if (rc) return rc;
-  if ((rc = bind_device(ctx))) return rc;
+  if ((rc = bind_device(ctx, stream))) return rc;
   for (int q = 0; q < nt; ++q) {
     KernelTimer kt(ctx, "limb_dot", to_stream(stream));
     hipError_t e = launch_limb_dot(prm[q], sh, to_stream(stream));
@@ -377,7 +420,8 @@ int mat_mul_check(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, co
   const bool approx = flags & ARBGPU_APPROX;
   const bool cplx = flags & ARBGPU_COMPLEX;
   const int nparts = cplx ? 2 : 1;
-  if (flags & ~(ARBGPU_APPROX | ARBGPU_COMPLEX | ARBGPU_ALGO_LIMB | ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS))
+  if (flags & ~(ARBGPU_APPROX | ARBGPU_COMPLEX | ARBGPU_ALGO_LIMB | ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS |
+                ARBGPU_COMPLEX_4M))
     return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul: unknown flags 0x%x", flags);
   const uint32_t algo = flags & (ARBGPU_ALGO_LIMB | ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS);
   if (algo & (algo - 1)) return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul: conflicting ALGO flags");
@@ -411,7 +455,7 @@ int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
   int rc = mat_mul_check(ctx, C, A, B, p, flags);
   if (rc) return rc;
   if (C->rows == 0 || C->cols == 0) return ARBGPU_OK;
-  if ((rc = bind_device(ctx))) return rc;
+  if ((rc = bind_device(ctx, stream))) return rc;
   const bool approx = flags & ARBGPU_APPROX;
   const bool cplx = flags & ARBGPU_COMPLEX;
   const int nparts = cplx ? 2 : 1;
@@ -472,8 +516,73 @@ int arbgpu_plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B
                                       (long long)A->cols, (long long)B->rows);
   *nblocks = 0;
   if (A->cols == 0) return ARBGPU_OK;
-  if ((rc = bind_device(ctx))) return rc;
+  if ((rc = bind_device(ctx, stream))) return rc;
   return plan_partition(ctx, A, B, p, flags, to_stream(stream), bounds, kinds, max_blocks, nblocks);
+}
+
+int arbgpu_reserve(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags) {
+  if (!ctx) return ARBGPU_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (flags & ~(ARBGPU_APPROX | ARBGPU_COMPLEX | ARBGPU_ALGO_LIMB | ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS |
+                ARBGPU_COMPLEX_4M))
+    return fail(ctx, ARBGPU_EINVAL, "arbgpu_reserve: unknown flags 0x%x", flags);
+  if (p < 2 || p > (1 << 20)) return fail(ctx, ARBGPU_EINVAL, "arbgpu_reserve: p=%lld out of range", (long long)p);
+  const int nparts = (flags & ARBGPU_COMPLEX) ? 2 : 1;
+  int rc;
+  if ((rc = validate_mat(ctx, A, nparts, "A"))) return rc;
+  if ((rc = validate_mat(ctx, B, nparts, "B"))) return rc;
+  if (A->cols != B->rows) return fail(ctx, ARBGPU_EINVAL, "inner dimensions differ (%lld vs %lld)",
+                                      (long long)A->cols, (long long)B->rows);
+  if (ctx->device < 0) return fail(ctx, ARBGPU_EDEVICE, "host-only context cannot hold a workspace");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  size_t sz[WS_COUNT];
+  mat_mul_ws_sizes(A, B, p, flags, sz);
+  return ws_reserve(ctx, sz);
+}
+
+int arbgpu_mat_mul_footprint(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags,
+                             size_t *bytes) {
+  if (!ctx) return ARBGPU_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (!bytes) return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul_footprint: NULL output");
+  if (flags & ~(ARBGPU_APPROX | ARBGPU_COMPLEX | ARBGPU_ALGO_LIMB | ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS |
+                ARBGPU_COMPLEX_4M))
+    return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul_footprint: unknown flags 0x%x", flags);
+  if (p < 2 || p > (1 << 20))
+    return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul_footprint: p=%lld out of range", (long long)p);
+  const int nparts = (flags & ARBGPU_COMPLEX) ? 2 : 1;
+  int rc;
+  if ((rc = validate_mat(ctx, A, nparts, "A"))) return rc;
+  if ((rc = validate_mat(ctx, B, nparts, "B"))) return rc;
+  if (A->cols != B->rows) return fail(ctx, ARBGPU_EINVAL, "inner dimensions differ (%lld vs %lld)",
+                                      (long long)A->cols, (long long)B->rows);
+  *bytes = mat_mul_footprint(A, B, p, flags);
+  return ARBGPU_OK;
+}
+
+int arbgpu_mat_mul_exact_t(arbgpu_ctx *ctx, uint32_t *T_re, uint32_t *T_im, int64_t ldT, int32_t capT,
+                           int32_t *row_v2, int32_t *col_v2, const arbgpu_mat *A, const arbgpu_mat *B,
+                           uint32_t flags, arbgpu_stream stream) {
+  if (!ctx) return ARBGPU_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (flags & ~(ARBGPU_COMPLEX | ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS | ARBGPU_COMPLEX_4M))
+    return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul_exact_t: unknown flags 0x%x", flags);
+  if ((flags & ARBGPU_ALGO_SLICED) && (flags & ARBGPU_ALGO_RNS))
+    return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul_exact_t: conflicting ALGO flags");
+  const int nparts = (flags & ARBGPU_COMPLEX) ? 2 : 1;
+  int rc;
+  if ((rc = validate_mat(ctx, A, nparts, "A"))) return rc;
+  if ((rc = validate_mat(ctx, B, nparts, "B"))) return rc;
+  if (A->cols != B->rows) return fail(ctx, ARBGPU_EINVAL, "inner dimensions differ (%lld vs %lld)",
+                                      (long long)A->cols, (long long)B->rows);
+  if (!T_re || (nparts == 2 && !T_im) || !row_v2 || !col_v2 || capT < 1 || ldT < 0)
+    return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul_exact_t: bad output arguments");
+  if (A->rows == 0 || B->cols == 0 || A->cols == 0)
+    return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul_exact_t: empty product");
+  if (ldT < A->rows * B->cols) return fail(ctx, ARBGPU_EINVAL, "arbgpu_mat_mul_exact_t: ldT below rows * cols");
+  if ((rc = bind_device(ctx, stream))) return rc;
+  return exact_block_product(ctx, T_re, T_im, ldT, capT, row_v2, col_v2, A, B, flags, to_stream(stream));
 }
 
 }  // extern "C"

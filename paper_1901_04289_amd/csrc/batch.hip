@@ -101,6 +101,10 @@ int device_cus(int device) {
 
 namespace arbgpu_impl {
 
+size_t dot_batch_ws(int64_t n, int nshapes) {
+  return sizeof(DotParams) * (size_t)n + sizeof(int32_t) * ((size_t)n + (size_t)nshapes) + 64;
+}
+
 int dot_batch_run(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, hipStream_t s) {
   std::vector<DotParams> tasks;
   std::vector<int32_t> order;
@@ -108,7 +112,7 @@ int dot_batch_run(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, hi
   int rc = plan_batch(ctx, jobs, njobs, "dot batch", tasks, order, runs);
   if (rc || tasks.empty()) return rc;
   const size_t tb = sizeof(DotParams) * tasks.size(), ob = sizeof(int32_t) * order.size();
-  char *w = (char *)ws_get(ctx, WS_BATCH, tb + ob + sizeof(int32_t) * runs.size() + 64);
+  char *w = (char *)ws_get(ctx, WS_BATCH, dot_batch_ws((int64_t)tasks.size(), (int)runs.size()));
   if (!w) return ARBGPU_ENOMEM;
   DotParams *d_tasks = (DotParams *)w;
   int32_t *d_order = (int32_t *)(w + tb);
@@ -231,6 +235,7 @@ int arbgpu_batch_create(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njo
     delete b;
     return set_error(ctx, ARBGPU_ENOMEM, "arbgpu_batch_create: %s", hipGetErrorString(e));
   }
+  ctx->allocs += 3;
   if (!tasks.empty() &&
       ((e = hipMemcpy(b->d_tasks, tasks.data(), sizeof(DotParams) * tasks.size(), hipMemcpyHostToDevice)) !=
            hipSuccess ||

@@ -26,8 +26,16 @@ struct arbgpu_ctx {
   struct Buf {
     void *ptr = nullptr;
     size_t size = 0;
+    bool owned = true;   // false: a view into memory the context does not free
   };
   std::vector<Buf> ws;   // indexed by workspace slot
+  // device allocations the context has made (workspace growth, batches)
+  int64_t allocs = 0;
+  // no workspace growth: a call that needs more fails with ENOMEM
+  bool ws_fixed = false;
+  // streams this context has enqueued work on since the workspace last
+  // grew; growth waits for them (and only them) before freeing a buffer
+  std::vector<hipStream_t> streams_seen;
   // per-kernel event timing (arbgpu_timing)
   bool timing = false;
   struct TimedLaunch {
@@ -58,9 +66,15 @@ enum WsSlot {
 };
 
 // Device buffer of at least `bytes` in workspace slot `slot` (nullptr and
-// the context error set on failure).  Grows by reallocation; the previous
-// contents are not kept.
+// the context error set on failure).  Grows by reallocation, after the
+// work this context enqueued has finished; the previous contents are not
+// kept.  A fixed workspace never grows.
 void *ws_get(arbgpu_ctx *ctx, int slot, size_t bytes);
+// Grows every slot to at least sizes[slot] bytes (outside any call's
+// work: for reservation ahead of the calls).
+int ws_reserve(arbgpu_ctx *ctx, const size_t sizes[WS_COUNT]);
+// Records that the current call enqueues work on s.
+void ctx_use_stream(arbgpu_ctx *ctx, hipStream_t s);
 
 int set_error(arbgpu_ctx *ctx, int code, const char *fmt, ...);
 
@@ -94,6 +108,10 @@ struct KernelTimer {
 constexpr int kNotApplicable = 100;
 int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B,
                    int64_t p, uint32_t flags, hipStream_t s, bool forced);
+
+// Exact integer block product over the whole inner range (arbgpu_mat_mul_exact_t).
+int exact_block_product(arbgpu_ctx *ctx, uint32_t *T_re, uint32_t *T_im, int64_t ldT, int32_t capT, int32_t *row_v2,
+                        int32_t *col_v2, const arbgpu_mat *A, const arbgpu_mat *B, uint32_t flags, hipStream_t s);
 
 // Block partition of Algorithm 2 for the product A B at precision p:
 // writes up to max_blocks (k0, k1) pairs and kinds to host arrays.
@@ -173,9 +191,15 @@ int dot_batch_run(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, hi
 int mat_mul_check(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p,
                   uint32_t flags);
 
-// Upper estimate of the workspace bytes a matrix product takes on the
-// scaled-integer path (for admission by HBM footprint).
+// Upper bound of the workspace bytes per slot a matrix product takes when
+// its inner range is one scaled-integer block (either INT8 form, unless an
+// ALGO flag fixes it) or a limb-kernel product; a product that splits into
+// several blocks holds its exact block values besides (WS_BLOCKS, not
+// included).  mat_mul_footprint is their sum (admission by HBM footprint).
+void mat_mul_ws_sizes(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags, size_t out[]);
 size_t mat_mul_footprint(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags);
+// Workspace of a one-shot dot batch of up to n tasks in up to nshapes shapes.
+size_t dot_batch_ws(int64_t n, int nshapes);
 
 // Validates one dot job and builds its kernel tasks (one per output part)
 // and kernel shape; sets the context error and returns EINVAL on a bad job.

@@ -265,21 +265,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   }
 }
 
-namespace {
-
-// Residue mod p of d0 + 256 d1 + 65536 d2 (the three digit-product
-// partial sums of one prime), Horner's rule from d2 down; every |d| < 2^30
-// (int32 planes of at most two pairs with 2 Kp 2^14 < 2^31), so each step
-// adds kp = p ceil(2^30 / p) to stay in [0, 2^32).
-__device__ __forceinline__ uint32_t residue3(int32_t d0, int32_t d1, int32_t d2, uint32_t p, uint32_t mu,
-                                             uint32_t kp) {
-  uint32_t r = mod_u32((uint32_t)d2 + kp, p, mu);
-  r = mod_u32((r << 8) + (uint32_t)d1 + kp, p, mu);
-  return mod_u32((r << 8) + (uint32_t)d0 + kp, p, mu);
-}
-
-}  // namespace
-
 // Explicit Chinese remainder formula per entry:
 //   T = sum_j y_j (P / p_j) - k P,  y_j = r_j (P / p_j)^-1 mod p_j (balanced),
 // with k the integer nearest to alpha = sum_j y_j / p_j (|T| < P / 4, so
@@ -325,15 +310,17 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
     const bool live = ij < MN;
     double alpha = 0.0;
     // lanes past the end read entry 0 (in bounds) and contribute nothing
-    const int32_t *Dij = P.D + (live ? ij : 0);
+    const int64_t ij0 = live ? ij : 0;
     for (int g = part; g < kc / 16; g += TPE) {
-      // the 24 partial-plane reads of 8 primes are issued before any use
+      // the residue reads of 8 primes (up to 3 products each) are issued
+      // before any use
       int32_t dv[8][3];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int jj = min(8 * g + u, m - 1);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) dv[u][c] = Dij[(int64_t)(3 * jj + c) * P.ds];
+        for (int c = 0; c < 3; ++c)
+          dv[u][c] = c < P.nsrc ? (int32_t)P.Y[((int64_t)P.src[c] * m + jj) * P.ds + ij0] : 0;
       }
       uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
@@ -341,7 +328,11 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
         const int j = 8 * g + u;
         if (j < m) {
           const uint32_t p = (uint32_t)cp(P.tab.prime)[j], mu = cp(P.tab.mu)[j];
-          const uint32_t r = residue3(dv[u][0], dv[u][1], dv[u][2], p, mu, cp(P.tab.kp)[j]);
+          // sum of at most three residues in [-p, p), made nonnegative
+          int32_t rs = 3 * (int32_t)p;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) rs += c < P.nsrc ? P.sgn[c] * dv[u][c] : 0;
+          const uint32_t r = mod_u32((uint32_t)rs, p, mu);
           const uint32_t y = mod_u32(r * cp(P.tab.c)[j], p, mu);
           int32_t yb = y > (p >> 1) ? (int32_t)y - (int32_t)p : (int32_t)y;
           yb = live ? yb : 0;
@@ -478,6 +469,9 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
       }
       c += co;
     }
+    if (P.t_out)
+      for (int q = 0; q < W; ++q) P.t_out[(int64_t)q * P.t_ld + ij] = T[q * EW];
+    if (!P.C.exp) return;   // the exact T only
     const int64_t i = ij / P.N, jj = ij - i * P.N;
     double m0 = 0.0;
     int e0r = 0;
@@ -487,72 +481,41 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
   }
 }
 
-// Residue planes of the inner layout [B_im; B_re] of a complex product's
-// imaginary part from those of [B_re; -B_im], its real part (Section 3.6:
-// Re = A_re B_re - A_im B_im, Im = A_re B_im + A_im B_re over the inner
-// index 0 .. 2K): position k < K takes the negated residue at k + K,
-// position K <= k < 2K the residue at k - K, the padding stays zero.  The
-// primes are odd, so a balanced residue r = lo + 256 hi negates within
-// range: (-lo, -hi), or (-128, 1 - hi) when lo = -128.  Thread: one prime
-// and line, 4 consecutive inner positions.
-__global__ __launch_bounds__(256) void rns_swap_neg_kernel(const int8_t *src, int8_t *dst, int m, int64_t lines_pad,
-                                                           int64_t k_pad, int64_t K) {
-  const int64_t words = k_pad >> 2;
+// Residue planes of x + y from those of x and y: per prime the balanced
+// residues (lo + 256 hi, |r| <= (p - 1) / 2) are added, brought back into
+// the balanced range and split again.  Thread: one prime, 4 consecutive
+// plane bytes.
+__global__ __launch_bounds__(256) void rns_add_kernel(const int8_t *x, const int8_t *y, int8_t *out,
+                                                      const int32_t *prime, int m, int64_t plane) {
+  const int64_t words = plane >> 2;
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (int64_t)m * lines_pad * words) return;
-  const int64_t w = t % words, r = t / words;
-  const int64_t line = r % lines_pad, j = r / lines_pad;
-  const int64_t plane = lines_pad * k_pad, o = line * k_pad;
-  const int8_t *slo = src + 2 * j * plane + o, *shi = slo + plane;
-  const int64_t k0 = 4 * w;
+  if (t >= (int64_t)m * words) return;
+  const int64_t j = t / words, w = t - j * words;
+  const int32_t p = prime[j], half = (p - 1) >> 1;
+  const int64_t olo = 2 * j * plane + 4 * w, ohi = olo + plane;
+  const uint32_t xl = *reinterpret_cast<const uint32_t *>(x + olo), xh = *reinterpret_cast<const uint32_t *>(x + ohi);
+  const uint32_t yl = *reinterpret_cast<const uint32_t *>(y + olo), yh = *reinterpret_cast<const uint32_t *>(y + ohi);
   uint32_t lo4 = 0u, hi4 = 0u;
-  // the 4 source bytes at k0 + d (d = K or -K), from the two aligned words
-  // holding them (both inside the line's row: 0 <= k0 + d and k0 + d + 3 < 2 K)
-  auto word_at = [&](const int8_t *row, int64_t b) -> uint32_t {
-    const int64_t a = b & ~(int64_t)3;
-    const uint32_t x = *reinterpret_cast<const uint32_t *>(row + a);
-    const uint32_t y = (b & 3) ? *reinterpret_cast<const uint32_t *>(row + a + 4) : 0u;
-    return __builtin_amdgcn_alignbyte(y, x, (uint32_t)(b & 3));
-  };
-  if (k0 + 3 < K) {
-    const uint32_t a = word_at(slo, k0 + K), b = word_at(shi, k0 + K);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int32_t l = (int8_t)(a >> (8 * u)), hv = (int8_t)(b >> (8 * u));
-      lo4 |= ((uint32_t)(l == -128 ? -128 : -l) & 0xFFu) << (8 * u);
-      hi4 |= ((uint32_t)(l == -128 ? 1 - hv : -hv) & 0xFFu) << (8 * u);
-    }
-  } else if (k0 >= K && k0 + 3 < 2 * K) {
-    lo4 = word_at(slo, k0 - K);
-    hi4 = word_at(shi, k0 - K);
-  } else {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t k = k0 + u;
-      int32_t lo = 0, hi = 0;
-      if (k < K) {
-        const int32_t a = slo[k + K], b = shi[k + K];
-        lo = a == -128 ? -128 : -a;
-        hi = a == -128 ? 1 - b : -b;
-      } else if (k < 2 * K) {
-        lo = slo[k - K];
-        hi = shi[k - K];
-      }
-      lo4 |= ((uint32_t)lo & 0xFFu) << (8 * u);
-      hi4 |= ((uint32_t)hi & 0xFFu) << (8 * u);
-    }
+  for (int u = 0; u < 4; ++u) {
+    const int32_t a = (int32_t)(int8_t)(xl >> (8 * u)) + 256 * (int32_t)(int8_t)(xh >> (8 * u));
+    const int32_t b = (int32_t)(int8_t)(yl >> (8 * u)) + 256 * (int32_t)(int8_t)(yh >> (8 * u));
+    int32_t r = a + b;
+    r = r > half ? r - p : (r < -half ? r + p : r);
+    const int32_t lo = ((r + 128) & 255) - 128;
+    lo4 |= ((uint32_t)lo & 0xFFu) << (8 * u);
+    hi4 |= ((uint32_t)((r - lo) >> 8) & 0xFFu) << (8 * u);
   }
-  *reinterpret_cast<uint32_t *>(dst + 2 * j * plane + o + 4 * w) = lo4;
-  *reinterpret_cast<uint32_t *>(dst + (2 * j + 1) * plane + o + 4 * w) = hi4;
+  *reinterpret_cast<uint32_t *>(out + olo) = lo4;
+  *reinterpret_cast<uint32_t *>(out + ohi) = hi4;
 }
 
-hipError_t launch_rns_swap_neg(const int8_t *src, int8_t *dst, int m, int64_t lines_pad, int64_t k_pad, int64_t K,
-                               hipStream_t s) {
-  if ((k_pad & 3) != 0 || 2 * K > k_pad || ((uintptr_t)dst & 3) != 0) return hipErrorInvalidValue;
-  const int64_t n = (int64_t)m * lines_pad * (k_pad >> 2);
+hipError_t launch_rns_add(const int8_t *x, const int8_t *y, int8_t *out, const int32_t *prime, int m,
+                          int64_t plane, hipStream_t s) {
+  if ((plane & 3) != 0 || (((uintptr_t)x | (uintptr_t)y | (uintptr_t)out) & 3) != 0) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)m * (plane >> 2);
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(rns_swap_neg_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, m, lines_pad,
-                     k_pad, K);
+  hipLaunchKernelGGL(rns_add_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, out, prime, m, plane);
   return hipGetLastError();
 }
 

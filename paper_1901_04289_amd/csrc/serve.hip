@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -91,6 +92,7 @@ struct Server {
         std::vector<arbgpu_dot_job> dots;
         for (auto &it : take) dots.push_back(it.job.dot);
         std::lock_guard<std::mutex> lk(c->mu);
+        ctx_use_stream(c, s);
         rc = dot_batch_run(c, dots.data(), (int64_t)dots.size(), s);
       } else {
         const arbgpu_job &j = take[0].job;
@@ -100,21 +102,9 @@ struct Server {
           if (e != hipSuccess) rc = set_error(c, ARBGPU_EDEVICE, "request: %s", hipGetErrorString(e));
         }
       }
+      // the slot keeps its workspace (at most its share of the budget) for
+      // the next request
       std::string err = rc ? c->err : std::string();
-      // a slot keeps its workspace only while it stays within its share
-      if (c->budget) {
-        size_t held = 0;
-        for (auto &b : c->ws) held += b.size;
-        if (held > budget / (size_t)nslots) {
-          (void)hipStreamSynchronize(s);
-          for (auto &b : c->ws) {
-            if (b.ptr) (void)hipFree(b.ptr);
-            b.ptr = nullptr;
-            b.size = 0;
-          }
-          c->rns_key = -1;   // the residue tables went with the workspace
-        }
-      }
       {
         std::lock_guard<std::mutex> lk(mu);
         const int64_t t = now_ns();
@@ -164,9 +154,10 @@ int start_server(arbgpu_ctx *ctx, int slots, size_t budget) {
   sv->nslots = slots;
   sv->budget = budget;
   hipError_t e = hipSetDevice(ctx->device);
+  // every slot holds at most its share of the budget as workspace
   for (int k = 0; k < slots && e == hipSuccess; ++k) {
     arbgpu_ctx *c = nullptr;
-    if (arbgpu_init(&c, ctx->device, budget, nullptr) != ARBGPU_OK) {
+    if (arbgpu_init(&c, ctx->device, budget / (size_t)slots, nullptr) != ARBGPU_OK) {
       e = hipErrorOutOfMemory;
       break;
     }
@@ -239,6 +230,11 @@ int arbgpu_submit(arbgpu_ctx *ctx, const arbgpu_job *jobs, int64_t njobs, uint64
   Server *sv = ctx->server;
   {
     std::lock_guard<std::mutex> sl(sv->mu);
+    const size_t share = sv->budget / (size_t)sv->nslots;
+    for (int64_t i = 0; i < njobs; ++i)
+      if (fp[i] > share)
+        return set_error(ctx, ARBGPU_ENOMEM, "arbgpu_submit: job %lld needs %zu bytes of workspace, a slot holds %zu",
+                         (long long)i, fp[i], share);
     if (need > sv->budget)
       return set_error(ctx, ARBGPU_ENOMEM, "arbgpu_submit: %zu bytes of workspace exceed the budget %zu", need,
                        sv->budget);
@@ -257,6 +253,58 @@ int arbgpu_submit(arbgpu_ctx *ctx, const arbgpu_job *jobs, int64_t njobs, uint64
     }
   }
   sv->cv_work.notify_all();
+  return ARBGPU_OK;
+}
+
+int arbgpu_serve_reserve(arbgpu_ctx *ctx, const arbgpu_job *jobs, int64_t njobs) {
+  if (!ctx) return ARBGPU_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (njobs < 0 || (njobs > 0 && !jobs)) return set_error(ctx, ARBGPU_EINVAL, "arbgpu_serve_reserve: bad arguments");
+  size_t sz[WS_COUNT] = {0};
+  for (int64_t i = 0; i < njobs; ++i) {
+    const arbgpu_job &j = jobs[i];
+    size_t js[WS_COUNT] = {0};
+    if (j.kind == ARBGPU_JOB_MATMUL) {
+      const int rc = mat_mul_check(ctx, &j.C, &j.A, &j.B, j.p, j.flags);
+      if (rc) return rc;
+      mat_mul_ws_sizes(&j.A, &j.B, j.p, j.flags, js);
+    } else if (j.kind == ARBGPU_JOB_DOT) {
+      js[WS_BATCH] = dot_batch_ws(2 * (int64_t)kMaxDotGroup, 16);
+    } else {
+      return set_error(ctx, ARBGPU_EINVAL, "arbgpu_serve_reserve: unknown job kind %d", j.kind);
+    }
+    for (int k = 0; k < WS_COUNT; ++k) sz[k] = std::max(sz[k], js[k]);
+  }
+  if (!ctx->server) {
+    const int rc = start_server(ctx, 4, ctx->budget / 2);
+    if (rc) return rc;
+  }
+  for (arbgpu_ctx *c : ctx->server->slot_ctx) {
+    std::lock_guard<std::mutex> cl(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "hipSetDevice");
+    const int rc = ws_reserve(c, sz);
+    if (rc) return set_error(ctx, rc, "arbgpu_serve_reserve: %s", c->err.c_str());
+  }
+  return ARBGPU_OK;
+}
+
+int arbgpu_workspace_info(arbgpu_ctx *ctx, int64_t *allocs, int64_t *bytes) {
+  if (!ctx) return ARBGPU_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  int64_t n = 0, held = 0;
+  auto add = [&](arbgpu_ctx *c) {
+    n += c->allocs;
+    for (auto &b : c->ws)
+      if (b.owned) held += (int64_t)b.size;
+  };
+  add(ctx);
+  if (ctx->server)
+    for (arbgpu_ctx *c : ctx->server->slot_ctx) {
+      std::lock_guard<std::mutex> cl(c->mu);
+      add(c);
+    }
+  if (allocs) *allocs = n;
+  if (bytes) *bytes = held;
   return ARBGPU_OK;
 }
 

@@ -270,6 +270,7 @@ __global__ __launch_bounds__(256) void recombine_kernel(RecombParams P) {
   T[(int64_t)nq * MN] = (uint32_t)carry;
   T[(int64_t)(nq + 1) * MN] = (uint32_t)((uint64_t)carry >> 32);
   const int nT = nq + 2;
+  if (!P.C.exp) return;   // the exact T only
 
   double m0 = 0.0;
   int e0 = 0;
@@ -546,6 +547,31 @@ hipError_t launch_recombine(const RecombParams &P, hipStream_t s) {
   const int64_t n = P.M * P.N;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(recombine_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+__global__ __launch_bounds__(256) void t_copy_kernel(const uint32_t *src, int n, int64_t mn, uint32_t *dst,
+                                                     int64_t ld, int cap) {
+  const int64_t ij = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (ij >= mn) return;
+  uint32_t top = 0u;
+  for (int k = 0; k < cap; ++k) {
+    const uint32_t v = k < n ? src[(int64_t)k * mn + ij] : (uint32_t)((int32_t)top >> 31);
+    dst[(int64_t)k * ld + ij] = v;
+    top = v;
+  }
+}
+__global__ __launch_bounds__(256) void v2_out_kernel(const int32_t *v2, int64_t n, int32_t *out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = v2[i] == INT32_MAX ? 0 : v2[i];
+}
+hipError_t launch_v2_out(const int32_t *v2, int64_t n, int32_t *out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(v2_out_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, v2, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_t_copy(const uint32_t *src, int n, int64_t mn, uint32_t *dst, int64_t ld, int cap, hipStream_t s) {
+  if (mn == 0 || cap == 0) return hipSuccess;
+  hipLaunchKernelGGL(t_copy_kernel, dim3(nblk(mn, 256)), dim3(256), 0, s, src, n, mn, dst, ld, cap);
   return hipGetLastError();
 }
 hipError_t launch_rad_prep(const RadPrepParams &P, hipStream_t s) {

@@ -158,8 +158,14 @@ struct RnsSliceParams {
 };
 
 struct RnsCrtParams {
-  const int32_t *D;          // [3m][ds]: digit products of weight 1, 256, 65536 per prime
+  // residues r_j of the block products (int16 in [-p_j, p_j)): product q,
+  // prime j, entry ij at Y[(q m + j) ds + ij]; the reconstructed value is
+  // sum_c sgn[c] * (product src[c]) for c < nsrc (complex parts: AC - BD,
+  // and AD + BC or (A + B)(C + D) - AC - BD)
+  const int16_t *Y;
   int64_t ds;                // plane stride in entries
+  int nsrc;
+  int src[3], sgn[3];
   RnsTables tab;
   int64_t M, N;
   int W;                     // two's-complement limbs of T
@@ -170,13 +176,44 @@ struct RnsCrtParams {
   int approx;
   const double *rin_m;
   const int32_t *rin_e;
+  uint32_t *t_out;           // nullable: the W limbs of T, limb q of entry ij at t_out[q t_ld + ij]
+  int64_t t_ld;
 };
 
+// Destination of the exact block integer T (two's-complement limbs, least
+// significant first, limb k of entry ij at T[q][k ld + ij], sign-extended
+// to cap limbs) for output part q.
+struct TSink {
+  uint32_t *T[2];
+  int64_t ld;
+  int32_t cap;
+};
+// Copies n limbs per entry from src (limb k of entry ij at src[k mn + ij])
+// and sign-extends them to cap limbs.
+// Lowest set-bit positions per line to the caller (0 for a line with no
+// nonzero entry).
+hipError_t launch_v2_out(const int32_t *v2, int64_t n, int32_t *out, hipStream_t s);
+hipError_t launch_t_copy(const uint32_t *src, int n, int64_t mn, uint32_t *dst, int64_t ld, int cap, hipStream_t s);
+
+// Residues of the block products on INT8 MFMA, reduced per prime on chip
+// (work item: product, prime, 256 x 256 tile).
+struct MfmaRnsParams {
+  const int8_t *A[4], *B[4]; // per product: digit planes [2m][Mp][Kp], [2m][Np][Kp]
+  int16_t *Y;                // [nprod][m][ds]
+  const int32_t *prime;      // [m]
+  const uint32_t *mu;        // [m] floor(2^32 / p_j)
+  int nprod, m, mpad;        // mpad: m rounded up to a multiple of 8
+  int64_t M, N, Mp, Np, Kp, ds;
+  int ntm, ntn;
+};
+hipError_t launch_mfma_rns(const MfmaRnsParams &P, hipStream_t s);
+
+// Residue planes of a sum of two operands (the (A + B) and (C + D) of the
+// three-product complex form): balanced residues added and re-split.
+hipError_t launch_rns_add(const int8_t *x, const int8_t *y, int8_t *out, const int32_t *prime, int m,
+                          int64_t plane, hipStream_t s);
+
 hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s);
-// residue planes of a complex product's [B_im; B_re] inner layout from
-// those of [B_re; -B_im] (inner length K per part, 2 K <= k_pad)
-hipError_t launch_rns_swap_neg(const int8_t *src, int8_t *dst, int m, int64_t lines_pad, int64_t k_pad, int64_t K,
-                               hipStream_t s);
 hipError_t launch_rns_crt(const RnsCrtParams &P, hipStream_t s);
 // dynamic LDS of the reconstruction kernel for ew entries per workgroup
 size_t rns_crt_lds(int ew, int kc, int W);

@@ -161,6 +161,29 @@ void balanced_digits(const std::vector<uint32_t> &X, int n, int8_t *d) {
   }
 }
 
+// Byte layout of the residue tables for m primes, nw digit words and W
+// limbs of T (offsets of the arrays of RnsTables in one buffer).
+struct RnsLayout {
+  int kc, ncc, kd, nrt;
+  size_t o_mu, o_kp, o_rp, o_c, o_wd, o_qd, bytes;
+};
+
+RnsLayout rns_layout(int m, int nw, int W) {
+  RnsLayout l;
+  l.kc = (int)round_up(2 * (int64_t)m + 2, 32);
+  l.ncc = (W + 7) / 8;
+  l.kd = (int)round_up(4 * (int64_t)nw, 32);
+  l.nrt = (m + 15) / 16;
+  l.o_mu = 4 * (size_t)m;
+  l.o_kp = l.o_mu + 4 * (size_t)m;
+  l.o_rp = (l.o_kp + 4 * (size_t)m + 7) & ~(size_t)7;
+  l.o_c = l.o_rp + 8 * (size_t)m;
+  l.o_wd = (l.o_c + 4 * (size_t)m + 15) & ~(size_t)15;
+  l.o_qd = l.o_wd + (size_t)l.nrt * 32 * l.kd;
+  l.bytes = l.o_qd + (size_t)l.ncc * 32 * l.kc;
+  return l;
+}
+
 // Residue tables for m primes, nw words of base-256 digits and W limbs of
 // T, uploaded to the context workspace (kept while m, nw and W stay the
 // same): primes and reduction constants, the digit weights 256^a mod p_j
@@ -168,14 +191,10 @@ void balanced_digits(const std::vector<uint32_t> &X, int n, int8_t *d) {
 // (P / p_j)^-1 mod p_j and the digits of P / p_j and P.
 int rns_tables(arbgpu_ctx *ctx, int m, int nw, int W, hipStream_t s, RnsTables &tab) {
   const std::vector<int32_t> &pr = rns_primes();
-  const int kc = (int)round_up(2 * (int64_t)m + 2, 32);
-  const int ncc = (W + 7) / 8;
-  const int kd = (int)round_up(4 * (int64_t)nw, 32);
-  const int nrt = (m + 15) / 16;
-  const size_t o_mu = 4 * (size_t)m, o_kp = o_mu + 4 * (size_t)m, o_rp = (o_kp + 4 * (size_t)m + 7) & ~(size_t)7,
-               o_c = o_rp + 8 * (size_t)m,
-               o_wd = (o_c + 4 * (size_t)m + 15) & ~(size_t)15, o_qd = o_wd + (size_t)nrt * 32 * kd,
-               bytes = o_qd + (size_t)ncc * 32 * kc;
+  const RnsLayout lay = rns_layout(m, nw, W);
+  const int kc = lay.kc, ncc = lay.ncc, kd = lay.kd;
+  const size_t o_mu = lay.o_mu, o_kp = lay.o_kp, o_rp = lay.o_rp, o_c = lay.o_c, o_wd = lay.o_wd, o_qd = lay.o_qd,
+               bytes = lay.bytes;
   char *d = (char *)ws_get(ctx, WS_RNS, bytes);
   if (!d) return ARBGPU_ENOMEM;
   tab.prime = (const int32_t *)d;
@@ -270,18 +289,24 @@ int64_t t_bits(int HA, int HB, int64_t Kt) {
   return (int64_t)HA + HB + lg + 1;
 }
 
-// The residue form applies when its LDS staging fits and the int32 partial
-// planes of two digit pairs stay exact.
+// Block values of `bits` two's-complement bits fit the reconstruction: the
+// kernel keeps 32 entries' digit rows and limbs in LDS.
+bool rns_fits_bits(int64_t bits) {
+  const int m = rns_count(bits);
+  if (m < 1) return false;
+  const int W = (int)((bits + 1 + 31) / 32) + 1;
+  return rns_crt_lds(32, (int)round_up(2 * (int64_t)m + 2, 32), W) <= kRnsCrtLds;
+}
+
+// The residue form applies when the on-chip Horner chain of the digit
+// products stays below 2^31 (K_pad < 2^16), the residue sums of the slicer
+// (at most 4 nw <= 508 digits) below 2^30, and the block values fit the
+// reconstruction.
 bool rns_fits(int HA, int HB, int64_t Kt) {
   const int64_t Kp = round_up(std::max<int64_t>(Kt, 1), kKStep);
   if (((int64_t)0x7FFFFFFF) / (Kp << 14) < 2) return false;
-  const int m = rns_count(t_bits(HA, HB, Kt));
-  if (m < 1) return false;
-  const int W = (int)((t_bits(HA, HB, Kt) + 1 + 31) / 32) + 1;
   const int nw = (std::max(slices_for(HA), slices_for(HB)) + 3) / 4;
-  // the reconstruction kernel keeps 32 entries' digit rows and limbs in LDS;
-  // the residue sums of at most 4 nw <= 508 digits stay below 2^30
-  return rns_crt_lds(32, (int)round_up(2 * (int64_t)m + 2, 32), W) <= kRnsCrtLds && nw <= 127;
+  return nw <= 127 && rns_fits_bits(t_bits(HA, HB, Kt));
 }
 
 // MFMA work of the two forms (digit pairs): base-256 slices L_A L_B, the
@@ -302,15 +327,23 @@ inline int t_limbs(int LA, int LB) { return (LA + LB - 1 + 3) / 4 + 2; }
 int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const Shape &sh, int64_t k0,
                       int64_t k1, const int32_t *st, int HA, int HB, const arbgpu_out *out, int64_t o_off,
                       int64_t o_rs, int64_t o_cs, int p, bool out_approx, double *const rin_m[2],
-                      int32_t *const rin_e[2], hipStream_t s);
+                      int32_t *const rin_e[2], hipStream_t s, bool four, const TSink *ts);
+
+// Copies the exact T of output part q (limbs [n][M N] in the workspace) to
+// the caller's sink, when there is one.
+int t_to_sink(arbgpu_ctx *ctx, const TSink *ts, int q, const uint32_t *T, int n, int64_t mn, hipStream_t s) {
+  if (!ts) return ARBGPU_OK;
+  ARB_TRY(launch_t_copy(T, n, mn, ts->T[q], ts->ld, ts->cap, s), "exact T copy");
+  return ARBGPU_OK;
+}
 
 int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const Shape &sh, int64_t k0, int64_t k1,
                   const int32_t *st, int HA, int HB, const arbgpu_out *out, int64_t o_off, int64_t o_rs, int64_t o_cs,
                   int p, bool out_approx, double *const rin_m[2], int32_t *const rin_e[2], hipStream_t s,
-                  bool rns) {
+                  bool rns, bool four = false, const TSink *ts = nullptr) {
   if (rns)
     return rns_block_product(ctx, A, B, sh, k0, k1, st, HA, HB, out, o_off, o_rs, o_cs, p, out_approx, rin_m, rin_e,
-                             s);
+                             s, four, ts);
   const int32_t *rv2 = st + sh.M, *cv2 = st + 2 * sh.M + sh.N;
   const int64_t Kb = k1 - k0;
   const int64_t Kt = sh.cplx ? 2 * Kb : Kb;
@@ -410,23 +443,31 @@ int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, con
     rp.approx = out_approx;
     rp.rin_m = rin_m[q];
     rp.rin_e = rin_e[q];
-    KernelTimer tr(ctx, "recombine", s);
-    ARB_TRY(launch_recombine(rp, s), "recombine");
+    {
+      KernelTimer tr(ctx, "recombine", s);
+      ARB_TRY(launch_recombine(rp, s), "recombine");
+    }
+    int rc = t_to_sink(ctx, ts, q, T, nT, sh.M * sh.N, s);
+    if (rc) return rc;
   }
   return ARBGPU_OK;
 }
 
-// The block product in residue form: slices of residues modulo m primes,
-// three int32 partial planes per prime from the MFMA kernel, Chinese
-// remainder reconstruction and rounding per entry.
+// The block product in residue form: residue digit planes of every operand
+// part modulo m primes, per prime the residues of the block products
+// reduced on chip, Chinese remainder reconstruction and rounding per entry.
+// A complex block takes three real products, AC, BD and (A + B)(C + D),
+// with Re = AC - BD and Im = (A + B)(C + D) - AC - BD formed on the
+// residues (eq. (2), Section 3.6); `four` takes AC, BD, AD and BC instead.
+// Both are exact, and so give the same T.
 int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const Shape &sh, int64_t k0,
                       int64_t k1, const int32_t *st, int HA, int HB, const arbgpu_out *out, int64_t o_off,
                       int64_t o_rs, int64_t o_cs, int p, bool out_approx, double *const rin_m[2],
-                      int32_t *const rin_e[2], hipStream_t s) {
+                      int32_t *const rin_e[2], hipStream_t s, bool four, const TSink *ts) {
   const int32_t *rv2 = st + sh.M, *cv2 = st + 2 * sh.M + sh.N;
   const int64_t Kb = k1 - k0;
-  const int64_t Kt = sh.cplx ? 2 * Kb : Kb;
-  const int64_t Kp = round_up(std::max<int64_t>(Kt, 1), kKStep);
+  const int64_t Kt = sh.cplx ? 2 * Kb : Kb;   // terms of one output value
+  const int64_t Kp = round_up(std::max<int64_t>(Kb, 1), kKStep);
   const int64_t Mp = round_up(std::max<int64_t>(sh.M, 1), kTile), Np = round_up(std::max<int64_t>(sh.N, 1), kTile);
   const int64_t bits = t_bits(HA, HB, Kt);
   const int m = rns_count(bits);
@@ -437,79 +478,83 @@ int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
   RnsTables tab;
   int rc = rns_tables(ctx, m, nw, W, s, tab);
   if (rc) return rc;
-  // per prime j: weight 1 (lo lo), 256 (lo hi + hi lo), 65536 (hi hi)
-  std::vector<DiagGroup> groups;
-  for (int j = 0; j < m; ++j) {
-    groups.push_back(DiagGroup{4 * j + 1, 2 * j, 2 * j + 2, 3 * j + 1});
-    groups.push_back(DiagGroup{4 * j, 2 * j, 2 * j + 1, 3 * j});
-    groups.push_back(DiagGroup{4 * j + 2, 2 * j + 1, 2 * j + 2, 3 * j + 2});
-  }
-  // sizes 2, 1, 1 repeat along the table, so every XCD (groups x, x + 8,
-  // ...) gets a similar share, and work items of both lengths run side by
-  // side instead of all finishing (and storing their planes) together
-  const int ngroups_real = (int)groups.size();
-  while (groups.size() % 8) groups.push_back(DiagGroup{0, 0, 0, -1});
+  // plane sets per operand: real 1; complex re, im (and re + im)
+  const int nsets = !sh.cplx ? 1 : (four ? 2 : 3);
+  const int nprod = !sh.cplx ? 1 : (four ? 4 : 3);
+  const int mpad = (m + 7) / 8 * 8;
   {
-    const int64_t plan[10] = {2 * m, 2 * m, 3 * m, ngroups_real, Kt, sh.M, sh.N, sh.nparts, m, 4 * (int64_t)m};
+    const int64_t plan[10] = {2 * m, 2 * m, (int64_t)nprod * m, (int64_t)nprod * m, Kp, sh.M, sh.N, sh.nparts, m,
+                              4 * (int64_t)nprod * m};
     memcpy(ctx->last_plan, plan, sizeof plan);
   }
-  const size_t bytesA = (size_t)2 * m * Mp * Kp, bytesB = (size_t)2 * m * Np * Kp;
-  int8_t *planesA = (int8_t *)ws_get(ctx, WS_PLANES_A, bytesA);
-  int8_t *planesB = (int8_t *)ws_get(ctx, WS_PLANES_B, bytesB);
-  int8_t *planesB2 = sh.cplx ? (int8_t *)ws_get(ctx, WS_PLANES_B2, bytesB) : nullptr;
+  const int64_t setA = 2 * (int64_t)m * Mp * Kp, setB = 2 * (int64_t)m * Np * Kp;
+  int8_t *planesA = (int8_t *)ws_get(ctx, WS_PLANES_A, (size_t)(nsets * setA));
+  int8_t *planesB = (int8_t *)ws_get(ctx, WS_PLANES_B, (size_t)(nsets * setB));
   const int64_t ds = plane_stride(sh.M * sh.N);
-  int32_t *D = (int32_t *)ws_get(ctx, WS_D, sizeof(int32_t) * (size_t)3 * m * ds);
-  char *tabs = (char *)ws_get(ctx, WS_TABLES, sizeof(DiagGroup) * groups.size());
-  if (!planesA || !planesB || (sh.cplx && !planesB2) || !D || !tabs) return ARBGPU_ENOMEM;
-  DiagGroup *dgroups = (DiagGroup *)tabs;
-  ARB_TRY(hipMemcpyAsync(dgroups, groups.data(), sizeof(DiagGroup) * groups.size(), hipMemcpyHostToDevice, s),
-          "table upload");
-  ARB_TRY(hipStreamSynchronize(s), "table upload");
+  int16_t *Y = (int16_t *)ws_get(ctx, WS_D, sizeof(int16_t) * (size_t)nprod * m * ds);
+  uint32_t *Tw = ts ? (uint32_t *)ws_get(ctx, WS_T, sizeof(uint32_t) * (size_t)W * sh.M * sh.N) : nullptr;
+  if (!planesA || !planesB || !Y || (ts && !Tw)) return ARBGPU_ENOMEM;
 
   RnsSliceParams sa;
   memset(&sa, 0, sizeof sa);
-  sa.part[0] = A->re;
-  sa.part[1] = sh.cplx ? A->im : A->re;
+  sa.part[0] = sa.part[1] = A->re;
   sa.lines = sh.M; sa.len = Kb; sa.off = A->off; sa.line_stride = A->rs; sa.elem_stride = A->cs; sa.k0 = k0;
-  sa.mode = sh.cplx ? 3 : 0;
+  sa.mode = 0;
   sa.lines_pad = Mp; sa.k_pad = Kp; sa.L = LA; sa.v2 = rv2; sa.tab = tab; sa.planes = planesA;
   Lines bl;
   {
     KernelTimer t_slice(ctx, "slice", s);
     rc = b_lines(ctx, B, sh.cplx, k0, k1, s, bl);
     if (rc) return rc;
-    ARB_TRY(launch_rns_slice(sa, s), "residue slice");
     for (int q = 0; q < sh.nparts; ++q) {
-      if (q == 1) {   // [B_im; B_re] from [B_re; -B_im] by moving and negating residues
-        ARB_TRY(launch_rns_swap_neg(planesB, planesB2, m, Np, Kp, Kb, s), "residue swap");
-        continue;
-      }
-      RnsSliceParams sb = sa;
-      sb.part[0] = bl.part[0];
-      sb.part[1] = bl.part[1];
-      sb.lines = sh.N; sb.off = bl.off; sb.line_stride = bl.line_stride; sb.elem_stride = bl.elem_stride;
-      sb.k0 = bl.k0;
-      sb.mode = !sh.cplx ? 0 : (q == 0 ? 1 : 2);
-      sb.lines_pad = Np; sb.L = LB; sb.v2 = cv2; sb.planes = q == 0 ? planesB : planesB2;
-      ARB_TRY(launch_rns_slice(sb, s), "residue slice");
+      RnsSliceParams pa = sa;
+      pa.part[0] = pa.part[1] = q == 0 ? A->re : A->im;
+      pa.planes = planesA + q * setA;
+      ARB_TRY(launch_rns_slice(pa, s), "residue slice");
+      RnsSliceParams pb = sa;
+      pb.part[0] = pb.part[1] = bl.part[q];
+      pb.lines = sh.N; pb.off = bl.off; pb.line_stride = bl.line_stride; pb.elem_stride = bl.elem_stride;
+      pb.k0 = bl.k0;
+      pb.lines_pad = Np; pb.L = LB; pb.v2 = cv2; pb.planes = planesB + q * setB;
+      ARB_TRY(launch_rns_slice(pb, s), "residue slice");
+    }
+    if (nsets == 3) {
+      ARB_TRY(launch_rns_add(planesA, planesA + setA, planesA + 2 * setA, tab.prime, m, Mp * Kp, s), "residue sum");
+      ARB_TRY(launch_rns_add(planesB, planesB + setB, planesB + 2 * setB, tab.prime, m, Np * Kp, s), "residue sum");
     }
   }
+  MfmaRnsParams mp;
+  memset(&mp, 0, sizeof mp);
+  // products: real A B; complex AC, BD, then (A + B)(C + D), or AD and BC
+  const int pa_of[4] = {0, 1, four ? 0 : 2, 1}, pb_of[4] = {0, 1, four ? 1 : 2, 0};
+  for (int q = 0; q < nprod; ++q) {
+    mp.A[q] = planesA + pa_of[q] * setA;
+    mp.B[q] = planesB + pb_of[q] * setB;
+  }
+  mp.Y = Y;
+  mp.prime = tab.prime;
+  mp.mu = tab.mu;
+  mp.nprod = nprod; mp.m = m; mp.mpad = mpad;
+  mp.M = sh.M; mp.N = sh.N; mp.Mp = Mp; mp.Np = Np; mp.Kp = Kp; mp.ds = ds;
+  mp.ntm = (int)(Mp / kTile); mp.ntn = (int)(Np / kTile);
+  {
+    KernelTimer tm(ctx, "mfma", s);
+    ARB_TRY(launch_mfma_rns(mp, s), "mfma");
+  }
   for (int q = 0; q < sh.nparts; ++q) {
-    MfmaParams mp;
-    mp.A = planesA;
-    mp.B = q == 0 ? planesB : planesB2;
-    mp.D = D;
-    mp.ds = ds;
-    mp.groups = dgroups;
-    mp.M = sh.M; mp.N = sh.N; mp.Mp = Mp; mp.Np = Np; mp.Kp = Kp;
-    mp.ntm = (int)(Mp / kTile); mp.ntn = (int)(Np / kTile);
-    mp.ngroups = (int)groups.size();
-    {
-      KernelTimer tm(ctx, "mfma", s);
-      ARB_TRY(launch_mfma(mp, s), "mfma");
-    }
     RnsCrtParams cp;
-    cp.D = D; cp.ds = ds; cp.tab = tab; cp.M = sh.M; cp.N = sh.N; cp.W = W;
+    memset(&cp, 0, sizeof cp);
+    cp.Y = Y; cp.ds = ds;
+    if (!sh.cplx) {
+      cp.nsrc = 1; cp.src[0] = 0; cp.sgn[0] = 1;
+    } else if (q == 0) {   // AC - BD
+      cp.nsrc = 2; cp.src[0] = 0; cp.sgn[0] = 1; cp.src[1] = 1; cp.sgn[1] = -1;
+    } else if (four) {     // AD + BC
+      cp.nsrc = 2; cp.src[0] = 2; cp.sgn[0] = 1; cp.src[1] = 3; cp.sgn[1] = 1;
+    } else {               // (A + B)(C + D) - AC - BD
+      cp.nsrc = 3; cp.src[0] = 2; cp.sgn[0] = 1; cp.src[1] = 0; cp.sgn[1] = -1; cp.src[2] = 1; cp.sgn[2] = -1;
+    }
+    cp.tab = tab; cp.M = sh.M; cp.N = sh.N; cp.W = W;
     cp.rowv2 = rv2; cp.colv2 = cv2;
     cp.C = out[q];
     cp.c_off = o_off; cp.c_rs = o_rs; cp.c_cs = o_cs;
@@ -517,8 +562,14 @@ int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
     cp.approx = out_approx;
     cp.rin_m = rin_m[q];
     cp.rin_e = rin_e[q];
-    KernelTimer tr(ctx, "recombine", s);
-    ARB_TRY(launch_rns_crt(cp, s), "residue reconstruction");
+    cp.t_out = Tw;
+    cp.t_ld = sh.M * sh.N;
+    {
+      KernelTimer tr(ctx, "recombine", s);
+      ARB_TRY(launch_rns_crt(cp, s), "residue reconstruction");
+    }
+    rc = t_to_sink(ctx, ts, q, Tw, W, sh.M * sh.N, s);
+    if (rc) return rc;
   }
   return ARBGPU_OK;
 }
@@ -613,26 +664,84 @@ constexpr int kBasecase = 30;   // Algorithm 2: shorter ranges use dot products
 
 }  // namespace
 
-size_t mat_mul_footprint(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags) {
+void mat_mul_ws_sizes(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags, size_t out[]) {
+  for (int k = 0; k < WS_COUNT; ++k) out[k] = 0;
   const bool cplx = flags & ARBGPU_COMPLEX;
   const int64_t parts = cplx ? 2 : 1;
   const int64_t M = A->rows, N = B->cols, K = A->cols;
   const int64_t Kt = cplx ? 2 * K : K;
-  const int64_t Kp = round_up(std::max<int64_t>(Kt, 1), kKStep);
+  const int64_t MN = M * N, ds = plane_stride(MN);
+  if (flags & ARBGPU_ALGO_LIMB) return;   // the limb kernel takes no workspace
   const int64_t Mp = round_up(std::max<int64_t>(M, 1), kTile), Np = round_up(std::max<int64_t>(N, 1), kTile);
   int cap = std::max(A->re.cap, B->re.cap);
   if (cplx) cap = std::max(cap, std::max(A->im.cap, B->im.cap));
-  const int64_t L = std::min<int64_t>(kMaxSlices, slices_for(height_bound(p, 32 * cap, 32 * cap)));
-  const int64_t pmax = std::max<int64_t>(1, ((int64_t)0x7FFFFFFF) / (Kp << 14));
-  const int64_t nslots = (2 * L - 1) + L * L / pmax;
-  const int64_t mn = M * N;
-  int64_t bytes = L * Mp * Kp + L * Np * Kp * parts;          // digit planes
-  bytes += 4 * nslots * plane_stride(mn) + 4 * (int64_t)t_limbs((int)L, (int)L) * mn;   // partial planes, T
-  bytes += 4 * (2 * M + 2 * N + 8);                            // statistics
-  bytes += 16 * (M + N) * Kt + 8 * (M + N) + 12 * parts * mn;  // radius products
-  const int sp = rad_gemm_splits(M, N, Kt);
-  if (sp > 1) bytes += 16 * (int64_t)sp * mn;                  // their split partials
-  return (size_t)bytes + 65536;
+  // integer heights of a single block are at most the height bound
+  const int hmax = height_bound(p, 32 * cap, 32 * cap);
+  auto grow = [&](int slot, int64_t bytes) { out[slot] = std::max(out[slot], (size_t)std::max<int64_t>(bytes, 256)); };
+  grow(WS_STATS, 4 * (2 * M + 2 * N + 8));
+  if (B->cs == 1 && B->rs != 1) {   // line-major copy of a row-major B
+    int64_t g = 4 * N * K * (B->re.cap + 2);
+    if (cplx) g += 4 * N * K * (B->im.cap + 2);
+    grow(WS_GATHER, g);
+  }
+  {   // the planner of several blocks
+    const int64_t maxb = K / kBasecase + 2, nline = 2 * M + 2 * N + ((2 * M + 2 * N) & 1);
+    grow(WS_PLAN, 4 * nline + 16 * maxb + 4 * (maxb + 1));
+  }
+  if (!(flags & ARBGPU_ALGO_RNS)) {   // base-256 slices
+    const int64_t L = std::min<int64_t>(kMaxSlices, slices_for(hmax));
+    const int64_t Kp = round_up(std::max<int64_t>(Kt, 1), kKStep);
+    const int64_t pmax = std::max<int64_t>(1, ((int64_t)0x7FFFFFFF) / (Kp << 14));
+    const int64_t nslots = (2 * L - 1) + L * L / pmax;
+    grow(WS_PLANES_A, L * Mp * Kp);
+    grow(WS_PLANES_B, L * Np * Kp);
+    if (cplx) grow(WS_PLANES_B2, L * Np * Kp);
+    grow(WS_D, 4 * nslots * ds);
+    grow(WS_T, 4 * (int64_t)t_limbs((int)L, (int)L) * MN);
+    grow(WS_TABLES, (int64_t)sizeof(DiagGroup) * (nslots + 8) + 4 * (2 * L));
+  }
+  if (!(flags & ARBGPU_ALGO_SLICED)) {   // residues: the largest heights the form holds
+    // every admissible pair of heights up to hmax: at most 4 * 127 digits
+    // per operand and the largest block-value width the reconstruction
+    // holds
+    const int h = std::min(hmax, 4 * 127 * 8 - 2);
+    int64_t bits = t_bits(h, h, Kt);
+    if (!rns_fits_bits(bits)) {   // the widest fitting values (the limit grows with bits)
+      int64_t lo = 0, hi = bits;
+      while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        (rns_fits_bits(mid) ? lo : hi) = mid;
+      }
+      bits = lo;
+    }
+    const int64_t Kp = round_up(std::max<int64_t>(K, 1), kKStep);
+    if (bits >= 1 && rns_fits_bits(bits) && ((int64_t)0x7FFFFFFF) / (round_up(std::max<int64_t>(Kt, 1), kKStep) << 14) >= 2) {
+      const int m = rns_count(bits);
+      const int W = (int)((bits + 1 + 31) / 32) + 1;
+      const int nw = (slices_for(h) + 3) / 4;
+      const int64_t nsets = cplx ? 3 : 1, nprod = cplx ? 4 : 1;
+      grow(WS_PLANES_A, nsets * 2 * m * Mp * Kp);
+      grow(WS_PLANES_B, nsets * 2 * m * Np * Kp);
+      grow(WS_D, 2 * nprod * m * ds);
+      grow(WS_RNS, (int64_t)rns_layout(m, nw, W).bytes);
+    }
+  }
+  const bool rad = A->re.rad_m || B->re.rad_m || (cplx && (A->im.rad_m || B->im.rad_m));
+  if (rad && !(flags & ARBGPU_APPROX)) {
+    grow(WS_RAD_A, 16 * M * Kt + 8 * M);
+    grow(WS_RAD_B, 16 * N * Kt + 8 * N);
+    grow(WS_RAD_OUT, parts * 12 * MN + 8);
+    const int sp = rad_gemm_splits(M, N, Kt);
+    if (sp > 1) grow(WS_RAD_PART, 16 * (int64_t)sp * MN);
+  }
+}
+
+size_t mat_mul_footprint(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags) {
+  size_t sz[WS_COUNT];
+  mat_mul_ws_sizes(A, B, p, flags, sz);
+  size_t t = 0;
+  for (int k = 0; k < WS_COUNT; ++k) t += sz[k];
+  return t;
 }
 
 int plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, bool cplx, int hmax, hipStream_t s,
@@ -750,7 +859,7 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
       if (rc) return rc;
     }
     return block_product(ctx, A, B, sh, 0, sh.K, st, g[0], g[4], outs, C->off, C->rs, C->cs, (int)p, sh.approx,
-                         rin_m, rin_e, s, rns);
+                         rin_m, rin_e, s, rns, (flags & ARBGPU_COMPLEX_4M) != 0);
   }
 
   // ---- several blocks (Algorithm 2's greedy partition) ----------------------
@@ -817,7 +926,7 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
     const int64_t ktb = sh.cplx ? 2 * (b.k1 - b.k0) : b.k1 - b.k0;
     const bool rns = use_rns(g[0], g[4], ktb) && rns_fits(g[0], g[4], ktb);
     rc = block_product(ctx, A, B, sh, b.k0, b.k1, st, g[0], g[4], tout, 0, sh.N, 1, 32 * capT, true, no_m, no_e, s,
-                       rns);
+                       rns, (flags & ARBGPU_COMPLEX_4M) != 0);
     if (rc) return rc;
     ++si;
   }
@@ -847,6 +956,41 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
     ARB_TRY(launch_merge(mp, ls.ns, s), "merge");
   }
   return ARBGPU_OK;
+}
+
+int exact_block_product(arbgpu_ctx *ctx, uint32_t *T_re, uint32_t *T_im, int64_t ldT, int32_t capT, int32_t *row_v2,
+                        int32_t *col_v2, const arbgpu_mat *A, const arbgpu_mat *B, uint32_t flags, hipStream_t s) {
+  Shape sh{(flags & ARBGPU_COMPLEX) != 0, true, (flags & ARBGPU_COMPLEX) ? 2 : 1, A->rows, B->cols, A->cols};
+  const int64_t Kt = sh.cplx ? 2 * sh.K : sh.K;
+  int32_t *st = stats_ws(ctx, sh);
+  if (!st) return ARBGPU_ENOMEM;
+  int32_t g[8];
+  int rc = line_stats(ctx, A, B, sh, 0, sh.K, st, s, g);
+  if (rc) return rc;
+  if (g[2] || g[6]) return set_error(ctx, ARBGPU_ERANGE, "an operand exponent is outside (-2^28, 2^28)");
+  if (slices_for(g[0]) > kMaxSlices || slices_for(g[4]) > kMaxSlices)
+    return set_error(ctx, ARBGPU_EINVAL, "exact block product: integer height too large");
+  bool rns;
+  if (flags & ARBGPU_ALGO_RNS) rns = true;
+  else if (flags & ARBGPU_ALGO_SLICED) rns = false;
+  else rns = rns_better(g[0], g[4], Kt);
+  if (rns && !rns_fits(g[0], g[4], Kt))
+    return set_error(ctx, ARBGPU_EINVAL, "exact block product: the residue form does not fit these heights");
+  if (!rns && ((int64_t)0x7FFFFFFF) / (round_up(std::max<int64_t>(Kt, 1), kKStep) << 14) < 1)
+    return set_error(ctx, ARBGPU_EINVAL, "exact block product: inner length %lld too long", (long long)Kt);
+  const int need = rns ? (int)((t_bits(g[0], g[4], Kt) + 1 + 31) / 32) + 1 : t_limbs(slices_for(g[0]), slices_for(g[4]));
+  if (capT < need) return set_error(ctx, ARBGPU_EINVAL, "exact block product: T needs %d limbs, cap is %d", need, capT);
+  if (ldT < sh.M * sh.N) return set_error(ctx, ARBGPU_EINVAL, "exact block product: ldT below rows * cols");
+  ARB_TRY(launch_v2_out(st + sh.M, sh.M, row_v2, s), "scalings");
+  ARB_TRY(launch_v2_out(st + 2 * sh.M + sh.N, sh.N, col_v2, s), "scalings");
+  const TSink ts{{T_re, T_im}, ldT, capT};
+  // the rounded outputs are not wanted: a sink without exponents writes none
+  const arbgpu_out none[2] = {arbgpu_out{nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr},
+                              arbgpu_out{nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr}};
+  double *no_m[2] = {nullptr, nullptr};
+  int32_t *no_e[2] = {nullptr, nullptr};
+  return block_product(ctx, A, B, sh, 0, sh.K, st, g[0], g[4], none, 0, sh.N, 1, 2, true, no_m, no_e, s, rns,
+                       (flags & ARBGPU_COMPLEX_4M) != 0, &ts);
 }
 
 }  // namespace arbgpu_impl

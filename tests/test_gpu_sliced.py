@@ -141,10 +141,10 @@ def test_sliced_complex(ctx, algo):
 
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 6, 131])
 def test_rns_complex_short_and_ragged_inner(ctx, N):
-    # the imaginary part's residue planes come from the real part's by
-    # moving residues K positions and negating them: inner lengths below 4,
-    # not a multiple of 4, and one whose doubled length crosses a 128-byte
-    # step, with residues of both signs (negative and zero entries)
+    # the three-product form adds the residues of the real and imaginary
+    # parts and combines three residue planes per prime: inner lengths
+    # below 4, not a multiple of 4, and one past a 128-byte step, with
+    # residues of both signs (negative and zero entries)
     rng = gen.rng_for(26, N)
     M, K, p = 7, 5, 150
     parts = [gen.random_operands(rng, c, rng.integers(1, 200, c), -12, 12, radius_shift=140, zero_frac=0.1)

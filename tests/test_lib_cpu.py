@@ -185,3 +185,33 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_host_only_context_validates_reserve_and_exact_t(hctx, lib):
+    def mat(rows, cols, ld=100):
+        return arbgpu.Mat(_arr(ld), _arr(ld), rows, cols, 0, cols, 1)
+
+    # a valid reservation reaches the device step and reports the host-only context
+    assert hctx.reserve_raw(mat(3, 5), mat(5, 4), 100, check=False) == arbgpu.EDEVICE
+    assert hctx.reserve_raw(mat(3, 5), mat(6, 4), 100, check=False) == arbgpu.EINVAL
+    assert hctx.reserve_raw(mat(3, 5), mat(5, 4), 1, check=False) == arbgpu.EINVAL
+    assert hctx.reserve_raw(mat(3, 5), mat(5, 4), 100, flags=0x1000, check=False) == arbgpu.EINVAL
+    assert hctx.alloc_count() == 0
+
+    class Fake:   # stands in for a device tensor: only its address is passed
+        def __init__(self, a):
+            self.a = a
+
+        def data_ptr(self):
+            return self.a
+
+    t, rv, cv = Fake(16), Fake(32), Fake(48)
+    args = dict(ldT=12, capT=4, row_v2=rv, col_v2=cv)
+    assert hctx.mat_mul_exact_t_raw(t, None, A=mat(3, 5), B=mat(5, 4), check=False, **args) == arbgpu.EDEVICE
+    assert hctx.mat_mul_exact_t_raw(t, None, A=mat(3, 5), B=mat(6, 4), check=False, **args) == arbgpu.EINVAL
+    assert hctx.mat_mul_exact_t_raw(t, None, A=mat(3, 5), B=mat(5, 4), check=False,
+                                    **dict(args, ldT=11)) == arbgpu.EINVAL                       # ldT < rows*cols
+    assert hctx.mat_mul_exact_t_raw(t, None, A=mat(3, 5), B=mat(5, 4), flags=arbgpu.COMPLEX,
+                                    check=False, **args) == arbgpu.EINVAL                        # no T_im
+    assert hctx.mat_mul_exact_t_raw(t, None, A=mat(3, 5), B=mat(5, 4), flags=arbgpu.ALGO_LIMB,
+                                    check=False, **args) == arbgpu.EINVAL
