@@ -39,21 +39,25 @@ from paper_1901_04289_amd import gen  # noqa: E402
 METRIC = "p-bit MACs/s, sliced-MFMA vs plain limb kernel, N=2048 p=512; p99 latency"
 PEAK_INT8_TOPS = 5000.0   # MI355X dense INT8 MFMA, 5.0 POP/s
 
-# HBM bytes per launch of mfma_diag_kernel at N = 2048, p = 512 for the two
-# INT8 forms, from the FETCH_SIZE (x2, copy-calibrated) and WRITE_SIZE (x1)
-# counter runs in profiles/mfma_diag_kernel_matmul2048_p512.txt; valid only
-# for the kernel source they were taken on (sha256 prefix of csrc/mfma.hip).
-MFMA_TRAFFIC_BYTES = {"residues": (1761777 * 2 + 3489792) * 1024.0,
-                      "slices": (30267872 * 2 + 2228224) * 1024.0}
-MFMA_TRAFFIC_SRC = "ef1395843d68b766"
+# HBM bytes per launch of the MFMA kernel of each INT8 form at N = 2048,
+# p = 512, from FETCH_SIZE (scaled by the copy calibration) and WRITE_SIZE
+# counter runs (profiles/mfma_*_matmul2048_p512.txt); each is valid only for
+# the kernel source it was taken on (sha256 prefix of that file), else the
+# traffic is reported as null.
+MFMA_KERNEL = {"residues": "mfma_rns_kernel<256>", "slices": "mfma_diag_kernel"}
+MFMA_TRAFFIC = {
+    # form: (kernel source, sha256 prefix, bytes per launch)
+    "residues": ("mfma_rns.hip", None, None),
+    "slices": ("mfma.hip", "ef1395843d68b766", (30267872 * 2 + 2228224) * 1024.0),
+}
 
 
 def _mfma_traffic(n, form):
     import hashlib
-    src = os.path.join(ROOT, "paper_1901_04289_amd", "csrc", "mfma.hip")
-    with open(src, "rb") as f:
+    src, want, nbytes = MFMA_TRAFFIC[form]
+    with open(os.path.join(ROOT, "paper_1901_04289_amd", "csrc", src), "rb") as f:
         h = hashlib.sha256(f.read()).hexdigest()[:16]
-    return MFMA_TRAFFIC_BYTES[form] if (h == MFMA_TRAFFIC_SRC and n == 2048) else None
+    return nbytes if (want is not None and h == want and n == 2048) else None
 
 
 # ---------------------------------------------------------------------------
@@ -393,7 +397,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
                      "frac": achieved / PEAK_INT8_TOPS,
                      "traffic": _mfma_traffic(a.n, "slices" if digits_path else "residues"),
-                     "kernel": "mfma_diag_kernel", "ops_per_launch": int8_ops,
+                     "kernel": MFMA_KERNEL["slices" if digits_path else "residues"], "ops_per_launch": int8_ops,
                      "avg_launch_ms": mfma_avg_s * 1e3},
         "int8_forms": forms,
         "cpu_baseline": cpu,

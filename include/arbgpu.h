@@ -211,6 +211,23 @@ int arbgpu_workspace_info(arbgpu_ctx *ctx, int64_t *allocs, int64_t *bytes);
 int arbgpu_mat_mul_footprint(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
                              int64_t p, uint32_t flags, size_t *bytes);
 
+/* Autotuner of the matrix product's path.  Runs the product C = A B (the
+ * arguments of arbgpu_mat_mul, no ALGO flag) on every applicable path --
+ * the limb kernel (unless its work is far beyond the INT8 path's), base-256
+ * slices, and residues on 256 x 256 and on 128 x 128 MFMA tiles -- once
+ * untimed and twice between HIP events on `stream`, and records the
+ * fastest for the product's class in the context's tune table (saved to
+ * the tune-cache file when the context has one): real or complex, balls or
+ * midpoints, and the ceiling base-2 logarithms of max(rows, cols), of the
+ * inner length and of p.  Later arbgpu_mat_mul calls without an ALGO flag
+ * take the recorded path for their class (results are the same on every
+ * path).  Writes the choice (1 limb, 2 slices, 3 residues/256, 4
+ * residues/128) to *choice when not NULL.  Overwrites C; synchronizes
+ * `stream`.  EINVAL on bad arguments or an ALGO flag. */
+int arbgpu_tune_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A,
+                        const arbgpu_mat *B, int64_t p, uint32_t flags,
+                        arbgpu_stream stream, int32_t *choice);
+
 /* Block partition of Algorithm 2 (Section 4.1) for the product A B at
  * precision p: the inner index range is cut greedily, from index 0 upward,
  * into ranges over which every row of A and every column of B keeps integer
@@ -294,6 +311,19 @@ typedef struct {
   int64_t p;
   uint32_t flags;
 } arbgpu_job;
+
+/* A resident batch of dot products and matrix products (arbgpu_job
+ * descriptors, the arguments of arbgpu_dot and arbgpu_mat_mul by value) in
+ * the same persistent launch: a matrix product becomes tiles of 64 entries
+ * of one row, each entry one lane's dot product on the limb kernel, queued
+ * with the dot products of the same kernel shape (longest first), so that
+ * many small products of uneven size and precision run in one graph
+ * launch.  Matrix products in a batch take the limb kernel: the INT8 ALGO
+ * flags and COMPLEX_4M are refused (EINVAL), as is a precision beyond the
+ * kernel's window.  Launch, tune, info and destroy as for a dot batch
+ * (info counts tasks plus tiles). */
+int arbgpu_batch_create_mixed(arbgpu_ctx *ctx, const arbgpu_job *jobs, int64_t njobs,
+                              arbgpu_batch **batch);
 
 /* (Re)starts the loop with `slots` workers (1..16) and an HBM budget in
  * bytes for the workspace of admitted jobs (0: half the context budget).

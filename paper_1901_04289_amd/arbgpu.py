@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libarbgpu.so")
 OK, NOTREADY, EINVAL, ERANGE, ENOMEM, EAGAIN, EDEVICE = 0, 1, -1, -2, -3, -4, -5
 APPROX, COMPLEX, REDUCE_PREC, ALGO_LIMB, ALGO_SLICED, ALGO_RNS = 0x01, 0x02, 0x04, 0x10, 0x20, 0x40
 COMPLEX_4M = 0x80
+CHOICE_LIMB, CHOICE_SLICES, CHOICE_RNS256, CHOICE_RNS128 = 1, 2, 3, 4
 ST_OK, ST_REFINED, ST_ERANGE = 0, 1, 2
 
 c_p = ctypes.c_void_p
@@ -83,6 +84,8 @@ EXPORTS = {
                                       c_i64, c_u32, c_p]),
     "arbgpu_mat_mul_exact_t": (ctypes.c_int, [c_p, c_p, c_p, c_i64, c_i32, c_p, c_p, ctypes.POINTER(Mat),
                                               ctypes.POINTER(Mat), c_u32, c_p]),
+    "arbgpu_tune_mat_mul": (ctypes.c_int, [c_p, ctypes.POINTER(OMat), ctypes.POINTER(Mat), ctypes.POINTER(Mat),
+                                           c_i64, c_u32, c_p, ctypes.POINTER(c_i32)]),
     "arbgpu_reserve": (ctypes.c_int, [c_p, ctypes.POINTER(Mat), ctypes.POINTER(Mat), c_i64, c_u32]),
     "arbgpu_workspace_info": (ctypes.c_int, [c_p, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
     "arbgpu_mat_mul_footprint": (ctypes.c_int, [c_p, ctypes.POINTER(Mat), ctypes.POINTER(Mat), c_i64, c_u32,
@@ -92,6 +95,7 @@ EXPORTS = {
                                           ctypes.POINTER(c_i64), ctypes.POINTER(ctypes.c_int32), c_i64,
                                           ctypes.POINTER(c_i64), c_p]),
     "arbgpu_batch_create": (ctypes.c_int, [c_p, ctypes.POINTER(DotJob), c_i64, ctypes.POINTER(c_p)]),
+    "arbgpu_batch_create_mixed": (ctypes.c_int, [c_p, ctypes.c_void_p, c_i64, ctypes.POINTER(c_p)]),
     "arbgpu_batch_launch": (ctypes.c_int, [c_p, c_p]),
     "arbgpu_batch_tune": (ctypes.c_int, [c_p, c_p]),
     "arbgpu_batch_info": (ctypes.c_int, [c_p, ctypes.POINTER(c_i64), ctypes.c_int]),
@@ -322,6 +326,15 @@ class Context:
         n = min(nb.value, cap)
         return [(bounds[2 * i], bounds[2 * i + 1], kinds[i]) for i in range(n)]
 
+    def tune_mat_mul_raw(self, C: OMat, A: Mat, B: Mat, p: int, flags: int = 0, stream=None) -> int:
+        """Time every path of this product and record the fastest for its
+        class; returns the choice (1 limb, 2 slices, 3 residues/256, 4
+        residues/128)."""
+        ch = c_i32()
+        self._check(self.lib.arbgpu_tune_mat_mul(self.h, ctypes.byref(C), ctypes.byref(A), ctypes.byref(B), p,
+                                                 flags, _stream_handle(stream), ctypes.byref(ch)))
+        return ch.value
+
     def reserve_raw(self, A: Mat, B: Mat, p: int, flags: int = 0, check: bool = True) -> int:
         """Grow the workspace for products of this shape (no allocation later)."""
         rc = self.lib.arbgpu_reserve(self.h, ctypes.byref(A), ctypes.byref(B), p, flags)
@@ -424,13 +437,19 @@ def dot_job(res: Sequence[Out], res_idx: int, x: Sequence[Arr], xoff: int, xstep
 
 
 class Batch:
-    """A resident batch of dot products replayed as one graph launch."""
+    """A resident batch replayed as one graph launch: dot products
+    (DotJob), or dot and matrix-product requests (Job) with mixed=True."""
 
-    def __init__(self, ctx: "Context", jobs: Sequence[DotJob]):
+    def __init__(self, ctx: "Context", jobs, mixed: bool = False):
         self.ctx = ctx
-        arr = (DotJob * max(1, len(jobs)))(*jobs)
         h = c_p()
-        ctx._check(ctx.lib.arbgpu_batch_create(ctx.h, arr, len(jobs), ctypes.byref(h)))
+        if mixed:
+            arr = (Job * max(1, len(jobs)))(*jobs)
+            ctx._check(ctx.lib.arbgpu_batch_create_mixed(ctx.h, ctypes.cast(arr, ctypes.c_void_p), len(jobs),
+                                                         ctypes.byref(h)))
+        else:
+            arr = (DotJob * max(1, len(jobs)))(*jobs)
+            ctx._check(ctx.lib.arbgpu_batch_create(ctx.h, arr, len(jobs), ctypes.byref(h)))
         self.h = h
 
     def launch(self, stream=None):

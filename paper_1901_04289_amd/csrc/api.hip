@@ -10,8 +10,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -456,6 +458,21 @@ int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
   if (rc) return rc;
   if (C->rows == 0 || C->cols == 0) return ARBGPU_OK;
   if ((rc = bind_device(ctx, stream))) return rc;
+  return mat_mul_run(ctx, C, A, B, p, flags, to_stream(stream));
+}
+
+}  // extern "C"
+
+namespace arbgpu_impl {
+
+int mat_mul_run(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p,
+                uint32_t flags, hipStream_t stream, int choice) {
+  int rc;
+  if (choice == kChoiceRule && !(flags & (ARBGPU_ALGO_LIMB | ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS)) &&
+      !ctx->tune.empty()) {
+    auto it = ctx->tune.find(mat_mul_class(A, B, p, flags));
+    if (it != ctx->tune.end()) choice = it->second;
+  }
   const bool approx = flags & ARBGPU_APPROX;
   const bool cplx = flags & ARBGPU_COMPLEX;
   const int nparts = cplx ? 2 : 1;
@@ -467,11 +484,11 @@ int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
   }
   LimbShape sh;
   const bool limb_ok = limb_shape_for((int)p, A->cols * nparts, cap, &sh);
-  if (!(flags & ARBGPU_ALGO_LIMB)) {
+  if (!(flags & ARBGPU_ALGO_LIMB) && !(choice == kChoiceLimb && limb_ok)) {
     // the scaled-integer path, forced when asked for or when the limb
     // kernel's window cannot hold the precision
-    rc = sliced_mat_mul(ctx, C, A, B, p, flags, to_stream(stream),
-                        (flags & (ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS)) != 0 || !limb_ok);
+    rc = sliced_mat_mul(ctx, C, A, B, p, flags, stream,
+                        (flags & (ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS)) != 0 || !limb_ok, choice);
     if (rc != kNotApplicable) return rc;
   }
   if (!limb_ok)
@@ -493,12 +510,16 @@ int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
     prm.p = (int)p;
     prm.approx = approx;
     prm.ct = !cplx ? comp_real() : (q == 0 ? comp_re() : comp_im());
-    KernelTimer kt(ctx, "limb_mm", to_stream(stream));
-    hipError_t e = launch_limb_mm(prm, sh, to_stream(stream));
+    KernelTimer kt(ctx, "limb_mm", stream);
+    hipError_t e = launch_limb_mm(prm, sh, stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "arbgpu_mat_mul launch");
   }
   return ARBGPU_OK;
 }
+
+}  // namespace arbgpu_impl
+
+extern "C" {
 
 int arbgpu_plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags,
                        int64_t *bounds, int32_t *kinds, int64_t max_blocks, int64_t *nblocks, arbgpu_stream stream) {
@@ -518,6 +539,60 @@ int arbgpu_plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B
   if (A->cols == 0) return ARBGPU_OK;
   if ((rc = bind_device(ctx, stream))) return rc;
   return plan_partition(ctx, A, B, p, flags, to_stream(stream), bounds, kinds, max_blocks, nblocks);
+}
+
+int arbgpu_tune_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p,
+                        uint32_t flags, arbgpu_stream stream, int32_t *choice) {
+  if (!ctx) return ARBGPU_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (flags & (ARBGPU_ALGO_LIMB | ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS))
+    return fail(ctx, ARBGPU_EINVAL, "arbgpu_tune_mat_mul: ALGO flags fix the path; nothing to tune");
+  int rc = mat_mul_check(ctx, C, A, B, p, flags);
+  if (rc) return rc;
+  if (C->rows == 0 || C->cols == 0 || A->cols == 0)
+    return fail(ctx, ARBGPU_EINVAL, "arbgpu_tune_mat_mul: empty product");
+  if ((rc = bind_device(ctx, stream))) return rc;
+  const hipStream_t s = to_stream(stream);
+  const bool cplx = flags & ARBGPU_COMPLEX;
+  int cap = std::max(A->re.cap, B->re.cap);
+  if (cplx) cap = std::max(cap, std::max(A->im.cap, B->im.cap));
+  LimbShape ls;
+  const bool limb_ok = limb_shape_for((int)p, A->cols * (cplx ? 2 : 1), cap, &ls);
+  // the limb kernel's work: (window-limb products per term) x terms; far
+  // beyond the INT8 path it is not timed
+  const double w = (double)std::min<int64_t>(cap, (p + 31) / 32 + 2);
+  const double limb_work = (double)A->rows * B->cols * A->cols * (cplx ? 4 : 1) * w * w;
+  std::vector<int> cand;
+  if (limb_ok && limb_work < 4e10) cand.push_back(kChoiceLimb);
+  cand.push_back(kChoiceSlices);
+  cand.push_back(kChoiceRns256);
+  cand.push_back(kChoiceRns128);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
+    return fail(ctx, ARBGPU_EDEVICE, "arbgpu_tune_mat_mul: hipEventCreate");
+  int best = kChoiceRule;
+  float tbest = 0.f;
+  for (int c : cand) {
+    // one untimed call (it sizes the workspace), then two timed
+    if (mat_mul_run(ctx, C, A, B, p, flags, s, c) != ARBGPU_OK) continue;
+    float ms = 0.f;
+    bool ok = hipEventRecord(ev[0], s) == hipSuccess;
+    for (int r = 0; r < 2 && ok; ++r) ok = mat_mul_run(ctx, C, A, B, p, flags, s, c) == ARBGPU_OK;
+    ok = ok && hipEventRecord(ev[1], s) == hipSuccess && hipEventSynchronize(ev[1]) == hipSuccess &&
+         hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess;
+    if (ok && (best == kChoiceRule || ms < tbest)) {
+      best = c;
+      tbest = ms;
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (best == kChoiceRule) return fail(ctx, ARBGPU_EDEVICE, "arbgpu_tune_mat_mul: no path ran: %s", ctx->err.c_str());
+  ctx->err.clear();
+  ctx->tune[mat_mul_class(A, B, p, flags)] = best;
+  if (!ctx->tune_path.empty()) tune_save(ctx);
+  if (choice) *choice = best;
+  return ARBGPU_OK;
 }
 
 int arbgpu_reserve(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags) {

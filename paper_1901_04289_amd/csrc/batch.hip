@@ -39,48 +39,123 @@ struct ShapeRun {
   float tuned_ms;         // time of this shape alone at `waves` (0: not tuned)
 };
 
-// Validates the jobs and builds the tasks, their order (by shape, longest
-// first) and the per-shape runs; sets the context error on a bad job.
-int plan_batch(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, const char *who,
-               std::vector<DotParams> &tasks, std::vector<int32_t> &order, std::vector<ShapeRun> &runs) {
-  std::vector<LimbShape> shape_of;
-  std::vector<double> cost;
-  tasks.clear();
-  runs.clear();
-  tasks.reserve((size_t)njobs * 2);
+// The work of a batch: dot tasks, matrix-product parts and their tiles,
+// and the per-shape runs over `order` (by shape, longest first).
+struct BatchPlan {
+  std::vector<DotParams> tasks;
+  std::vector<MmParams> mm;
+  std::vector<BatchTile> tiles;
+  std::vector<int32_t> order;   // dot task e >= 0, tile -e - 1
+  std::vector<ShapeRun> runs;
+};
+
+// Validates one matrix-product job of a batch and adds its parts and
+// tiles (the limb kernel, one 64-entry row segment per tile).
+int plan_matmul(arbgpu_ctx *ctx, const arbgpu_job &j, const char *who, BatchPlan &bp, std::vector<LimbShape> &shape_of,
+                std::vector<double> &cost) {
+  if (j.flags & (ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS | ARBGPU_COMPLEX_4M))
+    return set_error(ctx, ARBGPU_EINVAL, "%s: a batch runs matrix products on the limb kernel (no INT8 ALGO flag)", who);
+  int rc = mat_mul_check(ctx, &j.C, &j.A, &j.B, j.p, j.flags);
+  if (rc) return rc;
+  const bool cplx = j.flags & ARBGPU_COMPLEX;
+  const int nparts = cplx ? 2 : 1;
+  int cap = std::max(j.A.re.cap, j.B.re.cap);
+  if (cplx) cap = std::max(cap, std::max(j.A.im.cap, j.B.im.cap));
+  LimbShape sh;
+  if (!limb_shape_for((int)j.p, j.A.cols * nparts, cap, &sh))
+    return set_error(ctx, ARBGPU_EINVAL, "%s: precision %lld above the limb kernel's window", who, (long long)j.p);
+  const int64_t M = j.A.rows, N = j.A.cols, K = j.B.cols;
+  if ((int64_t)bp.tiles.size() + M * ((K + 63) / 64) * nparts > ((int64_t)1 << 30))
+    return set_error(ctx, ARBGPU_EINVAL, "%s: too many matrix tiles", who);
+  const double w = (double)std::min(cap, sh.na);
+  const arbgpu_out *cparts[2] = {&j.C.re, &j.C.im};
+  for (int q = 0; q < nparts; ++q) {
+    MmParams prm;
+    memset(&prm, 0, sizeof prm);
+    prm.A[0] = j.A.re;
+    prm.A[1] = cplx ? j.A.im : j.A.re;
+    prm.B[0] = j.B.re;
+    prm.B[1] = cplx ? j.B.im : j.B.re;
+    prm.C = *cparts[q];
+    prm.M = M; prm.N = N; prm.K = K;
+    prm.a_off = j.A.off; prm.a_rs = j.A.rs; prm.a_cs = j.A.cs;
+    prm.b_off = j.B.off; prm.b_rs = j.B.rs; prm.b_cs = j.B.cs;
+    prm.c_off = j.C.off; prm.c_rs = j.C.rs; prm.c_cs = j.C.cs;
+    prm.p = (int)j.p;
+    prm.approx = (j.flags & ARBGPU_APPROX) != 0;
+    prm.ct = !cplx ? comp_real() : (q == 0 ? comp_re() : comp_im());
+    const int32_t part = (int32_t)bp.mm.size();
+    bp.mm.push_back(prm);
+    for (int64_t i = 0; i < M; ++i)
+      for (int64_t j0 = 0; j0 < K; j0 += 64) {
+        bp.tiles.push_back(BatchTile{part, 0, i, j0});
+        shape_of.push_back(sh);
+        // 64 entries, each a whole dot of its own lane
+        cost.push_back(64.0 * (double)(N * prm.ct.ncomp + 1) * w * w);
+      }
+  }
+  return ARBGPU_OK;
+}
+
+// Validates the jobs (dot jobs from `dots`, or dot and matrix-product jobs
+// from `jobs`) and builds the batch's work; sets the context error on a
+// bad job.
+int plan_batch(arbgpu_ctx *ctx, const arbgpu_dot_job *dots, const arbgpu_job *jobs, int64_t njobs, const char *who,
+               BatchPlan &bp) {
+  // work item w < tasks: dot task w; else tile w - tasks (filled in below)
+  std::vector<LimbShape> shape_dot, shape_tile;
+  std::vector<double> cost_dot, cost_tile;
+  bp = BatchPlan();
   for (int64_t i = 0; i < njobs; ++i) {
-    DotParams prm[2];
-    int nt = 0;
-    LimbShape sh;
-    const int rc = dot_tasks(ctx, jobs[i], who, prm, &nt, &sh);
+    int rc;
+    if (jobs && jobs[i].kind == ARBGPU_JOB_MATMUL) {
+      rc = plan_matmul(ctx, jobs[i], who, bp, shape_tile, cost_tile);
+    } else if (jobs && jobs[i].kind != ARBGPU_JOB_DOT) {
+      rc = set_error(ctx, ARBGPU_EINVAL, "%s: unknown job kind %d", who, jobs[i].kind);
+    } else {
+      const arbgpu_dot_job &dj = jobs ? jobs[i].dot : dots[i];
+      DotParams prm[2];
+      int nt = 0;
+      LimbShape sh;
+      rc = dot_tasks(ctx, dj, who, prm, &nt, &sh);
+      if (!rc) {
+        int cap = 1;
+        for (int q = 0; q < nt; ++q) cap = std::max(cap, std::max(dj.x[q].cap, dj.y[q].cap));
+        const double w = (double)std::min(cap, sh.na);
+        for (int q = 0; q < nt; ++q) {
+          bp.tasks.push_back(prm[q]);
+          shape_dot.push_back(sh);
+          cost_dot.push_back((double)(prm[q].N * prm[q].ct.ncomp + 1) * w * w);
+        }
+      }
+    }
     if (rc) {
       ctx->err = "job " + std::to_string(i) + ": " + ctx->err;
       return rc;
     }
-    int cap = 1;
-    for (int q = 0; q < nt; ++q) cap = std::max(cap, std::max(jobs[i].x[q].cap, jobs[i].y[q].cap));
-    const double w = (double)std::min(cap, sh.na);
-    for (int q = 0; q < nt; ++q) {
-      tasks.push_back(prm[q]);
-      shape_of.push_back(sh);
-      cost.push_back((double)(prm[q].N * prm[q].ct.ncomp + 1) * w * w);
-    }
   }
-  order.resize(tasks.size());
-  for (size_t t = 0; t < tasks.size(); ++t) order[t] = (int32_t)t;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-    const LimbShape &a = shape_of[x], &c = shape_of[y];
+  const size_t nd = bp.tasks.size(), nt = bp.tiles.size();
+  if (nd + nt > (size_t)0x7FFFFFFF) return set_error(ctx, ARBGPU_EINVAL, "%s: too much work in one batch", who);
+  auto shape = [&](size_t w) -> const LimbShape & { return w < nd ? shape_dot[w] : shape_tile[w - nd]; };
+  auto cost = [&](size_t w) { return w < nd ? cost_dot[w] : cost_tile[w - nd]; };
+  std::vector<int32_t> work(nd + nt);
+  for (size_t w = 0; w < work.size(); ++w) work[w] = (int32_t)w;
+  std::stable_sort(work.begin(), work.end(), [&](int32_t x, int32_t y) {
+    const LimbShape &a = shape(x), &c = shape(y);
     if (a.ns != c.ns) return a.ns > c.ns;
     if (a.na != c.na) return a.na > c.na;
-    return cost[x] > cost[y];
+    return cost(x) > cost(y);
   });
-  for (size_t t = 0; t < order.size(); ++t) {
-    const LimbShape &sh = shape_of[order[t]];
-    if (runs.empty() || runs.back().sh.ns != sh.ns || runs.back().sh.na != sh.na) {
+  bp.order.resize(work.size());
+  for (size_t t = 0; t < work.size(); ++t) {
+    const size_t w = (size_t)work[t];
+    bp.order[t] = w < nd ? (int32_t)w : -(int32_t)(w - nd) - 1;
+    const LimbShape &sh = shape(w);
+    if (bp.runs.empty() || bp.runs.back().sh.ns != sh.ns || bp.runs.back().sh.na != sh.na) {
       auto it = ctx->tune.find(tune_key(sh));
-      runs.push_back({sh, (int64_t)t, 0, it != ctx->tune.end() ? it->second : kDefaultWaves, 0.f});
+      bp.runs.push_back({sh, (int64_t)t, 0, it != ctx->tune.end() ? it->second : kDefaultWaves, 0.f});
     }
-    runs.back().count++;
+    bp.runs.back().count++;
   }
   return ARBGPU_OK;
 }
@@ -106,10 +181,11 @@ size_t dot_batch_ws(int64_t n, int nshapes) {
 }
 
 int dot_batch_run(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, hipStream_t s) {
-  std::vector<DotParams> tasks;
-  std::vector<int32_t> order;
-  std::vector<ShapeRun> runs;
-  int rc = plan_batch(ctx, jobs, njobs, "dot batch", tasks, order, runs);
+  BatchPlan plan;
+  int rc = plan_batch(ctx, jobs, nullptr, njobs, "dot batch", plan);
+  const std::vector<DotParams> &tasks = plan.tasks;
+  const std::vector<int32_t> &order = plan.order;
+  const std::vector<ShapeRun> &runs = plan.runs;
   if (rc || tasks.empty()) return rc;
   const size_t tb = sizeof(DotParams) * tasks.size(), ob = sizeof(int32_t) * order.size();
   char *w = (char *)ws_get(ctx, WS_BATCH, dot_batch_ws((int64_t)tasks.size(), (int)runs.size()));
@@ -127,7 +203,7 @@ int dot_batch_run(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, hi
   }
   const int ncu = device_cus(ctx->device);
   for (size_t k = 0; k < runs.size() && e == hipSuccess; ++k) {
-    BatchShapeParams bp{d_tasks, d_order + runs[k].begin, runs[k].count, d_ctr + k};
+    BatchShapeParams bp{d_tasks, nullptr, nullptr, d_order + runs[k].begin, runs[k].count, d_ctr + k};
     void *args[] = {&bp};
     e = hipLaunchKernel(dot_batch_kernel(runs[k].sh), dim3(blocks_for(runs[k].count, runs[k].waves, ncu)),
                         dim3(256), args, 0, s);
@@ -144,8 +220,10 @@ struct arbgpu_batch {
   arbgpu_ctx *ctx = nullptr;
   int64_t njobs = 0;
   std::vector<ShapeRun> runs;
-  int64_t ntasks = 0;
+  int64_t ntasks = 0, ntiles = 0;
   DotParams *d_tasks = nullptr;
+  MmParams *d_mm = nullptr;
+  BatchTile *d_tiles = nullptr;
   int32_t *d_order = nullptr;
   int32_t *d_counters = nullptr;
   int num_cu = 256;
@@ -155,15 +233,14 @@ struct arbgpu_batch {
   ~arbgpu_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    if (d_tasks) (void)hipFree(d_tasks);
-    if (d_order) (void)hipFree(d_order);
-    if (d_counters) (void)hipFree(d_counters);
+    for (void *q : {(void *)d_tasks, (void *)d_mm, (void *)d_tiles, (void *)d_order, (void *)d_counters})
+      if (q) (void)hipFree(q);
   }
 
   unsigned blocks_for(const ShapeRun &r, int waves) const { return ::blocks_for(r.count, waves, num_cu); }
 
   BatchShapeParams params(size_t k) const {
-    return BatchShapeParams{d_tasks, d_order + runs[k].begin, runs[k].count, d_counters + k};
+    return BatchShapeParams{d_tasks, d_mm, d_tiles, d_order + runs[k].begin, runs[k].count, d_counters + k};
   }
 
   int build_graph() {
@@ -204,18 +281,17 @@ struct arbgpu_batch {
   }
 };
 
-extern "C" {
+namespace {
 
-int arbgpu_batch_create(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, arbgpu_batch **batch) {
+int batch_create(arbgpu_ctx *ctx, const arbgpu_dot_job *dots, const arbgpu_job *jobs, int64_t njobs,
+                 arbgpu_batch **batch, const char *who) {
   if (!ctx || !batch) return ARBGPU_EINVAL;
   *batch = nullptr;
   std::lock_guard<std::mutex> lk(ctx->mu);
-  if (njobs < 0 || (njobs > 0 && !jobs)) return set_error(ctx, ARBGPU_EINVAL, "arbgpu_batch_create: bad job list");
-  if (njobs > (int64_t)1 << 29) return set_error(ctx, ARBGPU_EINVAL, "arbgpu_batch_create: too many jobs");
-  std::vector<DotParams> tasks;
-  std::vector<int32_t> order;
-  std::vector<ShapeRun> runs;
-  const int prc = plan_batch(ctx, jobs, njobs, "arbgpu_batch_create", tasks, order, runs);
+  if (njobs < 0 || (njobs > 0 && !dots && !jobs)) return set_error(ctx, ARBGPU_EINVAL, "%s: bad job list", who);
+  if (njobs > (int64_t)1 << 29) return set_error(ctx, ARBGPU_EINVAL, "%s: too many jobs", who);
+  BatchPlan plan;
+  const int prc = plan_batch(ctx, dots, jobs, njobs, who, plan);
   if (prc) return prc;
   if (ctx->device < 0) return set_error(ctx, ARBGPU_EDEVICE, "host-only context cannot launch work");
   hipError_t e = hipSetDevice(ctx->device);
@@ -224,25 +300,24 @@ int arbgpu_batch_create(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njo
   if (!b) return ARBGPU_ENOMEM;
   b->ctx = ctx;
   b->njobs = njobs;
-  b->ntasks = (int64_t)tasks.size();
+  b->ntasks = (int64_t)plan.tasks.size();
+  b->ntiles = (int64_t)plan.tiles.size();
   b->num_cu = device_cus(ctx->device);
-  b->runs = runs;
-  const size_t tb = sizeof(DotParams) * std::max<size_t>(1, tasks.size());
-  const size_t ob = sizeof(int32_t) * std::max<size_t>(1, order.size());
-  const size_t cb = sizeof(int32_t) * std::max<size_t>(1, b->runs.size());
-  if ((e = hipMalloc(&b->d_tasks, tb)) != hipSuccess || (e = hipMalloc(&b->d_order, ob)) != hipSuccess ||
-      (e = hipMalloc(&b->d_counters, cb)) != hipSuccess) {
+  b->runs = plan.runs;
+  auto up = [&](void **dst, const void *src, size_t bytes) {
+    if (e != hipSuccess) return;
+    e = hipMalloc(dst, std::max<size_t>(bytes, 16));
+    if (e == hipSuccess) ++ctx->allocs;
+    if (e == hipSuccess && bytes && src) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  up((void **)&b->d_tasks, plan.tasks.data(), sizeof(DotParams) * plan.tasks.size());
+  up((void **)&b->d_mm, plan.mm.data(), sizeof(MmParams) * plan.mm.size());
+  up((void **)&b->d_tiles, plan.tiles.data(), sizeof(BatchTile) * plan.tiles.size());
+  up((void **)&b->d_order, plan.order.data(), sizeof(int32_t) * plan.order.size());
+  up((void **)&b->d_counters, nullptr, sizeof(int32_t) * std::max<size_t>(1, b->runs.size()));
+  if (e != hipSuccess) {
     delete b;
-    return set_error(ctx, ARBGPU_ENOMEM, "arbgpu_batch_create: %s", hipGetErrorString(e));
-  }
-  ctx->allocs += 3;
-  if (!tasks.empty() &&
-      ((e = hipMemcpy(b->d_tasks, tasks.data(), sizeof(DotParams) * tasks.size(), hipMemcpyHostToDevice)) !=
-           hipSuccess ||
-       (e = hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice)) !=
-           hipSuccess)) {
-    delete b;
-    return set_error(ctx, ARBGPU_EDEVICE, "arbgpu_batch_create upload: %s", hipGetErrorString(e));
+    return set_error(ctx, ARBGPU_ENOMEM, "%s: %s", who, hipGetErrorString(e));
   }
   const int rc = b->build_graph();
   if (rc) {
@@ -251,6 +326,18 @@ int arbgpu_batch_create(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njo
   }
   *batch = b;
   return ARBGPU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int arbgpu_batch_create(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, arbgpu_batch **batch) {
+  return batch_create(ctx, jobs, nullptr, njobs, batch, "arbgpu_batch_create");
+}
+
+int arbgpu_batch_create_mixed(arbgpu_ctx *ctx, const arbgpu_job *jobs, int64_t njobs, arbgpu_batch **batch) {
+  return batch_create(ctx, nullptr, jobs, njobs, batch, "arbgpu_batch_create_mixed");
 }
 
 int arbgpu_batch_launch(arbgpu_batch *b, arbgpu_stream stream) {
@@ -317,7 +404,7 @@ int arbgpu_batch_tune(arbgpu_batch *b, arbgpu_stream stream) {
 
 int arbgpu_batch_info(arbgpu_batch *b, int64_t *out, int n) {
   if (!b || !out || n < 0) return ARBGPU_EINVAL;
-  std::vector<int64_t> v = {b->njobs, b->ntasks, (int64_t)b->runs.size()};
+  std::vector<int64_t> v = {b->njobs, b->ntasks + b->ntiles, (int64_t)b->runs.size()};
   for (auto &r : b->runs) {
     v.push_back(r.sh.ns);
     v.push_back(r.sh.na);

@@ -101,13 +101,26 @@ struct KernelTimer {
   }
 };
 
+// Matrix product after validation: the INT8 path or the limb kernel.
+// Path choices of a matrix product (the autotuner's values): 0 the built-in
+// rule, then the limb kernel, base-256 slices, residues on 256 or 128 tiles.
+constexpr int kChoiceRule = 0, kChoiceLimb = 1, kChoiceSlices = 2, kChoiceRns256 = 3, kChoiceRns128 = 4;
+
+// `choice` forces a path (kChoice*); kChoiceRule takes the tuned choice of
+// the product's class when there is one, else the built-in rule.
+int mat_mul_run(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p,
+                uint32_t flags, hipStream_t s, int choice = kChoiceRule);
+
 // Scaled-integer INT8-MFMA matrix product; returns ARBGPU_OK, an error, or
 // kNotApplicable when the operands need the limb kernel (more than one
 // block under the height bound, inner length below the basecase, exponent
 // range errors to be flagged per element).
 constexpr int kNotApplicable = 100;
 int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B,
-                   int64_t p, uint32_t flags, hipStream_t s, bool forced);
+                   int64_t p, uint32_t flags, hipStream_t s, bool forced, int choice);
+// Tune-table key of a matrix product: complex or real, balls or midpoints,
+// and the ceiling base-2 logarithms of the output edge, inner length and p.
+std::string mat_mul_class(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags);
 
 // Exact integer block product over the whole inner range (arbgpu_mat_mul_exact_t).
 int exact_block_product(arbgpu_ctx *ctx, uint32_t *T_re, uint32_t *T_im, int64_t ldT, int32_t capT, int32_t *row_v2,
@@ -171,10 +184,20 @@ template <int NS, int NA>
 hipError_t launch_dot_shape(const DotParams &prm, hipStream_t s);
 hipError_t launch_limb_mm(const MmParams &prm, LimbShape sh, hipStream_t s);
 
-// Persistent batched dot kernel of one shape.
+// A tile of a matrix product in a batch: entries (i, j0 .. j0 + 63) of
+// output part `part` (an MmParams of the batch).
+struct BatchTile {
+  int32_t part;
+  int32_t pad;
+  int64_t i, j0;
+};
+
+// Persistent batched kernel of one shape.
 struct BatchShapeParams {
-  const DotParams *tasks;   // every task of the batch (device memory)
-  const int32_t *order;     // indices of this shape's tasks, longest first
+  const DotParams *tasks;   // every dot task of the batch (device memory)
+  const MmParams *mm;       // every matrix-product part of the batch
+  const BatchTile *tiles;   // every matrix-product tile of the batch
+  const int32_t *order;     // this shape's work, longest first: dot task e >= 0, tile -e - 1
   int64_t count;
   int32_t *counter;         // work counter, zero before the launch
 };

@@ -111,9 +111,9 @@ template <class AP>
 __device__ __forceinline__ arbgpu_arr pick(const AP &arr, int i) { return i ? arr[1] : arr[0]; }
 
 // Terms of output (i, j) of a matrix product.
-template <class Op>
+template <class Op, class PP = const MmParams *>
 struct MmSrc {
-  const MmParams *P;
+  PP P;
   int64_t abase, bbase;
   __device__ __forceinline__ int64_t nterms() const { return P->N * P->ct.ncomp; }
   __device__ __forceinline__ bool has_init() const { return false; }
@@ -261,8 +261,11 @@ __global__ __launch_bounds__(64) void limb_dot_kernel(DotParams prm) {
 }
 
 // Persistent batch: waves take tasks from a work counter until the list
-// of this shape is exhausted; each task is one dot output as in
-// limb_dot_kernel.  Four independent waves per workgroup.
+// of this shape is exhausted.  A task is one dot output as in
+// limb_dot_kernel (order entry e >= 0: dot task e), or a tile of 64
+// entries of one row of a matrix product, one entry per lane as in
+// limb_mm_kernel (e < 0: tile -e - 1).  Four independent waves per
+// workgroup.
 template <int NS, int NA>
 __global__ __launch_bounds__(256) void limb_dot_batch_kernel(BatchShapeParams bp) {
   const int lane = threadIdx.x & 63;
@@ -274,7 +277,28 @@ __global__ __launch_bounds__(256) void limb_dot_batch_kernel(BatchShapeParams bp
     if (t >= bp.count) break;   // uniform across the wave
     // uniform task index: the parameters are read with scalar loads
     const int tu = __builtin_amdgcn_readfirstlane(t);
-    const ARB_GLOBAL DotParams *prm = gp(bp.tasks) + gp(bp.order)[tu];
+    const int32_t e = __builtin_amdgcn_readfirstlane(gp(bp.order)[tu]);
+    if (e < 0) {
+      const BatchTile tl = gp(bp.tiles)[-e - 1];
+      const ARB_GLOBAL MmParams *mp = gp(bp.mm) + tl.part;
+      const int64_t i = tl.i, j = tl.j0 + lane;
+      if (j < mp->K) {
+        const int64_t abase = mp->a_off + i * mp->a_rs, bbase = mp->b_off + j * mp->b_cs;
+        DotOut<NS> out;
+        MmSrc<Opnd<NA>, const ARB_GLOBAL MmParams *> src{mp, abase, bbase};
+        run_dot<NS, Opnd<NA>, SoloReducer>(src, mp->p, !mp->approx, out);
+        bool fell_back = false;
+        if (out.st.bad) {
+          MmSrc<SOpnd, const ARB_GLOBAL MmParams *> s2{mp, abase, bbase};
+          run_dot<NS, SOpnd, SoloReducer>(s2, mp->p, !mp->approx, out);
+          fell_back = true;
+        }
+        store_out<NS>(mp->C, mp->c_off + i * mp->c_rs + j * mp->c_cs, out, mp->p, mp->approx,
+                      status_of(out, fell_back));
+      }
+      continue;
+    }
+    const ARB_GLOBAL DotParams *prm = gp(bp.tasks) + e;
     DotOut<NS> out;
     DotSrc<Opnd<NA>, const ARB_GLOBAL DotParams *> src{prm};
     run_dot<NS, Opnd<NA>, WaveReducer>(src, prm->p, !prm->approx, out, prm->reduce != 0);

@@ -34,15 +34,19 @@ __device__ __forceinline__ int32_t loose_mod(int32_t x, int32_t p, int32_t mu) {
 
 }  // namespace
 
-// Workgroup: 256 threads, output tile 256 x 256, wave w owns the 128 x 128
-// quarter (w / 2, w % 2) as 4 x 4 blocks of v_mfma_i32_32x32x32_i8 (lane l,
-// register r: column l % 32, row 8 (r / 4) + 4 (l / 32) + r % 4).  The
-// inner loop runs over (digit pair, 128-byte K step) with A and B tiles
-// staged through LDS, double buffered, 16-byte chunks XOR-swizzled by
-// (row >> 1) & 7, the next step's global loads spread over the current
-// step's MFMAs.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void mfma_rns_kernel(MfmaRnsParams P) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2][2][kTile * kKStep];  // [buf][A/B]
+// Workgroup: 256 threads, output tile TM x TM (256 or 128); wave w owns
+// the quarter (w / 2, w % 2) of WT = TM / 2 rows and columns as NB x NB
+// blocks of v_mfma_i32_32x32x32_i8 (lane l, register r: column l % 32,
+// row 8 (r / 4) + 4 (l / 32) + r % 4).  The inner loop runs over (digit
+// pair, 128-byte K step) with A and B tiles staged through LDS, double
+// buffered, 16-byte chunks XOR-swizzled by (row >> 1) & 7, the next step's
+// global loads spread over the current step's MFMAs.  The 128 tile keeps
+// small products from paying for a mostly empty 256 tile.
+template <int TM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, TM == 256 ? 1 : 2))) void mfma_rns_kernel(
+    MfmaRnsParams P) {
+  constexpr int WT = TM / 2, NB = WT / 32, U = TM / 32;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2][2][TM * kKStep];  // [buf][A/B]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 1, wn = wave & 1;
@@ -64,39 +68,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   const int nsteps = 4 * ksteps;
   const int64_t planeA = P.Mp * P.Kp, planeB = P.Np * P.Kp;
 
-  v16i acc[4][4];
+  v16i acc[NB][NB];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj)
+    for (int jj = 0; jj < NB; ++jj)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][jj][r] = 0;
 
   // global -> register staging: thread covers chunk (tid & 7) of rows
-  // (tid >> 3) + 32 u, u = 0..7, for A and for B (a scalar base per step
-  // plus a 32-bit lane offset; 256 rows of K_pad bytes stay below 2^31)
+  // (tid >> 3) + 32 u, u < U, for A and for B (a scalar base per step plus
+  // a 32-bit lane offset; TM rows of K_pad bytes stay below 2^31)
   const int srow = tid >> 3, schunk = tid & 7;
-  const char *tileA = reinterpret_cast<const char *>(P.A[q]) + (int64_t)2 * j * planeA + (int64_t)tm * kTile * P.Kp;
-  const char *tileB = reinterpret_cast<const char *>(P.B[q]) + (int64_t)2 * j * planeB + (int64_t)tn * kTile * P.Kp;
+  const char *tileA = reinterpret_cast<const char *>(P.A[q]) + (int64_t)2 * j * planeA + (int64_t)tm * TM * P.Kp;
+  const char *tileB = reinterpret_cast<const char *>(P.B[q]) + (int64_t)2 * j * planeB + (int64_t)tn * TM * P.Kp;
   const uint32_t goff = (uint32_t)srow * (uint32_t)P.Kp + (uint32_t)schunk * 16u;
   const uint32_t rowstep = 32u * (uint32_t)P.Kp;
-  v4i stA[8], stB[8];
+  v4i stA[U], stB[U];
   // pair pr: 0 (hi, hi'), 1 (lo, hi'), 2 (hi, lo'), 3 (lo, lo'); plane 0
   // of a prime is its low digit, plane 1 its high digit
-  auto gload = [&](v4i (&sa)[8], v4i (&sb)[8], int pr, int ks) {
+  auto gload = [&](v4i (&sa)[U], v4i (&sb)[U], int pr, int ks) {
     const int a = (pr == 0 || pr == 2) ? 1 : 0;
     const int b = pr < 2 ? 1 : 0;
     const char *pa = tileA + a * planeA + ks * kKStep;
     const char *pb = tileB + b * planeB + ks * kKStep;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < U; ++u) {
       sa[u] = *reinterpret_cast<const v4i *>(pa + (goff + u * rowstep));
       sb[u] = *reinterpret_cast<const v4i *>(pb + (goff + u * rowstep));
     }
   };
-  auto lstore = [&](const v4i (&sa)[8], const v4i (&sb)[8], int buf) {
+  auto lstore = [&](const v4i (&sa)[U], const v4i (&sb)[U], int buf) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int row = srow + 32 * u;
       *reinterpret_cast<v4i *>(&lds[buf][0][swz(row, schunk)]) = sa[u];
       *reinterpret_cast<v4i *>(&lds[buf][1][swz(row, schunk)]) = sb[u];
@@ -106,15 +110,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int chunk = kk * 2 + (lane >> 5);
-    offA[kk] = swz(wm * 128 + (lane & 31), chunk);
-    offB[kk] = swz(wn * 128 + (lane & 31), chunk);
+    offA[kk] = swz(wm * WT + (lane & 31), chunk);
+    offB[kk] = swz(wn * WT + (lane & 31), chunk);
   }
 
   gload(stA, stB, 0, 0);
   lstore(stA, stB, 0);
   __syncthreads();
   // one pipeline step: MFMAs on buffer step & 1 while the next step's
-  // tiles load; the Horner reductions sit between the three loops below
+  // tiles load
   auto run_step = [&](int step) __attribute__((always_inline)) {
     const int buf = step & 1;
     const int nstep = step + 1 < nsteps ? step + 1 : step;
@@ -124,9 +128,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     gload(stA, stB, npr, nstep - npr * ksteps);
     const uint8_t *la = lds[buf][0];
     const uint8_t *lb = lds[buf][1];
-    v4i fa[2][4], fb[2][4];
+    v4i fa[2][NB], fb[2][NB];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NB; ++i) {
       fa[0][i] = *reinterpret_cast<const v4i *>(la + offA[0] + i * 32 * kKStep);
       fb[0][i] = *reinterpret_cast<const v4i *>(lb + offB[0] + i * 32 * kKStep);
     }
@@ -135,39 +139,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       const int cur = kk & 1, nxt = cur ^ 1;
       if (kk + 1 < kKStep / 32) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < NB; ++i) {
           fa[nxt][i] = *reinterpret_cast<const v4i *>(la + offA[kk + 1] + i * 32 * kKStep);
           fb[nxt][i] = *reinterpret_cast<const v4i *>(lb + offB[kk + 1] + i * 32 * kKStep);
         }
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj)
+        for (int jj = 0; jj < NB; ++jj)
           acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[cur][i], fb[cur][jj], acc[i][jj], 0, 0, 0);
     }
     lstore(stA, stB, buf ^ 1);
     // instruction order (masks: 0x008 MFMA, 0x020 VMEM read, 0x100 DS
-    // read, 0x200 DS write): 4 of the next step's 16 global loads and the
-    // first slice's fragments first, then each slice's 16 MFMAs with the
-    // next slice's fragment reads and the other 12 loads between them, the
-    // LDS stores over the last slice
-    __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);
-    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+    // read, 0x200 DS write): a quarter of the next step's global loads and
+    // the first slice's fragments first, then each slice's MFMAs in pairs
+    // with the next slice's fragment reads and the other loads between
+    // them, the LDS stores over the last slice
+    constexpr int MF = NB * NB, GL = 2 * U, SL = 3 * MF / 2, FR = 2 * NB / (MF / 2);
+    __builtin_amdgcn_sched_group_barrier(0x020, GL / 4, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 2 * NB, 0);
 #pragma unroll
     for (int kk = 0; kk < kKStep / 32 - 1; ++kk) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < MF / 2; ++u) {
         __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-        const int sl = kk * 8 + u;
-        if ((sl + 1) * 12 / 24 > sl * 12 / 24) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, FR, 0);
+        const int sl = kk * (MF / 2) + u;   // SL slots carry the other 3 GL / 4 loads
+        const int nl = (sl + 1) * (3 * GL / 4) / SL - sl * (3 * GL / 4) / SL;
+#pragma unroll
+        for (int x = 0; x < nl; ++x) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
       }
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < MF; ++u) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x200, GL / MF > 0 ? GL / MF : 1, 0);
     }
     __syncthreads();
   };
@@ -176,13 +183,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   // next pairs add at most 2 K_pad 2^13 < 2^30 - 2^24 (K_pad < 2^16)
   auto horner = [&]() __attribute__((always_inline)) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NB; ++i)
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
+      for (int jj = 0; jj < NB; ++jj) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           // on the accumulation register itself, through two vector
-          // temporaries: left to the compiler, the 256 accumulators were
+          // temporaries: left to the compiler, all the accumulators were
           // moved to vector registers together and spilled
           int32_t acv = acc[i][jj][r], t0, t1;
           asm volatile(
@@ -196,8 +203,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
               : "s"(muj), "s"(pj));
           acc[i][jj][r] = acv;
         }
-        // one 16-register block at a time: the scheduler would otherwise
-        // move all 256 accumulators into vector registers together
+        // one block of 16 registers at a time
         __builtin_amdgcn_sched_barrier(0);
       }
   };
@@ -208,28 +214,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 
   // epilogue: x mod p_j in [-p_j, p_j) as int16 into plane (q, j).  The
   // accumulators go through LDS (free after the last step's barrier; each
-  // wave uses its own 32 KiB), one block row of 32 x 128 at a time, so that
+  // wave uses its own part), one block row of 32 x WT at a time, so that
   // every lane then reduces 8 consecutive entries of a row and writes them
-  // as one 16-byte store.  Row stride 136 words: the two lane halves of an
-  // accumulator write (rows 4 apart) fall in different bank halves.
-  const int64_t r0 = (int64_t)tm * kTile + wm * 128, c0 = (int64_t)tn * kTile + wn * 128;
+  // as one 16-byte store.  Row stride WT + 8 words: the two lane halves of
+  // an accumulator write (rows 4 apart) fall in different bank halves.
+  constexpr int RS = WT + 8, LPR = WT / 8, RP = 64 / LPR;
+  const int64_t r0 = (int64_t)tm * TM + wm * WT, c0 = (int64_t)tn * TM + wn * WT;
   int16_t *Y = P.Y + ((int64_t)q * P.m + j) * P.ds;
-  int32_t *wl = reinterpret_cast<int32_t *>(&lds[0][0][0]) + wave * (32 * 136);
-  const int rows_in = (int)min<int64_t>(P.M - r0, 128), cols_in = (int)min<int64_t>(P.N - c0, 128);
+  int32_t *wl = reinterpret_cast<int32_t *>(&lds[0][0][0]) + wave * (32 * RS);
+  const int rows_in = (int)min<int64_t>(P.M - r0, WT), cols_in = (int)min<int64_t>(P.N - c0, WT);
   const bool vec = (P.N & 7) == 0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < NB; ++i) {
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj)
+    for (int jj = 0; jj < NB; ++jj)
 #pragma unroll
       for (int r = 0; r < 16; ++r)
-        wl[((r >> 2) * 8 + 4 * (lane >> 5) + (r & 3)) * 136 + jj * 32 + (lane & 31)] = acc[i][jj][r];
+        wl[((r >> 2) * 8 + 4 * (lane >> 5) + (r & 3)) * RS + jj * 32 + (lane & 31)] = acc[i][jj][r];
     __syncthreads();
 #pragma unroll 2
-    for (int c = 0; c < 8; ++c) {
-      const int rr = (lane >> 4) + 4 * c, cc = (lane & 15) * 8;   // row in the block, first column
-      const v4i x0 = *reinterpret_cast<const v4i *>(wl + rr * 136 + cc);
-      const v4i x1 = *reinterpret_cast<const v4i *>(wl + rr * 136 + cc + 4);
+    for (int c = 0; c < 32 / RP; ++c) {
+      const int rr = lane / LPR + RP * c, cc = (lane % LPR) * 8;   // row in the block, first column
+      const v4i x0 = *reinterpret_cast<const v4i *>(wl + rr * RS + cc);
+      const v4i x1 = *reinterpret_cast<const v4i *>(wl + rr * RS + cc + 4);
       uint32_t w[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -256,12 +263,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 }
 
 hipError_t launch_mfma_rns(const MfmaRnsParams &P, hipStream_t s) {
-  if (P.mpad % 8 != 0 || P.m > P.mpad || P.nprod < 1 || P.nprod > 4 || P.N >= ((int64_t)1 << 22) ||
-      P.Kp >= ((int64_t)1 << 16) || P.Kp < kKStep || P.Kp % kKStep != 0)
+  if ((P.tile != 256 && P.tile != 128) || P.Mp % P.tile != 0 || P.Np % P.tile != 0 || P.ntm * P.tile != P.Mp ||
+      P.ntn * P.tile != P.Np || P.mpad % 8 != 0 || P.m > P.mpad || P.nprod < 1 || P.nprod > 4 ||
+      P.N >= ((int64_t)1 << 22) || P.Kp >= ((int64_t)1 << 16) || P.Kp < kKStep || P.Kp % kKStep != 0)
     return hipErrorInvalidValue;
   const int64_t n = (int64_t)P.nprod * P.mpad * P.ntm * P.ntn;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(mfma_rns_kernel, dim3((unsigned)n), dim3(256), 0, s, P);
+  if (P.tile == 256) hipLaunchKernelGGL(mfma_rns_kernel<256>, dim3((unsigned)n), dim3(256), 0, s, P);
+  else hipLaunchKernelGGL(mfma_rns_kernel<128>, dim3((unsigned)n), dim3(256), 0, s, P);
   return hipGetLastError();
 }
 

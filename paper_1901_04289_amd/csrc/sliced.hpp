@@ -204,6 +204,7 @@ struct MfmaRnsParams {
   const uint32_t *mu;        // [m] floor(2^32 / p_j)
   int nprod, m, mpad;        // mpad: m rounded up to a multiple of 8
   int64_t M, N, Mp, Np, Kp, ds;
+  int tile;                  // output tile edge: 256 or 128 (Mp, Np are multiples)
   int ntm, ntn;
 };
 hipError_t launch_mfma_rns(const MfmaRnsParams &P, hipStream_t s);

@@ -6,6 +6,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "sliced.hpp"
@@ -20,6 +23,7 @@ struct Shape {
   bool cplx, approx;
   int nparts;
   int64_t M, N, K;   // C is M x N, inner dimension K (per part)
+  int tile = 0;      // residue MFMA tile edge (0: rns_tile's choice)
 };
 
 #define ARB_TRY(expr, what)                                                                          \
@@ -129,13 +133,16 @@ const std::vector<int32_t> &rns_primes() {
 
 // Number of primes whose product exceeds 2^bits.
 int rns_count(int64_t bits) {
-  const std::vector<int32_t> &pr = rns_primes();
-  double acc = 0.0;
-  for (size_t j = 0; j < pr.size(); ++j) {
-    acc += log2((double)pr[j]);
-    if (acc > (double)bits + 1.0) return (int)j + 1;
-  }
-  return -1;
+  // cumulative log2 of the product of the first j + 1 primes, computed once
+  static const std::vector<double> cum = [] {
+    const std::vector<int32_t> &pr = rns_primes();
+    std::vector<double> c(pr.size());
+    double acc = 0.0;
+    for (size_t j = 0; j < pr.size(); ++j) c[j] = acc += log2((double)pr[j]);
+    return c;
+  }();
+  const auto it = std::upper_bound(cum.begin(), cum.end(), (double)bits + 1.0);
+  return it == cum.end() ? -1 : (int)(it - cum.begin()) + 1;
 }
 
 int64_t modinv(int64_t a, int64_t p) {   // a^-1 mod p, gcd(a, p) = 1
@@ -318,6 +325,23 @@ bool rns_better(int HA, int HB, int64_t Kt) {
   return 8 * m < (int64_t)slices_for(HA) * slices_for(HB);
 }
 
+int ceil_log2(int64_t v) {
+  int l = 0;
+  while (((int64_t)1 << l) < v) ++l;
+  return l;
+}
+
+// Output tile edge of the residue MFMA kernel for an M x N result over
+// `groups` (product, prime) pairs: 128 when it cuts the padded area by a
+// fifth or when 256 tiles would give fewer than two work items per
+// compute unit, else 256 (twice the MACs per staged byte).
+int rns_tile(int64_t M, int64_t N, int64_t groups) {
+  const int64_t a256 = round_up(std::max<int64_t>(M, 1), 256) * round_up(std::max<int64_t>(N, 1), 256);
+  const int64_t a128 = round_up(std::max<int64_t>(M, 1), 128) * round_up(std::max<int64_t>(N, 1), 128);
+  const int64_t items256 = groups * (a256 / (256 * 256));
+  return (5 * a128 < 4 * a256 || items256 < 512) ? 128 : 256;
+}
+
 // Limbs of the exact block result T for the given digit-plane counts.
 inline int t_limbs(int LA, int LB) { return (LA + LB - 1 + 3) / 4 + 2; }
 
@@ -468,9 +492,11 @@ int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
   const int64_t Kb = k1 - k0;
   const int64_t Kt = sh.cplx ? 2 * Kb : Kb;   // terms of one output value
   const int64_t Kp = round_up(std::max<int64_t>(Kb, 1), kKStep);
-  const int64_t Mp = round_up(std::max<int64_t>(sh.M, 1), kTile), Np = round_up(std::max<int64_t>(sh.N, 1), kTile);
+  const int nprod = !sh.cplx ? 1 : (four ? 4 : 3);
   const int64_t bits = t_bits(HA, HB, Kt);
   const int m = rns_count(bits);
+  const int tile = sh.tile ? sh.tile : rns_tile(sh.M, sh.N, (int64_t)nprod * ((m + 7) / 8 * 8));
+  const int64_t Mp = round_up(std::max<int64_t>(sh.M, 1), tile), Np = round_up(std::max<int64_t>(sh.N, 1), tile);
   const int W = (int)((bits + 1 + 31) / 32) + 1;
   const int LA = slices_for(HA), LB = slices_for(HB);
   const int nw = (std::max(LA, LB) + 3) / 4;
@@ -480,7 +506,6 @@ int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
   if (rc) return rc;
   // plane sets per operand: real 1; complex re, im (and re + im)
   const int nsets = !sh.cplx ? 1 : (four ? 2 : 3);
-  const int nprod = !sh.cplx ? 1 : (four ? 4 : 3);
   const int mpad = (m + 7) / 8 * 8;
   {
     const int64_t plan[10] = {2 * m, 2 * m, (int64_t)nprod * m, (int64_t)nprod * m, Kp, sh.M, sh.N, sh.nparts, m,
@@ -536,7 +561,8 @@ int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
   mp.mu = tab.mu;
   mp.nprod = nprod; mp.m = m; mp.mpad = mpad;
   mp.M = sh.M; mp.N = sh.N; mp.Mp = Mp; mp.Np = Np; mp.Kp = Kp; mp.ds = ds;
-  mp.ntm = (int)(Mp / kTile); mp.ntn = (int)(Np / kTile);
+  mp.tile = tile;
+  mp.ntm = (int)(Mp / tile); mp.ntn = (int)(Np / tile);
   {
     KernelTimer tm(ctx, "mfma", s);
     ARB_TRY(launch_mfma_rns(mp, s), "mfma");
@@ -664,6 +690,44 @@ constexpr int kBasecase = 30;   // Algorithm 2: shorter ranges use dot products
 
 }  // namespace
 
+// Largest digit-plane counts, partial planes and T limbs the base-256 form
+// can take for heights up to hmax: every height pair when the form is
+// forced, else the pairs for which the automatic choice gives this form
+// (each digit count taken at the largest height it holds, where the
+// residue form needs the most primes).  la = 0: the form is never chosen.
+struct SliceBound {
+  int64_t la, lb, nslots;
+  int tl;
+};
+
+SliceBound slice_bound(int hmax, int64_t Kt, bool forced) {
+  const int64_t Kp = round_up(std::max<int64_t>(Kt, 1), kKStep);
+  const int64_t pmax = std::max<int64_t>(1, ((int64_t)0x7FFFFFFF) / (Kp << 14));
+  const int lmax = std::min(kMaxSlices, slices_for(hmax));
+  auto nslots = [&](int64_t la, int64_t lb) { return (la + lb - 1) + la * lb / pmax; };
+  if (forced) return SliceBound{lmax, lmax, nslots(lmax, lmax), t_limbs(lmax, lmax)};
+  static std::mutex mu;
+  static std::map<std::pair<int, int64_t>, SliceBound> cache;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({hmax, Kt});
+    if (it != cache.end()) return it->second;
+  }
+  SliceBound b{0, 0, 0, 0};
+  auto top = [&](int l) { return std::min(hmax, l == 1 ? 7 : 8 * l - 2); };
+  for (int la = 1; la <= lmax; ++la)
+    for (int lb = 1; lb <= lmax; ++lb) {
+      if (rns_better(top(la), top(lb), Kt)) continue;
+      b.la = std::max<int64_t>(b.la, la);
+      b.lb = std::max<int64_t>(b.lb, lb);
+      b.nslots = std::max(b.nslots, nslots(la, lb));
+      b.tl = std::max(b.tl, t_limbs(la, lb));
+    }
+  std::lock_guard<std::mutex> lk(mu);
+  cache[{hmax, Kt}] = b;
+  return b;
+}
+
 void mat_mul_ws_sizes(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags, size_t out[]) {
   for (int k = 0; k < WS_COUNT; ++k) out[k] = 0;
   const bool cplx = flags & ARBGPU_COMPLEX;
@@ -689,16 +753,16 @@ void mat_mul_ws_sizes(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint3
     grow(WS_PLAN, 4 * nline + 16 * maxb + 4 * (maxb + 1));
   }
   if (!(flags & ARBGPU_ALGO_RNS)) {   // base-256 slices
-    const int64_t L = std::min<int64_t>(kMaxSlices, slices_for(hmax));
     const int64_t Kp = round_up(std::max<int64_t>(Kt, 1), kKStep);
-    const int64_t pmax = std::max<int64_t>(1, ((int64_t)0x7FFFFFFF) / (Kp << 14));
-    const int64_t nslots = (2 * L - 1) + L * L / pmax;
-    grow(WS_PLANES_A, L * Mp * Kp);
-    grow(WS_PLANES_B, L * Np * Kp);
-    if (cplx) grow(WS_PLANES_B2, L * Np * Kp);
-    grow(WS_D, 4 * nslots * ds);
-    grow(WS_T, 4 * (int64_t)t_limbs((int)L, (int)L) * MN);
-    grow(WS_TABLES, (int64_t)sizeof(DiagGroup) * (nslots + 8) + 4 * (2 * L));
+    const SliceBound b = slice_bound(hmax, Kt, (flags & ARBGPU_ALGO_SLICED) != 0);
+    if (b.la > 0) {
+      grow(WS_PLANES_A, b.la * Mp * Kp);
+      grow(WS_PLANES_B, b.lb * Np * Kp);
+      if (cplx) grow(WS_PLANES_B2, b.lb * Np * Kp);
+      grow(WS_D, 4 * b.nslots * ds);
+      grow(WS_T, 4 * (int64_t)b.tl * MN);
+      grow(WS_TABLES, (int64_t)sizeof(DiagGroup) * (b.nslots + 8) + 4 * (b.la + b.lb));
+    }
   }
   if (!(flags & ARBGPU_ALGO_SLICED)) {   // residues: the largest heights the form holds
     // every admissible pair of heights up to hmax: at most 4 * 127 digits
@@ -813,9 +877,10 @@ int plan_partition(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, in
 }
 
 int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p,
-                   uint32_t flags, hipStream_t s, bool forced) {
+                   uint32_t flags, hipStream_t s, bool forced, int choice) {
   Shape sh{(flags & ARBGPU_COMPLEX) != 0, (flags & ARBGPU_APPROX) != 0, (flags & ARBGPU_COMPLEX) ? 2 : 1,
            A->rows, B->cols, A->cols};
+  sh.tile = choice == kChoiceRns256 ? 256 : (choice == kChoiceRns128 ? 128 : 0);
   if (!forced && sh.K < kBasecase) return kNotApplicable;
   const int64_t Kt = sh.cplx ? 2 * sh.K : sh.K;
   if (((int64_t)0x7FFFFFFF) / (round_up(std::max<int64_t>(Kt, 1), kKStep) << 14) < 1) {
@@ -845,6 +910,8 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
   auto use_rns = [&](int ha, int hb, int64_t kt) {
     if (flags & ARBGPU_ALGO_RNS) return true;
     if (flags & ARBGPU_ALGO_SLICED) return false;
+    if (choice == kChoiceSlices) return false;
+    if (choice == kChoiceRns256 || choice == kChoiceRns128) return rns_fits(ha, hb, kt);
     return rns_better(ha, hb, kt);
   };
 
@@ -991,6 +1058,14 @@ int exact_block_product(arbgpu_ctx *ctx, uint32_t *T_re, uint32_t *T_im, int64_t
   int32_t *no_e[2] = {nullptr, nullptr};
   return block_product(ctx, A, B, sh, 0, sh.K, st, g[0], g[4], none, 0, sh.N, 1, 2, true, no_m, no_e, s, rns,
                        (flags & ARBGPU_COMPLEX_4M) != 0, &ts);
+}
+
+std::string mat_mul_class(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags) {
+  const bool cplx = flags & ARBGPU_COMPLEX;
+  const bool rad = !(flags & ARBGPU_APPROX) && (A->re.rad_m || B->re.rad_m || (cplx && (A->im.rad_m || B->im.rad_m)));
+  return std::string("mat_mul:") + (cplx ? "c" : "r") + (rad ? "b" : "m") + ":n" +
+         std::to_string(ceil_log2(std::max(A->rows, B->cols))) + ":k" + std::to_string(ceil_log2(A->cols)) + ":p" +
+         std::to_string(ceil_log2(p));
 }
 
 }  // namespace arbgpu_impl

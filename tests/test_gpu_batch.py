@@ -278,3 +278,58 @@ def test_batch_long_dots_that_cancel(ctx):
         m, rad = gen.to_canonical(host, k)
         assert m[1] == 1 and rad is None   # exactly the tiny term, zero radius
     b.close()
+
+
+def test_mixed_batch_of_dots_and_small_matmuls(ctx):
+    # one graph launch: 120 dot jobs and 60 small complex ball matrix
+    # products of uneven size and precision (tiles of 64 entries of a row
+    # on the limb kernel, queued with the dots of their kernel shape)
+    import torch
+    specs, inits = random_jobs(4, 120)
+    outs = [arbgpu.DeviceOut.empty(len(specs), 1100), arbgpu.DeviceOut.empty(len(specs), 1100)]
+    jobs = [arbgpu.dot_request(j) for j in make_jobs(specs, inits, outs)]
+    r = random.Random(5)
+    rng = gen.rng_for(44, 0)
+    mms = []
+    for k in range(60):
+        M, N, K = r.randint(1, 40), r.randint(1, 70), r.randint(1, 90)
+        p = r.choice([30, 64, 128, 256, 400])
+        host = [gen.random_operands(rng, c, rng.integers(1, p + 20, c), -10, 10, radius_shift=p, zero_frac=0.05)
+                for c in (M * N, M * N, N * K, N * K)]
+        dev = [arbgpu.DeviceArray.from_host(h) for h in host]
+        C = [arbgpu.DeviceOut.empty(M * K, p), arbgpu.DeviceOut.empty(M * K, p)]
+        Cr = [arbgpu.DeviceOut.empty(M * K, p), arbgpu.DeviceOut.empty(M * K, p)]
+        am = arbgpu.Mat(dev[0].arr(), dev[1].arr(), M, N, 0, N, 1)
+        bm = arbgpu.Mat(dev[2].arr(), dev[3].arr(), N, K, 0, K, 1)
+        cm = arbgpu.OMat(C[0].out(), C[1].out(), M, K, 0, K, 1)
+        crm = arbgpu.OMat(Cr[0].out(), Cr[1].out(), M, K, 0, K, 1)
+        ctx.mat_mul_raw(crm, am, bm, p, arbgpu.COMPLEX | arbgpu.ALGO_LIMB)
+        jobs.append(arbgpu.matmul_job(cm, am, bm, p, arbgpu.COMPLEX))
+        mms.append((M, N, K, p, host, dev, C, Cr))
+    r.shuffle(jobs)
+    say(f"mixed batch: {len(jobs)} jobs")
+    b = arbgpu.Batch(ctx, jobs, mixed=True)
+    info = b.info()
+    ntiles = sum(2 * M * ((K + 63) // 64) for (M, N, K, *_) in mms)
+    assert info["tasks"] == sum(2 if s["cplx"] else 1 for s in specs) + ntiles
+    b.tune()
+    b.launch()
+    _sync()
+    check_jobs(specs, inits, [o.to_host() for o in outs])
+    for (M, N, K, p, host, dev, C, Cr) in mms:
+        got = [c.to_host() for c in C]
+        ref = [c.to_host() for c in Cr]
+        for (a, sa), (c, sc) in zip(got, ref):
+            assert np.array_equal(a.limbs, c.limbs) and np.array_equal(a.exp, c.exp)
+            assert np.array_equal(a.nls, c.nls) and np.array_equal(sa, sc)
+            assert np.array_equal(a.rad_m, c.rad_m) and np.array_equal(a.rad_e, c.rad_e)
+    # and sampled entries of a few products against the oracle
+    for (M, N, K, p, host, dev, C, Cr) in mms[:8]:
+        (o_re, s_re), (o_im, s_im) = C[0].to_host(), C[1].to_host()
+        i, j = r.randrange(M), r.randrange(K)
+        x = [(gen.to_canonical(host[0], i * N + k), gen.to_canonical(host[1], i * N + k)) for k in range(N)]
+        y = [(gen.to_canonical(host[2], k * K + j), gen.to_canonical(host[3], k * K + j)) for k in range(N)]
+        wre, wim = oracle.cdot(x, y, p)
+        assert compare_entry(gen.to_canonical(o_re, i * K + j), wre, int(s_re[i * K + j])) is None
+        assert compare_entry(gen.to_canonical(o_im, i * K + j), wim, int(s_im[i * K + j])) is None
+    b.close()

@@ -157,8 +157,10 @@ def test_admission_by_footprint(ctx):
     assert rc == arbgpu.ENOMEM
     say("admission: measuring the footprint")
     one = None
+    # one slot: it holds the whole budget, so a job is admitted alone once
+    # its footprint fits the budget
     for mib in (256, 512, 1024, 2048, 4096, 8192, 16384):
-        ctx.serve_config(slots=2, budget=mib << 20)
+        ctx.serve_config(slots=1, budget=mib << 20)
         rc, t = ctx.submit([big.job()], check=False)
         if rc == arbgpu.OK:
             one = mib
@@ -167,7 +169,7 @@ def test_admission_by_footprint(ctx):
     assert one is not None
     # the footprint lies in (one/2, one] MiB: a budget of `one` holds one
     # of these products but not two
-    ctx.serve_config(slots=2, budget=one << 20)
+    ctx.serve_config(slots=1, budget=one << 20)
     t1 = ctx.submit([big.job()])
     rc, t2 = ctx.submit([other.job()], check=False)
     if rc == arbgpu.OK:

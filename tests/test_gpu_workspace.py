@@ -95,7 +95,9 @@ def test_footprint_bounds_the_workspace(n, p, cplx):
     pr.run(ctx)
     allocs, held = ctx.workspace_info()
     say(f"n={n} p={p} complex={cplx}: footprint {fp}, held {held} in {allocs} buffers")
-    assert 0 < held <= fp
+    assert held <= fp
+    if n >= 30:   # shorter inner lengths take the limb kernel, which needs no workspace
+        assert held > 0
     ctx.close()
 
 
