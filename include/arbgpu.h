@@ -186,6 +186,22 @@ int arbgpu_mat_mul_exact_t(arbgpu_ctx *ctx, uint32_t *T_re, uint32_t *T_im, int6
                            const arbgpu_mat *A, const arbgpu_mat *B, uint32_t flags,
                            arbgpu_stream stream);
 
+/* For callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * product of arbgpu_mat_mul, with the same arguments, results and errors,
+ * whose workspace is cut from one static 256 MiB device array instead of
+ * the context's buffers; it calls no device allocation or free.  Products
+ * whose footprint (arbgpu_mat_mul_footprint) exceeds 256 MiB are rejected
+ * with EINVAL before any work; a product that splits into several blocks
+ * fails with ENOMEM when its exact block values do not fit what is left.
+ * Each device holds its own copy of the array until the process ends, and
+ * every call on a device shares it: calls that overlap on one device
+ * (other streams, threads or contexts) race.  It keeps the last call's
+ * contents; each call sets up what it reads.  Not for device -1. */
+int arbgpu_mat_mul_noalloc(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A,
+                           const arbgpu_mat *B, int64_t p, uint32_t flags,
+                           arbgpu_stream stream);
+
 /* Workspace.  Each context keeps device workspace buffers that grow to
  * the largest call made so far (never beyond its HBM budget) and are
  * reused by later calls; growing one waits for the work the context has

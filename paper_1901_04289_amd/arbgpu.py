@@ -84,6 +84,8 @@ EXPORTS = {
                                       c_i64, c_u32, c_p]),
     "arbgpu_mat_mul_exact_t": (ctypes.c_int, [c_p, c_p, c_p, c_i64, c_i32, c_p, c_p, ctypes.POINTER(Mat),
                                               ctypes.POINTER(Mat), c_u32, c_p]),
+    "arbgpu_mat_mul_noalloc": (ctypes.c_int, [c_p, ctypes.POINTER(OMat), ctypes.POINTER(Mat), ctypes.POINTER(Mat),
+                                              c_i64, c_u32, c_p]),
     "arbgpu_tune_mat_mul": (ctypes.c_int, [c_p, ctypes.POINTER(OMat), ctypes.POINTER(Mat), ctypes.POINTER(Mat),
                                            c_i64, c_u32, c_p, ctypes.POINTER(c_i32)]),
     "arbgpu_reserve": (ctypes.c_int, [c_p, ctypes.POINTER(Mat), ctypes.POINTER(Mat), c_i64, c_u32]),
@@ -310,6 +312,13 @@ class Context:
                                              ldT, capT, ctypes.c_void_p(row_v2.data_ptr()),
                                              ctypes.c_void_p(col_v2.data_ptr()), ctypes.byref(A),
                                              ctypes.byref(B), flags,
+                                             _stream_handle(stream) if self.device >= 0 else None)
+        return self._check(rc) if check else rc
+
+    def mat_mul_noalloc_raw(self, C: OMat, A: Mat, B: Mat, p: int, flags: int = 0, stream=None,
+                            check: bool = True) -> int:
+        """arbgpu_mat_mul with its workspace in the library's static scratch."""
+        rc = self.lib.arbgpu_mat_mul_noalloc(self.h, ctypes.byref(C), ctypes.byref(A), ctypes.byref(B), p, flags,
                                              _stream_handle(stream) if self.device >= 0 else None)
         return self._check(rc) if check else rc
 

@@ -21,6 +21,7 @@ using namespace arbgpu_impl;
 
 arbgpu_ctx::~arbgpu_ctx() {
   if (server) arbgpu_impl::server_delete(server);
+  delete noalloc_view;
   for (auto &t : timed) {
     (void)hipEventDestroy(t.start);
     (void)hipEventDestroy(t.stop);
@@ -89,6 +90,19 @@ void *ws_get(arbgpu_ctx *ctx, int slot, size_t bytes) {
   arbgpu_ctx::Buf &b = ctx->ws[slot];
   if (bytes == 0) bytes = 256;
   if (b.size >= bytes) return b.ptr;
+  if (ctx->bump_base) {
+    const size_t off = (ctx->bump_top + 255) & ~(size_t)255;
+    if (off > ctx->bump_size || bytes > ctx->bump_size - off) {
+      set_error(ctx, ARBGPU_ENOMEM, "the call needs more than the %zu bytes of its fixed scratch", ctx->bump_size);
+      return nullptr;
+    }
+    b.ptr = ctx->bump_base + off;
+    b.size = bytes;
+    b.owned = false;
+    ctx->bump_top = off + bytes;
+    if (slot == WS_RNS) ctx->rns_key = -1;   // a new place: the tables are uploaded again
+    return b.ptr;
+  }
   if (ctx->ws_fixed) {
     set_error(ctx, ARBGPU_ENOMEM, "workspace slot %d holds %zu bytes, the call needs %zu (fixed workspace)", slot,
               b.size, bytes);
@@ -311,6 +325,16 @@ int arbgpu_init(arbgpu_ctx **ctx, int device, size_t hbm_budget_bytes, const cha
       size_t fr = 0, tot = 0;
       if (hipMemGetInfo(&fr, &tot) == hipSuccess) c->budget = fr / 4 * 3;
     }
+    // the allocation-free entry point's scratch address on this device, and
+    // the context its calls run on
+    c->noalloc_view = new (std::nothrow) arbgpu_ctx;
+    if (!c->noalloc_view || noalloc_setup(device) != ARBGPU_OK) {
+      delete c;
+      return ARBGPU_EDEVICE;
+    }
+    c->noalloc_view->device = device;
+    c->noalloc_view->budget = 0;
+    c->noalloc_view->ws.resize(WS_COUNT);
   }
   *ctx = c;
   return ARBGPU_OK;
@@ -539,6 +563,36 @@ int arbgpu_plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B
   if (A->cols == 0) return ARBGPU_OK;
   if ((rc = bind_device(ctx, stream))) return rc;
   return plan_partition(ctx, A, B, p, flags, to_stream(stream), bounds, kinds, max_blocks, nblocks);
+}
+
+int arbgpu_mat_mul_noalloc(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B,
+                           int64_t p, uint32_t flags, arbgpu_stream stream) {
+  if (!ctx) return ARBGPU_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  int rc = mat_mul_check(ctx, C, A, B, p, flags);
+  if (rc) return rc;
+  if (C->rows == 0 || C->cols == 0) return ARBGPU_OK;
+  if ((rc = bind_device(ctx, stream))) return rc;
+  const size_t need = mat_mul_footprint(A, B, p, flags), have = noalloc_scratch_bytes();
+  if (need > have)
+    return fail(ctx, ARBGPU_EINVAL,
+                "arbgpu_mat_mul_noalloc: the product may take %zu bytes of workspace; the fixed scratch holds %zu",
+                need, have);
+  char *base = noalloc_scratch(ctx->device);
+  arbgpu_ctx *v = ctx->noalloc_view;
+  if (!base || !v) return fail(ctx, ARBGPU_EDEVICE, "arbgpu_mat_mul_noalloc: no scratch on device %d", ctx->device);
+  // every buffer of this call is cut afresh from the scratch, whose
+  // contents the previous call left: the residue tables are uploaded again
+  for (auto &b : v->ws) b = arbgpu_ctx::Buf{nullptr, 0, false};
+  v->bump_base = base;
+  v->bump_size = have;
+  v->bump_top = 0;
+  v->rns_key = -1;
+  v->err.clear();
+  rc = mat_mul_run(v, C, A, B, p, flags, to_stream(stream));
+  if (rc) ctx->err = v->err;
+  memcpy(ctx->last_plan, v->last_plan, sizeof ctx->last_plan);
+  return rc;
 }
 
 int arbgpu_tune_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p,

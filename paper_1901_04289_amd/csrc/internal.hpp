@@ -33,6 +33,14 @@ struct arbgpu_ctx {
   int64_t allocs = 0;
   // no workspace growth: a call that needs more fails with ENOMEM
   bool ws_fixed = false;
+  // carve mode: every workspace buffer of a call is cut, in request order,
+  // from [bump_base, bump_base + bump_size) (memory the context does not
+  // own); bump_top is the next free offset
+  char *bump_base = nullptr;
+  size_t bump_size = 0, bump_top = 0;
+  // the context arbgpu_mat_mul_noalloc runs its calls on (carve mode over
+  // the device's static scratch); created with a device context
+  arbgpu_ctx *noalloc_view = nullptr;
   // streams this context has enqueued work on since the workspace last
   // grew; growth waits for them (and only them) before freeing a buffer
   std::vector<hipStream_t> streams_seen;
@@ -100,6 +108,13 @@ struct KernelTimer {
     }
   }
 };
+
+// The static scratch of the allocation-free entry point (noalloc.hip):
+// its size, the once-per-device lookup of its address (with the device
+// current) and that address (nullptr before the lookup).
+size_t noalloc_scratch_bytes();
+int noalloc_setup(int device);
+char *noalloc_scratch(int device);
 
 // Matrix product after validation: the INT8 path or the limb kernel.
 // Path choices of a matrix product (the autotuner's values): 0 the built-in
