@@ -47,7 +47,7 @@ PEAK_INT8_TOPS = 5000.0   # MI355X dense INT8 MFMA, 5.0 POP/s
 MFMA_KERNEL = {"residues": "mfma_rns_kernel<256>", "slices": "mfma_diag_kernel"}
 MFMA_TRAFFIC = {
     # form: (kernel source, sha256 prefix, bytes per launch)
-    "residues": ("mfma_rns.hip", None, None),
+    "residues": ("mfma_rns.hip", "f01cea3055db3e34", (1777060 * 2 + 645248) * 1024.0),
     "slices": ("mfma.hip", "ef1395843d68b766", (30267872 * 2 + 2228224) * 1024.0),
 }
 
