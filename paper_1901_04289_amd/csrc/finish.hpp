@@ -77,4 +77,43 @@ __device__ __forceinline__ void finish_entry(const Get &get, int nT, int64_t sca
   if (C.status) C.status[oidx] = ARBGPU_ST_OK;
 }
 
+// Whether truncating T' (limbs via get) to p bits is also the truncation of
+// every T with |T - T'| < 2^ebits: with bl the bit length of |T'| and
+// u = bl - p, the dropped bits D = |T'| mod 2^u must keep the interval
+// (|T'| - 2^ebits, |T'| + 2^ebits) strictly inside one cell (H 2^u,
+// (H + 1) 2^u) of the truncation grid; bits [ebits + 1, u) of |T'| being
+// neither all zero nor all one gives 2^(ebits+1) <= D <= 2^u - 2^(ebits+1) - 1.
+// Then |T| has the same bit length and leading p bits, and is inexact.
+template <class Get>
+__device__ __forceinline__ bool certify_truncation(const Get &get, int nT, int p, int ebits) {
+  const bool neg = (get(nT - 1) >> 31) != 0;
+  int z = nT;
+  for (int q = 0; q < nT; ++q)
+    if (get(q)) { z = q; break; }
+  auto mag = [&](int q) -> uint32_t {
+    if (q < 0 || q >= nT) return 0u;
+    const uint32_t v = get(q);
+    if (!neg) return v;
+    return q > z ? ~v : (q == z ? (uint32_t)(0u - v) : 0u);
+  };
+  int qt = -1;
+  for (int q = nT - 1; q >= 0; --q)
+    if (mag(q)) { qt = q; break; }
+  if (qt < 0) return false;
+  const int64_t bl = 32 * (int64_t)qt + (32 - __builtin_clz(mag(qt)));
+  const int64_t u = bl - p, lo = (int64_t)ebits + 1;
+  if (u < lo + 2) return false;
+  bool any1 = false, any0 = false;
+  for (int64_t b = lo; b < u && !(any1 && any0);) {
+    const int q = (int)(b >> 5), r = (int)(b & 31);
+    const int n = (int)((u - b) < (32 - r) ? (u - b) : (32 - r));
+    const uint32_t mask = (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u)) << r;
+    const uint32_t v = mag(q) & mask;
+    any1 |= v != 0;
+    any0 |= v != mask;
+    b += n;
+  }
+  return any1 && any0;
+}
+
 }  // namespace arbgpu_impl

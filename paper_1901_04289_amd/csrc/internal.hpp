@@ -193,11 +193,28 @@ struct LimbShape {
 };
 
 bool limb_shape_for(int p, int64_t nterms, int cap, LimbShape *out);
+// Dot products beyond every compiled window: the LDS-window kernel
+// (wide.hip), one workgroup per output, up to wide_max_precision() bits.
+// A LimbShape of {0, 0} stands for it.
+int wide_max_precision();
+int wide_max_limbs();   // operand limbs the LDS staging holds
+hipError_t launch_wide_dot(const DotParams &prm, hipStream_t s);
+hipError_t launch_wide_dot_batch(const DotParams *tasks, const int32_t *order, int64_t count, hipStream_t s);
+// the batch kernel (arguments: tasks, order; one workgroup per listed task)
+// and its dynamic LDS
+const void *wide_dot_batch_kernel_ptr(size_t *lds_bytes);
 template <int NS, int NA>
 hipError_t launch_mm_shape(const MmParams &prm, hipStream_t s);
 template <int NS, int NA>
 hipError_t launch_dot_shape(const DotParams &prm, hipStream_t s);
+template <int NS, int NA>
+hipError_t launch_mm_list_shape(const MmParams &prm, const int64_t *list, const int32_t *count, int64_t max_count,
+                                hipStream_t s);
 hipError_t launch_limb_mm(const MmParams &prm, LimbShape sh, hipStream_t s);
+// The entries listed in list[0 .. *count) (device memory, *count <=
+// max_count), by index i K + j, on the limb kernel.
+hipError_t launch_limb_mm_list(const MmParams &prm, LimbShape sh, const int64_t *list, const int32_t *count,
+                               int64_t max_count, hipStream_t s);
 
 // A tile of a matrix product in a batch: entries (i, j0 .. j0 + 63) of
 // output part `part` (an MmParams of the batch).

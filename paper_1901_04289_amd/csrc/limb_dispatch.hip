@@ -42,6 +42,15 @@ hipError_t launch_limb_mm(const MmParams &prm, LimbShape sh, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_limb_mm_list(const MmParams &prm, LimbShape sh, const int64_t *list, const int32_t *count,
+                               int64_t max_count, hipStream_t s) {
+#define X(a, b) \
+  if (sh.ns == a && sh.na == b) return launch_mm_list_shape<a, b>(prm, list, count, max_count, s);
+  ARB_LIMB_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
 const void *dot_batch_kernel(LimbShape sh) {
 #define X(a, b) \
   if (sh.ns == a && sh.na == b) return dot_batch_kernel_shape<a, b>();

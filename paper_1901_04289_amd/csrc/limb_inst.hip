@@ -1,6 +1,8 @@
 // One (window limbs, operand limbs) instantiation of the limb kernels.
 // Built once per shape with -DARB_NS=<window limbs> -DARB_NA=<operand limbs>
 // so the shapes compile in parallel.
+#include <algorithm>
+
 #include "limb_kernels.hpp"
 
 #if !defined(ARB_NS) || !defined(ARB_NA)
@@ -14,6 +16,15 @@ hipError_t launch_mm_shape<ARB_NS, ARB_NA>(const MmParams &prm, hipStream_t s) {
   const int64_t blocks = ((prm.K + 63) / 64) * ((prm.M + 3) / 4);
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL((limb_mm_kernel<ARB_NS, ARB_NA>), dim3((unsigned)blocks), dim3(256), 0, s, prm);
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_mm_list_shape<ARB_NS, ARB_NA>(const MmParams &prm, const int64_t *list, const int32_t *count,
+                                                int64_t max_count, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((max_count + 255) / 256, 1024);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((limb_mm_list_kernel<ARB_NS, ARB_NA>), dim3((unsigned)blocks), dim3(256), 0, s, prm, list, count);
   return hipGetLastError();
 }
 

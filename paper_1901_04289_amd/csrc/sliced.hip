@@ -271,6 +271,10 @@ __global__ __launch_bounds__(256) void recombine_kernel(RecombParams P) {
   T[(int64_t)(nq + 1) * MN] = (uint32_t)((uint64_t)carry >> 32);
   const int nT = nq + 2;
   if (!P.C.exp) return;   // the exact T only
+  if (P.ebits >= 0 && !certify_truncation([&](int q) { return T[(int64_t)q * MN]; }, nT, P.p, P.ebits)) {
+    P.fb_list[atomicAdd(P.fb_count, 1)] = ij;   // recomputed exactly by the limb kernel
+    return;
+  }
 
   double m0 = 0.0;
   int e0 = 0;

@@ -72,6 +72,13 @@ struct RecombParams {
   int approx;
   const double *rin_m;     // propagated radius per entry (nullable)
   const int32_t *rin_e;
+  // truncated diagonal set: ebits >= 0 when the diagonals below some c0
+  // were left out, their sum below 2^ebits in magnitude; an entry whose
+  // truncation this does not certify goes to fb_list (count fb_count) for
+  // the exact per-entry product
+  int ebits;
+  int64_t *fb_list;
+  int32_t *fb_count;
 };
 
 struct RadPrepParams {
@@ -233,7 +240,7 @@ struct PlanParams {
   int64_t a_off, a_rs, a_cs, b_off, b_rs, b_cs;
   int hmax;                 // largest admissible integer height (floor of h)
   int basecase;             // shorter blocks become dot-product chunks
-  int32_t *rtop, *rlow, *ctop, *clow;   // per-line running state [M], [N]
+  int2 *hlA, *hlB;          // (top exponent, lowest set bit) per element: A [inner][M], B [inner][N]
   int64_t *bounds;          // [2 * max_blocks]
   int32_t *kinds;           // [max_blocks]: 0 block, 1 basecase
   int64_t max_blocks;
@@ -259,16 +266,32 @@ struct MergeParams {
 };
 
 // One inner-index range of the partition: kind 0 is a scaled-integer block,
-// kind 1 a basecase chunk evaluated term by term.
+// kind 1 a basecase chunk evaluated term by term; ha, hb are the largest
+// row and column heights over the range.
 struct BlockSpan {
   int64_t k0, k1;
   int32_t kind;
+  int32_t ha, hb;
 };
 
-// Greedy partition of the inner range under the integer height bound hmax
-// (synchronizes s to read the result back).
+// Greedy partition of the inner range under the integer height bound hmax,
+// with every block's line statistics (synchronizes s to read the result
+// back): block b's statistics, laid out as line_stats leaves them (rtop[M],
+// rv2[M], ctop[N], cv2[N], gA[4], gB[4]), start at *stats + b * stride.
 int plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, bool cplx, int hmax, hipStream_t s,
-                std::vector<BlockSpan> &out);
+                std::vector<BlockSpan> &out, int32_t **stats = nullptr, int64_t *stride = nullptr);
+
+// Per-block line statistics from the planner's element table.
+struct BlockStatsParams {
+  const int2 *hlA, *hlB;
+  int64_t M, N;
+  const int64_t *bounds;    // [2 nb] (k0, k1) per block
+  const int32_t *nblocks;
+  int64_t max_blocks;
+  int32_t *out;             // [max_blocks][stride]
+  int64_t stride;
+};
+hipError_t launch_block_stats(const BlockStatsParams &P, hipStream_t s);
 
 // Line-major copy (limbs, exponents, counts) of an operand block.
 struct GatherParams {

@@ -361,10 +361,15 @@ int t_to_sink(arbgpu_ctx *ctx, const TSink *ts, int q, const uint32_t *T, int n,
   return ARBGPU_OK;
 }
 
+// Headroom of the truncated diagonal set: the left-out diagonals stay
+// below 2^(bits of |T|'s bound - p - kTruncSlack), so every entry within
+// kTruncSlack - 3 bits of that bound certifies its truncation.
+constexpr int kTruncSlack = 64;
+
 int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const Shape &sh, int64_t k0, int64_t k1,
                   const int32_t *st, int HA, int HB, const arbgpu_out *out, int64_t o_off, int64_t o_rs, int64_t o_cs,
                   int p, bool out_approx, double *const rin_m[2], int32_t *const rin_e[2], hipStream_t s,
-                  bool rns, bool four = false, const TSink *ts = nullptr) {
+                  bool rns, bool four = false, const TSink *ts = nullptr, bool trunc = false) {
   if (rns)
     return rns_block_product(ctx, A, B, sh, k0, k1, st, HA, HB, out, o_off, o_rs, o_cs, p, out_approx, rin_m, rin_e,
                              s, four, ts);
@@ -377,14 +382,37 @@ int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, con
   const int64_t Mp = round_up(std::max<int64_t>(sh.M, 1), kTile), Np = round_up(std::max<int64_t>(sh.N, 1), kTile);
   const int LA = slices_for(HA), LB = slices_for(HB);
 
-  // diagonal groups of at most pmax slice pairs, each one exact int32 plane
   const int Lc = LA + LB - 1;
+  // The truncated diagonal set (the slice-pair analogue of the products
+  // truncated below the window, Section 3.4): the diagonals c < c0, whose
+  // total sum_{c < c0} 256^c D_c (|D_c| <= pairs_c K_pad 2^14) stays below
+  // 2^ebits, are left out when that is far below the p bits the output
+  // keeps; the recombination certifies each entry's truncation against
+  // 2^ebits, and entries it cannot certify are recomputed exactly.
+  int c0 = 0, ebits = -1;
+  LimbShape fb_shape{0, 0};
+  if (trunc && !ts) {
+    int cap = std::max(A->re.cap, B->re.cap);
+    if (sh.cplx) cap = std::max(cap, std::max(A->im.cap, B->im.cap));
+    const int64_t limit = t_bits(HA, HB, Kt) - p - kTruncSlack;
+    double sc = 0.0;   // sum_{c' <= c} pairs_c' 256^(c' - c)
+    for (int c = 0; c < Lc && limit > 0 && limb_shape_for(p, sh.K * sh.nparts, cap, &fb_shape); ++c) {
+      const int np = std::min(c, LA - 1) + 1 - std::max(0, c - LB + 1);
+      sc = sc / 256.0 + (double)np;
+      const int64_t eb = (int64_t)floor(8.0 * c + log2(sc) + log2((double)Kp) + 14.0) + 2;
+      if (eb > limit) break;
+      c0 = c + 1;
+      ebits = (int)eb;
+    }
+  }
+  // diagonal groups of at most pmax slice pairs, each one exact int32 plane
   std::vector<DiagGroup> groups;
   std::vector<int32_t> slot_of(Lc + 1, 0);
   int nslots = 0;
   for (int c = 0; c < Lc; ++c) {
     const int lo = std::max(0, c - LB + 1), hi = std::min(c, LA - 1) + 1;
     slot_of[c] = nslots;
+    if (c < c0) continue;
     const int np = hi - lo;
     const int nch = (int)((np + pmax - 1) / pmax);
     const int per = (np + nch - 1) / nch;   // balanced chunks
@@ -397,7 +425,9 @@ int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, con
   while (groups.size() % 8) groups.push_back(DiagGroup{0, 0, 0, -1});   // padding for the XCD mapping
   const int nT = t_limbs(LA, LB);
   {
-    const int64_t plan[10] = {LA, LB, nslots, ngroups_real, Kt, sh.M, sh.N, sh.nparts, 0, (int64_t)LA * LB};
+    int64_t pairs = 0;
+    for (const DiagGroup &g : groups) pairs += g.a1 - g.a0;
+    const int64_t plan[10] = {LA, LB, nslots, ngroups_real, Kt, sh.M, sh.N, sh.nparts, 0, pairs};
     memcpy(ctx->last_plan, plan, sizeof plan);
   }
 
@@ -408,11 +438,15 @@ int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, con
   const int64_t ds = plane_stride(sh.M * sh.N);
   int32_t *D = (int32_t *)ws_get(ctx, WS_D, sizeof(int32_t) * (size_t)nslots * ds);
   uint32_t *T = (uint32_t *)ws_get(ctx, WS_T, sizeof(uint32_t) * (size_t)nT * sh.M * sh.N);
+  // tables, then (truncated set) the fallback counter and entry list
   const size_t tab_bytes = sizeof(DiagGroup) * groups.size() + sizeof(int32_t) * slot_of.size();
-  char *tabs = (char *)ws_get(ctx, WS_TABLES, tab_bytes);
+  const size_t fb_off = (tab_bytes + 7) & ~(size_t)7;
+  char *tabs = (char *)ws_get(ctx, WS_TABLES, fb_off + (ebits >= 0 ? 8 + 8 * (size_t)sh.M * sh.N : 0));
   if (!planesA || !planesB || (sh.cplx && !planesB2) || !D || !T || !tabs) return ARBGPU_ENOMEM;
   DiagGroup *dgroups = (DiagGroup *)tabs;
   int32_t *dslot = (int32_t *)(tabs + sizeof(DiagGroup) * groups.size());
+  int32_t *fb_count = ebits >= 0 ? (int32_t *)(tabs + fb_off) : nullptr;
+  int64_t *fb_list = ebits >= 0 ? (int64_t *)(tabs + fb_off + 8) : nullptr;
   ARB_TRY(hipMemcpyAsync(dgroups, groups.data(), sizeof(DiagGroup) * groups.size(), hipMemcpyHostToDevice, s),
           "table upload");
   ARB_TRY(hipMemcpyAsync(dslot, slot_of.data(), sizeof(int32_t) * slot_of.size(), hipMemcpyHostToDevice, s),
@@ -467,9 +501,31 @@ int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, con
     rp.approx = out_approx;
     rp.rin_m = rin_m[q];
     rp.rin_e = rin_e[q];
+    rp.ebits = ebits;
+    rp.fb_list = fb_list;
+    rp.fb_count = fb_count;
+    if (fb_count) ARB_TRY(launch_fill_i32(fb_count, 0, 1, s), "fill");
     {
       KernelTimer tr(ctx, "recombine", s);
       ARB_TRY(launch_recombine(rp, s), "recombine");
+    }
+    if (fb_count) {   // the entries whose truncation was not certified, exactly
+      MmParams mm;
+      memset(&mm, 0, sizeof mm);
+      mm.A[0] = A->re;
+      mm.A[1] = sh.cplx ? A->im : A->re;
+      mm.B[0] = B->re;
+      mm.B[1] = sh.cplx ? B->im : B->re;
+      mm.C = out[q];
+      mm.M = sh.M; mm.N = sh.K; mm.K = sh.N;
+      mm.a_off = A->off; mm.a_rs = A->rs; mm.a_cs = A->cs;
+      mm.b_off = B->off; mm.b_rs = B->rs; mm.b_cs = B->cs;
+      mm.c_off = o_off; mm.c_rs = o_rs; mm.c_cs = o_cs;
+      mm.p = p;
+      mm.approx = out_approx;
+      mm.ct = !sh.cplx ? comp_real() : (q == 0 ? comp_re() : comp_im());
+      KernelTimer tf(ctx, "fallback", s);
+      ARB_TRY(launch_limb_mm_list(mm, fb_shape, fb_list, fb_count, sh.M * sh.N, s), "fallback");
     }
     int rc = t_to_sink(ctx, ts, q, T, nT, sh.M * sh.N, s);
     if (rc) return rc;
@@ -688,6 +744,29 @@ int height_bound(int64_t p, int pA, int pB) {
 
 constexpr int kBasecase = 30;   // Algorithm 2: shorter ranges use dot products
 
+// Cost estimates (seconds) of one block of the partition, for the choice
+// between its integer product and its terms in the merge: a fixed cost of
+// the integer product's launches and host round trips, its MFMA work and
+// the exact block values it writes, against window-engine products of the
+// operand limbs that reach the window (about 3 ps per 32 x 32 limb product
+// per output entry at these sizes).
+double block_cost_int8(const Shape &sh, const BlockSpan &b, int p) {
+  const int64_t Kb = b.k1 - b.k0, Kt = sh.cplx ? 2 * Kb : Kb, MN = sh.M * sh.N;
+  const int64_t bits = t_bits(b.ha, b.hb, Kt);
+  const int64_t pairs = rns_better(b.ha, b.hb, Kt) ? 4 * (int64_t)rns_count(bits) * (sh.cplx ? 3 : 1)
+                                                  : (int64_t)slices_for(b.ha) * slices_for(b.hb) * sh.nparts;
+  const double W = (double)(bits + 63) / 32.0;
+  (void)p;
+  return 60e-6 + 2.0 * (double)pairs * (double)MN * (double)Kb / 1.5e15 + (double)MN * sh.nparts * 8.0 * W / 1.5e12;
+}
+
+double block_cost_base(const Shape &sh, const BlockSpan &b, int p, const arbgpu_mat *A, const arbgpu_mat *B) {
+  int cap = std::max(A->re.cap, B->re.cap);
+  if (sh.cplx) cap = std::max(cap, std::max(A->im.cap, B->im.cap));
+  const double w = (double)std::min<int64_t>(cap, (p + 64 + 31) / 32);
+  return (double)(sh.M * sh.N) * (double)(b.k1 - b.k0) * (sh.cplx ? 4.0 : 1.0) * w * w * 3e-12;
+}
+
 }  // namespace
 
 // Largest digit-plane counts, partial planes and T limbs the base-256 form
@@ -748,9 +827,10 @@ void mat_mul_ws_sizes(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint3
     if (cplx) g += 4 * N * K * (B->im.cap + 2);
     grow(WS_GATHER, g);
   }
-  {   // the planner of several blocks
-    const int64_t maxb = K / kBasecase + 2, nline = 2 * M + 2 * N + ((2 * M + 2 * N) & 1);
-    grow(WS_PLAN, 4 * nline + 16 * maxb + 4 * (maxb + 1));
+  {   // the planner of several blocks: element table, bounds, per-block statistics
+    const int64_t maxb = K / kBasecase + 2;
+    grow(WS_PLAN, round_up(8 * (M + N) * K + 16 * maxb + 4 * (maxb + 1), 256) +
+                      4 * maxb * round_up(2 * M + 2 * N + 8, 64));
   }
   if (!(flags & ARBGPU_ALGO_RNS)) {   // base-256 slices
     const int64_t Kp = round_up(std::max<int64_t>(Kt, 1), kKStep);
@@ -761,7 +841,8 @@ void mat_mul_ws_sizes(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint3
       if (cplx) grow(WS_PLANES_B2, b.lb * Np * Kp);
       grow(WS_D, 4 * b.nslots * ds);
       grow(WS_T, 4 * (int64_t)b.tl * MN);
-      grow(WS_TABLES, (int64_t)sizeof(DiagGroup) * (b.nslots + 8) + 4 * (b.la + b.lb));
+      // tables and the list of entries the truncated diagonal set leaves
+      grow(WS_TABLES, (int64_t)sizeof(DiagGroup) * (b.nslots + 8) + 4 * (b.la + b.lb) + 16 + 8 * MN);
     }
   }
   if (!(flags & ARBGPU_ALGO_SLICED)) {   // residues: the largest heights the form holds
@@ -809,11 +890,13 @@ size_t mat_mul_footprint(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, ui
 }
 
 int plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, bool cplx, int hmax, hipStream_t s,
-                std::vector<BlockSpan> &out) {
+                std::vector<BlockSpan> &out, int32_t **stats, int64_t *stride) {
   const int64_t M = A->rows, N = B->cols, K = A->cols;
   const int64_t maxb = K / kBasecase + 2;   // every block but the last has >= 30 indices or is basecase-extended
-  const int64_t nline = 2 * M + 2 * N + ((2 * M + 2 * N) & 1);
-  const size_t bytes = sizeof(int32_t) * (size_t)nline + sizeof(int64_t) * 2 * maxb + sizeof(int32_t) * (maxb + 1);
+  const int64_t sstride = round_up(2 * M + 2 * N + 8, 64);
+  const size_t hl_bytes = sizeof(int2) * (size_t)(M + N) * K;
+  const size_t o_st = round_up(hl_bytes + sizeof(int64_t) * 2 * maxb + sizeof(int32_t) * (maxb + 1), 256);
+  const size_t bytes = o_st + sizeof(int32_t) * (size_t)(maxb * sstride);
   char *w = (char *)ws_get(ctx, WS_PLAN, bytes);
   if (!w) return ARBGPU_ENOMEM;
   PlanParams pp;
@@ -828,15 +911,19 @@ int plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, bool 
   pp.b_off = B->off; pp.b_rs = B->rs; pp.b_cs = B->cs;
   pp.hmax = hmax;
   pp.basecase = kBasecase;
-  int32_t *iw = (int32_t *)w;
-  pp.rtop = iw; pp.rlow = iw + M; pp.ctop = iw + 2 * M; pp.clow = iw + 2 * M + N;
-  pp.bounds = (int64_t *)(iw + nline);
+  pp.hlA = (int2 *)w;
+  pp.hlB = pp.hlA + (size_t)M * K;
+  pp.bounds = (int64_t *)(w + hl_bytes);
   pp.kinds = (int32_t *)(pp.bounds + 2 * maxb);
   pp.max_blocks = maxb;
   pp.nblocks = pp.kinds + maxb;
+  int32_t *bst = (int32_t *)(w + o_st);
   {
     KernelTimer tp(ctx, "plan", s);
     ARB_TRY(launch_plan(pp, s), "plan");
+    BlockStatsParams bs{pp.hlA, pp.hlB, M, N, pp.bounds, pp.nblocks, maxb, bst, sstride};
+    ARB_TRY(launch_fill_i32(bst, 0, maxb * sstride, s), "fill");
+    ARB_TRY(launch_block_stats(bs, s), "block stats");
   }
   int32_t nb = 0;
   ARB_TRY(hipMemcpyAsync(&nb, pp.nblocks, sizeof nb, hipMemcpyDeviceToHost, s), "plan readback");
@@ -844,14 +931,20 @@ int plan_blocks(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, bool 
   if (nb < 0 || nb > maxb)
     return set_error(ctx, ARBGPU_EDEVICE, "planner produced %d blocks (bound %lld)", nb, (long long)maxb);
   std::vector<int64_t> b(2 * (size_t)nb + 2);
-  std::vector<int32_t> k((size_t)nb + 1);
+  std::vector<int32_t> k((size_t)nb + 1), g(8 * (size_t)nb + 8);
   if (nb) {
     ARB_TRY(hipMemcpyAsync(b.data(), pp.bounds, sizeof(int64_t) * 2 * nb, hipMemcpyDeviceToHost, s), "plan readback");
     ARB_TRY(hipMemcpyAsync(k.data(), pp.kinds, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s), "plan readback");
+    // the heights gA[0], gB[0] (8 words after the lines) of every block
+    ARB_TRY(hipMemcpy2DAsync(g.data(), 8 * sizeof(int32_t), bst + 2 * M + 2 * N, sizeof(int32_t) * sstride,
+                             8 * sizeof(int32_t), nb, hipMemcpyDeviceToHost, s),
+            "plan readback");
     ARB_TRY(hipStreamSynchronize(s), "plan readback");
   }
   out.clear();
-  for (int i = 0; i < nb; ++i) out.push_back(BlockSpan{b[2 * i], b[2 * i + 1], k[i]});
+  for (int i = 0; i < nb; ++i) out.push_back(BlockSpan{b[2 * i], b[2 * i + 1], k[i], g[8 * i], g[8 * i + 4]});
+  if (stats) *stats = bst;
+  if (stride) *stride = sstride;
   return ARBGPU_OK;
 }
 
@@ -926,7 +1019,7 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
       if (rc) return rc;
     }
     return block_product(ctx, A, B, sh, 0, sh.K, st, g[0], g[4], outs, C->off, C->rs, C->cs, (int)p, sh.approx,
-                         rin_m, rin_e, s, rns, (flags & ARBGPU_COMPLEX_4M) != 0);
+                         rin_m, rin_e, s, rns, (flags & ARBGPU_COMPLEX_4M) != 0, nullptr, true);
   }
 
   // ---- several blocks (Algorithm 2's greedy partition) ----------------------
@@ -936,21 +1029,24 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
   if (2 * (int64_t)std::max(g[3], g[7]) + 64 >= (int64_t)(1 << 28)) return not_here("exponents too large for blocks");
   if (slices_for(hmax) > kMaxSlices) return not_here("height bound too large");
   std::vector<BlockSpan> blocks;
-  rc = plan_blocks(ctx, A, B, sh.cplx, hmax, s, blocks);
+  int32_t *bstats = nullptr;
+  int64_t bstride = 0;
+  rc = plan_blocks(ctx, A, B, sh.cplx, hmax, s, blocks, &bstats, &bstride);
   if (rc) return rc;
+  // Per-block choice (unless an ALGO flag fixes the path): a block whose
+  // integer product costs more than its terms on the window engine becomes
+  // basecase indices of the merge.
+  if (!(flags & (ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS)))
+    for (BlockSpan &b : blocks)
+      if (b.kind == 0 && block_cost_int8(sh, b, (int)p) > block_cost_base(sh, b, (int)p, A, B)) b.kind = 1;
   std::vector<int64_t> bk;   // basecase inner indices
-  std::vector<int32_t> hts;  // (HA, HB) per scaled-integer block
   int nS = 0, capT = 1;
   for (const BlockSpan &b : blocks) {
     if (b.kind == 1) {
       for (int64_t k = b.k0; k < b.k1; ++k) bk.push_back(k);
       continue;
     }
-    rc = line_stats(ctx, A, B, sh, b.k0, b.k1, st, s, g);
-    if (rc) return rc;
-    hts.push_back(g[0]);
-    hts.push_back(g[4]);
-    capT = std::max(capT, t_limbs(slices_for(g[0]), slices_for(g[4])));
+    capT = std::max(capT, t_limbs(slices_for(b.ha), slices_for(b.hb)));
     ++nS;
   }
   if (nS == 0 && !forced) return kNotApplicable;   // only dot products: the limb kernel
@@ -978,10 +1074,10 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
   // part q, block si: limb plane k of entry ij at tl[q*nS*MN*capT + k*nS*MN + si*MN + ij]
   const int64_t ldT = (int64_t)nS * MN;
   int si = 0;
-  for (const BlockSpan &b : blocks) {
+  for (size_t bi = 0; bi < blocks.size(); ++bi) {
+    const BlockSpan &b = blocks[bi];
     if (b.kind == 1) continue;
-    rc = line_stats(ctx, A, B, sh, b.k0, b.k1, st, s, g);
-    if (rc) return rc;
+    const int32_t *bst = bstats + (int64_t)bi * bstride;
     arbgpu_out tout[2];
     for (int q = 0; q < sh.nparts; ++q) {
       const size_t e0 = (size_t)q * nS * MN + (size_t)si * MN;
@@ -991,8 +1087,8 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
     double *no_m[2] = {nullptr, nullptr};
     int32_t *no_e[2] = {nullptr, nullptr};
     const int64_t ktb = sh.cplx ? 2 * (b.k1 - b.k0) : b.k1 - b.k0;
-    const bool rns = use_rns(g[0], g[4], ktb) && rns_fits(g[0], g[4], ktb);
-    rc = block_product(ctx, A, B, sh, b.k0, b.k1, st, g[0], g[4], tout, 0, sh.N, 1, 32 * capT, true, no_m, no_e, s,
+    const bool rns = use_rns(b.ha, b.hb, ktb) && rns_fits(b.ha, b.hb, ktb);
+    rc = block_product(ctx, A, B, sh, b.k0, b.k1, bst, b.ha, b.hb, tout, 0, sh.N, 1, 32 * capT, true, no_m, no_e, s,
                        rns, (flags & ARBGPU_COMPLEX_4M) != 0);
     if (rc) return rc;
     ++si;

@@ -360,3 +360,41 @@ def test_rns_beyond_its_limits(ctx):
     Bc = gen.canonical_matrix(B, N, K, K, 1)
     check(out, st, lambda i, j: oracle.dot(Ac[i], [Bc[k][j] for k in range(N)], p),
           [(i, j) for i in range(M) for j in range(K)], K)
+
+
+def test_truncated_slices_certify_or_fall_back(ctx):
+    # Base-256 slices leave out the low diagonals of the integer product
+    # when they lie far below the output's p bits.  Rows whose terms cancel
+    # in pairs against columns that negate in pairs give exact zeros and
+    # tiny sums, which the truncated product cannot certify: those entries
+    # are recomputed exactly; every midpoint equals the limb kernel's
+    rng = gen.rng_for(29, 0)
+    M, N, K, p = 40, 64, 30, 200
+    A = gen.random_operands(rng, M * N, 220, -3, 3)
+    B = gen.random_operands(rng, N * K, 220, -3, 3)
+    a = [gen.to_canonical(A, i) for i in range(M * N)]
+    b = [gen.to_canonical(B, i) for i in range(N * K)]
+    rows, zero_cols, tiny_cols = (0, 5, 17), (0, 3, 29), (7,)
+    for i in rows:
+        for t in range(N // 2):
+            a[i * N + 2 * t + 1] = a[i * N + 2 * t]
+    for j in zero_cols + tiny_cols:
+        for t in range(N // 2):
+            b[(2 * t + 1) * K + j] = (oracle.fneg(b[2 * t * K + j][0]), None)
+    for j in tiny_cols:   # one pair does not cancel: its small leftover is the exact sum
+        b[1 * K + j] = (oracle.fmake(0, (1 << 30) + 1, -90), None)
+    A, B = gen.from_canonical(a, cap=A.cap), gen.from_canonical(b, cap=B.cap)
+    say("truncated slices with cancelling entries")
+    (out, st), _ = run(ctx, A, B, M, N, K, p, arbgpu.ALGO_SLICED)
+    plan = ctx.plan_info()
+    assert plan["pairs"] < plan["slices_a"] * plan["slices_b"]   # the truncated set was used
+    (o2, s2), _ = run(ctx, A, B, M, N, K, p, arbgpu.ALGO_LIMB)
+    assert np.array_equal(out.limbs, o2.limbs) and np.array_equal(out.exp, o2.exp)
+    assert np.array_equal(out.nls, o2.nls)
+    Ac = gen.canonical_matrix(A, M, N, N, 1)
+    Bc = gen.canonical_matrix(B, N, K, K, 1)
+    ent = [(i, j) for i in rows for j in zero_cols + tiny_cols] + [(1, 1), (39, 29)]
+    check(out, st, lambda i, j: oracle.dot(Ac[i], [Bc[k][j] for k in range(N)], p), ent, K)
+    for i in rows:
+        for j in zero_cols:
+            assert out.nls[i * K + j] == 0   # exact zeros
