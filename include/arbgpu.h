@@ -76,7 +76,10 @@ extern "C" {
                                   decide the truncation and the exact refinement
                                   passes were used                               */
 #define ARBGPU_ST_ERANGE   2   /* an input exponent had |e| >= 2^28 or a radius
-                                  was not finite; the output value is undefined  */
+                                  was not finite, or (dots beyond the register
+                                  windows) the exact fallback's exponent span
+                                  exceeded the LDS window; the output value is
+                                  undefined and its radius infinite              */
 
 typedef struct arbgpu_ctx arbgpu_ctx;
 typedef void *arbgpu_stream;   /* a hipStream_t; NULL is the null stream */
@@ -136,10 +139,17 @@ const char *arbgpu_last_error(const arbgpu_ctx *ctx);
  * ARBGPU_COMPLEX, `res`, `initial`, `x`, `y` each point to TWO structs
  * {real part, imaginary part} and the real and imaginary results are each
  * the exact sum of their 2N real terms, rounded once (Section 3.6).
+ * Precisions whose window (p + bitlength(t + 1) + 41 bits with t = N + 1
+ * terms, 2N + 1 for complex) fits the widest compiled register window
+ * (38 limbs, 1216 bits) run one wave per output; larger ones run one
+ * workgroup per output with the window in LDS, up to p = 65408 with
+ * operands of at most 2048 limbs.  There an exact fallback whose span from
+ * the top of the sum down to the lowest bit of any product exceeds 131072
+ * bits is not run: the output gets status ARBGPU_ST_ERANGE and an infinite
+ * radius.
  * EINVAL: p < 2, N < 0, NULL operand, cap of res < ceil(p/32), radius
- * output NULL without APPROX, or p too large for the widest compiled
- * window (38 limbs: p + bitlength(t + 1) + 41 <= 1216 with t = N + 1
- * terms, 2N + 1 for complex). */
+ * output NULL without APPROX, p above 65408, or operands wider than 2048
+ * limbs where the register windows do not hold p. */
 int arbgpu_dot(arbgpu_ctx *ctx, const arbgpu_out *res, int64_t res_idx,
                const arbgpu_arr *initial, int64_t init_idx, int sub,
                const arbgpu_arr *x, int64_t xoff, int64_t xstep,

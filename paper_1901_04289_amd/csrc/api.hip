@@ -266,8 +266,14 @@ int dot_tasks(arbgpu_ctx *ctx, const arbgpu_dot_job &job, const char *who, DotPa
     cap = job.x[q].cap > cap ? job.x[q].cap : cap;
     cap = job.y[q].cap > cap ? job.y[q].cap : cap;
   }
-  if (!limb_shape_for((int)p, N * nparts + 1, cap, shape))
-    return fail(ctx, ARBGPU_EINVAL, "%s: precision %lld above the limb kernel's window", who, (long long)p);
+  if (!limb_shape_for((int)p, N * nparts + 1, cap, shape)) {
+    // beyond every register window: the LDS-window kernel
+    if (p > wide_max_precision())
+      return fail(ctx, ARBGPU_EINVAL, "%s: precision %lld above %d bits", who, (long long)p, wide_max_precision());
+    if (cap > wide_max_limbs())
+      return fail(ctx, ARBGPU_EINVAL, "%s: operands of %d limbs above %d", who, cap, wide_max_limbs());
+    *shape = LimbShape{0, 0};
+  }
   for (int q = 0; q < nparts; ++q) {
     DotParams &d = prm[q];
     memset(&d, 0, sizeof d);
@@ -417,7 +423,7 @@ int arbgpu_dot(arbgpu_ctx *ctx, const arbgpu_out *res, int64_t res_idx, const ar
   if ((rc = bind_device(ctx, stream))) return rc;
   for (int q = 0; q < nt; ++q) {
     KernelTimer kt(ctx, "limb_dot", to_stream(stream));
-    hipError_t e = launch_limb_dot(prm[q], sh, to_stream(stream));
+    hipError_t e = sh.ns ? launch_limb_dot(prm[q], sh, to_stream(stream)) : launch_wide_dot(prm[q], to_stream(stream));
     if (e != hipSuccess) return hip_fail(ctx, e, "arbgpu_dot launch");
   }
   return ARBGPU_OK;

@@ -203,6 +203,10 @@ int dot_batch_run(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, hi
   }
   const int ncu = device_cus(ctx->device);
   for (size_t k = 0; k < runs.size() && e == hipSuccess; ++k) {
+    if (runs[k].sh.ns == 0) {   // beyond the register windows: one workgroup per dot
+      e = launch_wide_dot_batch(d_tasks, d_order + runs[k].begin, runs[k].count, s);
+      continue;
+    }
     BatchShapeParams bp{d_tasks, nullptr, nullptr, d_order + runs[k].begin, runs[k].count, d_ctr + k};
     void *args[] = {&bp};
     e = hipLaunchKernel(dot_batch_kernel(runs[k].sh), dim3(blocks_for(runs[k].count, runs[k].waves, ncu)),
@@ -264,13 +268,23 @@ struct arbgpu_batch {
     if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "graph node: %s", hipGetErrorString(e));
     for (size_t k = 0; k < runs.size(); ++k) {
       BatchShapeParams bp = params(k);
+      const int32_t *wide_order = d_order + runs[k].begin;
       void *args[] = {&bp};
+      void *wargs[] = {&d_tasks, &wide_order};
       hipKernelNodeParams np;
       memset(&np, 0, sizeof np);
-      np.func = const_cast<void *>(dot_batch_kernel(runs[k].sh));
-      np.gridDim = dim3(blocks_for(runs[k], runs[k].waves));
+      if (runs[k].sh.ns == 0) {   // beyond the register windows: one workgroup per dot
+        size_t lds = 0;
+        np.func = const_cast<void *>(wide_dot_batch_kernel_ptr(&lds));
+        np.gridDim = dim3((unsigned)runs[k].count);
+        np.sharedMemBytes = (unsigned)lds;
+        np.kernelParams = wargs;
+      } else {
+        np.func = const_cast<void *>(dot_batch_kernel(runs[k].sh));
+        np.gridDim = dim3(blocks_for(runs[k], runs[k].waves));
+        np.kernelParams = args;
+      }
       np.blockDim = dim3(256);
-      np.kernelParams = args;
       hipGraphNode_t node;
       e = hipGraphAddKernelNode(&node, graph, &reset, 1, &np);
       if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "graph node: %s", hipGetErrorString(e));
@@ -364,6 +378,7 @@ int arbgpu_batch_tune(arbgpu_batch *b, arbgpu_stream stream) {
   if (e == hipSuccess) e = hipEventCreate(&t0);
   if (e == hipSuccess) e = hipEventCreate(&t1);
   for (size_t k = 0; k < b->runs.size() && e == hipSuccess; ++k) {
+    if (b->runs[k].sh.ns == 0) continue;   // one workgroup per dot: no width to tune
     float best = 3.0e38f;
     int best_w = b->runs[k].waves;
     for (int w : kTuneWaves) {
