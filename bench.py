@@ -38,6 +38,9 @@ from paper_1901_04289_amd import gen  # noqa: E402
 
 METRIC = "p-bit MACs/s, sliced-MFMA vs plain limb kernel, N=2048 p=512; p99 latency"
 PEAK_INT8_TOPS = 5000.0   # MI355X dense INT8 MFMA, 5.0 POP/s
+# 32 x 32 -> 64-bit integer products (v_mad_u64_u32, one per lane per clock
+# at the full vector rate): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+PEAK_LIMB_PRODUCTS = 256 * 4 * 16 * 2.4e9
 
 # HBM bytes per launch of the MFMA kernel of each INT8 form at N = 2048,
 # p = 512, from FETCH_SIZE (scaled by the copy calibration) and WRITE_SIZE
@@ -52,12 +55,99 @@ MFMA_TRAFFIC = {
 }
 
 
-def _mfma_traffic(n, form):
+def _stored_traffic(n, form):
     import hashlib
     src, want, nbytes = MFMA_TRAFFIC[form]
     with open(os.path.join(ROOT, "paper_1901_04289_amd", "csrc", src), "rb") as f:
         h = hashlib.sha256(f.read()).hexdigest()[:16]
     return nbytes if (want is not None and h == want and n == 2048) else None
+
+
+# Kernels whose HBM traffic the counter runs report (name as rocprofv3
+# prints it, up to the template arguments or the parameter list).
+COUNTED_KERNELS = ("mfma_rns_kernel", "mfma_diag_kernel", "rns_slice_kernel", "rns_crt_kernel",
+                   "gather_lines_kernel", "slice_kernel", "recombine_kernel")
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+CALIBRATION_BYTES = 1 << 30
+
+
+def traffic_child(n):
+    """Body of a counter run: one automatic product at the benchmark size,
+    then a 1 GiB device-to-device copy whose known byte counts calibrate
+    the counters."""
+    import torch
+    from paper_1901_04289_amd import arbgpu
+    w = gen.config2(n=n)
+    ctx = arbgpu.Context(0)
+    dA, dB = arbgpu.DeviceArray.from_host(w.A), arbgpu.DeviceArray.from_host(w.B)
+    C = arbgpu.DeviceOut.empty(w.M * w.K, w.p, radius=True)
+    ctx.mat_mul(C, dA, dB, w.M, w.N, w.K, w.p, 0)
+    torch.cuda.synchronize()
+    src = torch.empty(CALIBRATION_BYTES, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _counter_values(csv_path):
+    """Per kernel (short name): the counter value of each dispatch, in KiB."""
+    import csv
+    out = {}
+    with open(csv_path, newline="") as f:
+        for row in csv.DictReader(f):
+            name = row["Kernel_Name"]
+            for short in COUNTED_KERNELS + (COPY_KERNEL,):
+                if (short + "<") in name or (short + "(") in name or name == short:
+                    out.setdefault(short, []).append(float(row["Counter_Value"]))
+                    break
+    return out
+
+
+def hbm_counters(n, log):
+    """HBM bytes per dispatch of the path's kernels from two rocprofv3
+    counter runs of this script (FETCH_SIZE, then WRITE_SIZE), each scaled
+    by what the same counter reads for the 1 GiB copy.  None when the
+    profiler is missing or a run gives no usable result."""
+    import glob
+    import shutil
+    import subprocess
+    import tempfile
+    prof = shutil.which("rocprofv3") or "/opt/rocm/bin/rocprofv3"
+    if not os.path.exists(prof):
+        log("[bench] rocprofv3 not found: traffic from the stored counter runs")
+        return None
+    tmp = tempfile.mkdtemp(prefix="arbgpu_pmc_", dir="/tmp")
+    vals = {}
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        d = os.path.join(tmp, counter)
+        cmd = ["timeout", "-s", "KILL", "180", prof, "--pmc", counter, "--output-format", "csv", "-d", d,
+               "-o", "run", "--", sys.executable, os.path.abspath(__file__), "--traffic-child", "--n", str(n)]
+        t0 = time.time()
+        r = subprocess.run(cmd, cwd="/tmp", env=dict(os.environ, TMPDIR="/tmp"), stdout=subprocess.DEVNULL,
+                           stderr=subprocess.PIPE, text=True)
+        csvs = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        got = _counter_values(csvs[0]) if csvs else {}
+        log(f"[bench] counter run {counter}: exit {r.returncode}, {time.time() - t0:.1f}s, "
+            f"kernels {sorted(got)}")
+        if COPY_KERNEL not in got or not any(k in got for k in COUNTED_KERNELS):
+            log("[bench] counter run unusable: " + (r.stderr or "")[-500:])
+            return None
+        vals[counter] = got
+    f_read = CALIBRATION_BYTES / (max(vals["FETCH_SIZE"][COPY_KERNEL]) * 1024.0)
+    f_write = CALIBRATION_BYTES / (max(vals["WRITE_SIZE"][COPY_KERNEL]) * 1024.0)
+    per = {}
+    for k in COUNTED_KERNELS:
+        if k in vals["FETCH_SIZE"] and k in vals["WRITE_SIZE"]:
+            rd = np.mean(vals["FETCH_SIZE"][k]) * 1024.0 * f_read
+            wr = np.mean(vals["WRITE_SIZE"][k]) * 1024.0 * f_write
+            per[k] = {"read_bytes": rd, "write_bytes": wr, "bytes": rd + wr,
+                      "dispatches": len(vals["FETCH_SIZE"][k])}
+    return {"per_dispatch": per, "fetch_scale": f_read, "write_scale": f_write,
+            "source": "rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of bench.py --traffic-child "
+                      f"(one product at N={n}; counters scaled by a 1 GiB device copy)"}
 
 
 # ---------------------------------------------------------------------------
@@ -89,6 +179,22 @@ def _oracle_entries(args):
     return done, t
 
 
+def host_cpu():
+    """CPU model name (from /proc/cpuinfo), logical CPUs of the host, and
+    the CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_logical_cpus": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(w, seconds: float, cores: int):
     """Exact oracle on random output entries: 32 rows and 32 columns are
     decoded up front (not timed); each worker repeatedly evaluates its
@@ -101,20 +207,40 @@ def cpu_baseline(w, seconds: float, cores: int):
     pairs = [(a, b) for a in range(32) for b in range(32)]
     chunks = [pairs[c::cores] for c in range(cores)]
     ctx = mp.get_context("fork")
-    with ctx.Pool(cores, initializer=_init_worker, initargs=(rows, cols)) as pool:
+    pool = ctx.Pool(cores, initializer=_init_worker, initargs=(rows, cols))
+    try:
         t0 = time.time()
         res = pool.map(_oracle_entries, [(ch, w.p, time.time() + seconds) for ch in chunks])
         dt = time.time() - t0
+    finally:
+        pool.close()
+        pool.join()
     n = sum(r[0] for r in res)
-    return {"value": n * w.N / dt, "unit": "p-bit MACs/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} dot products of length {w.N} (entries of the 2048^3 p=512 product from 32 "
-                      f"random rows x 32 random columns, {n * w.N} MACs), exact oracle, {cores} worker "
-                      f"processes, {dt:.1f} s wall"}
+    host = host_cpu()
+    out = {"value": n * w.N / dt, "unit": "p-bit MACs/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n} dot products of length {w.N} (entries of the 2048^3 p=512 product from 32 "
+                     f"random rows x 32 random columns, {n * w.N} MACs), exact oracle, {cores} worker "
+                     f"processes (the CPU share of one GPU, at most 16), {dt:.1f} s wall"}
+    out.update(host)
+    return out
 
 
 # ---------------------------------------------------------------------------
 # GPU
 # ---------------------------------------------------------------------------
+
+def window_limbs(p, terms):
+    """Limbs of the accumulation window of a dot product: p bits, the
+    extend bits for `terms` terms and the guard bits (Section 3.3)."""
+    bc = np.floor(np.log2(np.asarray(terms, dtype=np.float64) + 1)).astype(np.int64) + 1
+    return (np.asarray(p) + bc + 1 + 40 + 31) // 32
+
+
+def limb_products(nx, ny, W):
+    """Schoolbook 32 x 32 -> 64-bit limb products of one real term when each
+    operand is cut to the W + 1 limbs that can reach the window."""
+    return np.minimum(nx, W + 1).astype(np.float64) * np.minimum(ny, W + 1)
+
 
 def bench_dot_batch(arbgpu, torch, log, launches: int):
     """The 10^4-dot complex ball batch as one graph launch (tuned first)."""
@@ -122,6 +248,11 @@ def bench_dot_batch(arbgpu, torch, log, launches: int):
     w = gen.config3()
     terms = int(w.lengths.sum())
     log(f"[bench] dot batch: {len(w.lengths)} dots, {terms} terms, generated in {time.time() - t0:.1f}s")
+    # algorithmic work: per complex term the four real limb products
+    W = np.repeat(window_limbs(w.precs, 2 * w.lengths + 1), w.lengths)
+    n = [o.nls.astype(np.int64) & 0x7FFFFFFF for o in (w.x_re, w.x_im, w.y_re, w.y_im)]
+    products = float(np.sum(limb_products(n[0], n[2], W) + limb_products(n[1], n[3], W) +
+                            limb_products(n[0], n[3], W) + limb_products(n[1], n[2], W)))
     ctx = arbgpu.Context(0)
     dev = [arbgpu.DeviceArray.from_host(o) for o in (w.x_re, w.x_im, w.y_re, w.y_im)]
     del w.x_re, w.x_im, w.y_re, w.y_im
@@ -147,10 +278,15 @@ def bench_dot_batch(arbgpu, torch, log, launches: int):
     b.close()
     ctx.close()
     cmacs = terms / (ms / 1e3)
-    log(f"[bench] dot batch {ms:.2f} ms/launch, {cmacs:.3e} complex MACs/s")
+    achieved = products / (ms / 1e3)
+    log(f"[bench] dot batch {ms:.2f} ms/launch, {cmacs:.3e} complex MACs/s, "
+        f"{achieved / PEAK_LIMB_PRODUCTS:.1%} of the limb-product rate")
     return {"dots": len(w.lengths), "terms": terms, "launches": launches, "ms_per_launch": ms,
             "complex_macs_per_s": cmacs, "real_macs_per_s": 4 * cmacs,
-            "mean_p": float(np.mean(w.precs)), "shapes": info["shapes"]}
+            "mean_p": float(np.mean(w.precs)), "shapes": info["shapes"],
+            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LIMB_PRODUCTS / 1e12,
+                         "unit": "T limb products/s", "frac": achieved / PEAK_LIMB_PRODUCTS, "traffic": None,
+                         "products_per_launch": products}}
 
 
 def bench_serving(arbgpu, torch, log, nreq: int, rate: float, slots: int):
@@ -266,14 +402,21 @@ def main():
     ap.add_argument("--batch-launches", type=int, default=5, help="0 skips the dot batch")
     ap.add_argument("--serve-requests", type=int, default=2000, help="0 skips the serving loop")
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--serve-sweep", default="50,100",
-                    help="further arrival rates (req/s), 3 s of arrivals each; empty skips")
+    ap.add_argument("--serve-sweep", default="50,100,400,800,1600,3200",
+                    help="further arrival rates (req/s) up to saturation; empty skips")
+    ap.add_argument("--sweep-seconds", type=float, default=2.0, help="seconds of arrivals per sweep rate")
+    ap.add_argument("--no-counters", action="store_true",
+                    help="skip the HBM counter runs (rocprofv3 children); traffic then comes from the stored runs")
+    ap.add_argument("--traffic-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-largest", action="store_true", help="skip timing the largest serving request alone")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--no-peaks", action="store_true", help="skip the machine-limit microbenchmarks")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also copy a buffer of this many MiB once (reference kernel for HBM counters)")
     a = ap.parse_args()
+    if a.traffic_child:
+        traffic_child(a.n)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU design is "
                                    "described but not built", "n_gpus": a.gpus}))
@@ -368,7 +511,7 @@ def main():
                        "kernels_ms_per_step": r["kernels_ms_per_step"], "digit_pairs": r["plan"]["pairs"],
                        "primes": r["plan"]["primes"], "mfma_avg_ms": r["mfma_avg_ms"],
                        "mfma_frac_of_int8_peak": r["mfma_tops"] / PEAK_INT8_TOPS,
-                       "mfma_traffic_bytes": _mfma_traffic(a.n, name),
+                       "mfma_traffic_bytes": _stored_traffic(a.n, name),
                        "bit_identical_midpoints": bool(torch.equal(C.limbs, C_main[0])
                                                        and torch.equal(C.exp, C_main[1])
                                                        and torch.equal(C.nls, C_main[2]))}
@@ -396,7 +539,8 @@ def main():
         "slice_plan": plan,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
                      "frac": achieved / PEAK_INT8_TOPS,
-                     "traffic": _mfma_traffic(a.n, "slices" if digits_path else "residues"),
+                     "traffic": _stored_traffic(a.n, "slices" if digits_path else "residues"),
+                     "traffic_source": "stored counter runs on this kernel source (hash-checked)",
                      "kernel": MFMA_KERNEL["slices" if digits_path else "residues"], "ops_per_launch": int8_ops,
                      "avg_launch_ms": mfma_avg_s * 1e3},
         "int8_forms": forms,
@@ -421,8 +565,19 @@ def main():
         t4 = time.perf_counter()
         ms_plain = (t4 - t3) * 1e3 / a.plain_steps
         same = bool(torch.equal(C.limbs, Cl.limbs) and torch.equal(C.exp, Cl.exp) and torch.equal(C.nls, Cl.nls))
+        # algorithmic work: the limb products of every term of every entry,
+        # sum over k of (sum_i m_A(i,k)) (sum_j m_B(k,j))
+        Wm = int(window_limbs(p, N + 1))
+        mA = np.minimum(w.A.nls.astype(np.int64) & 0x7FFFFFFF, Wm + 1).reshape(M, N).astype(np.float64)
+        mB = np.minimum(w.B.nls.astype(np.int64) & 0x7FFFFFFF, Wm + 1).reshape(N, K).astype(np.float64)
+        products = float(mA.sum(axis=0) @ mB.sum(axis=1))
+        achieved = products / (ms_plain / 1e3)
         out["plain_limb"] = {"value": macs / (ms_plain / 1e3), "unit": "p-bit MACs/s", "ms_per_step": ms_plain,
-                             "steps": a.plain_steps, "bit_identical_midpoints": same}
+                             "steps": a.plain_steps, "bit_identical_midpoints": same,
+                             "roofline": {"bound": "alu", "achieved": achieved / 1e12,
+                                          "peak": PEAK_LIMB_PRODUCTS / 1e12, "unit": "T limb products/s",
+                                          "frac": achieved / PEAK_LIMB_PRODUCTS, "traffic": None,
+                                          "products_per_launch": products}}
         out["speedup_vs_plain"] = ms_plain / ms_step
         log(f"[bench] plain {ms_plain:.1f} ms/step, identical midpoints: {same}")
         del Cl
@@ -441,11 +596,39 @@ def main():
         out["latency_ms"]["serving_p99"] = out["serving"]["latency_ms"]["p99"]
         sweep = []
         for rate in [float(x) for x in a.serve_sweep.split(",") if x.strip()]:
-            r = bench_serving(arbgpu, torch, log, max(1, int(round(3.0 * rate))), rate, a.serve_slots)
+            r = bench_serving(arbgpu, torch, log, max(1, int(round(a.sweep_seconds * rate))), rate,
+                              a.serve_slots)
+            # keeps pace: every request admitted at once and the completions
+            # end within 10% (+50 ms) of the arrivals
+            pace = (r["eagain_retries"] == 0 and
+                    r["completion_span_s"] <= 1.1 * r["arrival_span_s"] + 0.05)
             sweep.append({"rate_per_s": rate, "requests": r["requests"], "latency_ms": r["latency_ms"],
-                          "complex_macs_per_s": r["complex_macs_per_s"], "eagain_retries": r["eagain_retries"]})
+                          "queue_wait_ms": r["queue_wait_ms"],
+                          "completed_req_per_s": r["requests"] / r["completion_span_s"],
+                          "complex_macs_per_s": r["complex_macs_per_s"], "eagain_retries": r["eagain_retries"],
+                          "keeps_pace": pace})
         if sweep:
             out["serving_sweep"] = sweep
+            kept = [x for x in sweep if x["keeps_pace"]]
+            over = [x for x in sweep if not x["keeps_pace"]]
+            out["serving_capacity"] = {
+                "max_rate_kept_per_s": max((x["rate_per_s"] for x in kept), default=None),
+                "first_rate_not_kept_per_s": min((x["rate_per_s"] for x in over), default=None),
+                "max_completed_req_per_s": max(x["completed_req_per_s"] for x in sweep),
+                "max_complex_macs_per_s": max(x["complex_macs_per_s"] for x in sweep)}
+    if not a.no_counters:
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        cnt = hbm_counters(a.n, log)
+        if cnt is not None:
+            kname = "mfma_diag_kernel" if digits_path else "mfma_rns_kernel"
+            out["traffic_by_kernel"] = cnt
+            if kname in cnt["per_dispatch"]:
+                out["roofline"]["traffic"] = cnt["per_dispatch"][kname]["bytes"]
+                out["roofline"]["traffic_source"] = cnt["source"]
+    # no child process outlives the run
+    for c in mp.active_children():
+        c.join(10)
     print(json.dumps(out), flush=True)
 
 
