@@ -495,6 +495,23 @@ int arbgpu_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
 
 namespace arbgpu_impl {
 
+// Seconds the limb kernel needs for a product, from measured rates: a wave
+// per entry below kMmWaveEntries entries (about 30 us per part to start,
+// then (3.5e-11 + 3.6e-13 w^2) s per real term at full occupancy, w the
+// operand limbs that reach the window), one lane per entry above
+// ((7e-12 + 2e-13 w^2) s per term).
+double limb_mm_seconds(int64_t M, int64_t N, int64_t K, int64_t p, int cap, bool cplx) {
+  const double w = (double)std::min<int64_t>(cap, (p + 64 + 31) / 32);
+  const double entries = (double)M * (double)K, nparts = cplx ? 2.0 : 1.0;
+  const double terms = entries * (double)N * nparts;   // per part
+  if (M * K < kMmWaveEntries) return nparts * (30e-6 + terms * (3.5e-11 + 3.6e-13 * w * w));
+  return nparts * terms * (7e-12 + 2e-13 * w * w);
+}
+
+// The least the scaled-integer path takes for any product (statistics,
+// slicing, product, reconstruction and their launches), real and complex.
+constexpr double kInt8FloorReal = 180e-6, kInt8FloorComplex = 250e-6;
+
 int mat_mul_run(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, const arbgpu_mat *B, int64_t p,
                 uint32_t flags, hipStream_t stream, int choice) {
   int rc;
@@ -514,6 +531,11 @@ int mat_mul_run(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, cons
   }
   LimbShape sh;
   const bool limb_ok = limb_shape_for((int)p, A->cols * nparts, cap, &sh);
+  // automatic choice: products the limb kernel finishes before the
+  // scaled-integer path could start go to the limb kernel
+  if (limb_ok && choice == kChoiceRule && !(flags & (ARBGPU_ALGO_SLICED | ARBGPU_ALGO_RNS)) &&
+      limb_mm_seconds(A->rows, A->cols, B->cols, p, cap, cplx) < (cplx ? kInt8FloorComplex : kInt8FloorReal))
+    choice = kChoiceLimb;
   if (!(flags & ARBGPU_ALGO_LIMB) && !(choice == kChoiceLimb && limb_ok)) {
     // the scaled-integer path, forced when asked for or when the limb
     // kernel's window cannot hold the precision

@@ -86,9 +86,13 @@ int plan_matmul(arbgpu_ctx *ctx, const arbgpu_job &j, const char *who, BatchPlan
     prm.ct = !cplx ? comp_real() : (q == 0 ? comp_re() : comp_im());
     const int32_t part = (int32_t)bp.mm.size();
     bp.mm.push_back(prm);
+    // the tiles take each entry the way the product alone would (a wave
+    // per entry below kMmWaveEntries entries, else a lane), so a product
+    // gives the same bits in a batch and alone
+    const int32_t wave = M * K < kMmWaveEntries ? 1 : 0;
     for (int64_t i = 0; i < M; ++i)
       for (int64_t j0 = 0; j0 < K; j0 += 64) {
-        bp.tiles.push_back(BatchTile{part, 0, i, j0});
+        bp.tiles.push_back(BatchTile{part, wave, i, j0});
         shape_of.push_back(sh);
         // 64 entries, each a whole dot of its own lane
         cost.push_back(64.0 * (double)(N * prm.ct.ncomp + 1) * w * w);

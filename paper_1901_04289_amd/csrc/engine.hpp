@@ -140,6 +140,82 @@ ARB_HD int rad_exp(const Opnd<NA> &a, const Opnd<NA> &b, bool &any) {
   return f;
 }
 
+// Sum of the radius terms (Section 3.5) in fixed point: units of 2^-kRadQ
+// of the frame 2^F, three 64-bit words (integer part below 2^42).  Each
+// term, an upper bound as a double of at most 4, is rounded up to the grid
+// and added exactly, so the sum does not depend on how the terms are split
+// among lanes, waves or workgroups, nor on the order of the additions.
+// Terms below 2^-kRadQ count as 2^-kRadQ: with the largest term at least
+// 1/4 of the frame, that raises the sum by less than 2^-100 of itself for
+// any count of terms the format allows.
+constexpr int kRadQ = 150;
+struct RadAcc {
+  uint64_t w[3];
+  ARB_HD void clear() { w[0] = w[1] = w[2] = 0; }
+  ARB_HD void add_words(uint64_t a0, uint64_t a1, uint64_t a2) {
+    const uint64_t s0 = w[0] + a0;
+    const uint64_t c0 = s0 < a0 ? 1u : 0u;
+    uint64_t s1 = w[1] + a1;
+    uint64_t c1 = s1 < a1 ? 1u : 0u;
+    s1 += c0;
+    c1 += s1 < c0 ? 1u : 0u;
+    w[0] = s0;
+    w[1] = s1;
+    w[2] = w[2] + a2 + c1;
+  }
+  ARB_HD void add(double x) {   // 0 <= x <= 4, zero or normal
+    if (!(x > 0.0)) return;
+    // x = m 2^(be - 1075) with m the 53-bit significand
+    const uint64_t bits = (uint64_t)__builtin_bit_cast(int64_t, x);
+    const int be = (int)(bits >> 52);
+    const uint64_t m = (bits & 0xFFFFFFFFFFFFFull) | (1ull << 52);
+    const int sh = be - 1075 + kRadQ;                              // x 2^Q = m 2^sh
+    uint64_t v0 = 0, v1 = 0, v2 = 0;
+    if (sh >= 128) {
+      v2 = m << (sh - 128);
+    } else if (sh >= 64) {
+      const int r = sh - 64;
+      v1 = m << r;
+      v2 = r ? m >> (64 - r) : 0;
+    } else if (sh >= 0) {
+      v0 = m << sh;
+      v1 = sh ? m >> (64 - sh) : 0;
+    } else {   // below the grid: round up
+      const int q = -sh;
+      v0 = q >= 64 ? 1u : (m >> q) + ((m & ((1ull << q) - 1)) ? 1u : 0u);
+    }
+    add_words(v0, v1, v2);
+  }
+  ARB_HD void add(const RadAcc &o) { add_words(o.w[0], o.w[1], o.w[2]); }
+  // The sum rounded up to m 2^e (m in [0.5, 1)) in units of the frame;
+  // false when it is zero.
+  ARB_HD bool get(double &m, int &e) const {
+    int q = 2;
+    while (q > 0 && w[q] == 0) --q;
+    if (w[q] == 0) return false;
+    const int L = 64 * q + (64 - __builtin_clzll(w[q]));   // bit length
+    // the top 64 bits and whether any bit below them is set
+    uint64_t t;
+    bool sticky = false;
+    const int lo = L - 64;
+    if (lo <= 0) {
+      t = w[0] << (-lo);
+    } else {
+      const int qw = lo >> 6, r = lo & 63;
+      const uint64_t hi = qw + 1 <= 2 ? w[qw + 1] : 0;
+      t = r ? (w[qw] >> r) | (hi << (64 - r)) : w[qw];
+      for (int k = 0; k < qw; ++k) sticky |= w[k] != 0;
+      if (r) sticky |= (w[qw] & ((1ull << r) - 1)) != 0;
+    }
+    uint64_t m53 = (t >> 11) + (((t & 0x7FFull) != 0 || sticky) ? 1u : 0u);
+    int Lr = L;
+    if (m53 >> 53) { m53 >>= 1; ++Lr; }   // rounded up to 2^53 (exact: it is even)
+    m = (double)m53 * 0x1p-53;
+    e = Lr - kRadQ;
+    return true;
+  }
+};
+
 // Setup-pass statistics (Section 3.3, steps 1-5).
 struct Setup {
   int emax;       // max(e + e') over nonzero midpoint products
@@ -499,7 +575,7 @@ struct SoloReducer {
   ARB_HD static void setup(Setup &) {}
   template <int NS>
   ARB_HD static void window(Window<NS> &) {}
-  ARB_HD static double rad(double r) { return r; }
+  ARB_HD static void rad(RadAcc &) {}
 };
 
 // The whole dot-product pipeline for one output.  `Src` supplies the terms:
@@ -548,7 +624,8 @@ ARB_HD void run_dot(const Src &src, int p, bool want_rad, DotOut<NS> &out, bool 
     out.st.zero = true;
     return;
   }
-  double racc = 0.0;
+  RadAcc racc;
+  racc.clear();
   bool rad_pending = want_rad && S.any_rad;
   if (S.nnz == 0) {
     out.st.zero = true;
@@ -563,17 +640,17 @@ ARB_HD void run_dot(const Src &src, int p, bool want_rad, DotOut<NS> &out, bool 
       uint32_t neg;
       src.term(t, a, b, neg, true);
       if (a.n && b.n) add_term(W, lo, a, b, neg);
-      if (rad_pending) racc = ru_add(racc, rad_term(a, b, S.F));
+      if (rad_pending) racc.add(rad_term(a, b, S.F));
     }
     if (hi) {
       Op a, b;
       src.init(a, b, true);
       if (a.n) add_term(W, lo, a, b, a.sign);
-      if (rad_pending) racc = ru_add(racc, rad_term(a, b, S.F));
+      if (rad_pending) racc.add(rad_term(a, b, S.F));
     }
     Red::template window<NS>(W);
     if (rad_pending) {
-      racc = Red::rad(racc);
+      Red::rad(racc);
       rad_pending = false;
     }
     decide<NS>(out.st, W, lo, p);
@@ -583,19 +660,22 @@ ARB_HD void run_dot(const Src &src, int p, bool want_rad, DotOut<NS> &out, bool 
       Op a, b;
       uint32_t neg;
       src.term(t, a, b, neg, true);
-      racc = ru_add(racc, rad_term(a, b, S.F));
+      racc.add(rad_term(a, b, S.F));
     }
     if (hi) {
       Op a, b;
       src.init(a, b, true);
-      racc = ru_add(racc, rad_term(a, b, S.F));
+      racc.add(rad_term(a, b, S.F));
     }
-    racc = Red::rad(racc);
+    Red::rad(racc);
   }
-  if (want_rad && S.any_rad && racc != 0.0) {
-    int ex;
-    out.rin_m = __builtin_frexp(racc, &ex);
-    out.rin_e = S.F + ex;
+  if (want_rad && S.any_rad) {
+    double m;
+    int e;
+    if (racc.get(m, e)) {
+      out.rin_m = m;
+      out.rin_e = S.F + e;
+    }
   }
 }
 

@@ -210,6 +210,12 @@ hipError_t launch_dot_shape(const DotParams &prm, hipStream_t s);
 template <int NS, int NA>
 hipError_t launch_mm_list_shape(const MmParams &prm, const int64_t *list, const int32_t *count, int64_t max_count,
                                 hipStream_t s);
+// Products with fewer entries than this run one wave per entry (the terms
+// split over its lanes), larger ones one lane per entry.
+constexpr int64_t kMmWaveEntries = 1 << 17;
+// A single dot of this many real terms or more runs on a workgroup of four
+// waves instead of one (same bits).
+constexpr int64_t kDotBlockTerms = 1024;
 hipError_t launch_limb_mm(const MmParams &prm, LimbShape sh, hipStream_t s);
 // The entries listed in list[0 .. *count) (device memory, *count <=
 // max_count), by index i K + j, on the limb kernel.
@@ -220,7 +226,7 @@ hipError_t launch_limb_mm_list(const MmParams &prm, LimbShape sh, const int64_t 
 // output part `part` (an MmParams of the batch).
 struct BatchTile {
   int32_t part;
-  int32_t pad;
+  int32_t wave;   // 1: the whole wave takes the tile's entries one by one
   int64_t i, j0;
 };
 

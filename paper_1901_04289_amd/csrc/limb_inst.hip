@@ -13,8 +13,14 @@ namespace arbgpu_impl {
 
 template <>
 hipError_t launch_mm_shape<ARB_NS, ARB_NA>(const MmParams &prm, hipStream_t s) {
+  const int64_t entries = prm.M * prm.K;
+  if (entries == 0) return hipSuccess;
+  if (entries < kMmWaveEntries) {   // a wave per entry
+    hipLaunchKernelGGL((limb_mm_wave_kernel<ARB_NS, ARB_NA>), dim3((unsigned)((entries + 3) / 4)), dim3(256), 0, s,
+                       prm);
+    return hipGetLastError();
+  }
   const int64_t blocks = ((prm.K + 63) / 64) * ((prm.M + 3) / 4);
-  if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL((limb_mm_kernel<ARB_NS, ARB_NA>), dim3((unsigned)blocks), dim3(256), 0, s, prm);
   return hipGetLastError();
 }
@@ -30,7 +36,10 @@ hipError_t launch_mm_list_shape<ARB_NS, ARB_NA>(const MmParams &prm, const int64
 
 template <>
 hipError_t launch_dot_shape<ARB_NS, ARB_NA>(const DotParams &prm, hipStream_t s) {
-  hipLaunchKernelGGL((limb_dot_kernel<ARB_NS, ARB_NA>), dim3(1), dim3(64), 0, s, prm);
+  if (prm.N * prm.ct.ncomp >= kDotBlockTerms)   // four waves share the terms
+    hipLaunchKernelGGL((limb_dot_block_kernel<ARB_NS, ARB_NA>), dim3(1), dim3(256), 0, s, prm);
+  else
+    hipLaunchKernelGGL((limb_dot_kernel<ARB_NS, ARB_NA>), dim3(1), dim3(64), 0, s, prm);
   return hipGetLastError();
 }
 

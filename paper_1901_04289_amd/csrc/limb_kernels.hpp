@@ -180,10 +180,72 @@ struct WaveReducer {
       W.bad = __shfl_xor((int)W.bad, m, 64) | W.bad;
     }
   }
-  __device__ __forceinline__ static double rad(double r) {
+  __device__ __forceinline__ static void rad(RadAcc &r) {
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1) r = ru_add(r, __shfl_xor(r, m, 64));
-    return r;
+    for (int m = 1; m < 64; m <<= 1) {
+      uint64_t o[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) o[k] = (uint64_t)__shfl_xor((long long)r.w[k], m, 64);
+      r.add_words(o[0], o[1], o[2]);
+    }
+  }
+};
+
+// Cross-wave reductions for NW waves per output (one workgroup): each wave
+// reduces with WaveReducer, the wave totals meet in LDS and every lane adds
+// them in wave order.  Window sums are modular, counts are integers and the
+// radius sum is exact, so the result is the one-wave result bit for bit.
+template <int NW>
+struct BlockReducer {
+  __device__ __forceinline__ static int lane() { return threadIdx.x; }
+  __device__ __forceinline__ static int group() { return 64 * NW; }
+  __device__ __forceinline__ static void setup(Setup &S) {
+    __shared__ Setup sh[NW];
+    WaveReducer::setup(S);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = S;
+    __syncthreads();
+    Setup T = sh[0];
+    for (int w = 1; w < NW; ++w) {
+      const Setup o = sh[w];
+      T.emax = o.emax > T.emax ? o.emax : T.emax;
+      T.nnz += o.nnz;
+      T.F = o.F > T.F ? o.F : T.F;
+      T.any_rad = T.any_rad || o.any_rad;
+      T.erange = T.erange || o.erange;
+    }
+    __syncthreads();
+    S = T;
+  }
+  template <int NS>
+  __device__ __forceinline__ static void window(Window<NS> &W) {
+    __shared__ Window<NS> sh[NW];
+    WaveReducer::window<NS>(W);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = W;
+    __syncthreads();
+    Window<NS> T = sh[0];
+    for (int w = 1; w < NW; ++w) {
+      uint32_t o[NS];
+#pragma unroll
+      for (int i = 0; i < NS; ++i) o[i] = sh[w].w[i];
+      madd<NS>(T.w, o);
+      T.err += sh[w].err;
+      T.pt += sh[w].pt;
+      T.below_cnt += sh[w].below_cnt;
+      T.below_max = sh[w].below_max > T.below_max ? sh[w].below_max : T.below_max;
+      T.bad = T.bad || sh[w].bad;
+    }
+    __syncthreads();
+    W = T;
+  }
+  __device__ __forceinline__ static void rad(RadAcc &r) {
+    __shared__ RadAcc sh[NW];
+    WaveReducer::rad(r);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = r;
+    __syncthreads();
+    RadAcc T = sh[0];
+    for (int w = 1; w < NW; ++w) T.add(sh[w]);
+    __syncthreads();
+    r = T;
   }
 };
 
@@ -246,6 +308,31 @@ __global__ __launch_bounds__(256) void limb_mm_kernel(MmParams prm) {
                 status_of(out, fell_back));
 }
 
+// One wave per output entry, the entry's terms split over the lanes and
+// merged as in limb_dot_kernel: for products with few entries, where one
+// lane per entry would leave most of the machine idle and run each entry's
+// terms one after another.  Four entries per workgroup.
+template <int NS, int NA>
+__global__ __launch_bounds__(256) void limb_mm_wave_kernel(MmParams prm) {
+  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (e >= prm.M * prm.K) return;   // whole waves leave together
+  const int64_t i = e / prm.K, j = e - i * prm.K;
+  const int64_t abase = prm.a_off + i * prm.a_rs;
+  const int64_t bbase = prm.b_off + j * prm.b_cs;
+  DotOut<NS> out;
+  MmSrc<Opnd<NA>> src{&prm, abase, bbase};
+  run_dot<NS, Opnd<NA>, WaveReducer>(src, prm.p, !prm.approx, out);
+  bool fell_back = false;
+  if (out.st.bad) {   // uniform across the wave
+    MmSrc<SOpnd> s2{&prm, abase, bbase};
+    run_dot<NS, SOpnd, WaveReducer>(s2, prm.p, !prm.approx, out);
+    fell_back = true;
+  }
+  if ((threadIdx.x & 63) == 0)
+    store_out<NS>(prm.C, prm.c_off + i * prm.c_rs + j * prm.c_cs, out, prm.p, prm.approx,
+                  status_of(out, fell_back));
+}
+
 // Listed entries (index i K + j) of a matrix product, one lane each, as
 // limb_mm_kernel: the exact recomputation of the entries whose truncation
 // a truncated integer product could not certify.  The grid strides over
@@ -286,12 +373,30 @@ __global__ __launch_bounds__(64) void limb_dot_kernel(DotParams prm) {
   if (threadIdx.x == 0) store_out<NS>(prm.R, prm.res_idx, out, prm.p, prm.approx, status_of(out, fell_back));
 }
 
+// One workgroup of four waves per dot product: the terms split over 256
+// lanes, the waves' windows, error counts and radius sums added in LDS.
+// The result is limb_dot_kernel's bit for bit.
+template <int NS, int NA>
+__global__ __launch_bounds__(256) void limb_dot_block_kernel(DotParams prm) {
+  DotOut<NS> out;
+  DotSrc<Opnd<NA>> src{&prm};
+  run_dot<NS, Opnd<NA>, BlockReducer<4>>(src, prm.p, !prm.approx, out, prm.reduce != 0);
+  bool fell_back = false;
+  if (out.st.bad) {   // uniform across the workgroup
+    DotSrc<SOpnd> s2{&prm};
+    run_dot<NS, SOpnd, BlockReducer<4>>(s2, prm.p, !prm.approx, out, prm.reduce != 0);
+    fell_back = true;
+  }
+  if (threadIdx.x == 0) store_out<NS>(prm.R, prm.res_idx, out, prm.p, prm.approx, status_of(out, fell_back));
+}
+
 // Persistent batch: waves take tasks from a work counter until the list
 // of this shape is exhausted.  A task is one dot output as in
 // limb_dot_kernel (order entry e >= 0: dot task e), or a tile of 64
-// entries of one row of a matrix product, one entry per lane as in
-// limb_mm_kernel (e < 0: tile -e - 1).  Four independent waves per
-// workgroup.
+// entries of one row of a matrix product (e < 0: tile -e - 1), one entry
+// per lane as in limb_mm_kernel or, for products that run a wave per
+// entry alone, entry by entry as in limb_mm_wave_kernel.  Four independent
+// waves per workgroup.
 template <int NS, int NA>
 __global__ __launch_bounds__(256) void limb_dot_batch_kernel(BatchShapeParams bp) {
   const int lane = threadIdx.x & 63;
@@ -307,6 +412,25 @@ __global__ __launch_bounds__(256) void limb_dot_batch_kernel(BatchShapeParams bp
     if (e < 0) {
       const BatchTile tl = gp(bp.tiles)[-e - 1];
       const ARB_GLOBAL MmParams *mp = gp(bp.mm) + tl.part;
+      if (tl.wave) {   // entry by entry, the terms split over the lanes
+        const int64_t i = tl.i, jend = tl.j0 + 64 < mp->K ? tl.j0 + 64 : mp->K;
+        for (int64_t j = tl.j0; j < jend; ++j) {
+          const int64_t abase = mp->a_off + i * mp->a_rs, bbase = mp->b_off + j * mp->b_cs;
+          DotOut<NS> out;
+          MmSrc<Opnd<NA>, const ARB_GLOBAL MmParams *> src{mp, abase, bbase};
+          run_dot<NS, Opnd<NA>, WaveReducer>(src, mp->p, !mp->approx, out);
+          bool fell_back = false;
+          if (out.st.bad) {
+            MmSrc<SOpnd, const ARB_GLOBAL MmParams *> s2{mp, abase, bbase};
+            run_dot<NS, SOpnd, WaveReducer>(s2, mp->p, !mp->approx, out);
+            fell_back = true;
+          }
+          if (lane == 0)
+            store_out<NS>(mp->C, mp->c_off + i * mp->c_rs + j * mp->c_cs, out, mp->p, mp->approx,
+                          status_of(out, fell_back));
+        }
+        continue;
+      }
       const int64_t i = tl.i, j = tl.j0 + lane;
       if (j < mp->K) {
         const int64_t abase = mp->a_off + i * mp->a_rs, bbase = mp->b_off + j * mp->b_cs;

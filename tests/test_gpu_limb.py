@@ -282,3 +282,72 @@ def test_config2_row_block_sampled(ctx):
     cols = {j: [gen.to_canonical(w.B, k * w.K + j) for k in range(w.N)] for _, j in ent}
     check_real(out, st, lambda i, j: oracle.dot(rows[i], cols[j], w.p), ent, w.K)
     assert (st <= 1).all()
+
+
+def test_long_dot_on_four_waves_equals_batch_and_oracle(ctx):
+    # a single dot of 1024 real terms or more runs on a workgroup of four
+    # waves; the same dot inside a batch runs on one wave: window sums are
+    # modular and the radius sum exact, so every bit agrees
+    import torch
+    rng = gen.rng_for(37, 0)
+    for N, p, cplx in ((1500, 200, False), (5000, 64, False), (700, 512, True)):
+        nparts = 2 if cplx else 1
+        X = [gen.random_operands(rng, N, rng.integers(1, p + 40, N), -20, 20, radius_shift=p, zero_frac=0.02)
+             for _ in range(nparts)]
+        Y = [gen.random_operands(rng, N, rng.integers(1, p + 40, N), -20, 20, radius_shift=p - 5)
+             for _ in range(nparts)]
+        dX = [arbgpu.DeviceArray.from_host(x) for x in X]
+        dY = [arbgpu.DeviceArray.from_host(y) for y in Y]
+        flags = arbgpu.COMPLEX if cplx else 0
+        single = [arbgpu.DeviceOut.empty(1, p) for _ in range(nparts)]
+        batched = [arbgpu.DeviceOut.empty(1, p) for _ in range(nparts)]
+        say(f"four-wave dot N={N} p={p} complex={cplx}")
+        ctx.dot_raw([o.out() for o in single], 0, None, 0, False, [d.arr() for d in dX], 0, 1,
+                    [d.arr() for d in dY], 0, 1, N, p, flags)
+        b = arbgpu.Batch(ctx, [arbgpu.dot_job([o.out() for o in batched], 0, [d.arr() for d in dX], 0, 1,
+                                              [d.arr() for d in dY], 0, 1, N, p, flags)])
+        b.launch()
+        torch.cuda.synchronize()
+        b.close()
+        for q in range(nparts):
+            (a, sa), (c, sc) = single[q].to_host(), batched[q].to_host()
+            assert np.array_equal(a.limbs, c.limbs) and np.array_equal(a.exp, c.exp)
+            assert np.array_equal(a.nls, c.nls) and np.array_equal(sa, sc)
+            assert np.array_equal(a.rad_m, c.rad_m) and np.array_equal(a.rad_e, c.rad_e)
+        if cplx:
+            xs = [(gen.to_canonical(X[0], k), gen.to_canonical(X[1], k)) for k in range(N)]
+            ys = [(gen.to_canonical(Y[0], k), gen.to_canonical(Y[1], k)) for k in range(N)]
+            want = oracle.cdot(xs, ys, p)
+        else:
+            want = (oracle.dot([gen.to_canonical(X[0], k) for k in range(N)],
+                               [gen.to_canonical(Y[0], k) for k in range(N)], p),)
+        for q in range(nparts):
+            ops, st = single[q].to_host()
+            assert compare_entry(gen.to_canonical(ops, 0), want[q], int(st[0])) is None, (N, p, q)
+
+
+def test_small_products_wave_per_entry_match_oracle(ctx):
+    # products with few entries run a wave per entry (terms split over the
+    # lanes); every entry against the oracle, real and complex, balls
+    rng = gen.rng_for(38, 0)
+    for M, N, K, p, cplx in ((3, 200, 5, 128, False), (7, 33, 2, 300, True), (1, 1, 1, 64, False)):
+        parts = [gen.random_operands(rng, c, rng.integers(1, p + 30, c), -8, 8, radius_shift=p, zero_frac=0.05)
+                 for c in ((M * N, N * K) * (2 if cplx else 1))]
+        A, B = parts[0], parts[1]
+        Ai, Bi = (parts[2], parts[3]) if cplx else (None, None)
+        say(f"wave-per-entry product {M}x{N}x{K} p={p} complex={cplx}")
+        (out, st), im = run_matmul(ctx, A, B, M, N, K, p, arbgpu.ALGO_LIMB | (arbgpu.COMPLEX if cplx else 0),
+                                   Ai=Ai, Bi=Bi)
+        for i in range(M):
+            for j in range(K):
+                if cplx:
+                    x = [(gen.to_canonical(A, i * N + k), gen.to_canonical(Ai, i * N + k)) for k in range(N)]
+                    y = [(gen.to_canonical(B, k * K + j), gen.to_canonical(Bi, k * K + j)) for k in range(N)]
+                    re, imv = oracle.cdot(x, y, p)
+                    assert compare_entry(gen.to_canonical(out, i * K + j), re, int(st[i * K + j])) is None
+                    (oi, si) = im
+                    assert compare_entry(gen.to_canonical(oi, i * K + j), imv, int(si[i * K + j])) is None
+                else:
+                    want = oracle.dot([gen.to_canonical(A, i * N + k) for k in range(N)],
+                                      [gen.to_canonical(B, k * K + j) for k in range(N)], p)
+                    assert compare_entry(gen.to_canonical(out, i * K + j), want, int(st[i * K + j])) is None

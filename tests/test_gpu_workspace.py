@@ -92,11 +92,14 @@ def test_footprint_bounds_the_workspace(n, p, cplx):
     ctx = arbgpu.Context(0)
     cm, am, bm = pr.mats()
     fp = ctx.footprint_raw(am, bm, pr.p, pr.flags)
+    ctx.timing(True)
     pr.run(ctx)
+    int8 = ctx.timing_read("mfma")[1] > 0
+    ctx.timing(False)
     allocs, held = ctx.workspace_info()
-    say(f"n={n} p={p} complex={cplx}: footprint {fp}, held {held} in {allocs} buffers")
+    say(f"n={n} p={p} complex={cplx}: footprint {fp}, held {held} in {allocs} buffers, int8 path {int8}")
     assert held <= fp
-    if n >= 30:   # shorter inner lengths take the limb kernel, which needs no workspace
+    if int8:   # the limb kernel needs no workspace
         assert held > 0
     ctx.close()
 
