@@ -111,14 +111,14 @@ __device__ __forceinline__ void digit_words4(const RnsSliceParams &P, const Slic
   }
 }
 
-// Residue of S = 256 shi + slo = sum_a d_a 256^a modulo p, balanced and
-// split into its int8 digits (lo, hi), returned as the bytes lo | hi << 8.
+// Residue of S = sum_a d_a 256^a (the lo sum plus 256 times the hi sum of
+// the weight digits) modulo p, balanced and split into its int8 digits
+// (lo, hi), returned as the bytes lo | hi << 8.
 // |S| < 2^30 (4 nw <= 508 digits of |d_a| <= 128 against weight digits of
 // magnitude <= 128 and <= 64), so S + kp, kp = p ceil(2^30 / p), lies in
 // [0, 2^32).
-__device__ __forceinline__ uint32_t residue_digits(uint32_t p, uint32_t mu, uint32_t kp, int32_t slo,
-                                                   int32_t shi) {
-  const uint32_t r = mod_u32((uint32_t)((shi << 8) + slo) + kp, p, mu);
+__device__ __forceinline__ uint32_t residue_digits(uint32_t p, uint32_t mu, uint32_t kp, int32_t sum) {
+  const uint32_t r = mod_u32((uint32_t)sum + kp, p, mu);
   const int32_t rb = r > (p >> 1) ? (int32_t)r - (int32_t)p : (int32_t)r;   // balanced, |rb| < 2^14
   const int32_t lo = ((rb + 128) & 255) - 128;
   return ((uint32_t)lo & 0xFFu) | ((((uint32_t)(rb - lo) >> 8) & 0xFFu) << 8);
@@ -144,12 +144,15 @@ __device__ __forceinline__ void frag_load4(v4i (&f)[4], const int8_t *a, int k0,
 // LDS row of kd bytes (+16 so that 8 consecutive rows fall in distinct
 // 16-byte bank groups).  Phase 2: each wave takes one or two blocks of 32
 // elements and loads each tile of 16 primes' weight fragments once for
-// them; per block and tile one 32 x 32 MFMA result, whose lane l holds the
-// (lo, hi) sums of 8 primes for element l % 32, reduced modulo p_j to two
-// int8 residue digits; a byte transpose within quads of lanes turns each lane's 4
-// digits of one element into 4 elements' digits of one plane, stored as
-// one word (the padded plane holds whole blocks of 32 elements and starts
-// 16-byte aligned).
+// them; per block and tile one 32 x 32 MFMA result (elements x weight
+// digits), whose lane l holds the lo or hi sum of one prime for 16
+// elements.  Lane pairs combine lo + 256 hi by DPP exchanges; each lane of
+// the pair reduces 8 of the 16 elements (its prime's constants sit in
+// registers, loaded a tile ahead) and stores the residue digits of 8
+// consecutive elements (the LDS rows are permuted for that) as 8 bytes of
+// each of the prime's two planes, the four lanes of a prime covering the
+// block's 32 bytes per store (the padded plane holds whole blocks of 32
+// elements and starts 16-byte aligned).
 //
 // Registers are capped for five waves per SIMD (four otherwise): at 2048^2
 // p = 512 the two operands' slicing took 1.24 -> 1.20 ms with that, despite
@@ -169,19 +172,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
       const int64_t line = gid / P.k_pad;
       e = slice_elem(P, line, gid - line * P.k_pad);
     }
+    // element x of a block of 32 sits in LDS row 16 x2 + 8 x4 + 4 x3 + x%4
+    // (x_b: bit b of x): the MFMA result row 8 G + 4 h + i then holds
+    // element 16 (G % 2) + 8 h + 4 (G / 2) + i, so that each lane reduces
+    // 8 consecutive elements
+    const int x = tid & 31;
+    const int row = (tid & ~31) | (((x >> 2) & 1) << 4) | ((x >> 4) << 3) | (((x >> 3) & 1) << 2) | (x & 3);
     uint32_t cy = 0;
     for (int w4 = 0; w4 < kd / 16; ++w4) {
       uint32_t x[4] = {0u, 0u, 0u, 0u};
       if (4 * w4 < nw) digit_words4(P, e, w4, cy, x);   // words past nw have no digits (bmask 0)
-      *reinterpret_cast<uint4 *>(dl + (size_t)tid * S + 16 * w4) = make_uint4(x[0], x[1], x[2], x[3]);
+      *reinterpret_cast<uint4 *>(dl + (size_t)row * S + 16 * w4) = make_uint4(x[0], x[1], x[2], x[3]);
     }
   }
   __syncthreads();
-  const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, q = lane & 3;
-  // byte selectors of the two transpose steps (quad partners at lane
-  // distance 2, then 1)
-  const uint32_t sel1 = q < 2 ? 0x05040100u : 0x03020706u;
-  const uint32_t sel2 = (q & 1) ? 0x03070105u : 0x06020400u;
+  // D = (element digits) x (weight digits): lane l holds column c = l % 32
+  // of each 32 x 32 result, the lo (even c) or hi (odd c) sum of prime
+  // 16 rt + c / 2, for elements 8 G + 4 h + i in register 4 G + i
+  const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, c = lane & 31, d = c & 1;
   // blocks of 32 elements per wave (waves past EL / 32 have none); the
   // weight fragments of a prime tile are loaded once for all of them
   constexpr int NBW = EL >= 128 ? EL / 128 : 1;
@@ -191,19 +199,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   bool inside[NBW];
 #pragma unroll
   for (int b = 0; b < NBW; ++b) {
-    const int wv = wave + 4 * b;
-    drow[b] = dl + (size_t)(32 * wv + (lane & 31)) * S + 16 * h;
-    // this lane stores elements 4 e' .. 4 e' + 3 (e' = (lane % 32) / 4) of
-    // its planes
-    out[b] = P.planes + g0 + 32 * wv + (lane & 28);
+    const int wv = NBW * wave + b;   // a wave's blocks are adjacent: 64-byte runs per plane
+    drow[b] = dl + (size_t)(32 * wv + c) * S + 16 * h;
+    // this lane reduces and stores elements 16 d + 8 h .. + 7 of the two
+    // planes of its prime
+    out[b] = P.planes + g0 + 32 * wv + 16 * d + 8 * h;
     inside[b] = g0 + 32 * wv < total;
   }
   const int nrt = (m + 15) / 16, nks = kd / 32;
-  const int8_t *wbase = P.tab.wd + (int64_t)(lane & 31) * kd + 16 * h;
+  const int8_t *wbase = P.tab.wd + (int64_t)c * kd + 16 * h;
   v4i fnext[4];
   frag_load4(fnext, wbase, 0, nks);
+  // reduction constants of this lane's prime, loaded a tile ahead
+  int jn = min(c >> 1, m - 1);
+  uint32_t pn = (uint32_t)P.tab.prime[jn], mun = P.tab.mu[jn], kpn = P.tab.kp[jn];
   for (int rt = 0; rt < nrt; ++rt) {
     const int8_t *wrow = wbase + (int64_t)rt * 32 * kd;
+    const uint32_t pj = pn, muj = mun, kpj = kpn;
+    const int j = 16 * rt + (c >> 1);
+    if (rt + 1 < nrt) {
+      jn = min(j + 16, m - 1);
+      pn = (uint32_t)P.tab.prime[jn];
+      mun = P.tab.mu[jn];
+      kpn = P.tab.kp[jn];
+    }
     v16i acc[NBW];
 #pragma unroll
     for (int b = 0; b < NBW; ++b)
@@ -230,36 +249,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (k0 + u < nks) acc[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[u], fb[u], acc[b], 0, 0, 0);
+          if (k0 + u < nks) acc[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fb[u], fa[u], acc[b], 0, 0, 0);
       }
     }
 #pragma unroll
     for (int b = 0; b < NBW; ++b) {
-      // register 4 G + 2 t (+1): lo (hi) sum of prime 16 rt + 8 h + 2 G + t,
-      // whose digits are planes 2 (8 h + 2 G + t) (+1) of the tile; the
-      // constants of both lane halves come by scalar loads
-      uint32_t wd[4];
+      // lo + 256 hi per element from the lane pair (2u, 2u + 1): the even
+      // lane reduces registers 8 g + i (elements 8 h + 4 g + i), the odd
+      // lane registers 8 g + 4 + i (elements 16 + 8 h + 4 g + i); each
+      // forms both candidates with one DPP exchange each and keeps its own
+      uint32_t w[8];
 #pragma unroll
-      for (int G = 0; G < 4; ++G) {
-        wd[G] = 0u;
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const int j0 = min(16 * rt + 2 * G + t, m - 1), j1 = min(j0 + 8, m - 1);
-          const uint32_t p0 = (uint32_t)cp(P.tab.prime)[j0], mu0 = cp(P.tab.mu)[j0], k0 = cp(P.tab.kp)[j0];
-          const uint32_t p1 = (uint32_t)cp(P.tab.prime)[j1], mu1 = cp(P.tab.mu)[j1], k1 = cp(P.tab.kp)[j1];
-          wd[G] |= residue_digits(h ? p1 : p0, h ? mu1 : mu0, h ? k1 : k0, acc[b][4 * G + 2 * t],
-                                  acc[b][4 * G + 2 * t + 1]) << (16 * t);
-        }
+      for (int k = 0; k < 8; ++k) {
+        const int re = 8 * (k >> 2) + (k & 3), ro = re + 4;
+        const int32_t te = __builtin_amdgcn_mov_dpp(acc[b][re], 0xB1, 0xF, 0xF, false);
+        const int32_t to = __builtin_amdgcn_mov_dpp(acc[b][ro], 0xB1, 0xF, 0xF, false);
+        const int32_t se = acc[b][re] + (te << 8), so = to + (acc[b][ro] << 8);
+        w[k] = residue_digits(pj, muj, kpj, d ? so : se);
       }
-      // 4 x 4 byte transpose within each quad of lanes: lane 4 e' + q then
-      // holds plane 32 rt + 16 h + 4 G + q of elements 4 e' .. 4 e' + 3
+      if (j < m && inside[b]) {
+        // bytes (lo, hi) of the 8 consecutive elements into two words of
+        // each plane
+        uint32_t lo[2], hi[2];
 #pragma unroll
-      for (int G = 0; G < 4; ++G) {
-        const uint32_t x = __builtin_amdgcn_perm((uint32_t)__builtin_amdgcn_mov_dpp((int)wd[G], 0x4E, 0xF, 0xF, false),
-                                                 wd[G], sel1);
-        wd[G] = __builtin_amdgcn_perm((uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false), x, sel2);
-        const int plane = 32 * rt + 16 * h + 4 * G + q;
-        if (plane < 2 * m && inside[b]) *reinterpret_cast<uint32_t *>(out[b] + (int64_t)plane * total) = wd[G];
+        for (int g = 0; g < 2; ++g) {
+          const uint32_t x01 = __builtin_amdgcn_perm(w[4 * g + 1], w[4 * g], 0x05010400u);
+          const uint32_t x23 = __builtin_amdgcn_perm(w[4 * g + 3], w[4 * g + 2], 0x05010400u);
+          lo[g] = __builtin_amdgcn_perm(x23, x01, 0x05040100u);
+          hi[g] = __builtin_amdgcn_perm(x23, x01, 0x07060302u);
+        }
+        int8_t *o = out[b] + (int64_t)(2 * j) * total;
+        *reinterpret_cast<uint2 *>(o) = make_uint2(lo[0], lo[1]);
+        *reinterpret_cast<uint2 *>(o + total) = make_uint2(hi[0], hi[1]);
       }
     }
   }

@@ -132,9 +132,8 @@ struct RnsTables {
   const uint32_t *kp;       // [m] p ceil(2^30 / p): makes values above -2^30 nonnegative
   // [nrt][32][kd] int8 digits (lo, hi) of the balanced 256^a mod p_j,
   // inner index a < 4 nw (zero beyond); row r of tile rt holds prime
-  // 16 rt + 8 ((r / 4) % 2) + 2 (r / 8) + (r / 2) % 2, lo for even r and hi
-  // for odd r (lane half h of a 32 x 32 MFMA result then holds the (lo, hi)
-  // pairs of primes 16 rt + 8 h .. + 7), nrt = ceil(m / 16)
+  // 16 rt + r / 2, lo for even r and hi for odd r (column r of a 32 x 32
+  // MFMA result, lane pairs then hold a prime's two sums), nrt = ceil(m / 16)
   const int8_t *wd;
   const uint32_t *c;        // [m] (P / p_j)^-1 mod p_j, P = prod p_j
   const double *rp;         // [m] 1 / p_j

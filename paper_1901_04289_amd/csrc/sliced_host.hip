@@ -257,9 +257,8 @@ int rns_tables(arbgpu_ctx *ctx, int m, int nw, int W, hipStream_t s, RnsTables &
     hmu[j] = (uint32_t)((((uint64_t)1) << 32) / (uint64_t)p);
     hkp[j] = (uint32_t)((((int64_t)1 << 30) + p - 1) / p * p);
     hrp[j] = 1.0 / (double)p;
-    // weight digits of prime j: tile j / 16, rows r with lo at even r
-    const int jt = j % 16;
-    const int rlo = 4 * ((jt >> 3) & 1) + 8 * ((jt >> 1) & 3) + 2 * (jt & 1);
+    // weight digits of prime j: tile j / 16, row 2 (j % 16) lo, + 1 hi
+    const int rlo = 2 * (j % 16);
     int8_t *wlo = hwd + ((size_t)(j / 16) * 32 + rlo) * kd, *whi = wlo + kd;
     int64_t w = 1;   // 256^a mod p
     for (int a = 0; a < 4 * nw; ++a) {
