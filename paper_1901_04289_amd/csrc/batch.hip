@@ -28,15 +28,16 @@ __global__ void batch_reset_kernel(int32_t *c, int n) {
 constexpr int kDefaultWaves = 8;          // waves per compute unit
 constexpr int kTuneWaves[] = {1, 2, 4, 8, 16};
 
-std::string tune_key(LimbShape sh) {
-  return "dot_batch:" + std::to_string(sh.ns) + "x" + std::to_string(sh.na);
+std::string tune_key(LimbShape sh, bool block) {
+  return "dot_batch:" + std::to_string(sh.ns) + "x" + std::to_string(sh.na) + (block ? ":w4" : "");
 }
 
 struct ShapeRun {
   LimbShape sh;
+  bool block;             // long dots: four waves per task
   int64_t begin, count;   // slice of the order array
   int waves;              // per compute unit
-  float tuned_ms;         // time of this shape alone at `waves` (0: not tuned)
+  float tuned_ms;         // time of this run alone at `waves` (0: not tuned)
 };
 
 // The work of a batch: dot tasks, matrix-product parts and their tiles,
@@ -142,12 +143,17 @@ int plan_batch(arbgpu_ctx *ctx, const arbgpu_dot_job *dots, const arbgpu_job *jo
   if (nd + nt > (size_t)0x7FFFFFFF) return set_error(ctx, ARBGPU_EINVAL, "%s: too much work in one batch", who);
   auto shape = [&](size_t w) -> const LimbShape & { return w < nd ? shape_dot[w] : shape_tile[w - nd]; };
   auto cost = [&](size_t w) { return w < nd ? cost_dot[w] : cost_tile[w - nd]; };
+  // dots of kDotBlockTerms real terms or more run on four waves each
+  auto is_long = [&](size_t w) {
+    return w < nd && shape_dot[w].ns > 0 && bp.tasks[w].N * bp.tasks[w].ct.ncomp >= kDotBlockTerms;
+  };
   std::vector<int32_t> work(nd + nt);
   for (size_t w = 0; w < work.size(); ++w) work[w] = (int32_t)w;
   std::stable_sort(work.begin(), work.end(), [&](int32_t x, int32_t y) {
     const LimbShape &a = shape(x), &c = shape(y);
     if (a.ns != c.ns) return a.ns > c.ns;
     if (a.na != c.na) return a.na > c.na;
+    if (is_long(x) != is_long(y)) return is_long(x);
     return cost(x) > cost(y);
   });
   bp.order.resize(work.size());
@@ -155,17 +161,21 @@ int plan_batch(arbgpu_ctx *ctx, const arbgpu_dot_job *dots, const arbgpu_job *jo
     const size_t w = (size_t)work[t];
     bp.order[t] = w < nd ? (int32_t)w : -(int32_t)(w - nd) - 1;
     const LimbShape &sh = shape(w);
-    if (bp.runs.empty() || bp.runs.back().sh.ns != sh.ns || bp.runs.back().sh.na != sh.na) {
-      auto it = ctx->tune.find(tune_key(sh));
-      bp.runs.push_back({sh, (int64_t)t, 0, it != ctx->tune.end() ? it->second : kDefaultWaves, 0.f});
+    const bool blk = is_long(w);
+    if (bp.runs.empty() || bp.runs.back().sh.ns != sh.ns || bp.runs.back().sh.na != sh.na ||
+        bp.runs.back().block != blk) {
+      auto it = ctx->tune.find(tune_key(sh, blk));
+      bp.runs.push_back({sh, blk, (int64_t)t, 0, it != ctx->tune.end() ? it->second : kDefaultWaves, 0.f});
     }
     bp.runs.back().count++;
   }
   return ARBGPU_OK;
 }
 
-unsigned blocks_for(int64_t count, int waves, int num_cu) {
-  const int64_t by_work = (count + 3) / 4;
+// Workgroups of a persistent run: four tasks per workgroup (a wave each),
+// or one (block runs), at most `waves` waves per compute unit.
+unsigned blocks_for(int64_t count, int waves, int num_cu, bool block) {
+  const int64_t by_work = block ? count : (count + 3) / 4;
   const int64_t by_width = std::max<int64_t>(1, (int64_t)num_cu * waves / 4);
   return (unsigned)std::max<int64_t>(1, std::min(by_work, by_width));
 }
@@ -213,8 +223,8 @@ int dot_batch_run(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, hi
     }
     BatchShapeParams bp{d_tasks, nullptr, nullptr, d_order + runs[k].begin, runs[k].count, d_ctr + k};
     void *args[] = {&bp};
-    e = hipLaunchKernel(dot_batch_kernel(runs[k].sh), dim3(blocks_for(runs[k].count, runs[k].waves, ncu)),
-                        dim3(256), args, 0, s);
+    e = hipLaunchKernel(dot_batch_kernel(runs[k].sh, runs[k].block),
+                        dim3(blocks_for(runs[k].count, runs[k].waves, ncu, runs[k].block)), dim3(256), args, 0, s);
   }
   // the host task list must outlive its asynchronous upload
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -245,7 +255,7 @@ struct arbgpu_batch {
       if (q) (void)hipFree(q);
   }
 
-  unsigned blocks_for(const ShapeRun &r, int waves) const { return ::blocks_for(r.count, waves, num_cu); }
+  unsigned blocks_for(const ShapeRun &r, int waves) const { return ::blocks_for(r.count, waves, num_cu, r.block); }
 
   BatchShapeParams params(size_t k) const {
     return BatchShapeParams{d_tasks, d_mm, d_tiles, d_order + runs[k].begin, runs[k].count, d_counters + k};
@@ -284,7 +294,7 @@ struct arbgpu_batch {
         np.sharedMemBytes = (unsigned)lds;
         np.kernelParams = wargs;
       } else {
-        np.func = const_cast<void *>(dot_batch_kernel(runs[k].sh));
+        np.func = const_cast<void *>(dot_batch_kernel(runs[k].sh, runs[k].block));
         np.gridDim = dim3(blocks_for(runs[k], runs[k].waves));
         np.kernelParams = args;
       }
@@ -396,8 +406,8 @@ int arbgpu_batch_tune(arbgpu_batch *b, arbgpu_stream stream) {
         e = hipLaunchKernel(reinterpret_cast<const void *>(&batch_reset_kernel), dim3(1), dim3(256), rargs, 0, s);
         if (e == hipSuccess) e = hipEventRecord(t0, s);
         if (e == hipSuccess)
-          e = hipLaunchKernel(dot_batch_kernel(b->runs[k].sh), dim3(b->blocks_for(b->runs[k], w)), dim3(256), args,
-                              0, s);
+          e = hipLaunchKernel(dot_batch_kernel(b->runs[k].sh, b->runs[k].block), dim3(b->blocks_for(b->runs[k], w)),
+                              dim3(256), args, 0, s);
         if (e == hipSuccess) e = hipEventRecord(t1, s);
         if (e == hipSuccess) e = hipEventSynchronize(t1);
         float ms = 0.f;
@@ -412,7 +422,7 @@ int arbgpu_batch_tune(arbgpu_batch *b, arbgpu_stream stream) {
     }
     b->runs[k].waves = best_w;
     b->runs[k].tuned_ms = best;
-    ctx->tune[tune_key(b->runs[k].sh)] = best_w;
+    ctx->tune[tune_key(b->runs[k].sh, b->runs[k].block)] = best_w;
   }
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);

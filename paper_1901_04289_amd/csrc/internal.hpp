@@ -240,8 +240,10 @@ struct BatchShapeParams {
   int32_t *counter;         // work counter, zero before the launch
 };
 template <int NS, int NA>
-const void *dot_batch_kernel_shape();
-const void *dot_batch_kernel(LimbShape sh);   // kernel taking (BatchShapeParams)
+const void *dot_batch_kernel_shape(bool block);
+// kernel taking (BatchShapeParams): a wave per task, or (block) a
+// workgroup of four waves per dot task
+const void *dot_batch_kernel(LimbShape sh, bool block = false);
 
 // One-shot batch of dot jobs on stream s (validated here; the task list is
 // staged in the context workspace; synchronizes s).

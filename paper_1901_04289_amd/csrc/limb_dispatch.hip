@@ -51,9 +51,9 @@ hipError_t launch_limb_mm_list(const MmParams &prm, LimbShape sh, const int64_t 
   return hipErrorInvalidValue;
 }
 
-const void *dot_batch_kernel(LimbShape sh) {
+const void *dot_batch_kernel(LimbShape sh, bool block) {
 #define X(a, b) \
-  if (sh.ns == a && sh.na == b) return dot_batch_kernel_shape<a, b>();
+  if (sh.ns == a && sh.na == b) return dot_batch_kernel_shape<a, b>(block);
   ARB_LIMB_SHAPES(X)
 #undef X
   return nullptr;

@@ -44,8 +44,9 @@ hipError_t launch_dot_shape<ARB_NS, ARB_NA>(const DotParams &prm, hipStream_t s)
 }
 
 template <>
-const void *dot_batch_kernel_shape<ARB_NS, ARB_NA>() {
-  return reinterpret_cast<const void *>(&limb_dot_batch_kernel<ARB_NS, ARB_NA>);
+const void *dot_batch_kernel_shape<ARB_NS, ARB_NA>(bool block) {
+  return block ? reinterpret_cast<const void *>(&limb_dot_batch_block_kernel<ARB_NS, ARB_NA>)
+               : reinterpret_cast<const void *>(&limb_dot_batch_kernel<ARB_NS, ARB_NA>);
 }
 
 }  // namespace arbgpu_impl

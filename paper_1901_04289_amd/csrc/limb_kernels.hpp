@@ -462,4 +462,31 @@ __global__ __launch_bounds__(256) void limb_dot_batch_kernel(BatchShapeParams bp
   }
 }
 
+// Persistent batch, long dots: each workgroup of four waves takes one dot
+// task at a time from the shape's counter and runs it as
+// limb_dot_block_kernel (same bits as one wave).
+template <int NS, int NA>
+__global__ __launch_bounds__(256) void limb_dot_batch_block_kernel(BatchShapeParams bp) {
+  __shared__ int task;
+  for (int64_t iter = 0; iter <= bp.count; ++iter) {
+    if (threadIdx.x == 0) task = atomicAdd(bp.counter, 1);
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(task);
+    __syncthreads();   // every thread has read it before the next take
+    if (t >= bp.count) break;   // uniform across the workgroup
+    const int32_t e = __builtin_amdgcn_readfirstlane(gp(bp.order)[t]);
+    const ARB_GLOBAL DotParams *prm = gp(bp.tasks) + e;
+    DotOut<NS> out;
+    DotSrc<Opnd<NA>, const ARB_GLOBAL DotParams *> src{prm};
+    run_dot<NS, Opnd<NA>, BlockReducer<4>>(src, prm->p, !prm->approx, out, prm->reduce != 0);
+    bool fell_back = false;
+    if (out.st.bad) {
+      DotSrc<SOpnd, const ARB_GLOBAL DotParams *> s2{prm};
+      run_dot<NS, SOpnd, BlockReducer<4>>(s2, prm->p, !prm->approx, out, prm->reduce != 0);
+      fell_back = true;
+    }
+    if (threadIdx.x == 0) store_out<NS>(prm->R, prm->res_idx, out, prm->p, prm->approx, status_of(out, fell_back));
+  }
+}
+
 }  // namespace arbgpu_impl
