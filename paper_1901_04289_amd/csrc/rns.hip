@@ -349,12 +349,16 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
         const int j = 8 * g + u;
         if (j < m) {
           const uint32_t p = (uint32_t)cp(P.tab.prime)[j], mu = cp(P.tab.mu)[j];
-          // sum of at most three residues in [-p, p), made nonnegative
-          int32_t rs = 3 * (int32_t)p;
+          // y = (sum of at most three residues in [-p, p)) times c mod p,
+          // with c balanced (|c| < p / 2): |sum c| < 1.5 p^2 < 1.5 2^30, and
+          // 2 kp (a multiple of p in [2^31, 2^31 + 2p)) keeps the value
+          // nonnegative and below 2^32, so one reduction suffices
+          const int32_t cj = (int32_t)cp(P.tab.c)[j];
+          const int32_t cb = cj > (int32_t)(p >> 1) ? cj - (int32_t)p : cj;
+          int32_t rs = 0;
 #pragma unroll
           for (int c = 0; c < 3; ++c) rs += c < P.nsrc ? P.sgn[c] * dv[u][c] : 0;
-          const uint32_t r = mod_u32((uint32_t)rs, p, mu);
-          const uint32_t y = mod_u32(r * cp(P.tab.c)[j], p, mu);
+          const uint32_t y = mod_u32((uint32_t)(rs * cb) + 2u * cp(P.tab.kp)[j], p, mu);
           int32_t yb = y > (p >> 1) ? (int32_t)y - (int32_t)p : (int32_t)y;
           yb = live ? yb : 0;
           alpha += (double)yb * cp(P.tab.rp)[j];
