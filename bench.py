@@ -51,7 +51,9 @@ MFMA_KERNEL = {"residues": "mfma_rns_kernel<256>", "slices": "mfma_diag_kernel"}
 MFMA_TRAFFIC = {
     # form: (kernel source, sha256 prefix, bytes per launch)
     "residues": ("mfma_rns.hip", "f01cea3055db3e34", (1777060 * 2 + 645248) * 1024.0),
-    "slices": ("mfma.hip", "ef1395843d68b766", (30267872 * 2 + 2228224) * 1024.0),
+    # the stored base-256 figure covered the full pair set (before the
+    # truncated diagonals): only live counters report that form
+    "slices": ("mfma.hip", None, None),
 }
 
 
@@ -72,9 +74,9 @@ CALIBRATION_BYTES = 1 << 30
 
 
 def traffic_child(n):
-    """Body of a counter run: one automatic product at the benchmark size,
-    then a 1 GiB device-to-device copy whose known byte counts calibrate
-    the counters."""
+    """Body of a counter run: one automatic product at the benchmark size
+    and one on base-256 slices, then a 1 GiB device-to-device copy whose
+    known byte counts calibrate the counters."""
     import torch
     from paper_1901_04289_amd import arbgpu
     w = gen.config2(n=n)
@@ -82,6 +84,7 @@ def traffic_child(n):
     dA, dB = arbgpu.DeviceArray.from_host(w.A), arbgpu.DeviceArray.from_host(w.B)
     C = arbgpu.DeviceOut.empty(w.M * w.K, w.p, radius=True)
     ctx.mat_mul(C, dA, dB, w.M, w.N, w.K, w.p, 0)
+    ctx.mat_mul(C, dA, dB, w.M, w.N, w.K, w.p, arbgpu.ALGO_SLICED)
     torch.cuda.synchronize()
     src = torch.empty(CALIBRATION_BYTES, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
@@ -147,7 +150,7 @@ def hbm_counters(n, log):
                       "dispatches": len(vals["FETCH_SIZE"][k])}
     return {"per_dispatch": per, "fetch_scale": f_read, "write_scale": f_write,
             "source": "rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of bench.py --traffic-child "
-                      f"(one product at N={n}; counters scaled by a 1 GiB device copy)"}
+                      f"(the automatic and the base-256 product at N={n}; counters scaled by a 1 GiB device copy)"}
 
 
 # ---------------------------------------------------------------------------
@@ -626,6 +629,9 @@ def main():
             if kname in cnt["per_dispatch"]:
                 out["roofline"]["traffic"] = cnt["per_dispatch"][kname]["bytes"]
                 out["roofline"]["traffic_source"] = cnt["source"]
+            for form, kn in (("residues", "mfma_rns_kernel"), ("slices", "mfma_diag_kernel")):
+                if kn in cnt["per_dispatch"]:
+                    out["int8_forms"][form]["mfma_traffic_bytes"] = cnt["per_dispatch"][kn]["bytes"]
     # no child process outlives the run
     for c in mp.active_children():
         c.join(10)
