@@ -4,10 +4,11 @@
 // reconstruction (introduction of Section 4).  Here every scaled integer Y
 // of a block is reduced modulo m odd primes p_j < 2^15, each residue
 // (balanced, |r| < 2^14) is split into two int8 digits r = lo + 256 hi, and
-// the digit products run on the INT8 MFMA kernel as three partial planes
-// per prime (weights 1, 256, 65536).  The exact T is rebuilt per entry by
-// the explicit Chinese remainder formula, exact whenever prod p_j > 4 |T|.
-// The MFMA work is 4 m digit products instead of L_A L_B base-256 slices.
+// the digit products run on the INT8 MFMA kernel (mfma_rns.hip), which
+// folds a prime's four digit products into one int16 residue per entry.
+// The exact T is rebuilt per entry by the explicit Chinese remainder
+// formula, exact whenever prod p_j > 4 |T|.  The MFMA work is 4 m digit
+// products instead of L_A L_B base-256 slices.
 //
 // The per-prime tables are the same for every thread and are read through
 // the constant address space, so they arrive by scalar loads; the digit
@@ -131,6 +132,102 @@ __device__ __forceinline__ void frag_load4(v4i (&f)[4], const int8_t *a, int k0,
   for (int u = 0; u < 4; ++u) {
     const int ks = k0 + u < nks ? k0 + u : k0;
     f[u] = *reinterpret_cast<const v4i *>(a + 32 * ks);
+  }
+}
+
+// Rounding of one entry's T (W two's-complement limbs, limb q at T[q EW])
+// to the output, by the G threads of the entry (part 0 .. G - 1; every
+// thread of the workgroup calls it, live or not): the result of
+// finish_entry, with the limb scans split into G ranges of limbs and the
+// output limbs dealt out in turn; partial results meet in xs (G EW ints of
+// LDS).
+template <int EW, int G>
+__device__ void finish_entry_split(const uint32_t *T, int W, int64_t scale, const arbgpu_out &C, int64_t oidx, int p,
+                                   int approx, double rin_m, int rin_e, bool live, int e, int part, int32_t *xs) {
+  auto get = [&](int q) -> uint32_t { return T[q * EW]; };
+  const bool neg = (get(W - 1) >> 31) != 0;
+  const int per = (W + G - 1) / G, qa = min(W, part * per), qb = min(W, qa + per);
+  int z = W;   // lowest nonzero limb
+  for (int q = qa; q < qb; ++q)
+    if (get(q)) { z = q; break; }
+  xs[part * EW + e] = z;
+  __syncthreads();
+  z = W;
+  for (int k = 0; k < G; ++k) z = min(z, xs[k * EW + e]);
+  __syncthreads();
+  auto mag = [&](int q) -> uint32_t {
+    if (q < 0 || q >= W) return 0u;
+    const uint32_t v = get(q);
+    if (!neg) return v;
+    return q > z ? ~v : (q == z ? (uint32_t)(0u - v) : 0u);
+  };
+  int qt = -1;   // top nonzero limb of |T|
+  for (int q = qb - 1; q >= qa; --q)
+    if (mag(q)) { qt = q; break; }
+  xs[part * EW + e] = qt;
+  __syncthreads();
+  qt = -1;
+  for (int k = 0; k < G; ++k) qt = max(qt, xs[k * EW + e]);
+  __syncthreads();
+  const int PL = (p + 31) >> 5;
+  int nout = 0;
+  bool inexact = false;
+  int64_t bl = 0;
+  if (qt >= 0) {
+    bl = 32 * (int64_t)qt + (32 - __builtin_clz(mag(qt)));
+    auto bits32 = [&](int64_t lo) -> uint32_t {   // bits [lo, lo + 32) of |T|
+      const int64_t q0 = lo >= 0 ? (lo >> 5) : -((31 - lo) >> 5);
+      const uint32_t r = (uint32_t)(lo - 32 * q0);
+      const uint32_t a = mag((int)q0), b = mag((int)q0 + 1);
+      return r ? ((a >> r) | (b << (32u - r))) : a;
+    };
+    for (int k = part; k < PL; k += G) {
+      uint32_t v = bits32(bl - 32 * (int64_t)(k + 1));
+      if (k == PL - 1) v &= 0xFFFFFFFFu << (32 * PL - p);
+      if (live) C.limbs[(int64_t)k * C.ld + oidx] = v;
+      if (v) nout = k + 1;
+    }
+    // bits of |T| below position bl - p, in this thread's limbs
+    const int64_t cut = bl - p;
+    if (cut > 0) {
+      const int64_t qc = cut >> 5;
+      const uint32_t rc = (uint32_t)(cut & 31);
+      for (int q = qa; q < qb && q < qc && !inexact; ++q) inexact = mag(q) != 0;
+      if (rc && qc >= qa && qc < qb) inexact = inexact || (mag((int)qc) & ((1u << rc) - 1u)) != 0;
+    }
+  } else if (live) {
+    for (int k = part; k < PL; k += G) C.limbs[(int64_t)k * C.ld + oidx] = 0u;
+  }
+  xs[part * EW + e] = nout | (inexact ? (1 << 30) : 0);
+  __syncthreads();
+  if (part == 0 && live) {
+    int no = 0;
+    bool ix = false;
+    for (int k = 0; k < G; ++k) {
+      const int v = xs[k * EW + e];
+      no = max(no, v & 0x3FFFFFFF);
+      ix = ix || ((v >> 30) & 1);
+    }
+    if (qt < 0) {
+      C.exp[oidx] = 0;
+      C.nls[oidx] = 0;
+      if (!approx) {
+        C.rad_m[oidx] = rin_m;
+        C.rad_e[oidx] = rin_m != 0.0 ? rin_e : 0;
+      }
+    } else {
+      const int em = (int)(bl + scale);
+      C.exp[oidx] = em;
+      C.nls[oidx] = (int32_t)((uint32_t)no | (neg ? 0x80000000u : 0u));
+      if (!approx) {
+        double rm = 0.0;
+        int re = 0;
+        arb::ru_add_ext(rin_m, rin_e, ix ? 0.5 : 0.0, em - p + 1, rm, re);
+        C.rad_m[oidx] = rm;
+        C.rad_e[oidx] = re;
+      }
+    }
+    if (C.status) C.status[oidx] = ARBGPU_ST_OK;
   }
 }
 
@@ -474,35 +571,77 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
   __syncthreads();
 
   // phase 3: rounding of the entry to the output
-  if (tid < EW) {
-    const int64_t ij = e0 + tid;
-    if (ij >= MN) return;
-    uint32_t *T = tl + tid;
-    // the runs' carries, added in limb order (a chunk's 8 limbs are read
-    // together)
-    int64_t c = 0;
-    for (int cc = 0; (EW == 32 || PAIR) && cc < P.tab.ncc; ++cc) {
-      uint32_t t[8];
+  if constexpr (!PAIR) {
+    if (tid < EW) {
+      const int64_t ij = e0 + tid;
+      if (ij >= MN) return;
+      uint32_t *T = tl + tid;
+      // the runs' carries, added in limb order (a chunk's 8 limbs are read
+      // together)
+      int64_t c = 0;
+      for (int cc = 0; EW == 32 && cc < P.tab.ncc; ++cc) {
+        uint32_t t[8];
 #pragma unroll
-      for (int g = 0; g < 8; ++g) t[g] = 8 * cc + g < W ? T[(8 * cc + g) * EW] : 0u;
-      const int32_t co = cyl[cc * EW + tid];
+        for (int g = 0; g < 8; ++g) t[g] = 8 * cc + g < W ? T[(8 * cc + g) * EW] : 0u;
+        const int32_t co = cyl[cc * EW + tid];
 #pragma unroll
-      for (int g = 0; g < 8; ++g) {
-        const int64_t v = (int64_t)t[g] + c;
-        if (8 * cc + g < W) T[(8 * cc + g) * EW] = (uint32_t)v;
-        c = v >> 32;
+        for (int g = 0; g < 8; ++g) {
+          const int64_t v = (int64_t)t[g] + c;
+          if (8 * cc + g < W) T[(8 * cc + g) * EW] = (uint32_t)v;
+          c = v >> 32;
+        }
+        c += co;
       }
-      c += co;
+      if (P.t_out)
+        for (int q = 0; q < W; ++q) P.t_out[(int64_t)q * P.t_ld + ij] = T[q * EW];
+      if (!P.C.exp) return;   // the exact T only
+      const int64_t i = ij / P.N, jj = ij - i * P.N;
+      double m0 = 0.0;
+      int e0r = 0;
+      if (P.rin_m) { m0 = P.rin_m[ij]; e0r = P.rin_e[ij]; }
+      finish_entry([&](int q) { return T[q * EW]; }, W, (int64_t)P.rowv2[i] + P.colv2[jj], P.C,
+                   P.c_off + i * P.c_rs + jj * P.c_cs, P.p, P.approx, m0, e0r);
     }
-    if (P.t_out)
-      for (int q = 0; q < W; ++q) P.t_out[(int64_t)q * P.t_ld + ij] = T[q * EW];
-    if (!P.C.exp) return;   // the exact T only
-    const int64_t i = ij / P.N, jj = ij - i * P.N;
+  } else {
+    // long T (from 8 limb chunks on): the runs' carries by one thread per
+    // entry, then the rounding by all the entry's threads, its limb scans
+    // split over them (the digit rows' LDS is free now)
+    constexpr int G = 256 / EW;
+    const int e3 = tid % EW, part3 = tid / EW;
+    const int64_t ij = e0 + e3;
+    const bool live = ij < MN;
+    uint32_t *T = tl + e3;
+    if (part3 == 0 && live) {
+      int64_t c = 0;
+      for (int cc = 0; cc < P.tab.ncc; ++cc) {
+        uint32_t t[8];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) t[g] = 8 * cc + g < W ? T[(8 * cc + g) * EW] : 0u;
+        const int32_t co = cyl[cc * EW + e3];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          const int64_t v = (int64_t)t[g] + c;
+          if (8 * cc + g < W) T[(8 * cc + g) * EW] = (uint32_t)v;
+          c = v >> 32;
+        }
+        c += co;
+      }
+    }
+    __syncthreads();
+    if (P.t_out && live)
+      for (int q = part3; q < W; q += G) P.t_out[(int64_t)q * P.t_ld + ij] = T[q * EW];
+    if (!P.C.exp) return;   // the exact T only (the same for every thread)
+    int64_t scale = 0, oidx = 0;
     double m0 = 0.0;
     int e0r = 0;
-    if (P.rin_m) { m0 = P.rin_m[ij]; e0r = P.rin_e[ij]; }
-    finish_entry([&](int q) { return T[q * EW]; }, W, (int64_t)P.rowv2[i] + P.colv2[jj], P.C,
-                 P.c_off + i * P.c_rs + jj * P.c_cs, P.p, P.approx, m0, e0r);
+    if (live) {
+      const int64_t i = ij / P.N, jj = ij - i * P.N;
+      scale = (int64_t)P.rowv2[i] + P.colv2[jj];
+      oidx = P.c_off + i * P.c_rs + jj * P.c_cs;
+      if (P.rin_m) { m0 = P.rin_m[ij]; e0r = P.rin_e[ij]; }
+    }
+    finish_entry_split<EW, G>(T, W, scale, P.C, oidx, P.p, P.approx, m0, e0r, live, e3, part3,
+                              reinterpret_cast<int32_t *>(ylds));
   }
 }
 
