@@ -245,19 +245,18 @@ __device__ void finish_entry_split(const uint32_t *T, int W, int64_t scale, cons
 // digits), whose lane l holds the lo or hi sum of one prime for 16
 // elements.  Lane pairs combine lo + 256 hi by DPP exchanges; each lane of
 // the pair reduces 8 of the 16 elements (its prime's constants sit in
-// registers, loaded a tile ahead) and stores the residue digits of 8
-// consecutive elements (the LDS rows are permuted for that) as 8 bytes of
-// each of the prime's two planes, the four lanes of a prime covering the
-// block's 32 bytes per store (the padded plane holds whole blocks of 32
+// registers, loaded a tile ahead) and puts the residue digits of 8
+// consecutive elements (the LDS rows are permuted for that) into an LDS
+// stage of the tile's 32 planes; the workgroup then stores each plane's
+// row of EL bytes whole (the padded plane holds whole blocks of 32
 // elements and starts 16-byte aligned).
 //
-// Registers are capped for five waves per SIMD (four otherwise): at 2048^2
-// p = 512 the two operands' slicing took 1.24 -> 1.20 ms with that, despite
-// an 8-byte spill in the 256-element form; six waves spilled 76 bytes and
-// took 1.76 ms.
+// With the stage the 256-element form's LDS (about 37 KiB at p = 512)
+// admits four workgroups per CU, so registers are capped for four waves
+// per SIMD (no spill) rather than five.
 template <int EL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void rns_slice_kernel(RnsSliceParams P) {
-  extern __shared__ __attribute__((aligned(16))) uint8_t dl[];   // [EL][kd + 16]
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void rns_slice_kernel(RnsSliceParams P) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t dl[];   // [EL][kd + 16], then [32][EL]
   const int tid = threadIdx.x;
   const int nw = P.tab.nw, kd = P.tab.kd, S = kd + 16, m = P.tab.m;
   const int64_t total = P.lines_pad * P.k_pad;
@@ -287,86 +286,88 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   // of each 32 x 32 result, the lo (even c) or hi (odd c) sum of prime
   // 16 rt + c / 2, for elements 8 G + 4 h + i in register 4 G + i
   const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, c = lane & 31, d = c & 1;
-  // blocks of 32 elements per wave (waves past EL / 32 have none); the
-  // weight fragments of a prime tile are loaded once for all of them
+  // blocks of 32 elements per wave (waves past EL / 32 have none but take
+  // part in the stores); the weight fragments of a prime tile are loaded
+  // once for all of them
   constexpr int NBW = EL >= 128 ? EL / 128 : 1;
-  if (wave >= EL / 32) return;
+  const bool act = wave < EL / 32;
+  // a tile's 32 planes x EL elements, staged so that the stores write
+  // whole plane rows of EL bytes
+  uint8_t *stage = dl + (size_t)EL * S;
   const uint8_t *drow[NBW];
-  int8_t *out[NBW];
-  bool inside[NBW];
+  int soff[NBW];
 #pragma unroll
   for (int b = 0; b < NBW; ++b) {
-    const int wv = NBW * wave + b;   // a wave's blocks are adjacent: 64-byte runs per plane
+    const int wv = NBW * wave + b;
     drow[b] = dl + (size_t)(32 * wv + c) * S + 16 * h;
-    // this lane reduces and stores elements 16 d + 8 h .. + 7 of the two
-    // planes of its prime
-    out[b] = P.planes + g0 + 32 * wv + 16 * d + 8 * h;
-    inside[b] = g0 + 32 * wv < total;
+    // this lane reduces elements 16 d + 8 h .. + 7 of its block for the two
+    // planes of its prime (stage rows c - d and c - d + 1)
+    soff[b] = (c - d) * EL + 32 * wv + 16 * d + 8 * h;
   }
   const int nrt = (m + 15) / 16, nks = kd / 32;
   const int8_t *wbase = P.tab.wd + (int64_t)c * kd + 16 * h;
   v4i fnext[4];
-  frag_load4(fnext, wbase, 0, nks);
+  if (act) frag_load4(fnext, wbase, 0, nks);
   // reduction constants of this lane's prime, loaded a tile ahead
   int jn = min(c >> 1, m - 1);
   uint32_t pn = (uint32_t)P.tab.prime[jn], mun = P.tab.mu[jn], kpn = P.tab.kp[jn];
   for (int rt = 0; rt < nrt; ++rt) {
-    const int8_t *wrow = wbase + (int64_t)rt * 32 * kd;
-    const uint32_t pj = pn, muj = mun, kpj = kpn;
-    const int j = 16 * rt + (c >> 1);
-    if (rt + 1 < nrt) {
-      jn = min(j + 16, m - 1);
-      pn = (uint32_t)P.tab.prime[jn];
-      mun = P.tab.mu[jn];
-      kpn = P.tab.kp[jn];
-    }
-    v16i acc[NBW];
+    if (act) {
+      const int8_t *wrow = wbase + (int64_t)rt * 32 * kd;
+      const uint32_t pj = pn, muj = mun, kpj = kpn;
+      const int j = 16 * rt + (c >> 1);
+      if (rt + 1 < nrt) {
+        jn = min(j + 16, m - 1);
+        pn = (uint32_t)P.tab.prime[jn];
+        mun = P.tab.mu[jn];
+        kpn = P.tab.kp[jn];
+      }
+      v16i acc[NBW];
 #pragma unroll
-    for (int b = 0; b < NBW; ++b)
+      for (int b = 0; b < NBW; ++b)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[b][r] = 0;
-    for (int k0 = 0; k0 < nks; k0 += 4) {
-      v4i fa[4];
-      if (k0 == 0) {
+        for (int r = 0; r < 16; ++r) acc[b][r] = 0;
+      for (int k0 = 0; k0 < nks; k0 += 4) {
+        v4i fa[4];
+        if (k0 == 0) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) fa[u] = fnext[u];
-        // the next tile's first weight fragments load during this tile's
-        // products and residue arithmetic
-        frag_load4(fnext, rt + 1 < nrt ? wrow + 32 * kd : wbase, 0, nks);
-      } else {
-        frag_load4(fa, wrow, k0, nks);
+          for (int u = 0; u < 4; ++u) fa[u] = fnext[u];
+          // the next tile's first weight fragments load during this tile's
+          // products and residue arithmetic
+          frag_load4(fnext, rt + 1 < nrt ? wrow + 32 * kd : wbase, 0, nks);
+        } else {
+          frag_load4(fa, wrow, k0, nks);
+        }
+#pragma unroll
+        for (int b = 0; b < NBW; ++b) {
+          v4i fb[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int ks = k0 + u < nks ? k0 + u : k0;
+            fb[u] = *reinterpret_cast<const v4i *>(drow[b] + 32 * ks);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (k0 + u < nks) acc[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fb[u], fa[u], acc[b], 0, 0, 0);
+        }
       }
 #pragma unroll
       for (int b = 0; b < NBW; ++b) {
-        v4i fb[4];
+        // lo + 256 hi per element from the lane pair (2u, 2u + 1): the even
+        // lane reduces registers 8 g + i (elements 8 h + 4 g + i), the odd
+        // lane registers 8 g + 4 + i (elements 16 + 8 h + 4 g + i); each
+        // forms both candidates with one DPP exchange each and keeps its own
+        uint32_t w[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int ks = k0 + u < nks ? k0 + u : k0;
-          fb[u] = *reinterpret_cast<const v4i *>(drow[b] + 32 * ks);
+        for (int k = 0; k < 8; ++k) {
+          const int re = 8 * (k >> 2) + (k & 3), ro = re + 4;
+          const int32_t te = __builtin_amdgcn_mov_dpp(acc[b][re], 0xB1, 0xF, 0xF, false);
+          const int32_t to = __builtin_amdgcn_mov_dpp(acc[b][ro], 0xB1, 0xF, 0xF, false);
+          const int32_t se = acc[b][re] + (te << 8), so = to + (acc[b][ro] << 8);
+          w[k] = residue_digits(pj, muj, kpj, d ? so : se);
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (k0 + u < nks) acc[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fb[u], fa[u], acc[b], 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < NBW; ++b) {
-      // lo + 256 hi per element from the lane pair (2u, 2u + 1): the even
-      // lane reduces registers 8 g + i (elements 8 h + 4 g + i), the odd
-      // lane registers 8 g + 4 + i (elements 16 + 8 h + 4 g + i); each
-      // forms both candidates with one DPP exchange each and keeps its own
-      uint32_t w[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int re = 8 * (k >> 2) + (k & 3), ro = re + 4;
-        const int32_t te = __builtin_amdgcn_mov_dpp(acc[b][re], 0xB1, 0xF, 0xF, false);
-        const int32_t to = __builtin_amdgcn_mov_dpp(acc[b][ro], 0xB1, 0xF, 0xF, false);
-        const int32_t se = acc[b][re] + (te << 8), so = to + (acc[b][ro] << 8);
-        w[k] = residue_digits(pj, muj, kpj, d ? so : se);
-      }
-      if (j < m && inside[b]) {
-        // bytes (lo, hi) of the 8 consecutive elements into two words of
-        // each plane
+        // bytes (lo, hi) of the 8 consecutive elements into the stage rows
+        // of the prime's two planes
         uint32_t lo[2], hi[2];
 #pragma unroll
         for (int g = 0; g < 2; ++g) {
@@ -375,11 +376,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
           lo[g] = __builtin_amdgcn_perm(x23, x01, 0x05040100u);
           hi[g] = __builtin_amdgcn_perm(x23, x01, 0x07060302u);
         }
-        int8_t *o = out[b] + (int64_t)(2 * j) * total;
-        *reinterpret_cast<uint2 *>(o) = make_uint2(lo[0], lo[1]);
-        *reinterpret_cast<uint2 *>(o + total) = make_uint2(hi[0], hi[1]);
+        *reinterpret_cast<uint2 *>(stage + soff[b]) = make_uint2(lo[0], lo[1]);
+        *reinterpret_cast<uint2 *>(stage + soff[b] + EL) = make_uint2(hi[0], hi[1]);
       }
     }
+    __syncthreads();
+    // the tile's planes 32 rt .. 32 rt + 31 (those of real primes), one
+    // word of a plane row per thread
+    for (int t = tid; t < 32 * (EL / 4); t += 256) {
+      const int r = t / (EL / 4), wd = t - r * (EL / 4);
+      const int plane = 32 * rt + r;
+      if (plane < 2 * m && g0 + 4 * wd < total)
+        *reinterpret_cast<uint32_t *>(P.planes + (int64_t)plane * total + g0 + 4 * wd) =
+            *reinterpret_cast<const uint32_t *>(stage + r * EL + 4 * wd);
+    }
+    __syncthreads();
   }
 }
 
@@ -687,13 +698,14 @@ hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s) {
   const int64_t total = P.lines_pad * P.k_pad;
   if (total == 0) return hipSuccess;
   const size_t S = (size_t)P.tab.kd + 16;
-  if (32 * S > 65536 || 4 * P.tab.nw > P.tab.kd) return hipErrorInvalidValue;
+  if (32 * (S + 32) > 65536 || 4 * P.tab.nw > P.tab.kd) return hipErrorInvalidValue;
   // whole blocks of 32 elements, 16-byte aligned plane rows
   if ((total & 31) != 0 || ((uintptr_t)P.planes & 15) != 0) return hipErrorInvalidValue;
+  // digit rows and a tile's staged planes (32 x el bytes)
   int el = 256;
-  while (el > 32 && (size_t)el * S > 65536) el >>= 1;
+  while (el > 32 && (size_t)el * (S + 32) > 65536) el >>= 1;
   const dim3 grid((unsigned)((total + el - 1) / el));
-  const size_t lds = (size_t)el * S;
+  const size_t lds = (size_t)el * (S + 32);
   if (el == 256) hipLaunchKernelGGL(rns_slice_kernel<256>, grid, dim3(256), lds, s, P);
   else if (el == 128) hipLaunchKernelGGL(rns_slice_kernel<128>, grid, dim3(256), lds, s, P);
   else if (el == 64) hipLaunchKernelGGL(rns_slice_kernel<64>, grid, dim3(256), lds, s, P);
