@@ -215,3 +215,20 @@ def test_host_only_context_validates_reserve_and_exact_t(hctx, lib):
                                     check=False, **args) == arbgpu.EINVAL                        # no T_im
     assert hctx.mat_mul_exact_t_raw(t, None, A=mat(3, 5), B=mat(5, 4), flags=arbgpu.ALGO_LIMB,
                                     check=False, **args) == arbgpu.EINVAL
+
+
+def test_host_only_context_validates_wide_dots(hctx):
+    # beyond the register windows (p + extend + 41 > 1216 bits) a dot runs on
+    # the LDS window: p up to 65408 and operands of up to 2048 limbs
+    def call(p, cap):
+        return hctx.dot_raw(res=[_out(cap=(p + 31) // 32)], res_idx=0, initial=None, init_idx=0, sub=False,
+                            x=[_arr(cap=cap)], xoff=0, xstep=1, y=[_arr(cap=cap)], yoff=0, ystep=1, N=5, p=p,
+                            check=False)
+    assert call(4096, 130) == arbgpu.EDEVICE
+    assert call(65408, 2048) == arbgpu.EDEVICE
+    assert call(65409, 2048) == arbgpu.EINVAL
+    assert "65408" in hctx.last_error()
+    assert call(4096, 2049) == arbgpu.EINVAL
+    assert "2048" in hctx.last_error()
+    # within the register windows wide operands are read in place
+    assert call(100, 4000) == arbgpu.EDEVICE
