@@ -242,7 +242,7 @@ int dot_tasks(arbgpu_ctx *ctx, const arbgpu_dot_job &job, const char *who, DotPa
   const int nparts = cplx ? 2 : 1;
   const bool has_init = job.init[0].limbs != nullptr;
   const int64_t p = job.p, N = job.N;
-  if (flags & ~(ARBGPU_APPROX | ARBGPU_COMPLEX | ARBGPU_REDUCE_PREC))
+  if (flags & ~(ARBGPU_APPROX | ARBGPU_COMPLEX | ARBGPU_REDUCE_PREC | ARBGPU_ALGO_LIMB))
     return fail(ctx, ARBGPU_EINVAL, "%s: unknown flags 0x%x", who, flags);
   if (p < 2 || p > (1 << 20)) return fail(ctx, ARBGPU_EINVAL, "%s: p=%lld out of range", who, (long long)p);
   if (N < 0) return fail(ctx, ARBGPU_EINVAL, "%s: N < 0", who);
@@ -294,7 +294,11 @@ int dot_tasks(arbgpu_ctx *ctx, const arbgpu_dot_job &job, const char *who, DotPa
     d.sub = job.sub ? 1u : 0u;
     d.reduce = (flags & ARBGPU_REDUCE_PREC) != 0;
     d.ct = !cplx ? comp_real() : (q == 0 ? comp_re() : comp_im());
+    d.na = shape->na;
+    d.fb = -1;
   }
+  const int lb = (flags & ARBGPU_ALGO_LIMB) ? 0 : digit_blocks(prm[0], *shape);
+  for (int q = 0; q < nparts; ++q) prm[q].digit = lb;
   *ntasks = nparts;
   return ARBGPU_OK;
 }
@@ -421,9 +425,25 @@ int arbgpu_dot(arbgpu_ctx *ctx, const arbgpu_out *res, int64_t res_idx, const ar
   int rc = dot_tasks(ctx, job, "arbgpu_dot", prm, &nt, &sh);
   if (rc) return rc;
   if ((rc = bind_device(ctx, stream))) return rc;
+  const hipStream_t s = to_stream(stream);
+  if (prm[0].digit) {
+    // the digit product, then the limb kernel for any part it hands back
+    int32_t *flags = (int32_t *)ws_get(ctx, WS_DOTFLAG, 2 * sizeof(int32_t));
+    if (!flags) return ARBGPU_ENOMEM;
+    {
+      KernelTimer kt(ctx, "digit_dot", s);
+      hipError_t e = launch_digit_dot(prm, prm[0].digit, flags, s);
+      if (e != hipSuccess) return hip_fail(ctx, e, "arbgpu_dot launch");
+    }
+    for (int q = 0; q < nt; ++q) {
+      hipError_t e = launch_limb_dot(prm[q], sh, s, flags + q);
+      if (e != hipSuccess) return hip_fail(ctx, e, "arbgpu_dot launch");
+    }
+    return ARBGPU_OK;
+  }
   for (int q = 0; q < nt; ++q) {
-    KernelTimer kt(ctx, "limb_dot", to_stream(stream));
-    hipError_t e = sh.ns ? launch_limb_dot(prm[q], sh, to_stream(stream)) : launch_wide_dot(prm[q], to_stream(stream));
+    KernelTimer kt(ctx, "limb_dot", s);
+    hipError_t e = sh.ns ? launch_limb_dot(prm[q], sh, s) : launch_wide_dot(prm[q], s);
     if (e != hipSuccess) return hip_fail(ctx, e, "arbgpu_dot launch");
   }
   return ARBGPU_OK;

@@ -32,22 +32,38 @@ std::string tune_key(LimbShape sh, bool block) {
   return "dot_batch:" + std::to_string(sh.ns) + "x" + std::to_string(sh.na) + (block ? ":w4" : "");
 }
 
+std::string tune_key_digit(int lb, bool cplx) {
+  return "dot_digit:" + std::to_string(lb) + (cplx ? "c" : "r");
+}
+
+// A run: a persistent kernel over a slice of the order array.  Limb runs
+// (one shape; four waves per task for long dots), digit-product runs (jobs
+// of one block count, real or complex) and fallback runs (the limb kernel
+// over the device-filled list of one shape's parts that a digit run handed
+// back; begin and count are the list's base and capacity).
 struct ShapeRun {
   LimbShape sh;
   bool block;             // long dots: four waves per task
   int64_t begin, count;   // slice of the order array
   int waves;              // per compute unit
   float tuned_ms;         // time of this run alone at `waves` (0: not tuned)
+  int digit = 0;          // > 0: digit-product run with this many blocks
+  bool cplx = false;      // digit run of complex jobs
+  int fb = -1;            // >= 0: fallback run over list fb
 };
 
 // The work of a batch: dot tasks, matrix-product parts and their tiles,
-// and the per-shape runs over `order` (by shape, longest first).
+// the runs over `order` (limb work by shape, longest first, then the digit
+// jobs by block count, longest first) and the fallback lists (one per limb
+// shape of a digit job's tasks).
 struct BatchPlan {
   std::vector<DotParams> tasks;
   std::vector<MmParams> mm;
   std::vector<BatchTile> tiles;
-  std::vector<int32_t> order;   // dot task e >= 0, tile -e - 1
+  std::vector<int32_t> order;   // dot task e >= 0, tile -e - 1; digit runs: the job's first task
   std::vector<ShapeRun> runs;
+  std::vector<int32_t> fb_base, fb_cap;   // per fallback list
+  int64_t fb_total = 0;
 };
 
 // Validates one matrix-product job of a batch and adds its parts and
@@ -110,6 +126,8 @@ int plan_batch(arbgpu_ctx *ctx, const arbgpu_dot_job *dots, const arbgpu_job *jo
   // work item w < tasks: dot task w; else tile w - tasks (filled in below)
   std::vector<LimbShape> shape_dot, shape_tile;
   std::vector<double> cost_dot, cost_tile;
+  std::vector<int32_t> digit_jobs;           // first task of each digit-product job
+  std::vector<LimbShape> fb_shapes;          // limb shape of each fallback list
   bp = BatchPlan();
   for (int64_t i = 0; i < njobs; ++i) {
     int rc;
@@ -127,6 +145,17 @@ int plan_batch(arbgpu_ctx *ctx, const arbgpu_dot_job *dots, const arbgpu_job *jo
         int cap = 1;
         for (int q = 0; q < nt; ++q) cap = std::max(cap, std::max(dj.x[q].cap, dj.y[q].cap));
         const double w = (double)std::min(cap, sh.na);
+        if (prm[0].digit) {
+          int f = 0;
+          while (f < (int)fb_shapes.size() && !(fb_shapes[f].ns == sh.ns && fb_shapes[f].na == sh.na)) ++f;
+          if (f == (int)fb_shapes.size()) {
+            fb_shapes.push_back(sh);
+            bp.fb_cap.push_back(0);
+          }
+          bp.fb_cap[f] += nt;
+          for (int q = 0; q < nt; ++q) prm[q].fb = f;
+          digit_jobs.push_back((int32_t)bp.tasks.size());
+        }
         for (int q = 0; q < nt; ++q) {
           bp.tasks.push_back(prm[q]);
           shape_dot.push_back(sh);
@@ -147,8 +176,11 @@ int plan_batch(arbgpu_ctx *ctx, const arbgpu_dot_job *dots, const arbgpu_job *jo
   auto is_long = [&](size_t w) {
     return w < nd && shape_dot[w].ns > 0 && bp.tasks[w].N * bp.tasks[w].ct.ncomp >= kDotBlockTerms;
   };
-  std::vector<int32_t> work(nd + nt);
-  for (size_t w = 0; w < work.size(); ++w) work[w] = (int32_t)w;
+  // limb work: dot tasks outside the digit runs, and the tiles
+  std::vector<int32_t> work;
+  work.reserve(nd + nt);
+  for (size_t w = 0; w < nd + nt; ++w)
+    if (w >= nd || !bp.tasks[w].digit) work.push_back((int32_t)w);
   std::stable_sort(work.begin(), work.end(), [&](int32_t x, int32_t y) {
     const LimbShape &a = shape(x), &c = shape(y);
     if (a.ns != c.ns) return a.ns > c.ns;
@@ -168,6 +200,36 @@ int plan_batch(arbgpu_ctx *ctx, const arbgpu_dot_job *dots, const arbgpu_job *jo
       bp.runs.push_back({sh, blk, (int64_t)t, 0, it != ctx->tune.end() ? it->second : kDefaultWaves, 0.f});
     }
     bp.runs.back().count++;
+  }
+  // digit jobs: by block count and kind, longest first
+  auto dcost = [&](int32_t e) { return (double)bp.tasks[e].N * bp.tasks[e].ct.ncomp * bp.tasks[e].digit; };
+  std::stable_sort(digit_jobs.begin(), digit_jobs.end(), [&](int32_t x, int32_t y) {
+    const DotParams &a = bp.tasks[x], &c = bp.tasks[y];
+    if (a.digit != c.digit) return a.digit > c.digit;
+    if (a.ct.ncomp != c.ct.ncomp) return a.ct.ncomp > c.ct.ncomp;
+    return dcost(x) > dcost(y);
+  });
+  for (int32_t e : digit_jobs) {
+    const DotParams &d = bp.tasks[e];
+    const bool cplx = d.ct.ncomp == 2;
+    if (bp.runs.empty() || bp.runs.back().digit != d.digit || bp.runs.back().cplx != cplx) {
+      auto it = ctx->tune.find(tune_key_digit(d.digit, cplx));
+      ShapeRun r{LimbShape{0, 0}, true, (int64_t)bp.order.size(), 0,
+                 it != ctx->tune.end() ? it->second : kDefaultWaves, 0.f};
+      r.digit = d.digit;
+      r.cplx = cplx;
+      bp.runs.push_back(r);
+    }
+    bp.order.push_back(e);
+    bp.runs.back().count++;
+  }
+  // fallback runs, one per list
+  for (size_t f = 0; f < fb_shapes.size(); ++f) {
+    bp.fb_base.push_back((int32_t)bp.fb_total);
+    ShapeRun r{fb_shapes[f], false, bp.fb_total, bp.fb_cap[f], kDefaultWaves, 0.f};
+    r.fb = (int)f;
+    bp.runs.push_back(r);
+    bp.fb_total += bp.fb_cap[f];
   }
   return ARBGPU_OK;
 }
@@ -190,9 +252,70 @@ int device_cus(int device) {
 
 namespace arbgpu_impl {
 
-size_t dot_batch_ws(int64_t n, int nshapes) {
-  return sizeof(DotParams) * (size_t)n + sizeof(int32_t) * ((size_t)n + (size_t)nshapes) + 64;
+// Runs a plan can have: two per limb shape, the LDS-window run, two per
+// digit block count and one fallback run per limb shape.
+constexpr int kMaxRuns = 128;
+
+size_t dot_batch_ws(int64_t n) {
+  // tasks, order (at most one entry per task), fallback lists, their bases,
+  // the run counters and the list counts
+  return sizeof(DotParams) * (size_t)n + sizeof(int32_t) * (2 * (size_t)n + 3 * (size_t)kMaxRuns) + 64;
 }
+
+// Device side of a plan.
+struct DevPlan {
+  DotParams *tasks;
+  MmParams *mm;
+  BatchTile *tiles;
+  int32_t *order;
+  int32_t *counters;   // a work counter per run, then an entry count per fallback list
+  int32_t *fb_list;
+  int32_t *fb_base;
+  int nruns;
+};
+
+// Kernel, grid, dynamic LDS and arguments of run k (the argument pointers
+// point into this object).
+struct RunLaunch {
+  BatchShapeParams bp;
+  DigitBatchParams dp;
+  const DotParams *wt;
+  const int32_t *wo;
+  void *args[2];
+  const void *func = nullptr;
+  dim3 grid;
+  size_t lds = 0;
+  RunLaunch(const ShapeRun &r, size_t k, const DevPlan &d, int num_cu, int waves) {
+    if (r.digit) {
+      dp = DigitBatchParams{d.tasks, d.order + r.begin, r.count, d.counters + k, d.fb_list, d.fb_base,
+                            d.counters + d.nruns};
+      func = digit_dot_batch_kernel(r.digit, r.cplx, &lds);
+      grid = dim3(blocks_for(r.count, waves, num_cu, true));
+      args[0] = &dp;
+    } else if (r.fb >= 0) {
+      bp = BatchShapeParams{d.tasks, d.mm, d.tiles, d.fb_list + r.begin, r.count, d.counters + k,
+                            d.counters + d.nruns + r.fb};
+      func = dot_batch_kernel(r.sh, false);
+      grid = dim3(blocks_for(r.count, waves, num_cu, false));
+      args[0] = &bp;
+    } else if (r.sh.ns == 0) {   // beyond the register windows: one workgroup per dot
+      wt = d.tasks;
+      wo = d.order + r.begin;
+      func = wide_dot_batch_kernel_ptr(&lds);
+      grid = dim3((unsigned)r.count);
+      args[0] = &wt;
+      args[1] = &wo;
+    } else {
+      bp = BatchShapeParams{d.tasks, d.mm, d.tiles, d.order + r.begin, r.count, d.counters + k, nullptr};
+      func = dot_batch_kernel(r.sh, r.block);
+      grid = dim3(blocks_for(r.count, waves, num_cu, r.block));
+      args[0] = &bp;
+    }
+  }
+  hipError_t launch(hipStream_t s) const {
+    return hipLaunchKernel(func, grid, dim3(256), const_cast<void **>(args), lds, s);
+  }
+};
 
 int dot_batch_run(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, hipStream_t s) {
   BatchPlan plan;
@@ -201,30 +324,35 @@ int dot_batch_run(arbgpu_ctx *ctx, const arbgpu_dot_job *jobs, int64_t njobs, hi
   const std::vector<int32_t> &order = plan.order;
   const std::vector<ShapeRun> &runs = plan.runs;
   if (rc || tasks.empty()) return rc;
+  if ((int)runs.size() > kMaxRuns) return set_error(ctx, ARBGPU_EINVAL, "dot batch: too many kernel runs");
   const size_t tb = sizeof(DotParams) * tasks.size(), ob = sizeof(int32_t) * order.size();
-  char *w = (char *)ws_get(ctx, WS_BATCH, dot_batch_ws((int64_t)tasks.size(), (int)runs.size()));
+  char *w = (char *)ws_get(ctx, WS_BATCH, dot_batch_ws((int64_t)tasks.size()));
   if (!w) return ARBGPU_ENOMEM;
-  DotParams *d_tasks = (DotParams *)w;
-  int32_t *d_order = (int32_t *)(w + tb);
-  int32_t *d_ctr = d_order + order.size();
-  hipError_t e = hipMemcpyAsync(d_tasks, tasks.data(), tb, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_order, order.data(), ob, hipMemcpyHostToDevice, s);
+  DevPlan d;
+  d.tasks = (DotParams *)w;
+  d.mm = nullptr;
+  d.tiles = nullptr;
+  d.order = (int32_t *)(w + tb);
+  d.fb_list = d.order + order.size();
+  d.fb_base = d.fb_list + plan.fb_total;
+  d.counters = d.fb_base + plan.fb_base.size();
+  d.nruns = (int)runs.size();
+  hipError_t e = hipMemcpyAsync(d.tasks, tasks.data(), tb, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d.order, order.data(), ob, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !plan.fb_base.empty())
+    e = hipMemcpyAsync(d.fb_base, plan.fb_base.data(), sizeof(int32_t) * plan.fb_base.size(), hipMemcpyHostToDevice,
+                       s);
   if (e == hipSuccess) {
-    int n = (int)runs.size();
-    void *rargs[] = {&d_ctr, &n};
+    int n = (int)(runs.size() + plan.fb_base.size());
+    void *rargs[] = {&d.counters, &n};
     e = hipLaunchKernel(reinterpret_cast<const void *>(&batch_reset_kernel), dim3((unsigned)((n + 255) / 256)),
                         dim3(256), rargs, 0, s);
   }
   const int ncu = device_cus(ctx->device);
+  // in stream order: the fallback runs come after every digit run
   for (size_t k = 0; k < runs.size() && e == hipSuccess; ++k) {
-    if (runs[k].sh.ns == 0) {   // beyond the register windows: one workgroup per dot
-      e = launch_wide_dot_batch(d_tasks, d_order + runs[k].begin, runs[k].count, s);
-      continue;
-    }
-    BatchShapeParams bp{d_tasks, nullptr, nullptr, d_order + runs[k].begin, runs[k].count, d_ctr + k};
-    void *args[] = {&bp};
-    e = hipLaunchKernel(dot_batch_kernel(runs[k].sh, runs[k].block),
-                        dim3(blocks_for(runs[k].count, runs[k].waves, ncu, runs[k].block)), dim3(256), args, 0, s);
+    RunLaunch rl(runs[k], k, d, ncu, runs[k].waves);
+    e = rl.launch(s);
   }
   // the host task list must outlive its asynchronous upload
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -239,11 +367,13 @@ struct arbgpu_batch {
   int64_t njobs = 0;
   std::vector<ShapeRun> runs;
   int64_t ntasks = 0, ntiles = 0;
+  int nfb = 0;   // fallback lists
   DotParams *d_tasks = nullptr;
   MmParams *d_mm = nullptr;
   BatchTile *d_tiles = nullptr;
   int32_t *d_order = nullptr;
-  int32_t *d_counters = nullptr;
+  int32_t *d_counters = nullptr;   // a work counter per run, then an entry count per fallback list
+  int32_t *d_fb = nullptr;         // fallback lists, then their bases
   int num_cu = 256;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -251,14 +381,30 @@ struct arbgpu_batch {
   ~arbgpu_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    for (void *q : {(void *)d_tasks, (void *)d_mm, (void *)d_tiles, (void *)d_order, (void *)d_counters})
+    for (void *q : {(void *)d_tasks, (void *)d_mm, (void *)d_tiles, (void *)d_order, (void *)d_counters, (void *)d_fb})
       if (q) (void)hipFree(q);
   }
 
-  unsigned blocks_for(const ShapeRun &r, int waves) const { return ::blocks_for(r.count, waves, num_cu, r.block); }
+  int64_t fb_total() const {
+    int64_t t = 0;
+    for (auto &r : runs)
+      if (r.fb >= 0) t += r.count;
+    return t;
+  }
 
-  BatchShapeParams params(size_t k) const {
-    return BatchShapeParams{d_tasks, d_mm, d_tiles, d_order + runs[k].begin, runs[k].count, d_counters + k};
+  DevPlan dev() const {
+    return DevPlan{d_tasks, d_mm, d_tiles, d_order, d_counters, d_fb, d_fb + fb_total(), (int)runs.size()};
+  }
+
+  // counters of every run and list cleared: a kernel node (no memset nodes)
+  hipKernelNodeParams reset_params(void **rargs) const {
+    hipKernelNodeParams kp;
+    memset(&kp, 0, sizeof kp);
+    kp.func = reinterpret_cast<void *>(&batch_reset_kernel);
+    kp.gridDim = dim3((unsigned)((*(int *)rargs[1] + 255) / 256));
+    kp.blockDim = dim3(256);
+    kp.kernelParams = rargs;
+    return kp;
   }
 
   int build_graph() {
@@ -268,41 +414,35 @@ struct arbgpu_batch {
     graph = nullptr;
     hipError_t e = hipGraphCreate(&graph, 0);
     if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "hipGraphCreate: %s", hipGetErrorString(e));
-    // counters are cleared by a kernel node: memset nodes are not used
-    int n = (int)std::max<size_t>(1, runs.size());
+    int n = (int)std::max<size_t>(1, runs.size() + nfb);
     void *rargs[] = {&d_counters, &n};
-    hipKernelNodeParams kp;
-    memset(&kp, 0, sizeof kp);
-    kp.func = reinterpret_cast<void *>(&batch_reset_kernel);
-    kp.gridDim = dim3((unsigned)((n + 255) / 256));
-    kp.blockDim = dim3(256);
-    kp.kernelParams = rargs;
+    hipKernelNodeParams kp = reset_params(rargs);
     hipGraphNode_t reset;
     e = hipGraphAddKernelNode(&reset, graph, nullptr, 0, &kp);
     if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "graph node: %s", hipGetErrorString(e));
-    for (size_t k = 0; k < runs.size(); ++k) {
-      BatchShapeParams bp = params(k);
-      const int32_t *wide_order = d_order + runs[k].begin;
-      void *args[] = {&bp};
-      void *wargs[] = {&d_tasks, &wide_order};
-      hipKernelNodeParams np;
-      memset(&np, 0, sizeof np);
-      if (runs[k].sh.ns == 0) {   // beyond the register windows: one workgroup per dot
-        size_t lds = 0;
-        np.func = const_cast<void *>(wide_dot_batch_kernel_ptr(&lds));
-        np.gridDim = dim3((unsigned)runs[k].count);
-        np.sharedMemBytes = (unsigned)lds;
-        np.kernelParams = wargs;
-      } else {
-        np.func = const_cast<void *>(dot_batch_kernel(runs[k].sh, runs[k].block));
-        np.gridDim = dim3(blocks_for(runs[k], runs[k].waves));
-        np.kernelParams = args;
+    const DevPlan d = dev();
+    // limb, LDS-window and digit runs after the reset; fallback runs after
+    // every digit run
+    std::vector<hipGraphNode_t> digit_nodes;
+    for (int pass = 0; pass < 2; ++pass)
+      for (size_t k = 0; k < runs.size(); ++k) {
+        if ((runs[k].fb >= 0) != (pass == 1)) continue;
+        RunLaunch rl(runs[k], k, d, num_cu, runs[k].waves);
+        hipKernelNodeParams np;
+        memset(&np, 0, sizeof np);
+        np.func = const_cast<void *>(rl.func);
+        np.gridDim = rl.grid;
+        np.blockDim = dim3(256);
+        np.sharedMemBytes = (unsigned)rl.lds;
+        np.kernelParams = rl.args;
+        hipGraphNode_t node;
+        if (pass == 0)
+          e = hipGraphAddKernelNode(&node, graph, &reset, 1, &np);
+        else
+          e = hipGraphAddKernelNode(&node, graph, digit_nodes.data(), digit_nodes.size(), &np);
+        if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "graph node: %s", hipGetErrorString(e));
+        if (runs[k].digit) digit_nodes.push_back(node);
       }
-      np.blockDim = dim3(256);
-      hipGraphNode_t node;
-      e = hipGraphAddKernelNode(&node, graph, &reset, 1, &np);
-      if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "graph node: %s", hipGetErrorString(e));
-    }
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return set_error(ctx, ARBGPU_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
     return ARBGPU_OK;
@@ -342,7 +482,13 @@ int batch_create(arbgpu_ctx *ctx, const arbgpu_dot_job *dots, const arbgpu_job *
   up((void **)&b->d_mm, plan.mm.data(), sizeof(MmParams) * plan.mm.size());
   up((void **)&b->d_tiles, plan.tiles.data(), sizeof(BatchTile) * plan.tiles.size());
   up((void **)&b->d_order, plan.order.data(), sizeof(int32_t) * plan.order.size());
-  up((void **)&b->d_counters, nullptr, sizeof(int32_t) * std::max<size_t>(1, b->runs.size()));
+  b->nfb = (int)plan.fb_base.size();
+  up((void **)&b->d_counters, nullptr, sizeof(int32_t) * std::max<size_t>(1, b->runs.size() + b->nfb));
+  {   // fallback lists (filled on the device), then their bases
+    std::vector<int32_t> fb((size_t)plan.fb_total, 0);
+    fb.insert(fb.end(), plan.fb_base.begin(), plan.fb_base.end());
+    up((void **)&b->d_fb, fb.data(), sizeof(int32_t) * fb.size());
+  }
   if (e != hipSuccess) {
     delete b;
     return set_error(ctx, ARBGPU_ENOMEM, "%s: %s", who, hipGetErrorString(e));
@@ -391,23 +537,25 @@ int arbgpu_batch_tune(arbgpu_batch *b, arbgpu_stream stream) {
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&t0);
   if (e == hipSuccess) e = hipEventCreate(&t1);
+  const DevPlan d = b->dev();
   for (size_t k = 0; k < b->runs.size() && e == hipSuccess; ++k) {
-    if (b->runs[k].sh.ns == 0) continue;   // one workgroup per dot: no width to tune
+    ShapeRun &r = b->runs[k];
+    // one workgroup per dot, or a device-filled list: no width to tune
+    if ((r.sh.ns == 0 && !r.digit) || r.fb >= 0) continue;
     float best = 3.0e38f;
-    int best_w = b->runs[k].waves;
+    int best_w = r.waves;
     for (int w : kTuneWaves) {
       float ms_min = 0.f;
       for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
-        BatchShapeParams bp = b->params(k);
-        void *args[] = {&bp};
-        int one = 1;
-        int32_t *ctr = bp.counter;
-        void *rargs[] = {&ctr, &one};
-        e = hipLaunchKernel(reinterpret_cast<const void *>(&batch_reset_kernel), dim3(1), dim3(256), rargs, 0, s);
+        RunLaunch rl(r, k, d, b->num_cu, w);
+        // every counter and list count (a digit run fills the lists)
+        int n = (int)(b->runs.size() + b->nfb);
+        int32_t *ctr = b->d_counters;
+        void *rargs[] = {&ctr, &n};
+        e = hipLaunchKernel(reinterpret_cast<const void *>(&batch_reset_kernel), dim3((unsigned)((n + 255) / 256)),
+                            dim3(256), rargs, 0, s);
         if (e == hipSuccess) e = hipEventRecord(t0, s);
-        if (e == hipSuccess)
-          e = hipLaunchKernel(dot_batch_kernel(b->runs[k].sh, b->runs[k].block), dim3(b->blocks_for(b->runs[k], w)),
-                              dim3(256), args, 0, s);
+        if (e == hipSuccess) e = rl.launch(s);
         if (e == hipSuccess) e = hipEventRecord(t1, s);
         if (e == hipSuccess) e = hipEventSynchronize(t1);
         float ms = 0.f;
@@ -420,9 +568,9 @@ int arbgpu_batch_tune(arbgpu_batch *b, arbgpu_stream stream) {
         best_w = w;
       }
     }
-    b->runs[k].waves = best_w;
-    b->runs[k].tuned_ms = best;
-    ctx->tune[tune_key(b->runs[k].sh, b->runs[k].block)] = best_w;
+    r.waves = best_w;
+    r.tuned_ms = best;
+    ctx->tune[r.digit ? tune_key_digit(r.digit, r.cplx) : tune_key(r.sh, r.block)] = best_w;
   }
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);
@@ -435,8 +583,9 @@ int arbgpu_batch_info(arbgpu_batch *b, int64_t *out, int n) {
   if (!b || !out || n < 0) return ARBGPU_EINVAL;
   std::vector<int64_t> v = {b->njobs, b->ntasks + b->ntiles, (int64_t)b->runs.size()};
   for (auto &r : b->runs) {
-    v.push_back(r.sh.ns);
-    v.push_back(r.sh.na);
+    // digit runs: (-blocks, 1 real | 2 complex)
+    v.push_back(r.digit ? -r.digit : r.sh.ns);
+    v.push_back(r.digit ? (r.cplx ? 2 : 1) : r.sh.na);
     v.push_back(r.count);
     v.push_back(r.waves);
     v.push_back((int64_t)(r.tuned_ms * 1000.f));

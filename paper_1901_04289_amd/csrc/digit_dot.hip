@@ -1,0 +1,628 @@
+// Dot products of moderate precision as one small exact integer product on
+// the INT8 matrix cores.
+//
+// Every operand of a dot is scaled to an integer in a frame of B = 224 LB
+// bits and cut into L = 32 LB digits of 7 bits, each carrying the
+// operand's sign, so that a digit fits an int8 whatever the sign.  With the
+// terms of the dot along the inner dimension, the digits of the x operands
+// as the rows of one matrix and those of the y operands as the columns of
+// the other, one INT8 matrix product gives, for every digit pair, its sum
+// over all terms; the integer sum of the dot is the sum of the product's
+// anti-diagonals d weighted by 2^(7 d).  This is the scaled-integer product
+// of Section 4 (Algorithm 2) for a 1 x N by N x 1 product with the digit
+// indices in the place of rows and columns.  Term t's x operands are scaled
+// by 2^(B - E + ey_t) and its y operands by 2^(B - ey_t) (ey_t the term's
+// largest y exponent, E the largest exponent sum of a term), so every
+// product has the unit 2^(E - 2B) and no term needs an alignment of its
+// own; a complex dot takes both parts from the same digits (Section 3.6:
+// the real part pairs x_re with y_re and x_im with -y_im, the imaginary part
+// x_re with y_im and x_im with y_re).
+//
+// Operand bits below the frame are dropped, as the truncated products of
+// Section 3.4 drop theirs: a product with a cut operand is off by less than
+// 2^(B+1) + 1 units, counted as 3 units of the window 2^(E - B).  The window
+// value with that bound either certifies the truncation of the exact sum to
+// p bits (window_certify) or the part goes back to the limb kernel, which
+// refines (the fast dot with a fallback of Section 2).  The frame needs
+// p + (E - e_max) + bitlen(terms) + 24 bits; a dot whose exponents spread
+// wider than its blocks allow goes back the same way.  The radius is the
+// limb engine's: the same per-term bounds (Section 3.5) added exactly in
+// fixed point (RadAcc).
+#include "finish.hpp"
+#include "limb_kernels.hpp"
+#include "window.hpp"
+
+using namespace arb;
+
+namespace arbgpu_impl {
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kDT = 256;           // threads per workgroup
+constexpr int kDW = kDT / 64;      // waves
+constexpr int kDigitGuard = 24;    // frame bits beyond p, the spread and the term count
+
+template <int LB, bool CPLX>
+struct DCfg {
+  static constexpr int L = 32 * LB;             // digits per operand
+  static constexpr int B = 224 * LB;            // frame bits
+  static constexpr int NOP = CPLX ? 4 : 2;      // operands per term: x_re, x_im, y_re, y_im | x, y
+  static constexpr int NPL = CPLX ? 5 : 2;      // digit planes (and -y_im)
+  static constexpr int KC = CPLX ? 64 : 128;    // terms per chunk
+  static constexpr int RS = KC + 16;            // bytes per digit row (padding against bank conflicts)
+  // 32 x 32 blocks of the digit product that are formed (bs + bu >= LB - 2)
+  static constexpr int NPAIR = LB * LB - (LB >= 3 ? (LB - 2) * (LB - 1) / 2 : 0);
+  static constexpr int PPW = (NPAIR + kDW - 1) / kDW;
+  static constexpr int NCOL = 14 * LB + 2;      // limbs of the integer sum (2 L digits + 64 bits)
+  static constexpr int C0 = 7 * LB;             // window bottom: limb C0 has weight 2^B
+};
+
+template <int LB, bool CPLX>
+struct DLds {
+  using C = DCfg<LB, CPLX>;
+  union {
+    int8_t dig[C::NPL][C::L][C::RS];   // digit s of a chunk's terms: row s, term k at byte k
+    struct {
+      int64_t diag[2][2 * C::L];       // anti-diagonal sums per part
+      int64_t col[2][C::NCOL];         // the integer sum per part, 32 bits per column
+      uint32_t hi[2][C::NCOL];         // certification scratch
+    } f;
+  } u;
+  // per operand and term of the chunk: the radius bound's inputs and flags
+  double mag[C::NOP][C::KC], rm[C::NOP][C::KC];
+  int re[C::NOP][C::KC], ex[C::NOP][C::KC], fl[C::NOP][C::KC];   // fl: 1 nonzero, 2 cut by the frame
+  int red[kDW][10];
+  RadAcc rad[kDW];
+  uint32_t ntr[kDW];
+  int job;
+};
+
+// An operand's sign, exponent, limb count and radius, as the limb kernels
+// load them (load_op), without the limbs.
+struct Meta {
+  int n;
+  uint32_t sign;
+  int e;
+  double rm;
+  int re;
+};
+
+__device__ __forceinline__ void load_meta(const arbgpu_arr &A, int64_t idx, Meta &m) {
+  const int32_t nl = gp(A.nls)[idx];
+  int n = nl & 0x7FFFFFFF;
+  if (n > A.cap) n = A.cap;
+  m.n = n;
+  m.sign = (uint32_t)nl >> 31;
+  m.e = gp(A.exp)[idx];
+  m.rm = 0.0;
+  m.re = 0;
+  if (A.rad_m) {
+    const double r = gp(A.rad_m)[idx];
+    if (r != 0.0) {
+      if (r > 0.0 && r < INFINITY) {
+        int ex;
+        m.rm = frexp(r, &ex);
+        m.re = gp(A.rad_e)[idx] + ex;
+      } else {
+        m.rm = 1.0;
+        m.re = kExpLimit;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ bool meta_out_of_range(const Meta &o) {
+  if (o.n && (o.e >= kExpLimit || o.e <= -kExpLimit)) return true;
+  if (o.rm != 0.0 && (o.re >= kExpLimit || o.re <= -kExpLimit)) return true;
+  return false;
+}
+
+__device__ __forceinline__ int meta_rad_exp(const Meta &a, const Meta &b, bool &any) {
+  int f = -0x7FFFFFFF;
+  if (b.rm != 0.0 && a.n) { f = a.e + b.re > f ? a.e + b.re : f; any = true; }
+  if (a.rm != 0.0 && b.n) { f = b.e + a.re > f ? b.e + a.re : f; any = true; }
+  if (a.rm != 0.0 && b.rm != 0.0) { f = a.re + b.re > f ? a.re + b.re : f; any = true; }
+  return f;
+}
+
+// rad_term of the limb engine on staged values (mag: mag_upper of the operand).
+__device__ __forceinline__ double staged_rad_term(bool an, int ae, double amag, double arm, int are, bool bn, int be,
+                                                  double bmag, double brm, int bre, int F) {
+  double acc = 0.0;
+  if (brm != 0.0 && an) acc = ru_add(acc, ru_scale_down(ru_mul(amag, brm), ae + bre - F));
+  if (arm != 0.0 && bn) acc = ru_add(acc, ru_scale_down(ru_mul(bmag, arm), be + are - F));
+  if (arm != 0.0 && brm != 0.0) acc = ru_add(acc, ru_scale_down(ru_mul(arm, brm), are + bre - F));
+  return acc;
+}
+
+__device__ __forceinline__ void write_erange(const arbgpu_out &R, int64_t idx, int p, bool approx) {
+  const int PL = (p + 31) >> 5;
+  for (int k = 0; k < PL; ++k) gpw(R.limbs)[(int64_t)k * R.ld + idx] = 0u;
+  gpw(R.exp)[idx] = 0;
+  gpw(R.nls)[idx] = 0;
+  if (!approx) {
+    gpw(R.rad_m)[idx] = INFINITY;
+    gpw(R.rad_e)[idx] = 0;
+  }
+  if (R.status) gpw(R.status)[idx] = ARBGPU_ST_ERANGE;
+}
+
+__device__ __forceinline__ int ifloor32(int v) { return v >= 0 ? (v >> 5) : -((31 - v) >> 5); }
+
+// One dot job on one workgroup.  P[q] is the task of part q (real part
+// first).  fb(q, bool) is called once per part by one thread: true when the
+// limb kernel must redo part q (nothing has been written for it then).
+template <int LB, bool CPLX, class PP, class FB>
+__device__ void digit_job(PP P0, PP P1, DLds<LB, CPLX> &S, const FB &fb) {
+  using C = DCfg<LB, CPLX>;
+  constexpr int NPART = CPLX ? 2 : 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t N = P0->N;
+  const bool approx = P0->approx != 0, want_rad = !approx, reduce = P0->reduce != 0;
+  const uint32_t sub = P0->sub;
+  const int NA = P0->na;
+  const arbgpu_arr Xr = P0->X[0], Yr = P0->Y[0];
+  const arbgpu_arr Xi = P0->X[CPLX ? 1 : 0], Yi = P0->Y[CPLX ? 1 : 0];
+  const int64_t xoff = P0->xoff, xstep = P0->xstep, yoff = P0->yoff, ystep = P0->ystep;
+
+  // ---- setup pass (Section 3.3): per part e_max, nonzero products and the
+  // radius frame; the job's exponent frame E and the range check
+  int emax[2] = {-0x7FFFFFFF, -0x7FFFFFFF}, F[2] = {-0x7FFFFFFF, -0x7FFFFFFF};
+  uint32_t nnz[2] = {0u, 0u};
+  int anyr[2] = {0, 0};
+  int erange = 0, E = -0x7FFFFFFF;
+  for (int64_t t = tid; t < N; t += kDT) {
+    Meta o[4];
+    load_meta(Xr, xoff + t * xstep, o[0]);
+    load_meta(Yr, yoff + t * ystep, o[2]);
+    if (CPLX) {
+      load_meta(Xi, xoff + t * xstep, o[1]);
+      load_meta(Yi, yoff + t * ystep, o[3]);
+    } else {
+      o[1].n = 0; o[1].rm = 0.0; o[3].n = 0; o[3].rm = 0.0;
+      o[1].e = o[3].e = 0; o[1].re = o[3].re = 0; o[1].sign = o[3].sign = 0;
+    }
+    // products (part, x operand, y operand)
+    constexpr int NPR = CPLX ? 4 : 1;
+    const int pa[4] = {0, 1, 0, 1}, pb[4] = {2, 3, 3, 2}, pp[4] = {0, 0, 1, 1};
+#pragma unroll
+    for (int r = 0; r < NPR; ++r) {
+      const Meta &a = o[pa[r]], &b = o[pb[r]];
+      const int q = pp[r];
+      if (meta_out_of_range(a) || meta_out_of_range(b)) erange = 1;
+      if (a.n && b.n) {
+        const int et = a.e + b.e;
+        emax[q] = et > emax[q] ? et : emax[q];
+        nnz[q] += 1;
+      }
+      if (want_rad || reduce) {
+        bool any = false;
+        const int f = meta_rad_exp(a, b, any);
+        if (any) { anyr[q] = 1; F[q] = f > F[q] ? f : F[q]; }
+      }
+    }
+    int exm = -0x7FFFFFFF, eym = -0x7FFFFFFF;
+    if (o[0].n) exm = o[0].e;
+    if (o[1].n && o[1].e > exm) exm = o[1].e;
+    if (o[2].n) eym = o[2].e;
+    if (o[3].n && o[3].e > eym) eym = o[3].e;
+    if (exm != -0x7FFFFFFF && eym != -0x7FFFFFFF && exm + eym > E) E = exm + eym;
+  }
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      int v = __shfl_xor(emax[q], m, 64);
+      emax[q] = v > emax[q] ? v : emax[q];
+      nnz[q] += (uint32_t)__shfl_xor((int)nnz[q], m, 64);
+      v = __shfl_xor(F[q], m, 64);
+      F[q] = v > F[q] ? v : F[q];
+      anyr[q] |= __shfl_xor(anyr[q], m, 64);
+    }
+    erange |= __shfl_xor(erange, m, 64);
+    const int v = __shfl_xor(E, m, 64);
+    E = v > E ? v : E;
+  }
+  if (lane == 0) {
+    int *r = S.red[wave];
+    r[0] = emax[0]; r[1] = (int)nnz[0]; r[2] = F[0]; r[3] = anyr[0];
+    r[4] = emax[1]; r[5] = (int)nnz[1]; r[6] = F[1]; r[7] = anyr[1];
+    r[8] = erange; r[9] = E;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 2; ++q) { emax[q] = -0x7FFFFFFF; nnz[q] = 0; F[q] = -0x7FFFFFFF; anyr[q] = 0; }
+  erange = 0;
+  E = -0x7FFFFFFF;
+  for (int w = 0; w < kDW; ++w) {
+    const int *r = S.red[w];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      emax[q] = r[4 * q] > emax[q] ? r[4 * q] : emax[q];
+      nnz[q] += (uint32_t)r[4 * q + 1];
+      F[q] = r[4 * q + 2] > F[q] ? r[4 * q + 2] : F[q];
+      anyr[q] |= r[4 * q + 3];
+    }
+    erange |= r[8];
+    E = r[9] > E ? r[9] : E;
+  }
+  __syncthreads();
+
+  // precision of each part (the radius-driven cut, Section 3.3 step 7(a))
+  int prec[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    int pq = P0->p;
+    if (reduce) {
+      int64_t v = nnz[q] ? pq : 2;
+      if (nnz[q] && anyr[q] && (int64_t)emax[q] - F[q] + 30 < v) v = (int64_t)emax[q] - F[q] + 30;
+      pq = v < 2 ? 2 : (int)v;
+    }
+    prec[q] = pq;
+  }
+  if (erange) {
+    if (tid == 0) write_erange(P0->R, P0->res_idx, P0->p, approx);
+    if (CPLX && tid == 64) write_erange(P1->R, P1->res_idx, P1->p, approx);
+    if (tid == 0) fb(0, false);
+    if (CPLX && tid == 64) fb(1, false);
+    __syncthreads();
+    return;
+  }
+  {   // does the frame hold every part's p bits, spread and guard?
+    const int64_t kp = N * (CPLX ? 2 : 1);
+    const int bk = 64 - __builtin_clzll((uint64_t)kp | 1ull);
+    bool fits = true;
+#pragma unroll
+    for (int q = 0; q < NPART; ++q)
+      if (nnz[q] && (int64_t)prec[q] + ((int64_t)E - emax[q]) + bk + kDigitGuard > C::B) fits = false;
+    if (!fits) {
+      if (tid == 0) fb(0, true);
+      if (CPLX && tid == 64) fb(1, true);
+      __syncthreads();
+      return;
+    }
+  }
+  if (E == -0x7FFFFFFF) E = 0;   // no term has a nonzero x and a nonzero y: every digit product is 0
+
+  // ---- main pass: digits of a chunk of terms, their product, the radius
+  v16i acc[NPART][C::PPW];
+#pragma unroll
+  for (int q = 0; q < NPART; ++q)
+#pragma unroll
+    for (int i = 0; i < C::PPW; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[q][i][r] = 0;
+  RadAcc racc;
+  racc.clear();
+  uint32_t ntr = 0;
+  // conversion: thread (operand, term of the chunk)
+  const int cop = CPLX ? wave : (wave & 1);
+  const int ck = CPLX ? lane : lane + 64 * (wave >> 1);
+  const bool isx = CPLX ? cop < 2 : cop == 0;
+  const arbgpu_arr A = CPLX ? (cop == 0 ? Xr : cop == 1 ? Xi : cop == 2 ? Yr : Yi) : (cop == 0 ? Xr : Yr);
+  // radius and cut counting: thread (product, term)
+  const int rpa = CPLX ? (wave & 1) : 0;
+  const int rpb = CPLX ? (wave == 0 ? 2 : wave == 1 ? 3 : wave == 2 ? 3 : 2) : 1;
+  const int rpart = CPLX ? (wave >> 1) : 0;
+  const int rk = CPLX ? lane : lane + 64 * (wave & 1);
+  const bool ract = CPLX ? true : wave < 2;
+  const bool rad_on = want_rad && (rpart ? anyr[1] : anyr[0]);
+  const int Fr = rpart ? F[1] : F[0];
+  // kept blocks of the digit product: (bs, bu) with bs + bu >= LB - 2; the
+  // others add less than 2^-200 units of the window together (each block's
+  // sum is below 2^(224 (bs + bu + 2 - LB)) K units, K < 2^18 products)
+  int pbs[C::PPW], pbu[C::PPW];
+#pragma unroll
+  for (int i = 0; i < C::PPW; ++i) {
+    pbs[i] = -1;
+    pbu[i] = 0;
+    int cnt = 0;
+    for (int a = 0; a < LB; ++a)
+      for (int b = 0; b < LB; ++b)
+        if (a + b >= LB - 2) {
+          if (cnt == wave + kDW * i) { pbs[i] = a; pbu[i] = b; }
+          ++cnt;
+        }
+  }
+
+  for (int64_t k0 = 0; k0 < N; k0 += C::KC) {
+    {
+      const int64_t t = k0 + ck;
+      Meta m;
+      m.n = 0; m.sign = 0; m.e = 0; m.rm = 0.0; m.re = 0;
+      int ey = -0x7FFFFFFF;
+      const int64_t idx = isx ? xoff + t * xstep : yoff + t * ystep;
+      if (t < N) {
+        load_meta(A, idx, m);
+        const int64_t yi = yoff + t * ystep;
+        const int32_t n0 = gp(Yr.nls)[yi] & 0x7FFFFFFF;
+        if (n0 && Yr.cap > 0) ey = gp(Yr.exp)[yi];
+        if (CPLX) {
+          const int32_t n1 = gp(Yi.nls)[yi] & 0x7FFFFFFF;
+          if (n1 && Yi.cap > 0) {
+            const int e1 = gp(Yi.exp)[yi];
+            ey = e1 > ey ? e1 : ey;
+          }
+        }
+      }
+      const bool zero = m.n == 0 || ey == -0x7FFFFFFF;
+      // leading zero bits of the operand in its frame
+      const int z = zero ? 0 : (isx ? E - ey - m.e : ey - m.e);
+      const bool cut = !zero && 32 * (int64_t)m.n > (int64_t)C::B - z;
+      const ARB_GLOBAL uint32_t *LB0 = gp(A.limbs) + idx;
+      const int64_t ld = A.ld;
+      auto limb = [&](int j) -> uint32_t { return (j >= 0 && j < m.n) ? LB0[(int64_t)j * ld] : 0u; };
+      double mg = 0.0;
+      if (want_rad && m.n) {   // mag_upper of the limb engine's operand (top min(n, NA) limbs)
+        const int nt = m.n < NA ? m.n : NA;
+        const uint32_t top = limb(0), second = nt > 1 ? limb(1) : 0u;
+        const uint64_t v = ((uint64_t)top << 32) | second;
+        bool rest = m.n > NA;
+        if (!rest && (v & 0x7FFull) == 0)
+          for (int j = 2; j < nt && !rest; ++j) rest = limb(j) != 0;
+        const uint64_t m53 = (v >> 11) + (((v & 0x7FFull) != 0 || rest) ? 1 : 0);
+        mg = (double)m53 * 0x1p-53;
+      }
+      S.mag[cop][ck] = mg;
+      S.rm[cop][ck] = m.rm;
+      S.re[cop][ck] = m.re;
+      S.ex[cop][ck] = m.e;
+      S.fl[cop][ck] = (m.n ? 1 : 0) | (cut ? 2 : 0);
+      const bool neg = ((m.sign ^ (isx ? sub : 0u)) & 1u) != 0;
+#pragma unroll 1
+      for (int g = 0; g < LB; ++g) {
+        // bits [a, a + 224) of the mantissa (from its top) are group g
+        uint32_t T[8];
+        if (!zero) {
+          const int a = C::B - 224 * (g + 1) - z;
+          const int J = ifloor32(a);
+          const uint32_t R = (uint32_t)(a - 32 * J);
+          uint32_t l8[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) l8[q] = limb(J + q);
+#pragma unroll
+          for (int q = 0; q < 7; ++q) T[q] = R ? ((l8[q] << R) | (l8[q + 1] >> (32u - R))) : l8[q];
+          T[7] = 0;
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) T[q] = 0;
+        }
+#pragma unroll
+        for (int dd = 0; dd < 32; ++dd) {   // dd = 0: the group's top digit
+          const int o = 7 * dd, q = o >> 5, r = o & 31;
+          uint32_t bits;
+          if (r <= 25) bits = (T[q] >> (25 - r)) & 0x7Fu;
+          else bits = ((T[q] << (r - 25)) | (T[q + 1] >> (57 - r))) & 0x7Fu;
+          const int v = neg ? -(int)bits : (int)bits;
+          const int row = 32 * g + 31 - dd;
+          S.u.dig[cop][row][ck] = (int8_t)v;
+          if (CPLX && cop == 3) S.u.dig[4][row][ck] = (int8_t)(-v);
+        }
+      }
+    }
+    __syncthreads();
+    // digit products: wave w takes the blocks w, w + 4, ...
+#pragma unroll
+    for (int i = 0; i < C::PPW; ++i) {
+      if (pbs[i] >= 0) {
+        const int bs = pbs[i], bu = pbu[i];
+#pragma unroll
+        for (int ks = 0; ks < C::KC / 32; ++ks) {
+          const int cb = 32 * ks + 16 * (lane >> 5);
+          const int ra = 32 * bs + (lane & 31), rb = 32 * bu + (lane & 31);
+          if (CPLX) {
+            const v4i ar = *reinterpret_cast<const v4i *>(&S.u.dig[0][ra][cb]);
+            const v4i ai = *reinterpret_cast<const v4i *>(&S.u.dig[1][ra][cb]);
+            const v4i br = *reinterpret_cast<const v4i *>(&S.u.dig[2][rb][cb]);
+            const v4i bi = *reinterpret_cast<const v4i *>(&S.u.dig[3][rb][cb]);
+            const v4i bn = *reinterpret_cast<const v4i *>(&S.u.dig[4][rb][cb]);
+            acc[0][i] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar, br, acc[0][i], 0, 0, 0);
+            acc[0][i] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ai, bn, acc[0][i], 0, 0, 0);
+            acc[NPART - 1][i] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar, bi, acc[NPART - 1][i], 0, 0, 0);
+            acc[NPART - 1][i] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ai, br, acc[NPART - 1][i], 0, 0, 0);
+          } else {
+            const v4i a = *reinterpret_cast<const v4i *>(&S.u.dig[0][ra][cb]);
+            const v4i b = *reinterpret_cast<const v4i *>(&S.u.dig[1][rb][cb]);
+            acc[0][i] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[0][i], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // radius terms and cut products of the chunk
+    if (ract && k0 + rk < N) {
+      const int fa = S.fl[rpa][rk], fbv = S.fl[rpb][rk];
+      if ((fa & fbv & 1) && ((fa | fbv) & 2)) ++ntr;
+      if (rad_on)
+        racc.add(staged_rad_term(fa & 1, S.ex[rpa][rk], S.mag[rpa][rk], S.rm[rpa][rk], S.re[rpa][rk], fbv & 1,
+                                 S.ex[rpb][rk], S.mag[rpb][rk], S.rm[rpb][rk], S.re[rpb][rk], Fr));
+    }
+    __syncthreads();
+  }
+
+  // ---- anti-diagonal sums, the integer sum, certification, output
+  for (int w = tid; w < NPART * (2 * C::L + C::NCOL); w += kDT) {
+    if (w < NPART * 2 * C::L) S.u.f.diag[w / (2 * C::L)][w % (2 * C::L)] = 0;
+    else {
+      const int v = w - NPART * 2 * C::L;
+      S.u.f.col[v / C::NCOL][v % C::NCOL] = 0;
+    }
+  }
+  WaveReducer::rad(racc);
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) ntr += (uint32_t)__shfl_xor((int)ntr, m, 64);
+  if (lane == 0) {
+    S.rad[wave] = racc;
+    S.ntr[wave] = ract ? ntr : 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < C::PPW; ++i) {
+    if (pbs[i] >= 0) {
+      const int bs = pbs[i], bu = pbu[i];
+#pragma unroll
+      for (int pt = 0; pt < NPART; ++pt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int s = 32 * bs + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), u = 32 * bu + (lane & 31);
+          atomicAdd(reinterpret_cast<unsigned long long *>(&S.u.f.diag[pt][s + u]),
+                    (unsigned long long)(int64_t)acc[pt][i][r]);
+        }
+    }
+  }
+  __syncthreads();
+  for (int w = tid; w < NPART * 2 * C::L; w += kDT) {
+    const int pt = w / (2 * C::L), d = w % (2 * C::L);
+    const int64_t v = S.u.f.diag[pt][d];
+    if (v) {
+      const int b = 7 * d, c = b >> 5, r = b & 31;
+      const uint64_t sl = ((uint64_t)v & 0xFFFFFFFFull) << r;
+      const int64_t hv = (v >> 32) * ((int64_t)1 << r);
+      atomicAdd(reinterpret_cast<unsigned long long *>(&S.u.f.col[pt][c]), sl & 0xFFFFFFFFull);
+      atomicAdd(reinterpret_cast<unsigned long long *>(&S.u.f.col[pt][c + 1]),
+                (unsigned long long)((int64_t)(sl >> 32) + hv));
+    }
+  }
+  __syncthreads();
+  if (lane == 0 && wave < NPART) {
+    const int pt = wave;
+    PP P = pt ? P1 : P0;
+    int64_t *col = S.u.f.col[pt];
+    int64_t cy = 0;
+    bool lownz = false;
+    for (int c = 0; c < C::NCOL; ++c) {
+      const int64_t v = col[c] + cy;
+      col[c] = v & 0xFFFFFFFFll;
+      cy = v >> 32;
+      if (c < C::C0 && (v & 0xFFFFFFFFll)) lownz = true;
+    }
+    uint32_t nt = 0;
+    RadAcc rt;
+    rt.clear();
+    for (int w = 0; w < kDW; ++w) {
+      const int wp = CPLX ? (w >> 1) : 0;
+      if (wp == pt) {
+        nt += S.ntr[w];
+        rt.add(S.rad[w]);
+      }
+    }
+    // 3 units per product with a cut operand, 1 for the bits below the
+    // window, 1 for the blocks left out
+    const uint64_t err = 3ull * nt + (lownz ? 1u : 0u) + (LB >= 3 ? 1u : 0u);
+    int64_t hb = 0;
+    const int p = pt ? prec[1] : prec[0];
+    const int Fp = pt ? F[1] : F[0];
+    const bool radp = want_rad && (pt ? anyr[1] : anyr[0]);
+    const bool ok = window_certify(C::NCOL - C::C0, err, p, col + C::C0, S.u.f.hi[pt], &hb);
+    if (ok) {
+      double rin_m = 0.0;
+      int rin_e = 0;
+      if (radp) {
+        double m;
+        int e;
+        if (rt.get(m, e)) {
+          rin_m = m;
+          rin_e = Fp + e;
+        }
+      }
+      const arbgpu_out &R = P->R;
+      const int64_t oidx = P->res_idx;
+      finish_entry([&](int q) { return (uint32_t)col[C::C0 + q]; }, C::NCOL - C::C0, (int64_t)E - C::B, R, oidx, p,
+                   approx, rin_m, rin_e);
+      // limbs of the requested precision beyond a cut one stay zero
+      for (int k = (p + 31) >> 5; k < ((P->p + 31) >> 5); ++k) gpw(R.limbs)[(int64_t)k * R.ld + oidx] = 0u;
+    }
+    fb(pt, !ok);
+  }
+  __syncthreads();
+}
+
+template <int LB, bool CPLX>
+__global__ __launch_bounds__(kDT) void digit_dot_kernel(DotParams p0, DotParams p1, int32_t *flags) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  auto &S = *reinterpret_cast<DLds<LB, CPLX> *>(smem);
+  auto fb = [&](int q, bool redo) { gpw(flags)[q] = redo ? 1 : 0; };
+  digit_job<LB, CPLX>(&p0, &p1, S, fb);
+}
+
+// Persistent batch: each workgroup takes jobs from the run's counter; a
+// part that needs the limb kernel is appended to its shape's list.
+template <int LB, bool CPLX>
+__global__ __launch_bounds__(kDT) void digit_dot_batch_kernel(DigitBatchParams bp) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  auto &S = *reinterpret_cast<DLds<LB, CPLX> *>(smem);
+  for (int64_t iter = 0; iter <= bp.count; ++iter) {
+    if (threadIdx.x == 0) S.job = atomicAdd(bp.counter, 1);
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(S.job);
+    __syncthreads();
+    if (t >= bp.count) break;   // uniform across the workgroup
+    const int32_t e = __builtin_amdgcn_readfirstlane(gp(bp.order)[t]);
+    const ARB_GLOBAL DotParams *P0 = gp(bp.tasks) + e;
+    auto fb = [&](int q, bool redo) {
+      if (!redo) return;
+      const int32_t task = e + q;
+      const int f = gp(bp.tasks)[task].fb;
+      const int32_t slot = atomicAdd(bp.fb_count + f, 1);
+      gpw(bp.fb_list)[gp(bp.fb_base)[f] + slot] = task;
+    };
+    digit_job<LB, CPLX>(P0, P0 + (CPLX ? 1 : 0), S, fb);
+  }
+}
+
+template <int LB, bool CPLX>
+size_t lds_of() {
+  return sizeof(DLds<LB, CPLX>);
+}
+
+}  // namespace
+
+int digit_blocks(const DotParams &prm, LimbShape sh) {
+  if (prm.has_init || sh.ns == 0 || prm.N <= 0 || prm.N > 65536) return 0;
+  // frame for p, the term count, the guard and the spread E - e_max: none
+  // for a real dot (E is its largest product exponent), 40 bits allowed
+  // for a complex one (E pairs each term's larger x and y parts)
+  const int64_t kp = prm.N * prm.ct.ncomp;
+  int bk = 0;
+  for (int64_t v = kp; v; v >>= 1) ++bk;
+  const int64_t need = (int64_t)prm.p + (prm.ct.ncomp == 2 ? 40 : 0) + bk + kDigitGuard;
+  const int64_t lb = (need + 223) / 224;
+  return lb <= kDigitMaxBlocks ? (int)lb : 0;
+}
+
+#define ARB_DIGIT_CASES(X) X(1) X(2) X(3) X(4) X(5)
+
+hipError_t launch_digit_dot(const DotParams *prm, int lb, int32_t *flags, hipStream_t s) {
+  const bool cplx = prm[0].ct.ncomp == 2;
+  const DotParams &p1 = cplx ? prm[1] : prm[0];
+#define X(b)                                                                                              \
+  if (lb == b) {                                                                                          \
+    if (cplx)                                                                                             \
+      hipLaunchKernelGGL((digit_dot_kernel<b, true>), dim3(1), dim3(kDT), (lds_of<b, true>()), s, prm[0], p1, \
+                         flags);                                                                          \
+    else                                                                                                  \
+      hipLaunchKernelGGL((digit_dot_kernel<b, false>), dim3(1), dim3(kDT), (lds_of<b, false>()), s, prm[0], \
+                         p1, flags);                                                                      \
+    return hipGetLastError();                                                                             \
+  }
+  ARB_DIGIT_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+const void *digit_dot_batch_kernel(int lb, bool cplx, size_t *lds_bytes) {
+#define X(b)                                                                              \
+  if (lb == b) {                                                                          \
+    *lds_bytes = cplx ? lds_of<b, true>() : lds_of<b, false>();                          \
+    return cplx ? reinterpret_cast<const void *>(&digit_dot_batch_kernel<b, true>)       \
+                : reinterpret_cast<const void *>(&digit_dot_batch_kernel<b, false>);     \
+  }
+  ARB_DIGIT_CASES(X)
+#undef X
+  *lds_bytes = 0;
+  return nullptr;
+}
+
+}  // namespace arbgpu_impl

@@ -70,7 +70,7 @@ namespace arbgpu_impl {
 // Workspace slots (each holds one growing device buffer).
 enum WsSlot {
   WS_STATS = 0, WS_PLANES_A, WS_PLANES_B, WS_PLANES_B2, WS_D, WS_T, WS_TABLES,
-  WS_RAD_A, WS_RAD_B, WS_RAD_OUT, WS_PLAN, WS_BLOCKS, WS_BATCH, WS_RNS, WS_GATHER, WS_RAD_PART, WS_COUNT
+  WS_RAD_A, WS_RAD_B, WS_RAD_OUT, WS_PLAN, WS_BLOCKS, WS_BATCH, WS_RNS, WS_GATHER, WS_RAD_PART, WS_DOTFLAG, WS_COUNT
 };
 
 // Device buffer of at least `bytes` in workspace slot `slot` (nullptr and
@@ -184,6 +184,9 @@ struct DotParams {
   int init_part;            // which part of the initial value feeds this output
   int reduce;               // radius-driven precision cut (Section 3.3, step 7(a))
   CompTab ct;
+  int na;                   // operand limbs of the job's limb-kernel shape (its radius bound)
+  int digit;                // digit-product blocks (digit_dot.hip) of the job, 0: the limb kernels
+  int fb;                   // in a batch: the fallback list of the task's limb shape
 };
 
 // Window / operand-limb template choice for the limb kernels.
@@ -206,7 +209,7 @@ const void *wide_dot_batch_kernel_ptr(size_t *lds_bytes);
 template <int NS, int NA>
 hipError_t launch_mm_shape(const MmParams &prm, hipStream_t s);
 template <int NS, int NA>
-hipError_t launch_dot_shape(const DotParams &prm, hipStream_t s);
+hipError_t launch_dot_shape(const DotParams &prm, hipStream_t s, const int32_t *gate);
 template <int NS, int NA>
 hipError_t launch_mm_list_shape(const MmParams &prm, const int64_t *list, const int32_t *count, int64_t max_count,
                                 hipStream_t s);
@@ -238,6 +241,7 @@ struct BatchShapeParams {
   const int32_t *order;     // this shape's work, longest first: dot task e >= 0, tile -e - 1
   int64_t count;
   int32_t *counter;         // work counter, zero before the launch
+  const int32_t *dcount;    // if set, only the first *dcount entries of `order` (a device-filled list)
 };
 template <int NS, int NA>
 const void *dot_batch_kernel_shape(bool block);
@@ -261,13 +265,37 @@ int mat_mul_check(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, co
 // included).  mat_mul_footprint is their sum (admission by HBM footprint).
 void mat_mul_ws_sizes(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags, size_t out[]);
 size_t mat_mul_footprint(const arbgpu_mat *A, const arbgpu_mat *B, int64_t p, uint32_t flags);
-// Workspace of a one-shot dot batch of up to n tasks in up to nshapes shapes.
-size_t dot_batch_ws(int64_t n, int nshapes);
+// Workspace of a one-shot dot batch of up to n tasks.
+size_t dot_batch_ws(int64_t n);
 
 // Validates one dot job and builds its kernel tasks (one per output part)
 // and kernel shape; sets the context error and returns EINVAL on a bad job.
 int dot_tasks(arbgpu_ctx *ctx, const arbgpu_dot_job &job, const char *who, DotParams prm[2], int *ntasks,
               LimbShape *shape);
-hipError_t launch_limb_dot(const DotParams &prm, LimbShape sh, hipStream_t s);
+// `gate` (device memory, may be null): the launch does nothing unless *gate
+// is nonzero (a dot the digit product handed over).
+hipError_t launch_limb_dot(const DotParams &prm, LimbShape sh, hipStream_t s, const int32_t *gate = nullptr);
+
+// Dot products as one small INT8 matrix product of operand digits each
+// (digit_dot.hip).  digit_blocks: the digit blocks (32 digits of 7 bits)
+// per operand a job takes on that path, 0 when it stays on the limb
+// kernels (initial value, length, precision, a forced path).
+constexpr int kDigitMaxBlocks = 5;
+int digit_blocks(const DotParams &prm, LimbShape sh);
+// One job (its tasks: the real part, or the real and imaginary parts of a
+// complex dot); flags[q] (device memory) receives 1 when part q must be
+// redone by the limb kernel, else 0.
+hipError_t launch_digit_dot(const DotParams *prm, int lb, int32_t *flags, hipStream_t s);
+struct DigitBatchParams {
+  const DotParams *tasks;   // every dot task of the batch
+  const int32_t *order;     // this run's jobs (index of the job's first task), longest first
+  int64_t count;
+  int32_t *counter;         // work counter, zero before the launch
+  int32_t *fb_list;         // fallback lists, list f at fb_base[f]
+  const int32_t *fb_base;
+  int32_t *fb_count;        // entries of each list, zero before the launch
+};
+// kernel taking (DigitBatchParams), one workgroup per job, and its dynamic LDS
+const void *digit_dot_batch_kernel(int lb, bool cplx, size_t *lds_bytes);
 
 }  // namespace arbgpu_impl

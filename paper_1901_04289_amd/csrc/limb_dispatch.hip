@@ -59,9 +59,9 @@ const void *dot_batch_kernel(LimbShape sh, bool block) {
   return nullptr;
 }
 
-hipError_t launch_limb_dot(const DotParams &prm, LimbShape sh, hipStream_t s) {
+hipError_t launch_limb_dot(const DotParams &prm, LimbShape sh, hipStream_t s, const int32_t *gate) {
 #define X(a, b) \
-  if (sh.ns == a && sh.na == b) return launch_dot_shape<a, b>(prm, s);
+  if (sh.ns == a && sh.na == b) return launch_dot_shape<a, b>(prm, s, gate);
   ARB_LIMB_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;

@@ -35,11 +35,11 @@ hipError_t launch_mm_list_shape<ARB_NS, ARB_NA>(const MmParams &prm, const int64
 }
 
 template <>
-hipError_t launch_dot_shape<ARB_NS, ARB_NA>(const DotParams &prm, hipStream_t s) {
+hipError_t launch_dot_shape<ARB_NS, ARB_NA>(const DotParams &prm, hipStream_t s, const int32_t *gate) {
   if (prm.N * prm.ct.ncomp >= kDotBlockTerms)   // four waves share the terms
-    hipLaunchKernelGGL((limb_dot_block_kernel<ARB_NS, ARB_NA>), dim3(1), dim3(256), 0, s, prm);
+    hipLaunchKernelGGL((limb_dot_block_kernel<ARB_NS, ARB_NA>), dim3(1), dim3(256), 0, s, prm, gate);
   else
-    hipLaunchKernelGGL((limb_dot_kernel<ARB_NS, ARB_NA>), dim3(1), dim3(64), 0, s, prm);
+    hipLaunchKernelGGL((limb_dot_kernel<ARB_NS, ARB_NA>), dim3(1), dim3(64), 0, s, prm, gate);
   return hipGetLastError();
 }
 

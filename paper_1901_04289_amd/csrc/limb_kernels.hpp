@@ -360,7 +360,8 @@ __global__ __launch_bounds__(256) void limb_mm_list_kernel(MmParams prm, const i
 }
 
 template <int NS, int NA>
-__global__ __launch_bounds__(64) void limb_dot_kernel(DotParams prm) {
+__global__ __launch_bounds__(64) void limb_dot_kernel(DotParams prm, const int32_t *gate) {
+  if (gate && *gp(gate) == 0) return;   // the digit product certified this dot
   DotOut<NS> out;
   DotSrc<Opnd<NA>> src{&prm};
   run_dot<NS, Opnd<NA>, WaveReducer>(src, prm.p, !prm.approx, out, prm.reduce != 0);
@@ -377,7 +378,8 @@ __global__ __launch_bounds__(64) void limb_dot_kernel(DotParams prm) {
 // lanes, the waves' windows, error counts and radius sums added in LDS.
 // The result is limb_dot_kernel's bit for bit.
 template <int NS, int NA>
-__global__ __launch_bounds__(256) void limb_dot_block_kernel(DotParams prm) {
+__global__ __launch_bounds__(256) void limb_dot_block_kernel(DotParams prm, const int32_t *gate) {
+  if (gate && *gp(gate) == 0) return;
   DotOut<NS> out;
   DotSrc<Opnd<NA>> src{&prm};
   run_dot<NS, Opnd<NA>, BlockReducer<4>>(src, prm.p, !prm.approx, out, prm.reduce != 0);
@@ -400,12 +402,17 @@ __global__ __launch_bounds__(256) void limb_dot_block_kernel(DotParams prm) {
 template <int NS, int NA>
 __global__ __launch_bounds__(256) void limb_dot_batch_kernel(BatchShapeParams bp) {
   const int lane = threadIdx.x & 63;
+  int64_t count = bp.count;
+  if (bp.dcount) {
+    const int64_t d = *gp(bp.dcount);
+    count = d < count ? d : count;
+  }
   // the counter only grows, so a wave takes at most `count` tasks
-  for (int64_t iter = 0; iter <= bp.count; ++iter) {
+  for (int64_t iter = 0; iter <= count; ++iter) {
     int t = 0;
     if (lane == 0) t = atomicAdd(bp.counter, 1);
     t = __shfl(t, 0, 64);
-    if (t >= bp.count) break;   // uniform across the wave
+    if (t >= count) break;   // uniform across the wave
     // uniform task index: the parameters are read with scalar loads
     const int tu = __builtin_amdgcn_readfirstlane(t);
     const int32_t e = __builtin_amdgcn_readfirstlane(gp(bp.order)[tu]);
@@ -468,12 +475,17 @@ __global__ __launch_bounds__(256) void limb_dot_batch_kernel(BatchShapeParams bp
 template <int NS, int NA>
 __global__ __launch_bounds__(256) void limb_dot_batch_block_kernel(BatchShapeParams bp) {
   __shared__ int task;
-  for (int64_t iter = 0; iter <= bp.count; ++iter) {
+  int64_t count = bp.count;
+  if (bp.dcount) {
+    const int64_t d = *gp(bp.dcount);
+    count = d < count ? d : count;
+  }
+  for (int64_t iter = 0; iter <= count; ++iter) {
     if (threadIdx.x == 0) task = atomicAdd(bp.counter, 1);
     __syncthreads();
     const int t = __builtin_amdgcn_readfirstlane(task);
     __syncthreads();   // every thread has read it before the next take
-    if (t >= bp.count) break;   // uniform across the workgroup
+    if (t >= count) break;   // uniform across the workgroup
     const int32_t e = __builtin_amdgcn_readfirstlane(gp(bp.order)[t]);
     const ARB_GLOBAL DotParams *prm = gp(bp.tasks) + e;
     DotOut<NS> out;

@@ -269,7 +269,7 @@ int arbgpu_serve_reserve(arbgpu_ctx *ctx, const arbgpu_job *jobs, int64_t njobs)
       if (rc) return rc;
       mat_mul_ws_sizes(&j.A, &j.B, j.p, j.flags, js);
     } else if (j.kind == ARBGPU_JOB_DOT) {
-      js[WS_BATCH] = dot_batch_ws(2 * (int64_t)kMaxDotGroup, 16);
+      js[WS_BATCH] = dot_batch_ws(2 * (int64_t)kMaxDotGroup);
     } else {
       return set_error(ctx, ARBGPU_EINVAL, "arbgpu_serve_reserve: unknown job kind %d", j.kind);
     }

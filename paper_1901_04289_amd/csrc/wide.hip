@@ -14,6 +14,7 @@
 // of every product (the fast dot with an exact fallback, Section 2).
 #include "finish.hpp"
 #include "limb_kernels.hpp"
+#include "window.hpp"
 
 using namespace arb;
 
@@ -41,14 +42,6 @@ struct WideLds {
 };
 
 __device__ __forceinline__ int64_t floor_div32(int64_t v) { return v >= 0 ? (v >> 5) : -((31 - v) >> 5); }
-
-// Bit length of the magnitude held in limbs x(0 .. n) (least significant first).
-template <class X>
-__device__ __forceinline__ int64_t bitlen_limbs(const X &x, int n) {
-  for (int q = n - 1; q >= 0; --q)
-    if (x(q)) return 32 * (int64_t)q + (32 - __builtin_clz(x(q)));
-  return 0;
-}
 
 __device__ __forceinline__ uint32_t limb(const WideLds &L, int c) { return (uint32_t)L.col[c]; }
 __device__ __forceinline__ void set_limb(WideLds &L, int c, uint32_t v) { L.col[c] = (int64_t)v; }
@@ -153,69 +146,6 @@ __device__ void wide_normalize(int nW, WideLds &L) {
   __syncthreads();
 }
 
-// Thread 0: whether the truncation to p bits is certified for every sum
-// within err units of the window value (L.a, nW limbs, two's complement).
-// With m = |V| - err and h = |V| + err the sum's magnitude lies strictly
-// between them, so when both have the same bit length l > p and the same
-// top p bits, the sum truncates to those bits and drops nonzero bits below
-// them.  On success L.a holds a value whose truncation is the result (m,
-// with its lowest bit set when no dropped bit of m is set, which keeps it
-// below h and inside the cell) with the sign of V.  *hb receives the bit
-// length of h: the sum's magnitude is below 2^hb units.
-__device__ bool wide_certify(int nW, uint64_t err, int p, WideLds &L, int64_t *hb) {
-  *hb = 0;
-  if (err == 0) return true;   // exact: the window value is the sum
-  const bool neg = (limb(L, nW - 1) >> 31) != 0;
-  uint32_t *hi = L.b;   // nW <= kWideStage in the first pass
-  auto m = [&](int c) { return limb(L, c); };
-  if (neg) {   // magnitude
-    uint32_t cy = 1;
-    for (int c = 0; c < nW; ++c) {
-      const uint32_t v = ~m(c) + cy;
-      cy = (cy && v == 0) ? 1u : 0u;
-      set_limb(L, c, v);
-    }
-  }
-  uint64_t cy = err;
-  for (int c = 0; c < nW; ++c) {
-    const uint64_t v = (uint64_t)m(c) + (cy & 0xFFFFFFFFull);
-    hi[c] = (uint32_t)v;
-    cy = (cy >> 32) + (v >> 32);
-  }
-  const int64_t lb = cy ? 32 * (int64_t)nW + 1 : bitlen_limbs([&](int c) { return hi[c]; }, nW);
-  *hb = lb;
-  if (cy) return false;
-  int64_t bw = (int64_t)err;
-  for (int c = 0; c < nW; ++c) {
-    const int64_t v = (int64_t)m(c) - (bw & 0xFFFFFFFFll);
-    set_limb(L, c, (uint32_t)v);
-    bw = (int64_t)((uint64_t)bw >> 32) + (v < 0 ? 1 : 0);
-  }
-  if (bw) return false;   // |V| < err: not even the sign is known
-  const int64_t la = bitlen_limbs(m, nW);
-  if (la == 0 || la != lb || la <= p) return false;
-  const int64_t cut = la - p;   // bits below `cut` are dropped
-  bool low = false;
-  for (int64_t bit = 0; bit < la; bit += 32) {
-    const int q = (int)(bit >> 5);
-    uint32_t keep = 0xFFFFFFFFu;
-    if (bit + 32 <= cut) keep = 0u;
-    else if (bit < cut) keep = 0xFFFFFFFFu << (uint32_t)(cut - bit);
-    if ((m(q) & keep) != (hi[q] & keep)) return false;
-    low |= (m(q) & ~keep) != 0;
-  }
-  if (!low) set_limb(L, 0, m(0) | 1u);   // cut >= 1, so bit 0 is a dropped bit
-  if (neg) {   // back to two's complement of the signed value
-    uint32_t c1 = 1;
-    for (int c = 0; c < nW; ++c) {
-      const uint32_t v = ~m(c) + c1;
-      c1 = (c1 && v == 0) ? 1u : 0u;
-      set_limb(L, c, v);
-    }
-  }
-  return true;
-}
-
 template <class PP>
 __device__ void wide_dot(PP prm, WideLds &L) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -298,7 +228,7 @@ __device__ void wide_dot(PP prm, WideLds &L) {
     wide_normalize(nW, L);
     if (tid == 0) {
       int64_t hb = 0;
-      L.certified = wide_certify(nW, err, p, L, &hb) ? 1 : 0;
+      L.certified = window_certify(nW, err, p, L.col, L.b, &hb) ? 1 : 0;
       L.hb = hb;
     }
     __syncthreads();

@@ -129,7 +129,10 @@ def test_host_only_context_validates_batch(hctx, lib):
     # the cut flag is accepted for dots; unknown flags are not
     okr = arbgpu.dot_job([_out()], 0, [_arr()], 0, 1, [_arr()], 0, 1, 5, 64, flags=arbgpu.REDUCE_PREC)
     assert lib.arbgpu_batch_create(hctx.h, (arbgpu.DotJob * 1)(okr), 1, ctypes.byref(h)) == arbgpu.EDEVICE
-    badf = arbgpu.dot_job([_out()], 0, [_arr()], 0, 1, [_arr()], 0, 1, 5, 64, flags=arbgpu.ALGO_LIMB)
+    # ALGO_LIMB keeps a dot on the limb kernels; the matrix-product path flags do not apply
+    okl = arbgpu.dot_job([_out()], 0, [_arr()], 0, 1, [_arr()], 0, 1, 5, 64, flags=arbgpu.ALGO_LIMB)
+    assert lib.arbgpu_batch_create(hctx.h, (arbgpu.DotJob * 1)(okl), 1, ctypes.byref(h)) == arbgpu.EDEVICE
+    badf = arbgpu.dot_job([_out()], 0, [_arr()], 0, 1, [_arr()], 0, 1, 5, 64, flags=arbgpu.ALGO_SLICED)
     assert lib.arbgpu_batch_create(hctx.h, (arbgpu.DotJob * 1)(badf), 1, ctypes.byref(h)) == arbgpu.EINVAL
 
 
