@@ -50,7 +50,7 @@ struct DCfg {
   static constexpr int L = 32 * LB;             // digits per operand
   static constexpr int B = 224 * LB;            // frame bits
   static constexpr int NOP = CPLX ? 4 : 2;      // operands per term: x_re, x_im, y_re, y_im | x, y
-  static constexpr int NPL = CPLX ? 5 : 2;      // digit planes (and -y_im)
+  static constexpr int NPL = NOP;               // digit planes
   static constexpr int KC = CPLX ? 64 : 128;    // terms per chunk
   static constexpr int RS = KC + 16;            // bytes per digit row (padding against bank conflicts)
   // 32 x 32 blocks of the digit product that are formed (bs + bu >= LB - 2)
@@ -90,28 +90,27 @@ struct Meta {
   int re;
 };
 
+// Branch-free: every load is issued whatever the values, so the loads of a
+// term go out together (a load under a value-dependent branch would wait
+// for the one before it).
 __device__ __forceinline__ void load_meta(const arbgpu_arr &A, int64_t idx, Meta &m) {
   const int32_t nl = gp(A.nls)[idx];
-  int n = nl & 0x7FFFFFFF;
-  if (n > A.cap) n = A.cap;
-  m.n = n;
-  m.sign = (uint32_t)nl >> 31;
-  m.e = gp(A.exp)[idx];
-  m.rm = 0.0;
-  m.re = 0;
-  if (A.rad_m) {
-    const double r = gp(A.rad_m)[idx];
-    if (r != 0.0) {
-      if (r > 0.0 && r < INFINITY) {
-        int ex;
-        m.rm = frexp(r, &ex);
-        m.re = gp(A.rad_e)[idx] + ex;
-      } else {
-        m.rm = 1.0;
-        m.re = kExpLimit;
-      }
-    }
+  const int e = gp(A.exp)[idx];
+  double r = 0.0;
+  int rexp = 0;
+  if (A.rad_m) {   // uniform
+    r = gp(A.rad_m)[idx];
+    rexp = gp(A.rad_e)[idx];
   }
+  int n = nl & 0x7FFFFFFF;
+  m.n = n > A.cap ? A.cap : n;
+  m.sign = (uint32_t)nl >> 31;
+  m.e = e;
+  int ex = 0;
+  const double fm = frexp(r, &ex);
+  const bool fin = r > 0.0 && r < INFINITY;
+  m.rm = fin ? fm : (r != 0.0 ? 1.0 : 0.0);
+  m.re = fin ? rexp + ex : (r != 0.0 ? kExpLimit : 0);
 }
 
 __device__ __forceinline__ bool meta_out_of_range(const Meta &o) {
@@ -150,7 +149,41 @@ __device__ __forceinline__ void write_erange(const arbgpu_out &R, int64_t idx, i
   if (R.status) gpw(R.status)[idx] = ARBGPU_ST_ERANGE;
 }
 
+// Job parameters read from memory are the same in every lane: held in
+// scalar registers (the compiler cannot prove that for a global load).
+__device__ __forceinline__ int32_t uni32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T *uniptr(T *p) {
+  return reinterpret_cast<T *>(uni64(reinterpret_cast<int64_t>(p)));
+}
+__device__ __forceinline__ arbgpu_arr uni_arr(const arbgpu_arr &a) {
+  arbgpu_arr r;
+  r.limbs = uniptr(a.limbs);
+  r.ld = uni64(a.ld);
+  r.cap = uni32(a.cap);
+  r.exp = uniptr(a.exp);
+  r.nls = uniptr(a.nls);
+  r.rad_m = uniptr(a.rad_m);
+  r.rad_e = uniptr(a.rad_e);
+  return r;
+}
+
 __device__ __forceinline__ int ifloor32(int v) { return v >= 0 ? (v >> 5) : -((31 - v) >> 5); }
+
+// Bytewise negation of int8 digits in [-127, 127]: with b' = b xor 0x80 in
+// [1, 255], -b xor 0x80 = 256 - b', and 0x01010100 - (b'3 b'2 b'1 b'0)
+// forms 256 - b' in every byte (each borrow is taken by the 1 above it).
+__device__ __forceinline__ v4i neg_digits(v4i a) {
+  v4i r;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r[k] = (int)((0x01010100u - ((uint32_t)a[k] ^ 0x80808080u)) ^ 0x80808080u);
+  return r;
+}
 
 // One dot job on one workgroup.  P[q] is the task of part q (real part
 // first).  fb(q, bool) is called once per part by one thread: true when the
@@ -160,13 +193,14 @@ __device__ void digit_job(PP P0, PP P1, DLds<LB, CPLX> &S, const FB &fb) {
   using C = DCfg<LB, CPLX>;
   constexpr int NPART = CPLX ? 2 : 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t N = P0->N;
-  const bool approx = P0->approx != 0, want_rad = !approx, reduce = P0->reduce != 0;
-  const uint32_t sub = P0->sub;
-  const int NA = P0->na;
-  const arbgpu_arr Xr = P0->X[0], Yr = P0->Y[0];
-  const arbgpu_arr Xi = P0->X[CPLX ? 1 : 0], Yi = P0->Y[CPLX ? 1 : 0];
-  const int64_t xoff = P0->xoff, xstep = P0->xstep, yoff = P0->yoff, ystep = P0->ystep;
+  const int64_t N = uni64(P0->N);
+  const bool approx = uni32(P0->approx) != 0, want_rad = !approx, reduce = uni32(P0->reduce) != 0;
+  const uint32_t sub = (uint32_t)uni32((int32_t)P0->sub);
+  const int NA = uni32(P0->na);
+  const int preq = uni32(P0->p);
+  const arbgpu_arr Xr = uni_arr(P0->X[0]), Yr = uni_arr(P0->Y[0]);
+  const arbgpu_arr Xi = CPLX ? uni_arr(P0->X[1]) : Xr, Yi = CPLX ? uni_arr(P0->Y[1]) : Yr;
+  const int64_t xoff = uni64(P0->xoff), xstep = uni64(P0->xstep), yoff = uni64(P0->yoff), ystep = uni64(P0->ystep);
 
   // ---- setup pass (Section 3.3): per part e_max, nonzero products and the
   // radius frame; the job's exponent frame E and the range check
@@ -255,7 +289,7 @@ __device__ void digit_job(PP P0, PP P1, DLds<LB, CPLX> &S, const FB &fb) {
   int prec[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    int pq = P0->p;
+    int pq = preq;
     if (reduce) {
       int64_t v = nnz[q] ? pq : 2;
       if (nnz[q] && anyr[q] && (int64_t)emax[q] - F[q] + 30 < v) v = (int64_t)emax[q] - F[q] + 30;
@@ -330,39 +364,58 @@ __device__ void digit_job(PP P0, PP P1, DLds<LB, CPLX> &S, const FB &fb) {
 
   for (int64_t k0 = 0; k0 < N; k0 += C::KC) {
     {
+      // every read below is from a valid index (term 0 stands in for terms
+      // past the end, plane 0 or n - 1 for planes outside the operand) and
+      // issued unconditionally, so the loads of a chunk go out together
       const int64_t t = k0 + ck;
+      const bool live = t < N;
+      const int64_t tt = live ? t : 0;
+      const int64_t idx = isx ? xoff + tt * xstep : yoff + tt * ystep;
+      const int64_t yix = yoff + tt * ystep;
+      const ARB_GLOBAL uint32_t *LB0 = gp(A.limbs) + idx;
+      const uint32_t ld32 = (uint32_t)A.ld;   // below 2^31 on this path
       Meta m;
-      m.n = 0; m.sign = 0; m.e = 0; m.rm = 0.0; m.re = 0;
-      int ey = -0x7FFFFFFF;
-      const int64_t idx = isx ? xoff + t * xstep : yoff + t * ystep;
-      if (t < N) {
-        load_meta(A, idx, m);
-        const int64_t yi = yoff + t * ystep;
-        const int32_t n0 = gp(Yr.nls)[yi] & 0x7FFFFFFF;
-        if (n0 && Yr.cap > 0) ey = gp(Yr.exp)[yi];
-        if (CPLX) {
-          const int32_t n1 = gp(Yi.nls)[yi] & 0x7FFFFFFF;
-          if (n1 && Yi.cap > 0) {
-            const int e1 = gp(Yi.exp)[yi];
-            ey = e1 > ey ? e1 : ey;
-          }
-        }
+      load_meta(A, idx, m);
+      const int32_t n0 = gp(Yr.nls)[yix] & 0x7FFFFFFF;
+      const int e0 = gp(Yr.exp)[yix];
+      int32_t n1 = 0;
+      int e1 = 0;
+      if (CPLX) {
+        n1 = gp(Yi.nls)[yix] & 0x7FFFFFFF;
+        e1 = gp(Yi.exp)[yix];
       }
+      const uint32_t top = LB0[0], second = LB0[A.cap > 1 ? (uint64_t)ld32 : 0];
+      int ey = n0 ? e0 : -0x7FFFFFFF;
+      ey = (n1 && e1 > ey) ? e1 : ey;
+      m.n = live ? m.n : 0;
       const bool zero = m.n == 0 || ey == -0x7FFFFFFF;
       // leading zero bits of the operand in its frame
       const int z = zero ? 0 : (isx ? E - ey - m.e : ey - m.e);
       const bool cut = !zero && 32 * (int64_t)m.n > (int64_t)C::B - z;
-      const ARB_GLOBAL uint32_t *LB0 = gp(A.limbs) + idx;
-      const int64_t ld = A.ld;
-      auto limb = [&](int j) -> uint32_t { return (j >= 0 && j < m.n) ? LB0[(int64_t)j * ld] : 0u; };
+      const int nc = m.n > 0 ? m.n - 1 : 0;
+      // limbs JL .. JL + 7 LB (from the top) cover the frame; R aligns them
+      constexpr int NL = 7 * LB + 1;
+      const int JL = ifloor32(-z);
+      const uint32_t R = (uint32_t)(-z - 32 * JL);
+      uint32_t lim[NL];
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int j = JL + q;
+        const uint32_t jc = (uint32_t)(j < 0 ? 0 : (j > nc ? nc : j));
+        lim[q] = LB0[(uint64_t)jc * ld32];
+      }
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int j = JL + q;
+        lim[q] = (!zero && j >= 0 && j < m.n) ? lim[q] : 0u;
+      }
       double mg = 0.0;
       if (want_rad && m.n) {   // mag_upper of the limb engine's operand (top min(n, NA) limbs)
         const int nt = m.n < NA ? m.n : NA;
-        const uint32_t top = limb(0), second = nt > 1 ? limb(1) : 0u;
-        const uint64_t v = ((uint64_t)top << 32) | second;
+        const uint64_t v = ((uint64_t)top << 32) | (nt > 1 ? second : 0u);
         bool rest = m.n > NA;
         if (!rest && (v & 0x7FFull) == 0)
-          for (int j = 2; j < nt && !rest; ++j) rest = limb(j) != 0;
+          for (int j = 2; j < nt && !rest; ++j) rest = LB0[(uint64_t)j * ld32] != 0;
         const uint64_t m53 = (v >> 11) + (((v & 0x7FFull) != 0 || rest) ? 1 : 0);
         mg = (double)m53 * 0x1p-53;
       }
@@ -371,36 +424,23 @@ __device__ void digit_job(PP P0, PP P1, DLds<LB, CPLX> &S, const FB &fb) {
       S.re[cop][ck] = m.re;
       S.ex[cop][ck] = m.e;
       S.fl[cop][ck] = (m.n ? 1 : 0) | (cut ? 2 : 0);
-      const bool neg = ((m.sign ^ (isx ? sub : 0u)) & 1u) != 0;
-#pragma unroll 1
-      for (int g = 0; g < LB; ++g) {
-        // bits [a, a + 224) of the mantissa (from its top) are group g
-        uint32_t T[8];
-        if (!zero) {
-          const int a = C::B - 224 * (g + 1) - z;
-          const int J = ifloor32(a);
-          const uint32_t R = (uint32_t)(a - 32 * J);
-          uint32_t l8[8];
+      // the frame's bits from the top, 32 to a word
 #pragma unroll
-          for (int q = 0; q < 8; ++q) l8[q] = limb(J + q);
+      for (int q = 0; q < NL - 1; ++q) lim[q] = R ? ((lim[q] << R) | (lim[q + 1] >> (32u - R))) : lim[q];
+      lim[NL - 1] = 0;
+      const int sg = ((m.sign ^ (isx ? sub : 0u)) & 1u) ? -1 : 1;
+      // digit s (weight 2^(7 s)) is bits [7 (L - 1 - s), +7) from the top
+      auto bits_of = [&](int s) -> int {
+        const int o = 7 * (C::L - 1 - s), q = o >> 5, r = o & 31;
+        return (int)(r <= 25 ? (lim[q] >> (25 - r)) & 0x7Fu : ((lim[q] << (r - 25)) | (lim[q + 1] >> (57 - r))) & 0x7Fu);
+      };
+      // (the empty asm after every 8 digits keeps the compiler from forming
+      // every digit before the first store, a register each)
+      int8_t *row0 = &S.u.dig[cop][0][ck];
 #pragma unroll
-          for (int q = 0; q < 7; ++q) T[q] = R ? ((l8[q] << R) | (l8[q + 1] >> (32u - R))) : l8[q];
-          T[7] = 0;
-        } else {
-#pragma unroll
-          for (int q = 0; q < 8; ++q) T[q] = 0;
-        }
-#pragma unroll
-        for (int dd = 0; dd < 32; ++dd) {   // dd = 0: the group's top digit
-          const int o = 7 * dd, q = o >> 5, r = o & 31;
-          uint32_t bits;
-          if (r <= 25) bits = (T[q] >> (25 - r)) & 0x7Fu;
-          else bits = ((T[q] << (r - 25)) | (T[q + 1] >> (57 - r))) & 0x7Fu;
-          const int v = neg ? -(int)bits : (int)bits;
-          const int row = 32 * g + 31 - dd;
-          S.u.dig[cop][row][ck] = (int8_t)v;
-          if (CPLX && cop == 3) S.u.dig[4][row][ck] = (int8_t)(-v);
-        }
+      for (int s = 0; s < C::L; ++s) {
+        row0[s * C::RS] = (int8_t)(bits_of(s) * sg);
+        if ((s & 7) == 7) asm volatile("" ::: "memory");
       }
     }
     __syncthreads();
@@ -418,9 +458,9 @@ __device__ void digit_job(PP P0, PP P1, DLds<LB, CPLX> &S, const FB &fb) {
             const v4i ai = *reinterpret_cast<const v4i *>(&S.u.dig[1][ra][cb]);
             const v4i br = *reinterpret_cast<const v4i *>(&S.u.dig[2][rb][cb]);
             const v4i bi = *reinterpret_cast<const v4i *>(&S.u.dig[3][rb][cb]);
-            const v4i bn = *reinterpret_cast<const v4i *>(&S.u.dig[4][rb][cb]);
+            const v4i an = neg_digits(ai);
             acc[0][i] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar, br, acc[0][i], 0, 0, 0);
-            acc[0][i] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ai, bn, acc[0][i], 0, 0, 0);
+            acc[0][i] = __builtin_amdgcn_mfma_i32_32x32x32_i8(an, bi, acc[0][i], 0, 0, 0);
             acc[NPART - 1][i] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar, bi, acc[NPART - 1][i], 0, 0, 0);
             acc[NPART - 1][i] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ai, br, acc[NPART - 1][i], 0, 0, 0);
           } else {
@@ -549,8 +589,15 @@ __global__ __launch_bounds__(kDT) void digit_dot_kernel(DotParams p0, DotParams 
 
 // Persistent batch: each workgroup takes jobs from the run's counter; a
 // part that needs the limb kernel is appended to its shape's list.
+// Waves per SIMD the batch kernel is compiled for (its register budget).
+template <int LB>
+constexpr int digit_waves() {
+  return LB <= 2 ? 4 : (LB == 3 ? 3 : 2);
+}
+
 template <int LB, bool CPLX>
-__global__ __launch_bounds__(kDT) void digit_dot_batch_kernel(DigitBatchParams bp) {
+__global__ __launch_bounds__(kDT) __attribute__((amdgpu_waves_per_eu(digit_waves<LB>(), 8))) void digit_dot_batch_kernel(
+    DigitBatchParams bp) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   auto &S = *reinterpret_cast<DLds<LB, CPLX> *>(smem);
   for (int64_t iter = 0; iter <= bp.count; ++iter) {
@@ -581,6 +628,8 @@ size_t lds_of() {
 
 int digit_blocks(const DotParams &prm, LimbShape sh) {
   if (prm.has_init || sh.ns == 0 || prm.N <= 0 || prm.N > 65536) return 0;
+  for (int k = 0; k < prm.ct.ncomp; ++k)   // 32-bit plane offsets
+    if (prm.X[k].ld >= ((int64_t)1 << 31) || prm.Y[k].ld >= ((int64_t)1 << 31)) return 0;
   // frame for p, the term count, the guard and the spread E - e_max: none
   // for a real dot (E is its largest product exponent), 40 bits allowed
   // for a complex one (E pairs each term's larger x and y parts)
