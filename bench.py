@@ -41,6 +41,7 @@ PEAK_INT8_TOPS = 5000.0   # MI355X dense INT8 MFMA, 5.0 POP/s
 # 32 x 32 -> 64-bit integer products (v_mad_u64_u32, one per lane per clock
 # at the full vector rate): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 PEAK_LIMB_PRODUCTS = 256 * 4 * 16 * 2.4e9
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E, 8 TB/s
 
 # HBM bytes per launch of the MFMA kernel of each INT8 form at N = 2048,
 # p = 512, from FETCH_SIZE (scaled by the copy calibration) and WRITE_SIZE
@@ -251,11 +252,18 @@ def bench_dot_batch(arbgpu, torch, log, launches: int):
     w = gen.config3()
     terms = int(w.lengths.sum())
     log(f"[bench] dot batch: {len(w.lengths)} dots, {terms} terms, generated in {time.time() - t0:.1f}s")
-    # algorithmic work: per complex term the four real limb products
+    # algorithmic work: per complex term the four real limb products; and
+    # the bytes a launch must move: every operand's limbs that can reach its
+    # dot's window (W + 1 of them) and its metadata (nls, exp 4 B each, the
+    # radius 8 + 4 B), and every output (p bits of limbs, exp, nls, radius,
+    # status)
     W = np.repeat(window_limbs(w.precs, 2 * w.lengths + 1), w.lengths)
     n = [o.nls.astype(np.int64) & 0x7FFFFFFF for o in (w.x_re, w.x_im, w.y_re, w.y_im)]
     products = float(np.sum(limb_products(n[0], n[2], W) + limb_products(n[1], n[3], W) +
                             limb_products(n[0], n[3], W) + limb_products(n[1], n[2], W)))
+    in_bytes = float(sum(np.sum(4 * np.minimum(nk, W + 1) + 20) for nk in n))
+    out_bytes = float(2 * np.sum(4 * ((w.precs + 31) // 32) + 21))
+    nbytes = in_bytes + out_bytes
     ctx = arbgpu.Context(0)
     dev = [arbgpu.DeviceArray.from_host(o) for o in (w.x_re, w.x_im, w.y_re, w.y_im)]
     del w.x_re, w.x_im, w.y_re, w.y_im
@@ -282,14 +290,19 @@ def bench_dot_batch(arbgpu, torch, log, launches: int):
     ctx.close()
     cmacs = terms / (ms / 1e3)
     achieved = products / (ms / 1e3)
-    log(f"[bench] dot batch {ms:.2f} ms/launch, {cmacs:.3e} complex MACs/s, "
-        f"{achieved / PEAK_LIMB_PRODUCTS:.1%} of the limb-product rate")
+    gbs = nbytes / (ms / 1e3) / 1e9
+    log(f"[bench] dot batch {ms:.2f} ms/launch, {cmacs:.3e} complex MACs/s, {gbs:.0f} GB/s of "
+        f"{nbytes / 1e9:.2f} GB algorithmic ({gbs / PEAK_HBM_GBS:.1%} of HBM); limb-product equivalent "
+        f"{achieved / PEAK_LIMB_PRODUCTS:.1%} of the v_mad_u64_u32 rate")
+    # digit runs report ns = -blocks, na = 1 (real) or 2 (complex)
     return {"dots": len(w.lengths), "terms": terms, "launches": launches, "ms_per_launch": ms,
             "complex_macs_per_s": cmacs, "real_macs_per_s": 4 * cmacs,
             "mean_p": float(np.mean(w.precs)), "shapes": info["shapes"],
-            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LIMB_PRODUCTS / 1e12,
-                         "unit": "T limb products/s", "frac": achieved / PEAK_LIMB_PRODUCTS, "traffic": None,
-                         "products_per_launch": products}}
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": gbs / PEAK_HBM_GBS, "traffic": None, "bytes_per_launch": nbytes},
+            "limb_product_equivalent": {"achieved": achieved / 1e12, "peak": PEAK_LIMB_PRODUCTS / 1e12,
+                                        "unit": "T limb products/s", "frac": achieved / PEAK_LIMB_PRODUCTS,
+                                        "products_per_launch": products}}
 
 
 def bench_serving(arbgpu, torch, log, nreq: int, rate: float, slots: int):

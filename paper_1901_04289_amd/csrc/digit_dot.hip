@@ -589,14 +589,16 @@ __global__ __launch_bounds__(kDT) void digit_dot_kernel(DotParams p0, DotParams 
 
 // Persistent batch: each workgroup takes jobs from the run's counter; a
 // part that needs the limb kernel is appended to its shape's list.
-// Waves per SIMD the batch kernel is compiled for (its register budget).
-template <int LB>
+// Waves per SIMD the batch kernel is compiled for (its register budget;
+// the complex kernel of 5 blocks holds 160 accumulators per lane and runs
+// one wave per SIMD rather than spill them).
+template <int LB, bool CPLX>
 constexpr int digit_waves() {
-  return LB <= 2 ? 4 : (LB == 3 ? 3 : 2);
+  return LB <= 2 ? 4 : (LB == 3 ? 3 : (LB == 5 && CPLX ? 1 : 2));
 }
 
 template <int LB, bool CPLX>
-__global__ __launch_bounds__(kDT) __attribute__((amdgpu_waves_per_eu(digit_waves<LB>(), 8))) void digit_dot_batch_kernel(
+__global__ __launch_bounds__(kDT) __attribute__((amdgpu_waves_per_eu(digit_waves<LB, CPLX>(), 8))) void digit_dot_batch_kernel(
     DigitBatchParams bp) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   auto &S = *reinterpret_cast<DLds<LB, CPLX> *>(smem);

@@ -407,6 +407,7 @@ __global__ __launch_bounds__(256) void limb_dot_batch_kernel(BatchShapeParams bp
     const int64_t d = *gp(bp.dcount);
     count = d < count ? d : count;
   }
+  if (count == 0) return;   // an empty list: no wave touches the counter
   // the counter only grows, so a wave takes at most `count` tasks
   for (int64_t iter = 0; iter <= count; ++iter) {
     int t = 0;
@@ -480,6 +481,7 @@ __global__ __launch_bounds__(256) void limb_dot_batch_block_kernel(BatchShapePar
     const int64_t d = *gp(bp.dcount);
     count = d < count ? d : count;
   }
+  if (count == 0) return;
   for (int64_t iter = 0; iter <= count; ++iter) {
     if (threadIdx.x == 0) task = atomicAdd(bp.counter, 1);
     __syncthreads();
