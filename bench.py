@@ -267,26 +267,38 @@ def bench_dot_batch(arbgpu, torch, log, launches: int):
     ctx = arbgpu.Context(0)
     dev = [arbgpu.DeviceArray.from_host(o) for o in (w.x_re, w.x_im, w.y_re, w.y_im)]
     del w.x_re, w.x_im, w.y_re, w.y_im
-    outs = [arbgpu.DeviceOut.empty(len(w.lengths), 1024), arbgpu.DeviceOut.empty(len(w.lengths), 1024)]
-    jobs = [arbgpu.dot_job([outs[0].out(), outs[1].out()], i, [dev[0].arr(), dev[1].arr()], int(w.offsets[i]), 1,
-                           [dev[2].arr(), dev[3].arr()], int(w.offsets[i]), 1, int(w.lengths[i]), int(w.precs[i]),
-                           arbgpu.COMPLEX) for i in range(len(w.lengths))]
-    b = arbgpu.Batch(ctx, jobs)
     stream = torch.cuda.current_stream()
-    b.launch(stream)
-    torch.cuda.synchronize()
-    b.tune(stream)
-    b.launch(stream)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(launches):
+
+    def timed_batch(flags):
+        """Build, tune and time the batch; its outputs and run list."""
+        outs = [arbgpu.DeviceOut.empty(len(w.lengths), 1024), arbgpu.DeviceOut.empty(len(w.lengths), 1024)]
+        jobs = [arbgpu.dot_job([outs[0].out(), outs[1].out()], i, [dev[0].arr(), dev[1].arr()], int(w.offsets[i]),
+                               1, [dev[2].arr(), dev[3].arr()], int(w.offsets[i]), 1, int(w.lengths[i]),
+                               int(w.precs[i]), arbgpu.COMPLEX | flags) for i in range(len(w.lengths))]
+        b = arbgpu.Batch(ctx, jobs)
         b.launch(stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / launches
-    info = b.info()
-    b.close()
+        torch.cuda.synchronize()
+        b.tune(stream)
+        b.launch(stream)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(launches):
+            b.launch(stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        info = b.info()
+        b.close()
+        return ev0.elapsed_time(ev1) / launches, [o.to_host() for o in outs], info
+
+    # the default path (digit products, the limb kernels for what they hand
+    # back), then the limb kernels alone on the same jobs
+    ms, res, info = timed_batch(0)
+    ms_limb, res_limb, _ = timed_batch(arbgpu.ALGO_LIMB)
+    same = all(np.array_equal(a.limbs, c.limbs) and np.array_equal(a.exp, c.exp) and np.array_equal(a.nls, c.nls)
+               and np.array_equal(a.rad_m, c.rad_m) and np.array_equal(a.rad_e, c.rad_e) and np.array_equal(sa, sc)
+               for (a, sa), (c, sc) in zip(res, res_limb))
+    log(f"[bench] dot batch on the limb kernels alone: {ms_limb:.2f} ms/launch; outputs identical: {same}")
     ctx.close()
     cmacs = terms / (ms / 1e3)
     achieved = products / (ms / 1e3)
@@ -296,6 +308,7 @@ def bench_dot_batch(arbgpu, torch, log, launches: int):
         f"{achieved / PEAK_LIMB_PRODUCTS:.1%} of the v_mad_u64_u32 rate")
     # digit runs report ns = -blocks, na = 1 (real) or 2 (complex)
     return {"dots": len(w.lengths), "terms": terms, "launches": launches, "ms_per_launch": ms,
+            "limb_kernels_alone_ms_per_launch": ms_limb, "identical_to_limb_kernels": same,
             "complex_macs_per_s": cmacs, "real_macs_per_s": 4 * cmacs,
             "mean_p": float(np.mean(w.precs)), "shapes": info["shapes"],
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -57,7 +57,8 @@ extern "C" {
 #define ARBGPU_REDUCE_PREC  0x04u /* radius-driven precision cut (Section 3.3,
                                      step 7(a)): p' = max(2, min(p,
                                      e_max - e_rad + 30)); changes the midpoint */
-#define ARBGPU_ALGO_LIMB    0x10u /* matmul: force the limb-window kernel       */
+#define ARBGPU_ALGO_LIMB    0x10u /* matmul and dot: force the limb-window
+                                     kernels (dots: no digit product)      */
 #define ARBGPU_ALGO_SLICED  0x20u /* matmul: force the scaled-integer INT8 path
                                      with base-256 digit slices               */
 #define ARBGPU_ALGO_RNS     0x40u /* matmul: force the scaled-integer INT8 path
@@ -139,10 +140,17 @@ const char *arbgpu_last_error(const arbgpu_ctx *ctx);
  * ARBGPU_COMPLEX, `res`, `initial`, `x`, `y` each point to TWO structs
  * {real part, imaginary part} and the real and imaginary results are each
  * the exact sum of their 2N real terms, rounded once (Section 3.6).
- * Precisions whose window (p + bitlength(t + 1) + 41 bits with t = N + 1
- * terms, 2N + 1 for complex) fits the widest compiled register window
- * (38 limbs, 1216 bits) run one wave per output; larger ones run one
- * workgroup per output with the window in LDS, up to p = 65408 with
+ * A dot without an initial value, of 1 to 65536 terms, whose p plus the
+ * term count's bit length plus 24 guard bits (plus 40 for a complex dot)
+ * fits 1120 bits runs first as one exact INT8 MFMA product of its
+ * operands' 7-bit digits (the scaled-integer product of Section 4 for a
+ * 1 x N by N x 1 product); the part whose truncation that window cannot
+ * certify, or a dot whose exponents spread beyond it, then runs on the
+ * limb kernels (same output bits; ARBGPU_ALGO_LIMB skips the digit
+ * product).  Precisions whose window (p + bitlength(t + 1) + 41 bits with
+ * t = N + 1 terms, 2N + 1 for complex) fits the widest compiled register
+ * window (38 limbs, 1216 bits) run one wave per output; larger ones run
+ * one workgroup per output with the window in LDS, up to p = 65408 with
  * operands of at most 2048 limbs.  There an exact fallback whose span from
  * the top of the sum down to the lowest bit of any product exceeds 131072
  * bits is not run: the output gets status ARBGPU_ST_ERANGE and an infinite
@@ -288,14 +296,18 @@ typedef struct {
 } arbgpu_dot_job;
 
 /* A resident batch of dot products (the persistent batched launch): the
- * jobs are validated, grouped by kernel shape (window and operand limbs,
- * chosen from p, N and operand widths), ordered longest first, copied to
- * device memory once, and bound into one HIP graph.  Each launch replays
- * the graph on `stream`: one persistent kernel per shape whose waves take
- * dots from a device work counter until the queue is empty.  The operand
- * and output arrays the jobs name must stay valid while the batch is
- * launched.  Waves per compute unit per shape come from the context's tune
- * table (arbgpu_batch_tune), else a default.
+ * jobs are validated, grouped by kernel (digit-product jobs by digit block
+ * count, real or complex; the others by limb-kernel shape: window and
+ * operand limbs, chosen from p, N and operand widths), ordered longest
+ * first, copied to device memory once, and bound into one HIP graph.  Each
+ * launch replays the graph on `stream`: one persistent kernel per group
+ * whose workgroups or waves take jobs from a device work counter until the
+ * queue is empty, then, per limb shape, the limb kernel over the parts the
+ * digit products handed back (a list the device fills).  A job gives the
+ * same bits as arbgpu_dot.  The operand and output arrays the jobs name
+ * must stay valid while the batch is launched.  Waves per compute unit per
+ * group come from the context's tune table (arbgpu_batch_tune), else a
+ * default.
  * create: EINVAL on a bad job (its index in the message), ENOMEM, EDEVICE.
  * launch: EDEVICE on HIP errors.  destroy waits for the device. */
 typedef struct arbgpu_batch arbgpu_batch;
@@ -307,9 +319,11 @@ int arbgpu_batch_launch(arbgpu_batch *batch, arbgpu_stream stream);
  * (written back to the context's tune_cache file when one was given), and
  * rebuilds the graph.  Synchronizes `stream`. */
 int arbgpu_batch_tune(arbgpu_batch *batch, arbgpu_stream stream);
-/* Writes up to n values {jobs, kernel tasks (one per output part), shapes,
- * then per shape (NS, NA, tasks, waves per CU, microseconds of the shape
- * alone when tuned, else 0)} to out (host memory). */
+/* Writes up to n values {jobs, kernel tasks (one per output part), runs,
+ * then per run (NS, NA, tasks, waves per CU, microseconds of the run alone
+ * when tuned, else 0)} to out (host memory).  A digit-product run reports
+ * NS = -(digit blocks) and NA = 1 (real) or 2 (complex); a fallback run
+ * its limb shape and its list's capacity. */
 int arbgpu_batch_info(arbgpu_batch *batch, int64_t *out, int n);
 void arbgpu_batch_destroy(arbgpu_batch *batch);
 
