@@ -21,16 +21,15 @@
 // Operand bits below the frame are dropped, as the truncated products of
 // Section 3.4 drop theirs: a product with a cut operand is off by less than
 // 2^(B+1) + 1 units, counted as 3 units of the window 2^(E - B).  The window
-// value with that bound either certifies the truncation of the exact sum to
-// p bits (window_certify) or the part goes back to the limb kernel, which
-// refines (the fast dot with a fallback of Section 2).  The frame needs
+// value with that bound either decides the truncation of the exact sum to p
+// bits (the limb engine's decision on one window level, in registers) or
+// the part goes back to the limb kernel, which refines (the fast dot with a
+// fallback of Section 2).  The frame needs
 // p + (E - e_max) + bitlen(terms) + 24 bits; a dot whose exponents spread
 // wider than its blocks allow goes back the same way.  The radius is the
 // limb engine's: the same per-term bounds (Section 3.5) added exactly in
 // fixed point (RadAcc).
-#include "finish.hpp"
 #include "limb_kernels.hpp"
-#include "window.hpp"
 
 using namespace arb;
 
@@ -68,7 +67,6 @@ struct DLds {
     struct {
       int64_t diag[2][2 * C::L];       // anti-diagonal sums per part
       int64_t col[2][C::NCOL];         // the integer sum per part, 32 bits per column
-      uint32_t hi[2][C::NCOL];         // certification scratch
     } f;
   } u;
   // per operand and term of the chunk: the radius bound's inputs and flags
@@ -526,17 +524,24 @@ __device__ void digit_job(PP P0, PP P1, DLds<LB, CPLX> &S, const FB &fb) {
     }
   }
   __syncthreads();
+  // per part, one lane: the columns' carries in registers, then the limb
+  // engine's decision (a single window level) and output; a part that the
+  // window does not decide goes to the limb kernel
   if (lane == 0 && wave < NPART) {
+    constexpr int NW = C::NCOL - C::C0;   // window limbs
     const int pt = wave;
     PP P = pt ? P1 : P0;
-    int64_t *col = S.u.f.col[pt];
+    const int64_t *col = S.u.f.col[pt];
+    Window<NW> Wd;
+    Wd.clear();
     int64_t cy = 0;
     bool lownz = false;
+#pragma unroll
     for (int c = 0; c < C::NCOL; ++c) {
       const int64_t v = col[c] + cy;
-      col[c] = v & 0xFFFFFFFFll;
       cy = v >> 32;
-      if (c < C::C0 && (v & 0xFFFFFFFFll)) lownz = true;
+      if (c < C::C0) lownz |= (v & 0xFFFFFFFFll) != 0;
+      else Wd.w[c - C::C0] = (uint32_t)v;
     }
     uint32_t nt = 0;
     RadAcc rt;
@@ -550,29 +555,30 @@ __device__ void digit_job(PP P0, PP P1, DLds<LB, CPLX> &S, const FB &fb) {
     }
     // 3 units per product with a cut operand, 1 for the bits below the
     // window, 1 for the blocks left out
-    const uint64_t err = 3ull * nt + (lownz ? 1u : 0u) + (LB >= 3 ? 1u : 0u);
-    int64_t hb = 0;
+    Wd.err = 3u * nt + (lownz ? 1u : 0u) + (LB >= 3 ? 1u : 0u);
+    Wd.pt = nt;
     const int p = pt ? prec[1] : prec[0];
     const int Fp = pt ? F[1] : F[0];
     const bool radp = want_rad && (pt ? anyr[1] : anyr[0]);
-    const bool ok = window_certify(C::NCOL - C::C0, err, p, col + C::C0, S.u.f.hi[pt], &hb);
+    const int lo = E - C::B;   // the window's unit 2^(E - B)
+    DotOut<NW> out;
+    level_init(out.st, lo + 32 * NW);
+    decide<NW>(out.st, Wd, lo, p);
+    const bool ok = out.st.done && !out.st.bad;
     if (ok) {
-      double rin_m = 0.0;
-      int rin_e = 0;
+      out.rin_m = 0.0;
+      out.rin_e = 0;
       if (radp) {
         double m;
         int e;
         if (rt.get(m, e)) {
-          rin_m = m;
-          rin_e = Fp + e;
+          out.rin_m = m;
+          out.rin_e = Fp + e;
         }
       }
-      const arbgpu_out &R = P->R;
-      const int64_t oidx = P->res_idx;
-      finish_entry([&](int q) { return (uint32_t)col[C::C0 + q]; }, C::NCOL - C::C0, (int64_t)E - C::B, R, oidx, p,
-                   approx, rin_m, rin_e);
-      // limbs of the requested precision beyond a cut one stay zero
-      for (int k = (p + 31) >> 5; k < ((P->p + 31) >> 5); ++k) gpw(R.limbs)[(int64_t)k * R.ld + oidx] = 0u;
+      out.erange = false;
+      out.p = p;
+      store_out<NW>(P->R, P->res_idx, out, P->p, approx, ARBGPU_ST_OK);
     }
     fb(pt, !ok);
   }
