@@ -103,7 +103,7 @@ ARB_HD void add_term(Window<NS> &W, int lo, const Opnd<NA> &a, const Opnd<NA> &b
   bool skipped;
   {
     uint32_t p[2 * NA];
-    mul_limbs<NA>(a.l, a.n, b.l, p, kc < 0 ? 0 : kc, skipped);
+    mul_limbs<NA>(a.l, a.n, b.l, b.n, p, kc < 0 ? 0 : kc, skipped);
 #pragma unroll
     for (int i = 0; i < 2 * NA; ++i) z[NS + i] = p[i];
   }

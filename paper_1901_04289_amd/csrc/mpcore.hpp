@@ -177,42 +177,83 @@ ARB_HD void shl_var(uint32_t (&x)[L], uint32_t S) {
   }
 }
 
-// Schoolbook product of LS-first limb arrays, p = a * b, with the low
-// products left out (the "mulhigh" of Section 3.4): in every row i < na a
-// leading run of BLK-column blocks whose pairs all have i + j < kc is
-// skipped and the rest of the row is an exact multiply-add chain (a[i]
-// b[j] + p[i + j] + carry < 2^64) from the first kept block.  The left-out
-// pairs sum below sum_{s<kc} (s+1) 2^(64 + 32 s) < kc 2^(32 kc + 32)
-// (1 + 2^-31) units of p's lowest limb.  `skipped` tells whether a pair was
-// left out.  Limbs of a at and above na are not read; rows are skipped
-// uniformly when the operands of a wave share a length, blocks when their
-// exponents put the same products below the window.
-template <int NA>
-ARB_HD void mul_limbs(const uint32_t (&a)[NA], int na, const uint32_t (&b)[NA], uint32_t (&p)[2 * NA], int kc,
-                      bool &skipped) {
-  constexpr int BLK = NA >= 24 ? 8 : 4;
-  static_assert(NA % BLK == 0, "operand limbs in whole blocks");
-  skipped = na > 0 && kc >= BLK;
+// acc + hi 2^64 += a * b: one v_mad_u64_u32 whose carry out of the 64
+// bits goes into hi.
+ARB_HD void mac64(uint64_t &acc, uint32_t &hi, uint32_t a, uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  uint64_t cy;
+  asm("v_mad_u64_u32 %0, %2, %3, %4, %0\n\t"
+      "v_addc_co_u32_e64 %1, %2, 0, %1, %2"
+      : "+v"(acc), "+v"(hi), "=&s"(cy)
+      : "v"(a), "v"(b));
+#else
+  const uint64_t pr = (uint64_t)a * b;
+  acc += pr;
+  hi += acc < pr ? 1u : 0u;
+#endif
+}
+
+// Whether c holds in any active lane of the wave (c itself outside device
+// code); the same in every lane, so a branch on it is uniform.
+ARB_HD bool any_lane(bool c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_ballot_w64(c) != 0;
+#else
+  return c;
+#endif
+}
+
+// The largest value of v in [0, 128) over the active lanes of the wave, the
+// same in every lane (one ballot per bit); v itself outside device code.
+ARB_HD int active_max7(int v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  int r = 0;
 #pragma unroll
-  for (int k = 0; k < 2 * NA; ++k) p[k] = 0;
-#pragma unroll
-  for (int i = 0; i < NA; ++i) {
-    if (i < na) {
-      uint32_t c = 0;
-#pragma unroll
-      for (int jb = 0; jb < NA; jb += BLK) {
-        if (i + jb + BLK - 1 >= kc) {
-#pragma unroll
-          for (int j = jb; j < jb + BLK; ++j) {
-            const uint64_t t = (uint64_t)a[i] * b[j] + p[i + j] + c;
-            p[i + j] = (uint32_t)t;
-            c = (uint32_t)(t >> 32);
-          }
-        }
-      }
-      p[i + NA] = c;
-    }
+  for (int b = 6; b >= 0; --b) {
+    const int c = r | (1 << b);
+    if (any_lane(v >= c)) r = c;
   }
+  return r;
+#else
+  return v;
+#endif
+}
+
+// Product of LS-first limb arrays, p = a * b, column by column (each
+// column's products in one 64-bit accumulator with a carry word), with
+// the low products left out (the "mulhigh" of Section 3.4): a column
+// k < kc is not formed unless another active lane of the wave needs it
+// (the left-out pairs sum below sum_{s<kc} (s+1) 2^(64 + 32 s) <
+// kc 2^(32 kc + 32) (1 + 2^-31) units of p's lowest limb), nor a product
+// of limbs at or above na of a or nb of b in every active lane (those limbs
+// are zero).  `skipped` tells whether a pair was left out.
+template <int NA>
+ARB_HD void mul_limbs(const uint32_t (&a)[NA], int na, const uint32_t (&b)[NA], int nb, uint32_t (&p)[2 * NA],
+                      int kc, bool &skipped) {
+  static_assert(NA < 128, "limb counts below 128");
+  skipped = na > 0 && !any_lane(kc <= 0);
+  const int nau = active_max7(na < NA ? na : NA), nbu = active_max7(nb < NA ? nb : NA);
+  const bool full = nau >= NA && nbu >= NA;
+  uint64_t acc = 0;
+  uint32_t hi = 0;
+#pragma unroll
+  for (int k = 0; k < 2 * NA - 1; ++k) {
+    if (any_lane(k >= kc)) {
+      if (full) {
+#pragma unroll
+        for (int i = (k - NA + 1 > 0 ? k - NA + 1 : 0); i <= (k < NA - 1 ? k : NA - 1); ++i)
+          mac64(acc, hi, a[i], b[k - i]);
+      } else {
+#pragma unroll
+        for (int i = (k - NA + 1 > 0 ? k - NA + 1 : 0); i <= (k < NA - 1 ? k : NA - 1); ++i)
+          if (i < nau && k - i < nbu) mac64(acc, hi, a[i], b[k - i]);   // uniform
+      }
+    }
+    p[k] = (uint32_t)acc;
+    acc = (acc >> 32) | ((uint64_t)hi << 32);
+    hi = 0;
+  }
+  p[2 * NA - 1] = (uint32_t)acc;
 }
 
 // ---------------------------------------------------------------------------
