@@ -64,37 +64,41 @@ __device__ __forceinline__ SliceElem slice_elem(const RnsSliceParams &P, int64_t
   return e;
 }
 
-// Words 4 g .. 4 g + 3 (4 balanced base-256 digits each, int8) of Y: the
-// digits of Y + B, B = sum_{a<L} 128 * 256^a, are bytes; those of Y are
-// the bytes minus 128.  cy carries between words.  The five limbs that
-// hold bits [128 g - s, 128 g - s + 128) of the mantissa are read first,
-// all at once.
-__device__ __forceinline__ void digit_words4(const RnsSliceParams &P, const SliceElem &e, int g, uint32_t &cy,
-                                             uint32_t (&x)[4]) {
-  uint32_t lim[5] = {0u, 0u, 0u, 0u, 0u};
+// Words 4 g .. 4 g + 4 NG - 1 (4 balanced base-256 digits each, int8) of
+// Y: the digits of Y + B, B = sum_{a<L} 128 * 256^a, are bytes; those of Y
+// are the bytes minus 128.  cy carries between words.  The 4 NG + 1 limbs
+// that hold bits [128 g - s, 128 (g + NG) - s) of the mantissa are read
+// first, all at once, so a run of NG words costs one memory round trip.
+template <int NG>
+__device__ __forceinline__ void digit_words(const RnsSliceParams &P, const SliceElem &e, int g, uint32_t &cy,
+                                            uint32_t (&x)[4 * NG]) {
+  constexpr int NL = 4 * NG + 1;
+  uint32_t lim[NL];
+#pragma unroll
+  for (int t = 0; t < NL; ++t) lim[t] = 0u;
   const int64_t o = 128 * (int64_t)g - e.s;   // bit offset of word 4 g into M (may be negative)
   const int64_t li = o >= 0 ? (o >> 5) : -((31 - o) >> 5);
   const uint32_t r = (uint32_t)(o - 32 * li);
   if (e.n) {
     const arbgpu_arr &A = part_of(P.part, e.part);
-    uint32_t v[5];
+    uint32_t v[NL];
 #pragma unroll
-    for (int t = 0; t < 5; ++t) {
+    for (int t = 0; t < NL; ++t) {
       // limb li + t counted from the least significant; clamped reads stay
       // inside the element's limbs and are discarded outside
       const int64_t i = li + t;
       const int64_t ic = i < 0 ? 0 : (i >= e.n ? e.n - 1 : i);
       v[t] = A.limbs[(int64_t)(e.n - 1 - ic) * A.ld + e.idx];
     }
-    // the values are taken unconditionally, so the five reads are issued
+    // the values are taken unconditionally, so the reads are issued
     // together rather than each behind its own range test
 #pragma unroll
-    for (int t = 0; t < 5; ++t) asm volatile("" : "+v"(v[t]));
+    for (int t = 0; t < NL; ++t) asm volatile("" : "+v"(v[t]));
 #pragma unroll
-    for (int t = 0; t < 5; ++t) lim[t] = (li + t >= 0 && li + t < e.n) ? v[t] : 0u;
+    for (int t = 0; t < NL; ++t) lim[t] = (li + t >= 0 && li + t < e.n) ? v[t] : 0u;
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < 4 * NG; ++u) {
     const int w = 4 * g + u;
     const int nbytes = P.L - 4 * w;
     const uint32_t bmask = nbytes >= 4 ? 0xFFFFFFFFu : (nbytes <= 0 ? 0u : ((1u << (8 * nbytes)) - 1u));
@@ -275,10 +279,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const int x = tid & 31;
     const int row = (tid & ~31) | (((x >> 2) & 1) << 4) | ((x >> 4) << 3) | (((x >> 3) & 1) << 2) | (x & 3);
     uint32_t cy = 0;
-    for (int w4 = 0; w4 < kd / 16; ++w4) {
+    uint8_t *drow0 = dl + (size_t)row * S;
+    int w4 = 0;
+    // runs of eight and of four 16-byte groups (one memory round trip
+    // each), then single groups; words past nw have no digits (bmask 0), so
+    // no run reaches there
+    for (; w4 + 8 <= kd / 16 && 4 * (w4 + 7) < nw; w4 += 8) {
+      uint32_t x[32];
+      digit_words<8>(P, e, w4, cy, x);
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        *reinterpret_cast<uint4 *>(drow0 + 16 * (w4 + q)) = make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+    }
+    for (; w4 + 4 <= kd / 16 && 4 * (w4 + 3) < nw; w4 += 4) {
+      uint32_t x[16];
+      digit_words<4>(P, e, w4, cy, x);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        *reinterpret_cast<uint4 *>(drow0 + 16 * (w4 + q)) = make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+    }
+    for (; w4 < kd / 16; ++w4) {
       uint32_t x[4] = {0u, 0u, 0u, 0u};
-      if (4 * w4 < nw) digit_words4(P, e, w4, cy, x);   // words past nw have no digits (bmask 0)
-      *reinterpret_cast<uint4 *>(dl + (size_t)row * S + 16 * w4) = make_uint4(x[0], x[1], x[2], x[3]);
+      if (4 * w4 < nw) digit_words<1>(P, e, w4, cy, x);
+      *reinterpret_cast<uint4 *>(drow0 + 16 * w4) = make_uint4(x[0], x[1], x[2], x[3]);
     }
   }
   __syncthreads();
@@ -290,6 +313,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   // part in the stores); the weight fragments of a prime tile are loaded
   // once for all of them
   constexpr int NBW = EL >= 128 ? EL / 128 : 1;
+  // runs of four weight fragments requested at a tile's start besides the
+  // prefetched first (register budget: one with two blocks per wave)
+  constexpr int NPRE = NBW > 1 ? 1 : 2;
   const bool act = wave < EL / 32;
   // a tile's 32 planes x EL elements, staged so that the stores write
   // whole plane rows of EL bytes
@@ -327,17 +353,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       for (int b = 0; b < NBW; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[b][r] = 0;
-      for (int k0 = 0; k0 < nks; k0 += 4) {
-        v4i fa[4];
-        if (k0 == 0) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) fa[u] = fnext[u];
-          // the next tile's first weight fragments load during this tile's
-          // products and residue arithmetic
-          frag_load4(fnext, rt + 1 < nrt ? wrow + 32 * kd : wbase, 0, nks);
-        } else {
-          frag_load4(fa, wrow, k0, nks);
-        }
+      auto products = [&](const v4i (&fa)[4], int k0) {
 #pragma unroll
         for (int b = 0; b < NBW; ++b) {
           v4i fb[4];
@@ -350,6 +366,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
           for (int u = 0; u < 4; ++u)
             if (k0 + u < nks) acc[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fb[u], fa[u], acc[b], 0, 0, 0);
         }
+      };
+      // the tile's next NPRE runs of four weight fragments are requested
+      // together, then the next tile's first run, which loads during this
+      // tile's products and residue arithmetic
+      v4i fx[NPRE][4];
+#pragma unroll
+      for (int q = 0; q < NPRE; ++q)
+        if (4 * (q + 1) < nks) frag_load4(fx[q], wrow, 4 * (q + 1), nks);
+      v4i fa0[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) fa0[u] = fnext[u];
+      frag_load4(fnext, rt + 1 < nrt ? wrow + 32 * kd : wbase, 0, nks);
+      products(fa0, 0);
+#pragma unroll
+      for (int q = 0; q < NPRE; ++q)
+        if (4 * (q + 1) < nks) products(fx[q], 4 * (q + 1));
+      for (int k0 = 4 * (NPRE + 1); k0 < nks; k0 += 4) {
+        v4i fa[4];
+        frag_load4(fa, wrow, k0, nks);
+        products(fa, k0);
       }
 #pragma unroll
       for (int b = 0; b < NBW; ++b) {
