@@ -476,36 +476,48 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
     double alpha = 0.0;
     // lanes past the end read entry 0 (in bounds) and contribute nothing
     const int64_t ij0 = live ? ij : 0;
+    // the source planes' signs as masks (x ^ s) - s, s = 0 or -1
+    int32_t sm[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sm[c] = P.sgn[c] < 0 ? -1 : 0;
     for (int g = part; g < kc / 16; g += TPE) {
       // the residue reads of 8 primes (up to 3 products each) are issued
-      // before any use
+      // before any use, each from a uniform base plus the entry's offset
+      // (planes past prime m - 1 repeat its plane and are not used)
       int32_t dv[8][3];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int jj = min(8 * g + u, m - 1);
+      for (int c = 0; c < 3; ++c) {
+        const int16_t *yp = P.Y + ((int64_t)P.src[c < P.nsrc ? c : 0] * m + min(8 * g, m - 1)) * P.ds + ij0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          dv[u][c] = c < P.nsrc ? (int32_t)P.Y[((int64_t)P.src[c] * m + jj) * P.ds + ij0] : 0;
+        for (int u = 0; u < 8; ++u) {
+          dv[u][c] = c < P.nsrc ? (int32_t)*yp : 0;
+          if (8 * g + u + 1 < m) yp += P.ds;
+        }
       }
       uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int j = 8 * g + u;
         if (j < m) {
-          const uint32_t p = (uint32_t)cp(P.tab.prime)[j], mu = cp(P.tab.mu)[j];
-          // y = (sum of at most three residues in [-p, p)) times c mod p,
-          // with c balanced (|c| < p / 2): |sum c| < 1.5 p^2 < 1.5 2^30, and
-          // 2 kp (a multiple of p in [2^31, 2^31 + 2p)) keeps the value
-          // nonnegative and below 2^32, so one reduction suffices
-          const int32_t cj = (int32_t)cp(P.tab.c)[j];
-          const int32_t cb = cj > (int32_t)(p >> 1) ? cj - (int32_t)p : cj;
+          const auto *crp = cp(P.tab.crt) + j;
+          struct { uint32_t p, mu; int32_t cb; uint32_t kp2; double rp; uint32_t half; } cr = {
+              crp->p, crp->mu, crp->cb, crp->kp2, crp->rp, crp->half};
+          // y = (sum of at most three residues in [-p, p)) times cb mod p:
+          // |sum cb| < 1.5 p^2 < 1.5 2^30 (24-bit signed factors, so the
+          // 24-bit product is exact), and 2 kp (a multiple of p in [2^31,
+          // 2^31 + 2p)) keeps the value nonnegative and below 2^32, so one
+          // reduction suffices; its quotient q < 2^18 and p < 2^15 again
+          // multiply exactly in 24 bits
           int32_t rs = 0;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) rs += c < P.nsrc ? P.sgn[c] * dv[u][c] : 0;
-          const uint32_t y = mod_u32((uint32_t)(rs * cb) + 2u * cp(P.tab.kp)[j], p, mu);
-          int32_t yb = y > (p >> 1) ? (int32_t)y - (int32_t)p : (int32_t)y;
+          for (int c = 0; c < 3; ++c) rs += (dv[u][c] ^ sm[c]) - sm[c];
+          const uint32_t x = (uint32_t)__mul24(rs, cr.cb) + cr.kp2;
+          const uint32_t q = __umulhi(x, cr.mu);
+          uint32_t y = x - __umul24(q, cr.p);
+          y = y >= cr.p ? y - cr.p : y;
+          int32_t yb = y > cr.half ? (int32_t)y - (int32_t)cr.p : (int32_t)y;
           yb = live ? yb : 0;
-          alpha += (double)yb * cp(P.tab.rp)[j];
+          alpha += (double)yb * cr.rp;
           const int32_t lo = ((yb + 128) & 255) - 128;
           const int32_t hi = (yb - lo) >> 8;
           w[u >> 1] |= (((uint32_t)lo & 0xFFu) | (((uint32_t)hi & 0xFFu) << 8)) << (16 * (u & 1));

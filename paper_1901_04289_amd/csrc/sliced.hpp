@@ -126,6 +126,17 @@ struct RadExactParams {
 // Multimodular form of the block product: residues of the scaled integers
 // modulo m odd primes below 2^15, each split into two balanced int8 digits
 // (planes 2j: low digit, 2j + 1: high digit of prime j).
+// Per-prime constants of the reconstruction's first phase in one 32-byte
+// record, so that a prime's constants arrive by one scalar load.
+struct RnsCrtPrime {
+  uint32_t p, mu;           // the prime and floor(2^32 / p)
+  int32_t cb;               // (P / p)^-1 mod p, balanced (|cb| < p / 2)
+  uint32_t kp2;             // 2 p ceil(2^30 / p)
+  double rp;                // 1 / p
+  uint32_t half, pad;       // (p - 1) / 2
+};
+static_assert(sizeof(RnsCrtPrime) == 32, "one 32-byte record per prime");
+
 struct RnsTables {
   const int32_t *prime;     // [m]
   const uint32_t *mu;       // [m] floor(2^32 / p)
@@ -137,6 +148,7 @@ struct RnsTables {
   const int8_t *wd;
   const uint32_t *c;        // [m] (P / p_j)^-1 mod p_j, P = prod p_j
   const double *rp;         // [m] 1 / p_j
+  const RnsCrtPrime *crt;   // [m]
   // [ncc][32][kc] balanced base-256 digits of the reconstruction weights:
   // inner index 2j -> P / p_j, 2j + 1 -> 256 P / p_j, 2m -> P, 2m + 1 ->
   // 256 P, zero beyond; digit column 32 cc + sigma(r) in row r, sigma(r) =

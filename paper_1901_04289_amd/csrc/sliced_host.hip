@@ -172,7 +172,7 @@ void balanced_digits(const std::vector<uint32_t> &X, int n, int8_t *d) {
 // limbs of T (offsets of the arrays of RnsTables in one buffer).
 struct RnsLayout {
   int kc, ncc, kd, nrt;
-  size_t o_mu, o_kp, o_rp, o_c, o_wd, o_qd, bytes;
+  size_t o_mu, o_kp, o_rp, o_c, o_cp, o_wd, o_qd, bytes;
 };
 
 RnsLayout rns_layout(int m, int nw, int W) {
@@ -185,7 +185,8 @@ RnsLayout rns_layout(int m, int nw, int W) {
   l.o_kp = l.o_mu + 4 * (size_t)m;
   l.o_rp = (l.o_kp + 4 * (size_t)m + 7) & ~(size_t)7;
   l.o_c = l.o_rp + 8 * (size_t)m;
-  l.o_wd = (l.o_c + 4 * (size_t)m + 15) & ~(size_t)15;
+  l.o_cp = (l.o_c + 4 * (size_t)m + 31) & ~(size_t)31;
+  l.o_wd = (l.o_cp + sizeof(RnsCrtPrime) * (size_t)m + 15) & ~(size_t)15;
   l.o_qd = l.o_wd + (size_t)l.nrt * 32 * l.kd;
   l.bytes = l.o_qd + (size_t)l.ncc * 32 * l.kc;
   return l;
@@ -200,8 +201,8 @@ int rns_tables(arbgpu_ctx *ctx, int m, int nw, int W, hipStream_t s, RnsTables &
   const std::vector<int32_t> &pr = rns_primes();
   const RnsLayout lay = rns_layout(m, nw, W);
   const int kc = lay.kc, ncc = lay.ncc, kd = lay.kd;
-  const size_t o_mu = lay.o_mu, o_kp = lay.o_kp, o_rp = lay.o_rp, o_c = lay.o_c, o_wd = lay.o_wd, o_qd = lay.o_qd,
-               bytes = lay.bytes;
+  const size_t o_mu = lay.o_mu, o_kp = lay.o_kp, o_rp = lay.o_rp, o_c = lay.o_c, o_cp = lay.o_cp, o_wd = lay.o_wd,
+               o_qd = lay.o_qd, bytes = lay.bytes;
   char *d = (char *)ws_get(ctx, WS_RNS, bytes);
   if (!d) return ARBGPU_ENOMEM;
   tab.prime = (const int32_t *)d;
@@ -210,6 +211,7 @@ int rns_tables(arbgpu_ctx *ctx, int m, int nw, int W, hipStream_t s, RnsTables &
   tab.wd = (const int8_t *)(d + o_wd);
   tab.rp = (const double *)(d + o_rp);
   tab.c = (const uint32_t *)(d + o_c);
+  tab.crt = (const RnsCrtPrime *)(d + o_cp);
   tab.qd = (const int8_t *)(d + o_qd);
   tab.m = m;
   tab.nw = nw;
@@ -236,6 +238,7 @@ int rns_tables(arbgpu_ctx *ctx, int m, int nw, int W, hipStream_t s, RnsTables &
   int8_t *hwd = (int8_t *)(h.data() + o_wd);
   double *hrp = (double *)(h.data() + o_rp);
   uint32_t *hc = (uint32_t *)(h.data() + o_c);
+  RnsCrtPrime *hcp = (RnsCrtPrime *)(h.data() + o_cp);
   int8_t *hqd = (int8_t *)(h.data() + o_qd);
   const int nd = 32 * ncc;                 // digit columns
   std::vector<int8_t> dig((size_t)nd + 1);
@@ -278,6 +281,14 @@ int rns_tables(arbgpu_ctx *ctx, int m, int nw, int W, hipStream_t s, RnsTables &
     uint64_t qm = 0;
     for (int q = (int)P.size() - 1; q >= 0; --q) qm = ((qm << 32) | Q[q]) % (uint64_t)p;
     hc[j] = (uint32_t)modinv((int64_t)qm, p);
+    RnsCrtPrime &cr = hcp[j];
+    cr.p = (uint32_t)p;
+    cr.mu = hmu[j];
+    cr.cb = (int32_t)(hc[j] > (uint32_t)(p >> 1) ? (int64_t)hc[j] - p : (int64_t)hc[j]);
+    cr.kp2 = 2u * hkp[j];
+    cr.rp = hrp[j];
+    cr.half = (uint32_t)(p >> 1);
+    cr.pad = 0u;
     put(2 * j, Q);
   }
   put(2 * m, P);
