@@ -116,6 +116,27 @@ __device__ __forceinline__ void digit_words(const RnsSliceParams &P, const Slice
   }
 }
 
+// Residues of a sum from those of its terms, for 4 consecutive elements of
+// a prime's planes: the terms' balanced residues (lo + 256 hi, |r| <=
+// (p - 1) / 2) are added, brought back into the balanced range and split
+// again.  lo4 / hi4 hold 4 bytes each.
+__device__ __forceinline__ void residue_sum4(uint32_t xl, uint32_t xh, uint32_t yl, uint32_t yh, int32_t p,
+                                             uint32_t &lo4, uint32_t &hi4) {
+  const int32_t half = (p - 1) >> 1;
+  lo4 = 0u;
+  hi4 = 0u;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int32_t a = (int32_t)(int8_t)(xl >> (8 * u)) + 256 * (int32_t)(int8_t)(xh >> (8 * u));
+    const int32_t b = (int32_t)(int8_t)(yl >> (8 * u)) + 256 * (int32_t)(int8_t)(yh >> (8 * u));
+    int32_t r = a + b;
+    r = r > half ? r - p : (r < -half ? r + p : r);
+    const int32_t lo = ((r + 128) & 255) - 128;
+    lo4 |= ((uint32_t)lo & 0xFFu) << (8 * u);
+    hi4 |= ((uint32_t)((r - lo) >> 8) & 0xFFu) << (8 * u);
+  }
+}
+
 // Residue of S = sum_a d_a 256^a (the lo sum plus 256 times the hi sum of
 // the weight digits) modulo p, balanced and split into its int8 digits
 // (lo, hi), returned as the bytes lo | hi << 8.
@@ -258,7 +279,7 @@ __device__ void finish_entry_split(const uint32_t *T, int W, int64_t scale, cons
 // With the stage the 256-element form's LDS (about 37 KiB at p = 512)
 // admits four workgroups per CU, so registers are capped for four waves
 // per SIMD (no spill) rather than five.
-template <int EL>
+template <int EL, bool SUM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void rns_slice_kernel(RnsSliceParams P) {
   extern __shared__ __attribute__((aligned(16))) uint8_t dl[];   // [EL][kd + 16], then [32][EL]
   const int tid = threadIdx.x;
@@ -337,7 +358,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   // reduction constants of this lane's prime, loaded a tile ahead
   int jn = min(c >> 1, m - 1);
   uint32_t pn = (uint32_t)P.tab.prime[jn], mun = P.tab.mu[jn], kpn = P.tab.kp[jn];
+  // with the residue sums: this thread's items of a tile's store (prime
+  // rp of the tile, word wd of its plane rows: 4 elements) and the
+  // addend's words for them, requested at the tile's start
+  constexpr int NIT = SUM ? (4 * EL + 255) / 256 : 1;
+  uint32_t ya[NIT][2], yp[NIT];
+  auto item = [&](int i, int rt_, int &rp, int &wd, int &j) {
+    const int t = tid + 256 * i;
+    rp = t / (EL / 4);
+    wd = t - rp * (EL / 4);
+    j = 16 * rt_ + rp;
+    return t < 4 * EL && j < m && g0 + 4 * wd < total;
+  };
   for (int rt = 0; rt < nrt; ++rt) {
+    if constexpr (SUM) {
+#pragma unroll
+      for (int i = 0; i < NIT; ++i) {
+        int rp, wd, j;
+        if (item(i, rt, rp, wd, j)) {
+          const int64_t olo = (int64_t)(2 * j) * total + g0 + 4 * wd;
+          ya[i][0] = *reinterpret_cast<const uint32_t *>(P.addend + olo);
+          ya[i][1] = *reinterpret_cast<const uint32_t *>(P.addend + olo + total);
+          yp[i] = (uint32_t)P.tab.prime[j];
+        }
+      }
+    }
     if (act) {
       const int8_t *wrow = wbase + (int64_t)rt * 32 * kd;
       const uint32_t pj = pn, muj = mun, kpj = kpn;
@@ -417,14 +462,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       }
     }
     __syncthreads();
-    // the tile's planes 32 rt .. 32 rt + 31 (those of real primes), one
-    // word of a plane row per thread
-    for (int t = tid; t < 32 * (EL / 4); t += 256) {
-      const int r = t / (EL / 4), wd = t - r * (EL / 4);
-      const int plane = 32 * rt + r;
-      if (plane < 2 * m && g0 + 4 * wd < total)
-        *reinterpret_cast<uint32_t *>(P.planes + (int64_t)plane * total + g0 + 4 * wd) =
-            *reinterpret_cast<const uint32_t *>(stage + r * EL + 4 * wd);
+    if constexpr (!SUM) {
+      // the tile's planes 32 rt .. 32 rt + 31 (those of real primes), one
+      // word of a plane row per thread
+      for (int t = tid; t < 32 * (EL / 4); t += 256) {
+        const int r = t / (EL / 4), wd = t - r * (EL / 4);
+        const int plane = 32 * rt + r;
+        if (plane < 2 * m && g0 + 4 * wd < total)
+          *reinterpret_cast<uint32_t *>(P.planes + (int64_t)plane * total + g0 + 4 * wd) =
+              *reinterpret_cast<const uint32_t *>(stage + r * EL + 4 * wd);
+      }
+    } else {
+      // the same per prime (its two planes' words for 4 elements), and the
+      // residues of the sum with the addend's into the sum planes
+#pragma unroll
+      for (int i = 0; i < NIT; ++i) {
+        int rp, wd, j;
+        if (item(i, rt, rp, wd, j)) {
+          const int64_t olo = (int64_t)(2 * j) * total + g0 + 4 * wd, ohi = olo + total;
+          const uint32_t xl = *reinterpret_cast<const uint32_t *>(stage + 2 * rp * EL + 4 * wd);
+          const uint32_t xh = *reinterpret_cast<const uint32_t *>(stage + (2 * rp + 1) * EL + 4 * wd);
+          *reinterpret_cast<uint32_t *>(P.planes + olo) = xl;
+          *reinterpret_cast<uint32_t *>(P.planes + ohi) = xh;
+          uint32_t lo4, hi4;
+          residue_sum4(xl, xh, ya[i][0], ya[i][1], (int32_t)yp[i], lo4, hi4);
+          *reinterpret_cast<uint32_t *>(P.sum + olo) = lo4;
+          *reinterpret_cast<uint32_t *>(P.sum + ohi) = hi4;
+        }
+      }
     }
     __syncthreads();
   }
@@ -704,44 +769,6 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
   }
 }
 
-// Residue planes of x + y from those of x and y: per prime the balanced
-// residues (lo + 256 hi, |r| <= (p - 1) / 2) are added, brought back into
-// the balanced range and split again.  Thread: one prime, 4 consecutive
-// plane bytes.
-__global__ __launch_bounds__(256) void rns_add_kernel(const int8_t *x, const int8_t *y, int8_t *out,
-                                                      const int32_t *prime, int m, int64_t plane) {
-  const int64_t words = plane >> 2;
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (int64_t)m * words) return;
-  const int64_t j = t / words, w = t - j * words;
-  const int32_t p = prime[j], half = (p - 1) >> 1;
-  const int64_t olo = 2 * j * plane + 4 * w, ohi = olo + plane;
-  const uint32_t xl = *reinterpret_cast<const uint32_t *>(x + olo), xh = *reinterpret_cast<const uint32_t *>(x + ohi);
-  const uint32_t yl = *reinterpret_cast<const uint32_t *>(y + olo), yh = *reinterpret_cast<const uint32_t *>(y + ohi);
-  uint32_t lo4 = 0u, hi4 = 0u;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int32_t a = (int32_t)(int8_t)(xl >> (8 * u)) + 256 * (int32_t)(int8_t)(xh >> (8 * u));
-    const int32_t b = (int32_t)(int8_t)(yl >> (8 * u)) + 256 * (int32_t)(int8_t)(yh >> (8 * u));
-    int32_t r = a + b;
-    r = r > half ? r - p : (r < -half ? r + p : r);
-    const int32_t lo = ((r + 128) & 255) - 128;
-    lo4 |= ((uint32_t)lo & 0xFFu) << (8 * u);
-    hi4 |= ((uint32_t)((r - lo) >> 8) & 0xFFu) << (8 * u);
-  }
-  *reinterpret_cast<uint32_t *>(out + olo) = lo4;
-  *reinterpret_cast<uint32_t *>(out + ohi) = hi4;
-}
-
-hipError_t launch_rns_add(const int8_t *x, const int8_t *y, int8_t *out, const int32_t *prime, int m,
-                          int64_t plane, hipStream_t s) {
-  if ((plane & 3) != 0 || (((uintptr_t)x | (uintptr_t)y | (uintptr_t)out) & 3) != 0) return hipErrorInvalidValue;
-  const int64_t n = (int64_t)m * (plane >> 2);
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(rns_add_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, out, prime, m, plane);
-  return hipGetLastError();
-}
-
 hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s) {
   const int64_t total = P.lines_pad * P.k_pad;
   if (total == 0) return hipSuccess;
@@ -749,15 +776,24 @@ hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s) {
   if (32 * (S + 32) > 65536 || 4 * P.tab.nw > P.tab.kd) return hipErrorInvalidValue;
   // whole blocks of 32 elements, 16-byte aligned plane rows
   if ((total & 31) != 0 || ((uintptr_t)P.planes & 15) != 0) return hipErrorInvalidValue;
+  if (P.sum && (!P.addend || (((uintptr_t)P.addend | (uintptr_t)P.sum) & 15) != 0)) return hipErrorInvalidValue;
   // digit rows and a tile's staged planes (32 x el bytes)
-  int el = 256;
+  // (with the residue sums at most 128 elements: their addend words take
+  // the registers of a second block per wave)
+  int el = P.sum ? 128 : 256;
   while (el > 32 && (size_t)el * (S + 32) > 65536) el >>= 1;
   const dim3 grid((unsigned)((total + el - 1) / el));
   const size_t lds = (size_t)el * (S + 32);
-  if (el == 256) hipLaunchKernelGGL(rns_slice_kernel<256>, grid, dim3(256), lds, s, P);
-  else if (el == 128) hipLaunchKernelGGL(rns_slice_kernel<128>, grid, dim3(256), lds, s, P);
-  else if (el == 64) hipLaunchKernelGGL(rns_slice_kernel<64>, grid, dim3(256), lds, s, P);
-  else hipLaunchKernelGGL(rns_slice_kernel<32>, grid, dim3(256), lds, s, P);
+  auto go = [&](auto sum) {
+    constexpr bool SUM = decltype(sum)::value;
+    if (el == 256) {
+      if constexpr (!SUM) hipLaunchKernelGGL((rns_slice_kernel<256, false>), grid, dim3(256), lds, s, P);
+    } else if (el == 128) hipLaunchKernelGGL((rns_slice_kernel<128, SUM>), grid, dim3(256), lds, s, P);
+    else if (el == 64) hipLaunchKernelGGL((rns_slice_kernel<64, SUM>), grid, dim3(256), lds, s, P);
+    else hipLaunchKernelGGL((rns_slice_kernel<32, SUM>), grid, dim3(256), lds, s, P);
+  };
+  if (P.sum) go(std::true_type{});
+  else go(std::false_type{});
   return hipGetLastError();
 }
 

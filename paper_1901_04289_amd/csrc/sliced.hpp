@@ -173,6 +173,10 @@ struct RnsSliceParams {
   const int32_t *v2;
   RnsTables tab;
   int8_t *planes;            // [2m][lines_pad][k_pad]
+  // nullable: residue planes of another operand of the same layout; when
+  // set, sum receives the residues of the sum of the two operands
+  const int8_t *addend;
+  int8_t *sum;
 };
 
 struct RnsCrtParams {
@@ -229,8 +233,6 @@ hipError_t launch_mfma_rns(const MfmaRnsParams &P, hipStream_t s);
 
 // Residue planes of a sum of two operands (the (A + B) and (C + D) of the
 // three-product complex form): balanced residues added and re-split.
-hipError_t launch_rns_add(const int8_t *x, const int8_t *y, int8_t *out, const int32_t *prime, int m,
-                          int64_t plane, hipStream_t s);
 
 hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s);
 hipError_t launch_rns_crt(const RnsCrtParams &P, hipStream_t s);

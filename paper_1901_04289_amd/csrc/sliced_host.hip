@@ -601,17 +601,21 @@ int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
       RnsSliceParams pa = sa;
       pa.part[0] = pa.part[1] = q == 0 ? A->re : A->im;
       pa.planes = planesA + q * setA;
+      if (nsets == 3 && q == 1) {   // the imaginary part also forms re + im
+        pa.addend = planesA;
+        pa.sum = planesA + 2 * setA;
+      }
       ARB_TRY(launch_rns_slice(pa, s), "residue slice");
       RnsSliceParams pb = sa;
       pb.part[0] = pb.part[1] = bl.part[q];
       pb.lines = sh.N; pb.off = bl.off; pb.line_stride = bl.line_stride; pb.elem_stride = bl.elem_stride;
       pb.k0 = bl.k0;
       pb.lines_pad = Np; pb.L = LB; pb.v2 = cv2; pb.planes = planesB + q * setB;
+      if (nsets == 3 && q == 1) {
+        pb.addend = planesB;
+        pb.sum = planesB + 2 * setB;
+      }
       ARB_TRY(launch_rns_slice(pb, s), "residue slice");
-    }
-    if (nsets == 3) {
-      ARB_TRY(launch_rns_add(planesA, planesA + setA, planesA + 2 * setA, tab.prime, m, Mp * Kp, s), "residue sum");
-      ARB_TRY(launch_rns_add(planesB, planesB + setB, planesB + 2 * setB, tab.prime, m, Np * Kp, s), "residue sum");
     }
   }
   MfmaRnsParams mp;
