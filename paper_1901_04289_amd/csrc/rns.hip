@@ -30,11 +30,12 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *cp(const T
   return (const __attribute__((address_space(4))) T *)p;
 }
 
-// x mod p for 0 <= x < 2^32 (Barrett with mu = floor(2^32 / p): the
-// quotient estimate is short by at most one, so one correction suffices).
+// x mod p for 0 <= x < 2^32 and 2^14 < p < 2^15 (Barrett with mu =
+// floor(2^32 / p): the quotient estimate is short by at most one, so one
+// correction suffices; it is below 2^18, so q p is an exact 24-bit product).
 __device__ __forceinline__ uint32_t mod_u32(uint32_t x, uint32_t p, uint32_t mu) {
   const uint32_t q = __umulhi(x, mu);
-  const uint32_t r = x - q * p;
+  const uint32_t r = x - __umul24(q, p);
   return r >= p ? r - p : r;
 }
 
@@ -736,17 +737,21 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
     const bool live = ij < MN;
     uint32_t *T = tl + e3;
     if (part3 == 0 && live) {
+      // a chunk changes only where a carry reaches it (after a run's end,
+      // until the carry is absorbed)
       int64_t c = 0;
       for (int cc = 0; cc < P.tab.ncc; ++cc) {
-        uint32_t t[8];
-#pragma unroll
-        for (int g = 0; g < 8; ++g) t[g] = 8 * cc + g < W ? T[(8 * cc + g) * EW] : 0u;
         const int32_t co = cyl[cc * EW + e3];
+        if (c != 0) {
+          uint32_t t[8];
 #pragma unroll
-        for (int g = 0; g < 8; ++g) {
-          const int64_t v = (int64_t)t[g] + c;
-          if (8 * cc + g < W) T[(8 * cc + g) * EW] = (uint32_t)v;
-          c = v >> 32;
+          for (int g = 0; g < 8; ++g) t[g] = 8 * cc + g < W ? T[(8 * cc + g) * EW] : 0u;
+#pragma unroll
+          for (int g = 0; g < 8; ++g) {
+            const int64_t v = (int64_t)t[g] + c;
+            if (8 * cc + g < W) T[(8 * cc + g) * EW] = (uint32_t)v;
+            c = v >> 32;
+          }
         }
         c += co;
       }
