@@ -28,6 +28,8 @@ arbgpu_ctx::~arbgpu_ctx() {
   }
   for (auto &b : ws)
     if (b.ptr && b.owned) (void)hipFree(b.ptr);
+  if (ev_stats) (void)hipEventDestroy(ev_stats);
+  if (stats_host) (void)hipHostFree(stats_host);
 }
 
 namespace arbgpu_impl {

@@ -62,6 +62,10 @@ struct arbgpu_ctx {
   std::string tune_path;
   arbgpu_impl::Server *server = nullptr;   // started by the first submit
   int64_t rns_key = -1;                    // residue tables in the workspace (primes, digit words)
+  // the line statistics' maxima read back through pinned memory, and the
+  // event that marks their arrival (created on first use)
+  int32_t *stats_host = nullptr;
+  hipEvent_t ev_stats = nullptr;
   ~arbgpu_ctx();
 };
 

@@ -37,12 +37,18 @@ int32_t *stats_ws(arbgpu_ctx *ctx, const Shape &sh) {
   return (int32_t *)ws_get(ctx, WS_STATS, sizeof(int32_t) * (size_t)(2 * sh.M + 2 * sh.N + 8));
 }
 
+struct Lines;
+int b_lines(arbgpu_ctx *ctx, const arbgpu_mat *B, bool cplx, int64_t k0, int64_t k1, hipStream_t s, Lines &L);
+
 // Line statistics of A's rows and B's columns over the inner range [k0, k1):
 // per-line lowest set bit (left in the workspace for slicing) and the
 // global maxima g[0..3] (A) and g[4..7] (B) as described in StatsParams.
-// Synchronizes s to read the maxima back.
+// Waits for the maxima to read them back.  With `pre` (not for a context
+// on fixed scratch), B's lines for [k0, k1) are also prepared, their copy
+// queued behind the readback so that it runs while the host waits and
+// plans; *pre_ok tells whether that was done.
 int line_stats(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const Shape &sh, int64_t k0, int64_t k1,
-               int32_t *st, hipStream_t s, int32_t g[8]) {
+               int32_t *st, hipStream_t s, int32_t g[8], Lines *pre = nullptr, bool *pre_ok = nullptr) {
   int32_t *rtop = st, *rv2 = st + sh.M, *ctop = st + 2 * sh.M, *cv2 = st + 2 * sh.M + sh.N;
   int32_t *gA = st + 2 * sh.M + 2 * sh.N, *gB = gA + 4;
   ARB_TRY(launch_fill_i32(gA, 0, 8, s), "fill");
@@ -64,6 +70,22 @@ int line_stats(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const 
     KernelTimer t_stats(ctx, "stats", s);
     ARB_TRY(launch_stats_rows(sp, s), "stats");
     ARB_TRY(launch_stats_cols(sq, s), "stats");
+  }
+  if (pre_ok) *pre_ok = false;
+  if (pre && ctx->bump_size == 0) {
+    if (!ctx->stats_host) ARB_TRY(hipHostMalloc((void **)&ctx->stats_host, 8 * sizeof(int32_t)), "stats readback");
+    if (!ctx->ev_stats) ARB_TRY(hipEventCreateWithFlags(&ctx->ev_stats, hipEventDisableTiming), "stats readback");
+    ARB_TRY(hipMemcpyAsync(ctx->stats_host, gA, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s), "stats readback");
+    ARB_TRY(hipEventRecord(ctx->ev_stats, s), "stats readback");
+    {
+      KernelTimer t_slice(ctx, "slice", s);
+      const int rc = b_lines(ctx, B, sh.cplx, k0, k1, s, *pre);
+      if (rc) return rc;
+    }
+    ARB_TRY(hipEventSynchronize(ctx->ev_stats), "stats readback");
+    memcpy(g, ctx->stats_host, 8 * sizeof(int32_t));
+    if (pre_ok) *pre_ok = true;
+    return ARBGPU_OK;
   }
   ARB_TRY(hipMemcpyAsync(g, gA, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s), "stats readback");
   ARB_TRY(hipStreamSynchronize(s), "stats readback");
@@ -112,6 +134,14 @@ int b_lines(arbgpu_ctx *ctx, const arbgpu_mat *B, bool cplx, int64_t k0, int64_t
   }
   if (!cplx) L.part[1] = L.part[0];
   L.off = 0; L.line_stride = Kb; L.elem_stride = 1; L.k0 = 0;
+  return ARBGPU_OK;
+}
+
+// B's lines for the inner range from k0 on, from lines prepared for the
+// whole inner range (b_lines from 0).
+int lines_of(const Lines &whole, int64_t k0, Lines &L) {
+  L = whole;
+  L.k0 = whole.k0 + k0;
   return ARBGPU_OK;
 }
 
@@ -361,7 +391,7 @@ inline int t_limbs(int LA, int LB) { return (LA + LB - 1 + 3) / 4 + 2; }
 int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const Shape &sh, int64_t k0,
                       int64_t k1, const int32_t *st, int HA, int HB, const arbgpu_out *out, int64_t o_off,
                       int64_t o_rs, int64_t o_cs, int p, bool out_approx, double *const rin_m[2],
-                      int32_t *const rin_e[2], hipStream_t s, bool four, const TSink *ts);
+                      int32_t *const rin_e[2], hipStream_t s, bool four, const TSink *ts, const Lines *pre);
 
 // Copies the exact T of output part q (limbs [n][M N] in the workspace) to
 // the caller's sink, when there is one.
@@ -379,10 +409,11 @@ constexpr int kTruncSlack = 64;
 int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const Shape &sh, int64_t k0, int64_t k1,
                   const int32_t *st, int HA, int HB, const arbgpu_out *out, int64_t o_off, int64_t o_rs, int64_t o_cs,
                   int p, bool out_approx, double *const rin_m[2], int32_t *const rin_e[2], hipStream_t s,
-                  bool rns, bool four = false, const TSink *ts = nullptr, bool trunc = false) {
+                  bool rns, bool four = false, const TSink *ts = nullptr, bool trunc = false,
+                  const Lines *pre = nullptr) {
   if (rns)
     return rns_block_product(ctx, A, B, sh, k0, k1, st, HA, HB, out, o_off, o_rs, o_cs, p, out_approx, rin_m, rin_e,
-                             s, four, ts);
+                             s, four, ts, pre);
   const int32_t *rv2 = st + sh.M, *cv2 = st + 2 * sh.M + sh.N;
   const int64_t Kb = k1 - k0;
   const int64_t Kt = sh.cplx ? 2 * Kb : Kb;
@@ -474,7 +505,7 @@ int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, con
   Lines bl;
   {
     KernelTimer t_slice(ctx, "slice", s);
-    int rc = b_lines(ctx, B, sh.cplx, k0, k1, s, bl);
+    int rc = pre ? lines_of(*pre, k0, bl) : b_lines(ctx, B, sh.cplx, k0, k1, s, bl);
     if (rc) return rc;
     ARB_TRY(launch_slice(sa, s), "slice");
     for (int q = 0; q < sh.nparts; ++q) {
@@ -553,7 +584,7 @@ int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, con
 int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const Shape &sh, int64_t k0,
                       int64_t k1, const int32_t *st, int HA, int HB, const arbgpu_out *out, int64_t o_off,
                       int64_t o_rs, int64_t o_cs, int p, bool out_approx, double *const rin_m[2],
-                      int32_t *const rin_e[2], hipStream_t s, bool four, const TSink *ts) {
+                      int32_t *const rin_e[2], hipStream_t s, bool four, const TSink *ts, const Lines *pre) {
   const int32_t *rv2 = st + sh.M, *cv2 = st + 2 * sh.M + sh.N;
   const int64_t Kb = k1 - k0;
   const int64_t Kt = sh.cplx ? 2 * Kb : Kb;   // terms of one output value
@@ -595,7 +626,7 @@ int rns_block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B,
   Lines bl;
   {
     KernelTimer t_slice(ctx, "slice", s);
-    rc = b_lines(ctx, B, sh.cplx, k0, k1, s, bl);
+    rc = pre ? lines_of(*pre, k0, bl) : b_lines(ctx, B, sh.cplx, k0, k1, s, bl);
     if (rc) return rc;
     for (int q = 0; q < sh.nparts; ++q) {
       RnsSliceParams pa = sa;
@@ -999,8 +1030,11 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
   int32_t *st = stats_ws(ctx, sh);
   if (!st) return ARBGPU_ENOMEM;
   int32_t g[8];
-  int rc = line_stats(ctx, A, B, sh, 0, sh.K, st, s, g);
+  Lines pre;
+  bool pre_ok = false;
+  int rc = line_stats(ctx, A, B, sh, 0, sh.K, st, s, g, &pre, &pre_ok);
   if (rc) return rc;
+  const Lines *bpre = pre_ok ? &pre : nullptr;
   if (g[2] || g[6]) return kNotApplicable;   // out-of-range exponents: flagged per entry by the limb kernel
   const int hmax = height_bound(p, g[1], g[5]);
   const bool radA = A->re.rad_m || (sh.cplx && A->im.rad_m);
@@ -1033,7 +1067,7 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
       if (rc) return rc;
     }
     return block_product(ctx, A, B, sh, 0, sh.K, st, g[0], g[4], outs, C->off, C->rs, C->cs, (int)p, sh.approx,
-                         rin_m, rin_e, s, rns, (flags & ARBGPU_COMPLEX_4M) != 0, nullptr, true);
+                         rin_m, rin_e, s, rns, (flags & ARBGPU_COMPLEX_4M) != 0, nullptr, true, bpre);
   }
 
   // ---- several blocks (Algorithm 2's greedy partition) ----------------------
@@ -1103,7 +1137,7 @@ int sliced_mat_mul(arbgpu_ctx *ctx, const arbgpu_omat *C, const arbgpu_mat *A, c
     const int64_t ktb = sh.cplx ? 2 * (b.k1 - b.k0) : b.k1 - b.k0;
     const bool rns = use_rns(b.ha, b.hb, ktb) && rns_fits(b.ha, b.hb, ktb);
     rc = block_product(ctx, A, B, sh, b.k0, b.k1, bst, b.ha, b.hb, tout, 0, sh.N, 1, 32 * capT, true, no_m, no_e, s,
-                       rns, (flags & ARBGPU_COMPLEX_4M) != 0);
+                       rns, (flags & ARBGPU_COMPLEX_4M) != 0, nullptr, false, bpre);
     if (rc) return rc;
     ++si;
   }
