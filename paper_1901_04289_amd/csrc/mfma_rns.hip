@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, TM == 25
   const int t = slot % ntiles;
   const int q = g / P.mpad, j = g - q * P.mpad;
   if (j >= P.m) return;   // padding prime
-  const int32_t pj = P.prime[j], muj = (int32_t)P.mu[j];
+  const int32_t pj = P.prime[j], muj = (int32_t)P.mu[j], m256p = -256 * pj;
   const int tm = t / P.ntn, tn = t - tm * P.ntn;
   const int ksteps = (int)(P.Kp / kKStep);
   const int nsteps = 4 * ksteps;
@@ -92,10 +92,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, TM == 25
     const int b = pr < 2 ? 1 : 0;
     const char *pa = tileA + a * planeA + ks * kKStep;
     const char *pb = tileB + b * planeB + ks * kKStep;
+    // the lane offset is opaque here, so the compiler keeps a scalar base
+    // per step and the 32-bit offset instead of 64-bit lane addresses
+    // hoisted out of the loop (which spilled)
+    uint32_t go = goff;
+    asm volatile("" : "+v"(go));
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      sa[u] = *reinterpret_cast<const v4i *>(pa + (goff + u * rowstep));
-      sb[u] = *reinterpret_cast<const v4i *>(pb + (goff + u * rowstep));
+      sa[u] = *reinterpret_cast<const v4i *>(pa + (go + u * rowstep));
+      sb[u] = *reinterpret_cast<const v4i *>(pb + (go + u * rowstep));
     }
   };
   auto lstore = [&](const v4i (&sa)[U], const v4i (&sb)[U], int buf) {
@@ -191,16 +196,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, TM == 25
           // on the accumulation register itself, through two vector
           // temporaries: left to the compiler, all the accumulators were
           // moved to vector registers together and spilled
+          // 256 x - q (256 p_j) in one 24-bit multiply-add: |q| < 2^17 and
+          // 256 p_j < 2^23 fit its signed 24-bit factors, and the result,
+          // 256 (x - q p_j), is below 2^24 in magnitude, so its value mod
+          // 2^32 is exact
           int32_t acv = acc[i][jj][r], t0, t1;
           asm volatile(
               "v_accvgpr_read_b32 %1, %0\n\t"
               "v_mul_hi_i32 %2, %1, %3\n\t"
-              "v_mul_i32_i24 %2, %4, %2\n\t"
-              "v_sub_u32 %1, %1, %2\n\t"
               "v_lshlrev_b32 %1, 8, %1\n\t"
+              "v_mad_i32_i24 %1, %2, %4, %1\n\t"
               "v_accvgpr_write_b32 %0, %1"
               : "+a"(acv), "=&v"(t0), "=&v"(t1)
-              : "s"(muj), "s"(pj));
+              : "s"(muj), "s"(m256p));
           acc[i][jj][r] = acv;
         }
         // one block of 16 registers at a time
