@@ -611,14 +611,13 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
   // carry out (zero for the other chunks)
   {
     const int lane = tid & 63, wave = tid >> 6, h = lane >> 5;
-    // entry blocks; runs per block: with 64 entries two waves walk all
-    // chunks of a block each (splitting them further measured slower, the
-    // carry pass below costing more than the shorter walks gain), unless
-    // PAIR: then each wave takes a quarter of the chunks of both blocks,
+    // entry blocks; runs per block: with 64 entries two runs of chunks per
+    // block, one wave each (phase 3 adds the runs' carries), unless PAIR:
+    // then each wave takes a quarter of the chunks of both blocks,
     // and every weight fragment feeds the products of both (for long
     // limb counts, where those fragments' traffic dominates); with 32
     // entries the four waves share the one block
-    constexpr int NB = EW / 32, RB = (EW == 32 || PAIR) ? 4 : 1, NBW = PAIR ? 2 : 1;
+    constexpr int NB = EW / 32, RB = (EW == 32 || PAIR) ? 4 : 2, NBW = PAIR ? 2 : 1;
     const int ncc = P.tab.ncc, rl = (ncc + RB - 1) / RB, nks = kc / 32;
     const int wv0 = PAIR ? 0 : wave % NB, run = PAIR ? wave : wave / NB;
     const int c0 = run * rl, c1 = min(c0 + rl, ncc);
@@ -702,18 +701,20 @@ __global__ __launch_bounds__(256) void rns_crt_kernel(RnsCrtParams P) {
       if (ij >= MN) return;
       uint32_t *T = tl + tid;
       // the runs' carries, added in limb order (a chunk's 8 limbs are read
-      // together)
+      // together; a chunk changes only where a carry reaches it)
       int64_t c = 0;
-      for (int cc = 0; EW == 32 && cc < P.tab.ncc; ++cc) {
-        uint32_t t[8];
-#pragma unroll
-        for (int g = 0; g < 8; ++g) t[g] = 8 * cc + g < W ? T[(8 * cc + g) * EW] : 0u;
+      for (int cc = 0; cc < P.tab.ncc; ++cc) {
         const int32_t co = cyl[cc * EW + tid];
+        if (c != 0) {
+          uint32_t t[8];
 #pragma unroll
-        for (int g = 0; g < 8; ++g) {
-          const int64_t v = (int64_t)t[g] + c;
-          if (8 * cc + g < W) T[(8 * cc + g) * EW] = (uint32_t)v;
-          c = v >> 32;
+          for (int g = 0; g < 8; ++g) t[g] = 8 * cc + g < W ? T[(8 * cc + g) * EW] : 0u;
+#pragma unroll
+          for (int g = 0; g < 8; ++g) {
+            const int64_t v = (int64_t)t[g] + c;
+            if (8 * cc + g < W) T[(8 * cc + g) * EW] = (uint32_t)v;
+            c = v >> 32;
+          }
         }
         c += co;
       }
@@ -827,9 +828,9 @@ hipError_t launch_rns_crt(const RnsCrtParams &P, hipStream_t s) {
   if (many && P.tab.ncc >= 8 && rns_crt_lds(64, kc, W, true) <= 81920) {
     hipLaunchKernelGGL((rns_crt_kernel<64, true>), dim3((unsigned)((MN + 63) / 64)), dim3(256),
                        rns_crt_lds(64, kc, W, true), s, P);
-  } else if (many && rns_crt_lds(64, kc, W, false) <= 65536) {
+  } else if (many && rns_crt_lds(64, kc, W, true) <= 65536) {
     hipLaunchKernelGGL((rns_crt_kernel<64, false>), dim3((unsigned)((MN + 63) / 64)), dim3(256),
-                       rns_crt_lds(64, kc, W, false), s, P);
+                       rns_crt_lds(64, kc, W, true), s, P);
   } else {
     hipLaunchKernelGGL((rns_crt_kernel<32, false>), dim3((unsigned)((MN + 31) / 32)), dim3(256),
                        rns_crt_lds(32, kc, W, true), s, P);
