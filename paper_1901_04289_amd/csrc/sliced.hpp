@@ -231,9 +231,6 @@ struct MfmaRnsParams {
 };
 hipError_t launch_mfma_rns(const MfmaRnsParams &P, hipStream_t s);
 
-// Residue planes of a sum of two operands (the (A + B) and (C + D) of the
-// three-product complex form): balanced residues added and re-split.
-
 hipError_t launch_rns_slice(const RnsSliceParams &P, hipStream_t s);
 hipError_t launch_rns_crt(const RnsCrtParams &P, hipStream_t s);
 // dynamic LDS of the reconstruction kernel for ew entries per workgroup
