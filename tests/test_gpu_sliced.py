@@ -398,3 +398,34 @@ def test_truncated_slices_certify_or_fall_back(ctx):
     for i in rows:
         for j in zero_cols:
             assert out.nls[i * K + j] == 0   # exact zeros
+
+
+@pytest.mark.parametrize("p", [512, 1024])
+def test_rns_complex_three_products_equal_four_and_limb(ctx, p):
+    # 65536 complex entries: the imaginary parts' slicers form the residues
+    # of re + im (128 elements per workgroup), the reconstruction runs 64
+    # entries per workgroup (two runs of chunks per block at p = 512, the
+    # paired blocks at p = 1024); the three-product form, the four-product
+    # form and the limb kernel give the same midpoints everywhere
+    rng = gen.rng_for(31, p)
+    M, N, K = 256, 64, 256
+    prec = rng.integers(p // 2, p + 1, 4 * M * N)
+    A = gen.random_operands(rng, M * N, prec[:M * N], -6, 6, radius_shift=p - 8, zero_frac=0.05)
+    B = gen.random_operands(rng, N * K, prec[M * N:M * N + N * K], -6, 6, zero_frac=0.05)
+    Ai = gen.random_operands(rng, M * N, prec[2 * M * N:3 * M * N], -6, 6, zero_frac=0.05)
+    Bi = gen.random_operands(rng, N * K, prec[3 * M * N:3 * M * N + N * K], -6, 6, radius_shift=p - 8)
+    say(f"complex 256x64x256 p={p}: three products, four products, limb kernel")
+    base = arbgpu.COMPLEX | arbgpu.ALGO_RNS
+    (o3, s3), (i3, t3) = run(ctx, A, B, M, N, K, p, base, Ai=Ai, Bi=Bi)
+    (o4, s4), (i4, t4) = run(ctx, A, B, M, N, K, p, base | arbgpu.COMPLEX_4M, Ai=Ai, Bi=Bi)
+    (ol, sl), (il, tl) = run(ctx, A, B, M, N, K, p, arbgpu.COMPLEX | arbgpu.ALGO_LIMB, Ai=Ai, Bi=Bi)
+    for a, b in ((o3, o4), (i3, i4), (o3, ol), (i3, il)):
+        assert np.array_equal(a.limbs, b.limbs)
+        assert np.array_equal(a.exp, b.exp) and np.array_equal(a.nls, b.nls)
+    r = random.Random(31)
+    for i, j in [(r.randrange(M), r.randrange(K)) for _ in range(6)] + [(0, 0), (M - 1, K - 1)]:
+        x = [(gen.to_canonical(A, i * N + k), gen.to_canonical(Ai, i * N + k)) for k in range(N)]
+        y = [(gen.to_canonical(B, k * K + j), gen.to_canonical(Bi, k * K + j)) for k in range(N)]
+        re, imv = oracle.cdot(x, y, p)
+        assert compare_entry(gen.to_canonical(o3, i * K + j), re, int(s3[i * K + j])) is None
+        assert compare_entry(gen.to_canonical(i3, i * K + j), imv, int(t3[i * K + j])) is None
