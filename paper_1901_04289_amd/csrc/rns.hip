@@ -275,7 +275,10 @@ __device__ void finish_entry_split(const uint32_t *T, int W, int64_t scale, cons
 // consecutive elements (the LDS rows are permuted for that) into an LDS
 // stage of the tile's 32 planes; the workgroup then stores each plane's
 // row of EL bytes whole (the padded plane holds whole blocks of 32
-// elements and starts 16-byte aligned).
+// elements and starts 16-byte aligned).  SUM (the imaginary part of an
+// operand of the three-product complex form): the store pass also adds
+// the real part's residues (P.addend, same layout), requested at the
+// tile's start, and stores the residues of re + im into P.sum.
 //
 // With the stage the 256-element form's LDS (about 37 KiB at p = 512)
 // admits four workgroups per CU, so registers are capped for four waves
