@@ -28,7 +28,7 @@ hipError_t launch_mm_shape<ARB_NS, ARB_NA>(const MmParams &prm, hipStream_t s) {
 template <>
 hipError_t launch_mm_list_shape<ARB_NS, ARB_NA>(const MmParams &prm, const int64_t *list, const int32_t *count,
                                                 int64_t max_count, hipStream_t s) {
-  const int64_t blocks = std::min<int64_t>((max_count + 255) / 256, 1024);
+  const int64_t blocks = std::min<int64_t>((max_count + 3) / 4, 1024);   // four entries (waves) per workgroup
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL((limb_mm_list_kernel<ARB_NS, ARB_NA>), dim3((unsigned)blocks), dim3(256), 0, s, prm, list, count);
   return hipGetLastError();

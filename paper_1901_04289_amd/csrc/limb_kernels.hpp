@@ -333,29 +333,33 @@ __global__ __launch_bounds__(256) void limb_mm_wave_kernel(MmParams prm) {
                   status_of(out, fell_back));
 }
 
-// Listed entries (index i K + j) of a matrix product, one lane each, as
-// limb_mm_kernel: the exact recomputation of the entries whose truncation
-// a truncated integer product could not certify.  The grid strides over
-// the list, whose length the device holds.
+// Listed entries (index i K + j) of a matrix product, one wave each, as
+// limb_mm_wave_kernel: the exact recomputation of the entries whose
+// truncation a truncated integer product could not certify (a few entries
+// of a large product, each with its whole inner length: a wave per entry
+// keeps one such entry from taking a single lane through all its terms).
+// The waves stride over the list, whose length the device holds.
 template <int NS, int NA>
 __global__ __launch_bounds__(256) void limb_mm_list_kernel(MmParams prm, const int64_t *list, const int32_t *count) {
   const int64_t n = *gp(count);
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) {
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); t < n; t += nw) {   // uniform across the wave
     const int64_t ij = gp(list)[t];
     const int64_t i = ij / prm.K, j = ij - i * prm.K;
     const int64_t abase = prm.a_off + i * prm.a_rs;
     const int64_t bbase = prm.b_off + j * prm.b_cs;
     DotOut<NS> out;
     MmSrc<Opnd<NA>> src{&prm, abase, bbase};
-    run_dot<NS, Opnd<NA>, SoloReducer>(src, prm.p, !prm.approx, out);
+    run_dot<NS, Opnd<NA>, WaveReducer>(src, prm.p, !prm.approx, out);
     bool fell_back = false;
-    if (out.st.bad) {
+    if (out.st.bad) {   // uniform across the wave
       MmSrc<SOpnd> s2{&prm, abase, bbase};
-      run_dot<NS, SOpnd, SoloReducer>(s2, prm.p, !prm.approx, out);
+      run_dot<NS, SOpnd, WaveReducer>(s2, prm.p, !prm.approx, out);
       fell_back = true;
     }
-    store_out<NS>(prm.C, prm.c_off + i * prm.c_rs + j * prm.c_cs, out, prm.p, prm.approx,
-                  status_of(out, fell_back));
+    if ((threadIdx.x & 63) == 0)
+      store_out<NS>(prm.C, prm.c_off + i * prm.c_rs + j * prm.c_cs, out, prm.p, prm.approx,
+                    status_of(out, fell_back));
   }
 }
 

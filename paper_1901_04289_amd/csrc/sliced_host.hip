@@ -403,8 +403,11 @@ int t_to_sink(arbgpu_ctx *ctx, const TSink *ts, int q, const uint32_t *T, int n,
 
 // Headroom of the truncated diagonal set: the left-out diagonals stay
 // below 2^(bits of |T|'s bound - p - kTruncSlack), so every entry within
-// kTruncSlack - 3 bits of that bound certifies its truncation.
-constexpr int kTruncSlack = 64;
+// kTruncSlack - 3 bits of that bound certifies its truncation.  Entries
+// further below it (cancellation) are recomputed exactly, a wave each; at
+// 32 bits they are rare, and each 8 bits less leave out about one more
+// diagonal of slice pairs.
+constexpr int kTruncSlack = 32;
 
 int block_product(arbgpu_ctx *ctx, const arbgpu_mat *A, const arbgpu_mat *B, const Shape &sh, int64_t k0, int64_t k1,
                   const int32_t *st, int HA, int HB, const arbgpu_out *out, int64_t o_off, int64_t o_rs, int64_t o_cs,
